@@ -1,0 +1,218 @@
+/*
+ * pa.h -- C ABI of the MI355X hot path for preconditioned adjoint data
+ * assimilation of 2D turbulence (Ke, You & Wang, arXiv 2602.14016).
+ *
+ * What is computed
+ *   Forward model: 2D incompressible Navier-Stokes (Sec. II.A, Eq. (1)), with
+ *   the Kolmogorov body force f = (A sin(n_f y), 0) when forcing_amp != 0
+ *   (Sec. III.E, Eq. (24)), integrated in vorticity form on the periodic box
+ *   [0, 2pi)^2 on an N x N grid:
+ *       d omega/dt = -(nu |k|^2 + mu) omega - P(u . grad omega) + P curl f
+ *   with the 2/3-rule projector P (modes |kx|, |ky| <= Kc, k != 0, Kc the
+ *   largest integer below N/3), u = d_y psi, v = -d_x psi, -Lap psi = omega,
+ *   and the integrating-factor (Lawson) RK4 scheme with step dt.
+ *   Cost (Sec. II.A, Eqs. (2)-(3)): J = 1/2 sum over observation steps and
+ *   probes (x = i*stride, y = j*stride) of |u - m|^2, both components.
+ *   Gradient: the exact discrete adjoint of that scheme (the paper's
+ *   summation-by-parts adjoint, Sec. III; continuous form Eqs. (11)-(12)),
+ *   returned as dJ/d omega0 in the grid-Euclidean inner product.
+ *   Preconditioner: Fourier multiplier (m(k)^2 W(|k|))^p with W one of the
+ *   kernels of Sec. III.B (plus exp(-sigma|k|)), m^2 = |k|^2 (velocity
+ *   metric) or 1 (vorticity metric); latent control s = G^(-1/2) omega0 and
+ *   latent gradient G^(1/2) dJ/domega0 (Sec. II.B-C, Eqs. (13)-(19)).
+ *   Optimiser: L-BFGS or steepest descent in the latent control (Sec. II.C).
+ *
+ * Conventions
+ *   - Every function returns pa_status: PA_OK (0) or a negative error code.
+ *     Nothing throws or aborts across the ABI; pa_last_error() returns a
+ *     message for the calling thread's most recent failure.
+ *   - Arguments are validated before any device call; on a validation error
+ *     nothing is enqueued and no output is touched.
+ *   - "device" pointers are HIP device memory owned by the caller (e.g. torch
+ *     tensors); "host" pointers are ordinary host memory.  The library owns only
+ *     the opaque context (plans and small constant tables it allocates in
+ *     pa_create and frees in pa_destroy).
+ *   - Work is enqueued asynchronously on the context's HIP stream (set at
+ *     creation or with pa_set_stream).  Functions that return host values
+ *     synchronise that stream; the others do not.
+ *   - Physical fields are FP64 arrays [B][N][N], row-major, f[b][j][i] at
+ *     (x_i, y_j) = (2 pi i / N, 2 pi j / N).  All arithmetic is FP64.
+ *   - Workspaces and checkpoint buffers are opaque device memory of the size
+ *     reported by the *_bytes queries, 256-byte aligned, caller-owned.  Calls
+ *     that share a workspace on one stream are serialised by the stream;
+ *     concurrent calls on different streams need different workspaces.
+ */
+#ifndef PA_H
+#define PA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t pa_status;
+
+#define PA_OK            0
+#define PA_EINVAL       (-1)  /* bad argument (size, pointer, parameter)      */
+#define PA_ENOMEM       (-2)  /* workspace too small / device allocation failed */
+#define PA_EDEVICE      (-3)  /* HIP runtime error or no device                */
+#define PA_ENONFINITE   (-4)  /* non-finite value met (reported per member)    */
+#define PA_ELINESEARCH  (-5)  /* Armijo line search failed (step collapse)     */
+#define PA_EUNSUPPORTED (-6)  /* valid request this build does not support     */
+
+typedef struct pa_ctx pa_ctx;
+
+/* Physical parameters (Sec. II.A Eq. (1), Sec. III.E Eq. (24)).
+ * nu >= 0 viscosity, mu >= 0 linear drag, dt > 0 time step,
+ * forcing_amp = A and forcing_k = n_f of f = (A sin(n_f y), 0); A = 0: decaying. */
+typedef struct pa_physics {
+    double  nu;
+    double  mu;
+    double  dt;
+    double  forcing_amp;
+    int32_t forcing_k;
+    int32_t reserved;          /* must be 0 */
+} pa_physics;
+
+/* Observation set (Sec. II.A Eq. (3)).  Probes at (x, y) = (i*stride, j*stride)
+ * grid points, i, j in [0, M), M = N / stride; stride must divide N.
+ * steps: host array of n_times strictly increasing step indices in
+ * [0, n_steps].  values: device array [B][n_times][2][M][M] (component 0 = u,
+ * 1 = v), or NULL when only model observations are wanted.  Caller-owned. */
+typedef struct pa_obs {
+    int32_t        stride;
+    int32_t        n_times;
+    const int32_t* steps;
+    const double*  values;
+} pa_obs;
+
+/* Weighting kernel W(|k|) and control metric (Sec. II.B-C; Sec. III.B).
+ * kind 0: identity W = 1
+ *      1: exponential W = exp(-param |k|)
+ *      2: fractional  W = |k|^(-2 param)
+ *      3: heat kernel W = exp(-param |k|^2)    (param = nu*beta of the paper)
+ * metric 0: velocity (m^2 = |k|^2), 1: vorticity (m^2 = 1).  W(0) = 1. */
+typedef struct pa_kernel {
+    int32_t kind;
+    int32_t metric;
+    double  param;
+} pa_kernel;
+
+/* Create a context for B fields of size N x N (N a power of two in
+ * [8, 1024], B >= 1) with the given physics, enqueueing on hip_stream
+ * (hipStream_t, NULL = default stream).  Allocates small constant tables on
+ * the current device.  Errors: PA_EINVAL (bad sizes/parameters, NULL out),
+ * PA_EDEVICE (no device / HIP failure), PA_ENOMEM. */
+pa_status pa_create(const pa_physics* phys, int32_t N, int32_t B,
+                    void* hip_stream, pa_ctx** out);
+
+/* Destroy a context (NULL is accepted).  Synchronises its stream first. */
+pa_status pa_destroy(pa_ctx* ctx);
+
+/* Change the stream later calls enqueue on. */
+pa_status pa_set_stream(pa_ctx* ctx, void* hip_stream);
+
+/* Message for the calling thread's most recent error ("" if none). */
+const char* pa_last_error(void);
+
+/* Query: N, B, Kc (band limit) of a context. */
+pa_status pa_get_shape(const pa_ctx* ctx, int32_t* N, int32_t* B, int32_t* Kc);
+
+/* Workspace bytes for a gradient over n_steps with checkpoints every
+ * ckpt_every steps (1 <= ckpt_every), n_obs_times observation times, and an
+ * L-BFGS memory lbfgs_m (0 when not assimilating).  Any call documented as
+ * taking "a workspace" accepts one of at least this size for its arguments;
+ * pa_precondition and pa_init_field need pa_workspace_bytes(ctx,0,1,0,0). */
+pa_status pa_workspace_bytes(const pa_ctx* ctx, int32_t n_steps, int32_t ckpt_every,
+                             int32_t n_obs_times, int32_t lbfgs_m, size_t* bytes);
+
+/* Bytes of the checkpoint buffer written by pa_forward (ceil(n_steps /
+ * ckpt_every) + 1 spectral states per member). */
+pa_status pa_checkpoint_bytes(const pa_ctx* ctx, int32_t n_steps, int32_t ckpt_every,
+                              size_t* bytes);
+
+/* Seeded initial vorticity fields (Sec. III: prescribed spectrum, random
+ * phases, normalised energy).  seeds: host [B].  kind 0: random phase with
+ * |omega_hat| = sqrt(|k| E(|k|)), E(k) = k^4 exp(-2 (k/k0)^2), kinetic
+ * energy 1/2 <|u|^2> = target; kind 1: same spectrum with complex Gaussian
+ * coefficients; kind 2: white noise on the de-aliased band with RMS(omega) =
+ * target.  Random numbers: SplitMix64 keyed by (seed, wavevector, stream), so
+ * a seed gives the same low modes at every N.  omega_out: device [B][N][N]. */
+pa_status pa_init_field(pa_ctx* ctx, const uint64_t* seeds, int32_t kind, double k0,
+                        double target, double* omega_out, void* workspace,
+                        size_t workspace_bytes);
+
+/* Forward solve over n_steps from omega0 (device [B][N][N]; P is applied to
+ * it first).  Optional outputs (NULL to skip):
+ *   omega_T  device [B][N][N]   final vorticity
+ *   obs      observation set; with obs->values the cost J is computed
+ *   J_out    device [B]         cost per member (needs obs->values)
+ *   obs_out  device [B][n_times][2][M][M]  model observations M u
+ *   ckpt     device, pa_checkpoint_bytes: spectral states every ckpt_every
+ *            steps, the input of pa_adjoint_from_checkpoints. */
+pa_status pa_forward(pa_ctx* ctx, const double* omega0, int32_t n_steps,
+                     const pa_obs* obs, double* J_out, double* obs_out, double* omega_T,
+                     int32_t ckpt_every, void* ckpt, void* workspace, size_t workspace_bytes);
+
+/* Gradient dJ/d omega0 (device [B][N][N]) and J (device [B], may be NULL)
+ * by a checkpointed forward sweep, segment-wise recomputation and the
+ * discrete adjoint sweep.  obs->values is required. */
+pa_status pa_adjoint_gradient(pa_ctx* ctx, const double* omega0, int32_t n_steps,
+                              const pa_obs* obs, double* J_out, double* grad_out,
+                              int32_t ckpt_every, void* workspace, size_t workspace_bytes);
+
+/* Same gradient from the checkpoints a previous pa_forward wrote (same
+ * n_steps, ckpt_every, obs steps).  scale: device [B] or NULL; the gradient of
+ * member b is multiplied by scale[b] (the autograd backward's grad_output). */
+pa_status pa_adjoint_from_checkpoints(pa_ctx* ctx, const void* ckpt, int32_t n_steps,
+                                      const pa_obs* obs, const double* scale,
+                                      double* grad_out, int32_t ckpt_every,
+                                      void* workspace, size_t workspace_bytes);
+
+/* out = F^-1[(m^2 W)^power 1_S F in] (device [B][N][N] each; in == out is
+ * allowed).  power = -1/2 maps omega0 to the latent control, +1/2 maps back
+ * and turns dJ/domega0 into the latent gradient, 1 gives the filtered
+ * gradient G dJ/domega0 (Eq. (17)). */
+pa_status pa_precondition(pa_ctx* ctx, const pa_kernel* kernel, double power,
+                          const double* in, double* out, void* workspace,
+                          size_t workspace_bytes);
+
+/* Preconditioned 4D-Var (Sec. II.C): minimise J over the latent control
+ * s = precondition(omega, -1/2) from the first guess omega_inout (device
+ * [B][N][N]; overwritten with precondition(s_final, +1/2)).  method 0:
+ * L-BFGS with memory lbfgs_m (two-loop recursion, H0 = (s.y / y.y) I);
+ * 1: steepest descent.  Trial step J/|g|^2 on the first iteration or after a
+ * memory reset, else 1; backtracking Armijo (c1 = 1e-4, halving, 30 trials).
+ * J_hist: host [B][max_iter + 1], the cost after each accepted iteration
+ * (unused entries NaN).  iters_done: host [B], iterations completed, negated
+ * minus one (-(k+1)) if member b stopped on a line-search failure after k
+ * iterations.  Members run in one batch; a failure stops only that member.
+ * Synchronises the stream. */
+pa_status pa_assimilate(pa_ctx* ctx, double* omega_inout, int32_t n_steps, const pa_obs* obs,
+                        const pa_kernel* kernel, int32_t method, int32_t max_iter,
+                        int32_t lbfgs_m, int32_t ckpt_every, double* J_hist,
+                        int32_t* iters_done, void* workspace, size_t workspace_bytes);
+
+/* Adjoint impulse response (Sec. IV): forward n_steps from omega0, then the
+ * adjoint from a unit u-impulse at grid point (ix, iy) at the final step.
+ * shells_out: device [B][n_steps + 1][n_shells], row r = backward step r
+ * (tau = r dt, row 0 the terminal field), entry k-1 = sum over
+ * k <= |k| < k+1 of 1/2 |k|^2 |lambda_hat|^2 / N^4 (Eq. (20) with unit shell
+ * width).  field_out: device [B][N][N] or NULL, P lambda at step 0. */
+pa_status pa_adjoint_impulse(pa_ctx* ctx, const double* omega0, int32_t n_steps,
+                             int32_t ix, int32_t iy, int32_t n_shells, double* shells_out,
+                             double* field_out, int32_t ckpt_every, void* workspace,
+                             size_t workspace_bytes);
+
+/* FFT tile choice for this context (the autotuner's knob): col_block = kx
+ * columns per column-pass workgroup (1, 2, 4 or 8), row_teams = rows per
+ * row-pass workgroup (1, 2, 4 or 8).  0 keeps the current value. */
+pa_status pa_set_tiles(pa_ctx* ctx, int32_t col_block, int32_t row_teams);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PA_H */

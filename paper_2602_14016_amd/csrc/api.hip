@@ -1,0 +1,1030 @@
+// api.hip -- host side of the C ABI declared in include/pa.h.
+//
+// The context owns only constant tables (twiddles, 1/|k|^2, integrating
+// factors, shell lists).  Every buffer a solve needs is carved from the
+// caller's workspace by one layout routine that also answers the size query.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/pa.h"
+#include "kernels.hpp"
+
+using namespace pa;
+
+namespace {
+
+thread_local std::string g_err;
+
+pa_status fail(pa_status code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+
+#define PA_HIP(expr)                                                                         \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return fail(PA_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));      \
+    } while (0)
+
+#define PA_TRY(expr)                       \
+    do {                                   \
+        pa_status s_ = (expr);             \
+        if (s_ != PA_OK) return s_;        \
+    } while (0)
+
+bool is_pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
+
+int threads_per_fft(int N) {
+    switch (N) {
+        case 8: return Plan<8>::T;
+        case 16: return Plan<16>::T;
+        case 32: return Plan<32>::T;
+        case 64: return Plan<64>::T;
+        case 128: return Plan<128>::T;
+        case 256: return Plan<256>::T;
+        case 512: return Plan<512>::T;
+        default: return Plan<1024>::T;
+    }
+}
+bool finite_nonneg(double v) { return std::isfinite(v) && v >= 0.0; }
+
+}  // namespace
+
+struct pa_ctx {
+    Dims d;
+    pa_physics ph;
+    hipStream_t stream;
+    int device;
+    cd* tw;             // [N]
+    double* invk2;      // [KY][KXP]
+    double* ex2;        // [KXP]
+    double* ey2;        // [KY]
+    int* shell_start;   // [n_shell_max + 1]
+    int* shell_modes;
+    int n_shell_max;
+    double forcing;     // curl-force spectrum value at (0, +-n_f)
+    int nf;             // n_f if inside the band, else 0
+};
+
+namespace {
+
+// ----------------------------------------------------------- workspace --
+
+struct WS {
+    cd* Y0;
+    cd* Yf[4];
+    cd* Yp[4];
+    cd* YL;
+    cd* omega;
+    cd* acc;
+    cd* lam;
+    cd* omb;
+    cd* seg;            // segment stage fields, (4K+1) slots x 4 fields
+    cd* ckpt;           // internal checkpoints
+    double* jpart;      // [B][n_obs][N]
+    double* J;          // [B]
+    double* J2;         // [B]
+    double* mult;       // [KY][KXP] (two tables)
+    double* norm;       // [B]
+    uint64_t* seeds;    // [B]
+    double* partial;    // [B][DOT_BLOCKS]
+    double* dots;       // [B][4]
+    double* coef;       // [B][8]
+    int* active;        // [B]
+    // optimiser vectors [B][N*N]
+    double *x, *g, *dv, *xt, *gt, *w, *gw;
+    double* S;          // [m][B][N*N]
+    double* Yv;         // [m][B][N*N]
+    size_t total;
+};
+
+struct Carver {
+    char* base;
+    size_t off = 0;
+    template <class T>
+    T* take(size_t count) {
+        off = (off + 255) & ~size_t(255);
+        T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+        off += count * sizeof(T);
+        return p;
+    }
+};
+
+int seg_len(int n_steps, int ckpt_every) { return std::max(1, std::min(ckpt_every, std::max(n_steps, 1))); }
+int n_segments(int n_steps, int K) { return n_steps <= 0 ? 0 : (n_steps + K - 1) / K; }
+
+WS carve(const pa_ctx* c, int n_steps, int ckpt_every, int n_obs, int m, void* base) {
+    const Dims& d = c->d;
+    const size_t SY = (size_t)d.B * d.N * d.KXP;
+    const size_t SC = (size_t)d.B * d.KY * d.KXP;
+    const size_t SP = (size_t)d.B * d.N * d.N;
+    const int K = seg_len(n_steps, ckpt_every);
+    const int nseg = n_segments(n_steps, K);
+    Carver cv{reinterpret_cast<char*>(base)};
+    WS w{};
+    w.Y0 = cv.take<cd>(SY);
+    for (int i = 0; i < 4; ++i) w.Yf[i] = cv.take<cd>(SY);
+    for (int i = 0; i < 4; ++i) w.Yp[i] = cv.take<cd>(SY);
+    w.YL = cv.take<cd>(SY);
+    w.omega = cv.take<cd>(SC);
+    w.acc = cv.take<cd>(SC);
+    w.lam = cv.take<cd>(SC);
+    w.omb = cv.take<cd>(SC);
+    w.seg = n_steps > 0 ? cv.take<cd>((size_t)(4 * K + 1) * 4 * SY) : nullptr;
+    w.ckpt = cv.take<cd>((size_t)(nseg + 1) * SC);
+    w.jpart = cv.take<double>((size_t)d.B * std::max(n_obs, 1) * d.N);
+    w.J = cv.take<double>(d.B);
+    w.J2 = cv.take<double>(d.B);
+    w.mult = cv.take<double>((size_t)2 * d.KY * d.KXP);
+    w.norm = cv.take<double>(d.B);
+    w.seeds = cv.take<uint64_t>(d.B);
+    w.partial = cv.take<double>((size_t)d.B * DOT_BLOCKS);
+    w.dots = cv.take<double>((size_t)d.B * 4);
+    w.coef = cv.take<double>((size_t)d.B * 8);
+    w.active = cv.take<int>(d.B);
+    if (m > 0) {
+        w.x = cv.take<double>(SP);
+        w.g = cv.take<double>(SP);
+        w.dv = cv.take<double>(SP);
+        w.xt = cv.take<double>(SP);
+        w.gt = cv.take<double>(SP);
+        w.w = cv.take<double>(SP);
+        w.gw = cv.take<double>(SP);
+        w.S = cv.take<double>((size_t)m * SP);
+        w.Yv = cv.take<double>((size_t)m * SP);
+    }
+    w.total = cv.off + 256;
+    return w;
+}
+
+size_t ckpt_bytes(const pa_ctx* c, int n_steps, int ckpt_every) {
+    const int K = seg_len(n_steps, ckpt_every);
+    return (size_t)(n_segments(n_steps, K) + 1) * c->d.B * c->d.KY * c->d.KXP * sizeof(cd);
+}
+
+cd* ckpt_slot(const pa_ctx* c, cd* base, int i) {
+    return base + (size_t)i * c->d.B * c->d.KY * c->d.KXP;
+}
+
+// 4 stage-field pointers of segment slot (j, s)
+void seg_fields(const pa_ctx* c, const WS& w, int j, int s, cd* out[4]) {
+    const size_t SY = (size_t)c->d.B * c->d.N * c->d.KXP;
+    const size_t slot = (size_t)j * 4 + s;
+    for (int f = 0; f < 4; ++f) out[f] = w.seg + (slot * 4 + f) * SY;
+}
+
+// --------------------------------------------------------- validation --
+
+struct ObsPlan {
+    std::vector<int> slot_of;   // step -> slot or -1
+    int stride = 1, M = 1, n_times = 0;
+    const double* values = nullptr;
+};
+
+pa_status make_obs_plan(const pa_ctx* c, const pa_obs* obs, int n_steps, bool need_values, ObsPlan* p) {
+    p->slot_of.assign((size_t)n_steps + 1, -1);
+    if (!obs) {
+        if (need_values) return fail(PA_EINVAL, "observations required");
+        return PA_OK;
+    }
+    if (obs->stride < 1 || obs->stride > c->d.N || c->d.N % obs->stride)
+        return fail(PA_EINVAL, "obs stride must divide N");
+    if (obs->n_times < 0 || obs->n_times > n_steps + 1) return fail(PA_EINVAL, "bad n_times");
+    if (obs->n_times > 0 && !obs->steps) return fail(PA_EINVAL, "obs steps is NULL");
+    if (need_values && !obs->values) return fail(PA_EINVAL, "obs values required");
+    int prev = -1;
+    for (int i = 0; i < obs->n_times; ++i) {
+        const int s = obs->steps[i];
+        if (s <= prev || s > n_steps) return fail(PA_EINVAL, "obs steps must increase within [0, n_steps]");
+        p->slot_of[(size_t)s] = i;
+        prev = s;
+    }
+    p->stride = obs->stride;
+    p->M = c->d.N / obs->stride;
+    p->n_times = obs->n_times;
+    p->values = obs->values;
+    return PA_OK;
+}
+
+pa_status check_ws(const pa_ctx* c, void* ws, size_t bytes, int n_steps, int K, int n_obs, int m, WS* out) {
+    if (!ws) return fail(PA_EINVAL, "workspace is NULL");
+    if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(PA_EINVAL, "workspace must be 256-byte aligned");
+    WS w = carve(c, n_steps, K, n_obs, m, ws);
+    if (w.total > bytes)
+        return fail(PA_ENOMEM, "workspace too small: need " + std::to_string(w.total) + " bytes");
+    *out = w;
+    return PA_OK;
+}
+
+// -------------------------------------------------------------- sweeps --
+
+RowObs row_obs_args(const ObsPlan& op, int slot, double* obs_out, double* jpart) {
+    RowObs o{};
+    o.slot = slot;
+    o.stride = op.stride;
+    o.M = op.M;
+    o.n_times = op.n_times;
+    o.values = op.values;
+    o.obs_out = obs_out;
+    o.jpart = jpart;
+    o.imp_x = o.imp_y = -1;
+    return o;
+}
+
+ColArgs col_base(const pa_ctx* c) {
+    ColArgs a{};
+    a.invk2 = c->invk2;
+    a.ex2 = c->ex2;
+    a.ey2 = c->ey2;
+    a.tw = c->tw;
+    a.h = c->ph.dt;
+    a.forcing = c->forcing;
+    a.nf = c->nf;
+    return a;
+}
+
+void set_stage_fields(ColArgs& a, cd* const f[4]) {
+    a.nout = 4;
+    a.fields[0] = F_U;
+    a.fields[1] = F_V;
+    a.fields[2] = F_WX;
+    a.fields[3] = F_WY;
+    for (int i = 0; i < 4; ++i) a.yout[i] = f[i];
+}
+
+// Transform physical omega0 to the band-limited state (P omega0), write
+// checkpoint slot 0 if given, and the stage-a fields to `fields`.
+pa_status start_state(pa_ctx* c, WS& w, const double* omega0, cd* ck0, cd* const fields[4]) {
+    PA_HIP(launch_row_r2c(c->d, omega0, w.Y0, c->tw, c->stream));
+    ColArgs a = col_base(c);
+    a.yin[0] = w.Y0;
+    a.omega = w.omega;
+    a.ckpt = ck0;
+    set_stage_fields(a, fields);
+    PA_HIP(launch_col(c->d, COL_INIT, a, c->stream));
+    return PA_OK;
+}
+
+// Steps n0 .. n1-1 from the state in w.omega whose stage-a fields are in
+// `start` (which must equal the segment slot (0,0) when store).  With store
+// the fields of every stage are kept in the segment slots; otherwise they
+// live in w.Yf.  Checkpoints are written to ckpt (if non-null) at multiples
+// of K and at the final step n_total.  Observations via op (J partials).
+pa_status run_steps(pa_ctx* c, WS& w, int n0, int n1, int n_total, int K, bool store, const ObsPlan* op,
+                    double* obs_out, cd* ckpt, bool final_fields) {
+    const int nseg = n_segments(n_total, K);
+    for (int n = n0; n < n1; ++n) {
+        const int j = n - n0;
+        for (int s = 0; s < 4; ++s) {
+            cd* fin[4];
+            cd* fout[4];
+            if (store) {
+                seg_fields(c, w, j, s, fin);
+                if (s < 3) seg_fields(c, w, j, s + 1, fout);
+                else seg_fields(c, w, j + 1, 0, fout);
+            } else {
+                for (int i = 0; i < 4; ++i) fin[i] = fout[i] = w.Yf[i];
+            }
+            RowArgs ra{};
+            for (int i = 0; i < 4; ++i) ra.yin[i] = fin[i];
+            ra.yout[0] = w.Yp[0];
+            ra.tw = c->tw;
+            const int slot = (s == 0 && op) ? op->slot_of[(size_t)n] : -1;
+            ra.obs = op ? row_obs_args(*op, slot, obs_out, w.jpart) : row_obs_args(ObsPlan(), -1, nullptr, nullptr);
+            PA_HIP(launch_row_nl(c->d, ra, c->stream));
+            ColArgs a = col_base(c);
+            a.yin[0] = w.Yp[0];
+            a.omega = w.omega;
+            a.acc = w.acc;
+            set_stage_fields(a, fout);
+            if (s == 3) {
+                const int nn = n + 1;
+                if (ckpt && (nn % K == 0 || nn == n_total)) a.ckpt = ckpt_slot(c, ckpt, nn == n_total ? nseg : nn / K);
+                if (nn == n1 && !final_fields) a.nout = 0;
+            }
+            PA_HIP(launch_col(c->d, COL_A + s, a, c->stream));
+        }
+    }
+    return PA_OK;
+}
+
+// Observation at the final step from the stage-a fields of omega_H.
+pa_status observe_final(pa_ctx* c, WS& w, const ObsPlan& op, int n_steps, cd* const fields[4], double* obs_out) {
+    const int slot = op.slot_of[(size_t)n_steps];
+    if (slot < 0) return PA_OK;
+    RowArgs ra{};
+    ra.yin[0] = fields[0];
+    ra.yin[1] = fields[1];
+    ra.tw = c->tw;
+    ra.obs = row_obs_args(op, slot, obs_out, w.jpart);
+    PA_HIP(launch_row_obs(c->d, ra, c->stream));
+    return PA_OK;
+}
+
+// Physical field from a compact state.
+pa_status state_to_phys(pa_ctx* c, WS& w, const cd* state, double* out) {
+    ColArgs a = col_base(c);
+    a.state_in = state;
+    a.nout = 1;
+    a.fields[0] = F_OMEGA;
+    a.yout[0] = w.Y0;
+    PA_HIP(launch_col(c->d, COL_FROM_STATE, a, c->stream));
+    PA_HIP(launch_row_c2r(c->d, w.Y0, out, c->tw, c->stream));
+    return PA_OK;
+}
+
+// Forward sweep with checkpoints into `ckpt` and J into w.J (if values).
+pa_status forward_sweep(pa_ctx* c, WS& w, const double* omega0, int n_steps, const ObsPlan& op,
+                        double* obs_out, cd* ckpt, int K) {
+    PA_TRY(start_state(c, w, omega0, ckpt ? ckpt_slot(c, ckpt, 0) : nullptr, w.Yf));
+    const bool final_obs = op.slot_of[(size_t)n_steps] >= 0;
+    PA_TRY(run_steps(c, w, 0, n_steps, n_steps, K, false, &op, obs_out, ckpt, final_obs));
+    if (final_obs) PA_TRY(observe_final(c, w, op, n_steps, w.Yf, obs_out));
+    if (op.values && op.n_times > 0)
+        PA_HIP(launch_reduce_j(c->d.B, op.n_times * op.M, w.jpart, w.J, c->stream));
+    return PA_OK;
+}
+
+// Adjoint stage: row products + column transposes for stage `mode`.
+pa_status adj_stage(pa_ctx* c, WS& w, cd* const fields[4], int mode, const ObsPlan* op, int obs_slot,
+                    int final_out, const double* scale, cd* yl_out) {
+    RowArgs ra{};
+    for (int i = 0; i < 4; ++i) ra.yin[i] = fields[i];
+    ra.yin[4] = w.YL;
+    for (int i = 0; i < 4; ++i) ra.yout[i] = w.Yp[i];
+    ra.tw = c->tw;
+    ra.obs = op ? row_obs_args(*op, obs_slot, nullptr, nullptr) : row_obs_args(ObsPlan(), -1, nullptr, nullptr);
+    PA_HIP(launch_row_adj(c->d, ra, c->stream));
+    ColArgs a = col_base(c);
+    for (int i = 0; i < 4; ++i) a.yin[i] = w.Yp[i];
+    a.lam = w.lam;
+    a.omb = w.omb;
+    a.final_out = final_out;
+    a.scale = scale;
+    a.nout = 1;
+    a.fields[0] = F_OMEGA;
+    a.yout[0] = yl_out;
+    PA_HIP(launch_col(c->d, mode, a, c->stream));
+    return PA_OK;
+}
+
+struct Shells {
+    double* out = nullptr;
+    int n = 0;
+    size_t stride = 0;
+};
+
+pa_status record_shells(pa_ctx* c, WS& w, const Shells& sh, int row) {
+    if (!sh.out) return PA_OK;
+    PA_HIP(launch_shells(c->d, w.lam, c->shell_start, c->shell_modes, sh.n, sh.out + (size_t)row * sh.n,
+                         sh.stride, c->stream));
+    return PA_OK;
+}
+
+// Terminal adjoint state lambda_H from observations (op) or an impulse.
+pa_status terminal(pa_ctx* c, WS& w, const ObsPlan* op, int n_steps, cd* const fieldsH[4], int impulse, int ix,
+                   int iy, bool final_out, const double* scale) {
+    const size_t SC = (size_t)c->d.B * c->d.KY * c->d.KXP;
+    const size_t SY = (size_t)c->d.B * c->d.N * c->d.KXP;
+    const int slot = op ? op->slot_of[(size_t)n_steps] : -1;
+    if (!impulse && slot < 0) {
+        PA_HIP(launch_fill(reinterpret_cast<double*>(w.lam), 0.0, 2 * SC, c->stream));
+        PA_HIP(launch_fill(reinterpret_cast<double*>(w.YL), 0.0, 2 * SY, c->stream));
+        return PA_OK;
+    }
+    RowArgs ra{};
+    ra.yin[0] = fieldsH[0];
+    ra.yin[1] = fieldsH[1];
+    ra.yout[0] = w.Yp[0];
+    ra.yout[1] = w.Yp[1];
+    ra.tw = c->tw;
+    ra.obs = op ? row_obs_args(*op, slot, nullptr, nullptr) : row_obs_args(ObsPlan(), -1, nullptr, nullptr);
+    ra.obs.imp_x = ix;
+    ra.obs.imp_y = iy;
+    PA_HIP(launch_row_src(c->d, ra, impulse, c->stream));
+    ColArgs a = col_base(c);
+    a.yin[0] = w.Yp[0];
+    a.yin[1] = w.Yp[1];
+    a.lam = w.lam;
+    a.final_out = final_out ? 1 : 0;
+    a.scale = scale;
+    a.nout = 1;
+    a.fields[0] = F_OMEGA;
+    a.yout[0] = w.YL;
+    PA_HIP(launch_col(c->d, COL_ADJ_SRC, a, c->stream));
+    return PA_OK;
+}
+
+// Backward sweep from checkpoints: recompute each segment storing every
+// stage's fields, then run the adjoint steps of the segment in reverse.  The
+// final field (P lambda_0 times scale) is written to grad_out (physical).
+pa_status backward_sweep(pa_ctx* c, WS& w, const cd* ckpt, int n_steps, int K, const ObsPlan* op, int impulse,
+                         int ix, int iy, const double* scale, double* grad_out, const Shells& sh) {
+    const int nseg = n_segments(n_steps, K);
+    if (n_steps == 0) {
+        // no segment buffer exists for a zero horizon: the stage fields of omega_0 go to w.Yf
+        cd* f0[4] = {w.Yf[0], w.Yf[1], w.Yf[2], w.Yf[3]};
+        ColArgs a = col_base(c);
+        a.state_in = ckpt_slot(c, const_cast<cd*>(ckpt), 0);
+        a.omega = w.omega;
+        set_stage_fields(a, f0);
+        PA_HIP(launch_col(c->d, COL_FROM_STATE, a, c->stream));
+        const int slot = op ? op->slot_of[0] : -1;
+        if (!impulse && slot < 0) {
+            if (grad_out) PA_HIP(launch_fill(grad_out, 0.0, (size_t)c->d.B * c->d.N * c->d.N, c->stream));
+            return PA_OK;
+        }
+        PA_TRY(terminal(c, w, op, 0, f0, impulse, ix, iy, true, scale));
+        PA_TRY(record_shells(c, w, sh, 0));
+        if (grad_out) PA_HIP(launch_row_c2r(c->d, w.YL, grad_out, c->tw, c->stream));
+        return PA_OK;
+    }
+    if (!w.seg) return fail(PA_EINVAL, "workspace carved without a segment buffer");
+    for (int seg = nseg - 1; seg >= 0; --seg) {
+        const int n0 = seg * K, n1 = std::min(n_steps, n0 + K), L = n1 - n0;
+        cd* f0[4];
+        seg_fields(c, w, 0, 0, f0);
+        ColArgs a = col_base(c);
+        a.state_in = ckpt_slot(c, const_cast<cd*>(ckpt), seg);
+        a.omega = w.omega;
+        set_stage_fields(a, f0);
+        PA_HIP(launch_col(c->d, COL_FROM_STATE, a, c->stream));
+        const bool last = seg == nseg - 1;
+        PA_TRY(run_steps(c, w, n0, n1, n_steps, K, true, nullptr, nullptr, nullptr, last));
+        if (last) {
+            cd* fH[4];
+            seg_fields(c, w, L, 0, fH);
+            PA_TRY(terminal(c, w, op, n_steps, fH, impulse, ix, iy, false, scale));
+            PA_TRY(record_shells(c, w, sh, 0));
+        }
+        for (int j = L - 1; j >= 0; --j) {
+            const int n = n0 + j;
+            cd* fs[4];
+            seg_fields(c, w, j, 3, fs);
+            PA_TRY(adj_stage(c, w, fs, COL_ADJ_C, nullptr, -1, 0, nullptr, w.YL));
+            seg_fields(c, w, j, 2, fs);
+            PA_TRY(adj_stage(c, w, fs, COL_ADJ_B, nullptr, -1, 0, nullptr, w.YL));
+            seg_fields(c, w, j, 1, fs);
+            PA_TRY(adj_stage(c, w, fs, COL_ADJ_A, nullptr, -1, 0, nullptr, w.YL));
+            seg_fields(c, w, j, 0, fs);
+            const int slot = (op && !impulse) ? op->slot_of[(size_t)n] : -1;
+            PA_TRY(adj_stage(c, w, fs, COL_ADJ_N, op, slot, n == 0 ? 1 : 0, scale, w.YL));
+            PA_TRY(record_shells(c, w, sh, n_steps - n));
+        }
+    }
+    if (grad_out) PA_HIP(launch_row_c2r(c->d, w.YL, grad_out, c->tw, c->stream));
+    return PA_OK;
+}
+
+// precondition with the multiplier table mult (per context, computed before)
+pa_status apply_filter(pa_ctx* c, WS& w, const double* mult, const double* in, double* out) {
+    PA_HIP(launch_row_r2c(c->d, in, w.Y0, c->tw, c->stream));
+    ColArgs a = col_base(c);
+    a.yin[0] = w.Y0;
+    a.mult = mult;
+    a.nout = 1;
+    a.fields[0] = F_OMEGA;
+    a.yout[0] = w.Yf[0];
+    PA_HIP(launch_col(c->d, COL_FILTER, a, c->stream));
+    PA_HIP(launch_row_c2r(c->d, w.Yf[0], out, c->tw, c->stream));
+    return PA_OK;
+}
+
+pa_status valid_kernel(const pa_kernel* k) {
+    if (!k) return fail(PA_EINVAL, "kernel is NULL");
+    if (k->kind < 0 || k->kind > 3) return fail(PA_EINVAL, "kernel kind must be 0..3");
+    if (k->metric < 0 || k->metric > 1) return fail(PA_EINVAL, "kernel metric must be 0 or 1");
+    if (!std::isfinite(k->param)) return fail(PA_EINVAL, "kernel parameter must be finite");
+    return PA_OK;
+}
+
+// host twiddle exp(-2 pi i m/N) from the first octant with exact symmetries
+void host_twiddles(int N, std::vector<cd>& tw) {
+    tw.resize(N);
+    const long double pi2 = 1.57079632679489661923132169163975144L;   // pi / 2
+    for (int m = 0; m < N; ++m) {
+        const long q = (4L * m) / N, r = (4L * m) % N;     // angle = (pi/2)(q + r/N)
+        const bool flip = 2 * r > N;
+        const long rr = flip ? N - r : r;
+        const long double ang = pi2 * (long double)rr / (long double)N;
+        long double cphi = cosl(ang), sphi = sinl(ang);
+        if (flip) std::swap(cphi, sphi);
+        long double cs, sn;
+        switch (q & 3) {
+            case 0: cs = cphi; sn = sphi; break;
+            case 1: cs = -sphi; sn = cphi; break;
+            case 2: cs = -cphi; sn = -sphi; break;
+            default: cs = sphi; sn = -cphi; break;
+        }
+        tw[m].x = (double)cs;
+        tw[m].y = -(double)sn;
+    }
+}
+
+}  // namespace
+
+// ================================================================= ABI ==
+
+extern "C" {
+
+const char* pa_last_error(void) { return g_err.c_str(); }
+
+pa_status pa_create(const pa_physics* phys, int32_t N, int32_t B, void* hip_stream, pa_ctx** out) {
+    g_err.clear();
+    if (!out) return fail(PA_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!phys) return fail(PA_EINVAL, "physics is NULL");
+    if (!is_pow2(N) || N < 8 || N > 1024) return fail(PA_EINVAL, "N must be a power of two in [8, 1024]");
+    if (B < 1) return fail(PA_EINVAL, "B must be >= 1");
+    if (!finite_nonneg(phys->nu) || !finite_nonneg(phys->mu)) return fail(PA_EINVAL, "nu, mu must be finite, >= 0");
+    if (!std::isfinite(phys->dt) || phys->dt <= 0) return fail(PA_EINVAL, "dt must be finite and > 0");
+    if (!std::isfinite(phys->forcing_amp)) return fail(PA_EINVAL, "forcing amplitude must be finite");
+    if (phys->forcing_amp != 0.0 && (phys->forcing_k < 1 || phys->forcing_k >= N / 2))
+        return fail(PA_EINVAL, "forcing wavenumber must be in [1, N/2)");
+    if (phys->reserved != 0) return fail(PA_EINVAL, "reserved must be 0");
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(PA_EDEVICE, "no HIP device");
+
+    int dev = 0;
+    PA_HIP(hipGetDevice(&dev));
+    pa_ctx* c = new pa_ctx();
+    c->ph = *phys;
+    c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    c->device = dev;
+    Dims& d = c->d;
+    d.N = N;
+    d.B = B;
+    d.K = (N - 1) / 3;
+    d.KX = d.K + 1;
+    d.KXP = (d.KX + 7) / 8 * 8;
+    d.KY = 2 * d.K + 1;
+    d.cb = 8;
+    while (d.cb > 1 && (d.cb * threads_per_fft(N) > 256 ||
+                        (size_t)d.cb * (N + N / 16 + 1) * sizeof(cd) > 65536)) d.cb >>= 1;
+    d.tpb = 4;
+
+    std::vector<cd> tw;
+    host_twiddles(N, tw);
+    std::vector<double> invk2((size_t)d.KY * d.KXP, 0.0), ex2(d.KXP, 0.0), ey2(d.KY, 0.0);
+    const double h2 = 0.5 * phys->dt;
+    for (int r = 0; r < d.KY; ++r) {
+        const int ky = (r <= d.K) ? r : r - d.KY;
+        ey2[r] = std::exp(-phys->nu * h2 * (double)ky * ky);
+        for (int kx = 0; kx <= d.K; ++kx) {
+            const double k2 = (double)kx * kx + (double)ky * ky;
+            if (k2 > 0) invk2[(size_t)r * d.KXP + kx] = 1.0 / k2;
+        }
+    }
+    for (int kx = 0; kx < d.KXP; ++kx) ex2[kx] = std::exp(-(phys->nu * (double)kx * kx + phys->mu) * h2);
+    // shells: compact indices grouped by floor(|k|), k = 1..floor(sqrt(2) K)
+    const int smax = (int)std::floor(std::sqrt(2.0) * d.K);
+    std::vector<std::vector<int>> lists(smax + 1);
+    for (int r = 0; r < d.KY; ++r) {
+        const int ky = (r <= d.K) ? r : r - d.KY;
+        for (int kx = 0; kx <= d.K; ++kx) {
+            const long m2 = (long)kx * kx + (long)ky * ky;
+            long s = (long)std::sqrt((double)m2);
+            while (s * s > m2) --s;
+            while ((s + 1) * (s + 1) <= m2) ++s;
+            if (s >= 1 && s <= smax) lists[s].push_back(r * d.KXP + kx);
+        }
+    }
+    std::vector<int> start(smax + 1, 0), modes;
+    for (int k = 1; k <= smax; ++k) {
+        start[k - 1] = (int)modes.size();
+        modes.insert(modes.end(), lists[k].begin(), lists[k].end());
+    }
+    start[smax] = (int)modes.size();
+    c->n_shell_max = smax;
+    c->nf = (phys->forcing_amp != 0.0 && phys->forcing_k <= d.K) ? phys->forcing_k : 0;
+    c->forcing = -phys->forcing_amp * phys->forcing_k * 0.5 * (double)N * (double)N;
+
+    auto cleanup = [&](pa_status s) { pa_destroy(c); return s; };
+    if (hipMalloc(&c->tw, sizeof(cd) * N) != hipSuccess) return cleanup(fail(PA_ENOMEM, "hipMalloc tables"));
+    if (hipMalloc(&c->invk2, sizeof(double) * invk2.size()) != hipSuccess) return cleanup(fail(PA_ENOMEM, "hipMalloc tables"));
+    if (hipMalloc(&c->ex2, sizeof(double) * ex2.size()) != hipSuccess) return cleanup(fail(PA_ENOMEM, "hipMalloc tables"));
+    if (hipMalloc(&c->ey2, sizeof(double) * ey2.size()) != hipSuccess) return cleanup(fail(PA_ENOMEM, "hipMalloc tables"));
+    if (hipMalloc(&c->shell_start, sizeof(int) * start.size()) != hipSuccess) return cleanup(fail(PA_ENOMEM, "hipMalloc tables"));
+    if (hipMalloc(&c->shell_modes, sizeof(int) * std::max<size_t>(modes.size(), 1)) != hipSuccess)
+        return cleanup(fail(PA_ENOMEM, "hipMalloc tables"));
+    bool ok = hipMemcpy(c->tw, tw.data(), sizeof(cd) * N, hipMemcpyHostToDevice) == hipSuccess &&
+              hipMemcpy(c->invk2, invk2.data(), sizeof(double) * invk2.size(), hipMemcpyHostToDevice) == hipSuccess &&
+              hipMemcpy(c->ex2, ex2.data(), sizeof(double) * ex2.size(), hipMemcpyHostToDevice) == hipSuccess &&
+              hipMemcpy(c->ey2, ey2.data(), sizeof(double) * ey2.size(), hipMemcpyHostToDevice) == hipSuccess &&
+              hipMemcpy(c->shell_start, start.data(), sizeof(int) * start.size(), hipMemcpyHostToDevice) == hipSuccess &&
+              (modes.empty() || hipMemcpy(c->shell_modes, modes.data(), sizeof(int) * modes.size(),
+                                          hipMemcpyHostToDevice) == hipSuccess);
+    if (!ok) return cleanup(fail(PA_EDEVICE, "copying constant tables failed"));
+    *out = c;
+    return PA_OK;
+}
+
+pa_status pa_destroy(pa_ctx* c) {
+    if (!c) return PA_OK;
+    (void)hipStreamSynchronize(c->stream);
+    (void)hipFree(c->tw);
+    (void)hipFree(c->invk2);
+    (void)hipFree(c->ex2);
+    (void)hipFree(c->ey2);
+    (void)hipFree(c->shell_start);
+    (void)hipFree(c->shell_modes);
+    delete c;
+    return PA_OK;
+}
+
+pa_status pa_set_stream(pa_ctx* c, void* s) {
+    if (!c) return fail(PA_EINVAL, "ctx is NULL");
+    c->stream = reinterpret_cast<hipStream_t>(s);
+    return PA_OK;
+}
+
+pa_status pa_get_shape(const pa_ctx* c, int32_t* N, int32_t* B, int32_t* Kc) {
+    if (!c) return fail(PA_EINVAL, "ctx is NULL");
+    if (N) *N = c->d.N;
+    if (B) *B = c->d.B;
+    if (Kc) *Kc = c->d.K;
+    return PA_OK;
+}
+
+pa_status pa_set_tiles(pa_ctx* c, int32_t col_block, int32_t row_teams) {
+    if (!c) return fail(PA_EINVAL, "ctx is NULL");
+    const int T = threads_per_fft(c->d.N);
+    if (col_block) {
+        if (col_block != 1 && col_block != 2 && col_block != 4 && col_block != 8)
+            return fail(PA_EINVAL, "col_block must be 1, 2, 4 or 8");
+        if (col_block * T > 256 || (size_t)col_block * (c->d.N + c->d.N / 16 + 1) * sizeof(cd) > 65536)
+            return fail(PA_EINVAL, "col_block too large for this N");
+        c->d.cb = col_block;
+    }
+    if (row_teams) {
+        if (row_teams != 1 && row_teams != 2 && row_teams != 4 && row_teams != 8)
+            return fail(PA_EINVAL, "row_teams must be 1, 2, 4 or 8");
+        c->d.tpb = row_teams;
+    }
+    return PA_OK;
+}
+
+pa_status pa_workspace_bytes(const pa_ctx* c, int32_t n_steps, int32_t ckpt_every, int32_t n_obs_times,
+                             int32_t lbfgs_m, size_t* bytes) {
+    if (!c || !bytes) return fail(PA_EINVAL, "NULL argument");
+    if (n_steps < 0 || ckpt_every < 1 || n_obs_times < 0 || lbfgs_m < 0) return fail(PA_EINVAL, "bad sizes");
+    *bytes = carve(c, n_steps, ckpt_every, n_obs_times, lbfgs_m, nullptr).total;
+    return PA_OK;
+}
+
+pa_status pa_checkpoint_bytes(const pa_ctx* c, int32_t n_steps, int32_t ckpt_every, size_t* bytes) {
+    if (!c || !bytes) return fail(PA_EINVAL, "NULL argument");
+    if (n_steps < 0 || ckpt_every < 1) return fail(PA_EINVAL, "bad sizes");
+    *bytes = ckpt_bytes(c, n_steps, ckpt_every);
+    return PA_OK;
+}
+
+pa_status pa_init_field(pa_ctx* c, const uint64_t* seeds, int32_t kind, double k0, double target,
+                        double* omega_out, void* workspace, size_t wbytes) {
+    g_err.clear();
+    if (!c || !seeds || !omega_out) return fail(PA_EINVAL, "NULL argument");
+    if (kind < 0 || kind > 2) return fail(PA_EINVAL, "kind must be 0, 1 or 2");
+    if (!(std::isfinite(target) && target > 0)) return fail(PA_EINVAL, "target must be > 0");
+    if (kind != 2 && !(std::isfinite(k0) && k0 > 0)) return fail(PA_EINVAL, "k0 must be > 0");
+    WS w;
+    PA_TRY(check_ws(c, workspace, wbytes, 0, 1, 0, 0, &w));
+    PA_HIP(hipMemcpyAsync(w.seeds, seeds, sizeof(uint64_t) * c->d.B, hipMemcpyHostToDevice, c->stream));
+    PA_HIP(hipStreamSynchronize(c->stream));   // seeds is pageable host memory owned by the caller
+    PA_HIP(launch_init_spectrum(c->d, w.seeds, kind, k0, w.omega, c->stream));
+    PA_HIP(launch_state_norm(c->d, w.omega, kind, w.norm, c->stream));
+    PA_HIP(launch_state_scale(c->d, w.omega, kind, target, w.norm, c->stream));
+    return state_to_phys(c, w, w.omega, omega_out);
+}
+
+pa_status pa_forward(pa_ctx* c, const double* omega0, int32_t n_steps, const pa_obs* obs, double* J_out,
+                     double* obs_out, double* omega_T, int32_t ckpt_every, void* ckpt, void* workspace,
+                     size_t wbytes) {
+    g_err.clear();
+    if (!c || !omega0) return fail(PA_EINVAL, "NULL argument");
+    if (n_steps < 0) return fail(PA_EINVAL, "n_steps must be >= 0");
+    if (ckpt_every < 1) return fail(PA_EINVAL, "ckpt_every must be >= 1");
+    if (J_out && (!obs || !obs->values)) return fail(PA_EINVAL, "J_out needs observation values");
+    if (obs_out && !obs) return fail(PA_EINVAL, "obs_out needs observations");
+    ObsPlan op;
+    PA_TRY(make_obs_plan(c, obs, n_steps, false, &op));
+    WS w;
+    PA_TRY(check_ws(c, workspace, wbytes, 0, ckpt_every, op.n_times, 0, &w));
+    const int K = seg_len(n_steps, ckpt_every);
+    PA_TRY(forward_sweep(c, w, omega0, n_steps, op, obs_out, reinterpret_cast<cd*>(ckpt), K));
+    if (J_out) {
+        if (op.n_times > 0) PA_HIP(launch_copy(J_out, w.J, c->d.B, c->stream));
+        else PA_HIP(launch_fill(J_out, 0.0, c->d.B, c->stream));
+    }
+    if (omega_T) PA_TRY(state_to_phys(c, w, w.omega, omega_T));
+    return PA_OK;
+}
+
+pa_status pa_adjoint_from_checkpoints(pa_ctx* c, const void* ckpt, int32_t n_steps, const pa_obs* obs,
+                                      const double* scale, double* grad_out, int32_t ckpt_every, void* workspace,
+                                      size_t wbytes) {
+    g_err.clear();
+    if (!c || !ckpt || !grad_out) return fail(PA_EINVAL, "NULL argument");
+    if (n_steps < 0 || ckpt_every < 1) return fail(PA_EINVAL, "bad sizes");
+    ObsPlan op;
+    PA_TRY(make_obs_plan(c, obs, n_steps, true, &op));
+    WS w;
+    PA_TRY(check_ws(c, workspace, wbytes, n_steps, ckpt_every, op.n_times, 0, &w));
+    const int K = seg_len(n_steps, ckpt_every);
+    return backward_sweep(c, w, reinterpret_cast<const cd*>(ckpt), n_steps, K, &op, 0, -1, -1, scale, grad_out,
+                          Shells());
+}
+
+pa_status pa_adjoint_gradient(pa_ctx* c, const double* omega0, int32_t n_steps, const pa_obs* obs, double* J_out,
+                              double* grad_out, int32_t ckpt_every, void* workspace, size_t wbytes) {
+    g_err.clear();
+    if (!c || !omega0 || !grad_out) return fail(PA_EINVAL, "NULL argument");
+    if (n_steps < 0 || ckpt_every < 1) return fail(PA_EINVAL, "bad sizes");
+    ObsPlan op;
+    PA_TRY(make_obs_plan(c, obs, n_steps, true, &op));
+    WS w;
+    PA_TRY(check_ws(c, workspace, wbytes, n_steps, ckpt_every, op.n_times, 0, &w));
+    const int K = seg_len(n_steps, ckpt_every);
+    PA_TRY(forward_sweep(c, w, omega0, n_steps, op, nullptr, w.ckpt, K));
+    if (J_out) {
+        if (op.n_times > 0) PA_HIP(launch_copy(J_out, w.J, c->d.B, c->stream));
+        else PA_HIP(launch_fill(J_out, 0.0, c->d.B, c->stream));
+    }
+    return backward_sweep(c, w, w.ckpt, n_steps, K, &op, 0, -1, -1, nullptr, grad_out, Shells());
+}
+
+pa_status pa_adjoint_impulse(pa_ctx* c, const double* omega0, int32_t n_steps, int32_t ix, int32_t iy,
+                             int32_t n_shells, double* shells_out, double* field_out, int32_t ckpt_every,
+                             void* workspace, size_t wbytes) {
+    g_err.clear();
+    if (!c || !omega0 || !shells_out) return fail(PA_EINVAL, "NULL argument");
+    if (n_steps < 0 || ckpt_every < 1) return fail(PA_EINVAL, "bad sizes");
+    if (ix < 0 || iy < 0 || ix >= c->d.N || iy >= c->d.N) return fail(PA_EINVAL, "impulse point outside the grid");
+    if (n_shells < 1 || n_shells > c->n_shell_max)
+        return fail(PA_EINVAL, "n_shells must be in [1, floor(sqrt(2) Kc)]");
+    WS w;
+    PA_TRY(check_ws(c, workspace, wbytes, n_steps, ckpt_every, 0, 0, &w));
+    const int K = seg_len(n_steps, ckpt_every);
+    ObsPlan none;
+    none.slot_of.assign((size_t)n_steps + 1, -1);
+    PA_TRY(forward_sweep(c, w, omega0, n_steps, none, nullptr, w.ckpt, K));
+    Shells sh;
+    sh.out = shells_out;
+    sh.n = n_shells;
+    sh.stride = (size_t)(n_steps + 1) * n_shells;
+    return backward_sweep(c, w, w.ckpt, n_steps, K, nullptr, 1, ix, iy, nullptr, field_out, sh);
+}
+
+pa_status pa_precondition(pa_ctx* c, const pa_kernel* k, double power, const double* in, double* out,
+                          void* workspace, size_t wbytes) {
+    g_err.clear();
+    if (!c || !in || !out) return fail(PA_EINVAL, "NULL argument");
+    PA_TRY(valid_kernel(k));
+    if (!std::isfinite(power)) return fail(PA_EINVAL, "power must be finite");
+    WS w;
+    PA_TRY(check_ws(c, workspace, wbytes, 0, 1, 0, 0, &w));
+    PA_HIP(launch_make_mult(c->d, k->kind, k->metric, k->param, power, w.mult, c->stream));
+    return apply_filter(c, w, w.mult, in, out);
+}
+
+}  // extern "C"
+
+namespace {
+
+// Host-side driver state for the batched optimiser.  All O(N^2) work (maps,
+// solves, dot products, axpys) runs on the device; only O(B m) scalars and
+// the accept/reject decisions of the line searches live on the host.
+struct Opt {
+    pa_ctx* c;
+    WS& w;
+    size_t n;        // N*N
+    int B;
+    std::vector<double> hbuf;
+
+    pa_status sync() {
+        PA_HIP(hipStreamSynchronize(c->stream));
+        return PA_OK;
+    }
+    pa_status dot(const double* x, const double* y, std::vector<double>& out) {
+        PA_HIP(launch_dot(B, n, x, y, w.dots, w.partial, c->stream));
+        out.resize(B);
+        PA_HIP(hipMemcpyAsync(out.data(), w.dots, sizeof(double) * B, hipMemcpyDeviceToHost, c->stream));
+        return sync();
+    }
+    pa_status upload(const std::vector<double>& v, double* dst) {
+        PA_HIP(hipMemcpyAsync(dst, v.data(), sizeof(double) * B, hipMemcpyHostToDevice, c->stream));
+        return sync();
+    }
+    pa_status upload_mask(const std::vector<int>& v) {
+        PA_HIP(hipMemcpyAsync(w.active, v.data(), sizeof(int) * B, hipMemcpyHostToDevice, c->stream));
+        return sync();
+    }
+    pa_status read_J(std::vector<double>& out) {
+        out.resize(B);
+        PA_HIP(hipMemcpyAsync(out.data(), w.J, sizeof(double) * B, hipMemcpyDeviceToHost, c->stream));
+        return sync();
+    }
+};
+
+}  // namespace
+
+extern "C" pa_status pa_assimilate(pa_ctx* c, double* omega_inout, int32_t n_steps, const pa_obs* obs,
+                                   const pa_kernel* kernel, int32_t method, int32_t max_iter, int32_t lbfgs_m,
+                                   int32_t ckpt_every, double* J_hist, int32_t* iters_done, void* workspace,
+                                   size_t wbytes) {
+    g_err.clear();
+    if (!c || !omega_inout || !J_hist || !iters_done) return fail(PA_EINVAL, "NULL argument");
+    PA_TRY(valid_kernel(kernel));
+    if (method != 0 && method != 1) return fail(PA_EINVAL, "method must be 0 (L-BFGS) or 1 (steepest descent)");
+    if (max_iter < 0 || n_steps < 0 || ckpt_every < 1) return fail(PA_EINVAL, "bad sizes");
+    if (method == 0 && lbfgs_m < 1) return fail(PA_EINVAL, "lbfgs_m must be >= 1");
+    ObsPlan op;
+    PA_TRY(make_obs_plan(c, obs, n_steps, true, &op));
+    if (op.n_times == 0) return fail(PA_EINVAL, "assimilation needs at least one observation time");
+    const int m = std::max(1, (int)lbfgs_m);
+    WS w;
+    PA_TRY(check_ws(c, workspace, wbytes, n_steps, ckpt_every, op.n_times, m, &w));
+    const int B = c->d.B;
+    const int K = seg_len(n_steps, ckpt_every);
+    const size_t n = (size_t)c->d.N * c->d.N;
+    const size_t SP = (size_t)B * n;
+    const size_t MT = (size_t)c->d.KY * c->d.KXP;
+    double* mult_p = w.mult;        // (m^2 W)^(+1/2)
+    double* mult_m = w.mult + MT;   // (m^2 W)^(-1/2)
+    PA_HIP(launch_make_mult(c->d, kernel->kind, kernel->metric, kernel->param, 0.5, mult_p, c->stream));
+    PA_HIP(launch_make_mult(c->d, kernel->kind, kernel->metric, kernel->param, -0.5, mult_m, c->stream));
+    Opt o{c, w, n, B, {}};
+
+    auto eval_J = [&](const double* x) -> pa_status {
+        PA_TRY(apply_filter(c, w, mult_p, x, w.w));
+        return forward_sweep(c, w, w.w, n_steps, op, nullptr, w.ckpt, K);
+    };
+    // gradient at the point whose forward sweep last filled w.ckpt
+    auto eval_grad = [&](double* gout) -> pa_status {
+        PA_TRY(backward_sweep(c, w, w.ckpt, n_steps, K, &op, 0, -1, -1, nullptr, w.gw, Shells()));
+        return apply_filter(c, w, mult_p, w.gw, gout);
+    };
+
+    for (int i = 0; i < B * (max_iter + 1); ++i) J_hist[i] = NAN;
+    std::vector<double> J(B), Jt(B), gg, gd, alpha(B), coef(B), tmp;
+    std::vector<int> running(B, 1), done(B, 0), pend(B, 0), acc(B, 0);
+    // pair ring: push p lives in slot p % m; ok[slot][b] marks a stored pair of member b
+    std::vector<std::vector<int>> ok(m, std::vector<int>(B, 0));
+    std::vector<std::vector<double>> rho(m, std::vector<double>(B, 0.0)), gam(m, std::vector<double>(B, 1.0));
+    std::vector<std::vector<double>> al(m, std::vector<double>(B, 0.0));
+    int head = 0;
+
+    PA_TRY(apply_filter(c, w, mult_m, omega_inout, w.x));
+    PA_TRY(eval_J(w.x));
+    PA_TRY(eval_grad(w.g));
+    PA_TRY(o.read_J(J));
+    for (int b = 0; b < B; ++b) J_hist[(size_t)b * (max_iter + 1)] = J[b];
+
+    for (int it = 0; it < max_iter; ++it) {
+        bool any = false;
+        for (int b = 0; b < B; ++b) any = any || running[b];
+        if (!any) break;
+        // ---- search direction
+        std::vector<int> mem(B, 0);
+        if (method == 0) {
+            for (int p = std::max(0, head - m); p < head; ++p)
+                for (int b = 0; b < B; ++b) mem[b] |= ok[p % m][b];
+        }
+        bool any_mem = false;
+        for (int b = 0; b < B; ++b) any_mem = any_mem || (mem[b] && running[b]);
+        if (any_mem) {
+            // two-loop recursion with per-member coefficients (0 for pairs a member does not hold)
+            PA_HIP(launch_copy(w.dv, w.g, SP, c->stream));
+            for (int p = head - 1; p >= std::max(0, head - m); --p) {
+                const int sl = p % m;
+                PA_TRY(o.dot(w.S + sl * SP, w.dv, tmp));
+                for (int b = 0; b < B; ++b) {
+                    al[sl][b] = ok[sl][b] ? rho[sl][b] * tmp[b] : 0.0;
+                    coef[b] = -al[sl][b];
+                }
+                PA_TRY(o.upload(coef, w.coef));
+                PA_HIP(launch_axpy(B, n, w.coef, 1.0, w.Yv + sl * SP, w.dv, nullptr, c->stream));
+            }
+            // H0 = gamma I from each member's newest stored pair
+            for (int b = 0; b < B; ++b) {
+                coef[b] = 1.0;
+                for (int p = head - 1; p >= std::max(0, head - m); --p)
+                    if (ok[p % m][b]) { coef[b] = gam[p % m][b]; break; }
+            }
+            PA_TRY(o.upload(coef, w.coef));
+            PA_HIP(launch_scal_copy(B, n, w.coef, w.dv, w.dv, c->stream));
+            for (int p = std::max(0, head - m); p < head; ++p) {
+                const int sl = p % m;
+                PA_TRY(o.dot(w.Yv + sl * SP, w.dv, tmp));
+                for (int b = 0; b < B; ++b) coef[b] = ok[sl][b] ? al[sl][b] - rho[sl][b] * tmp[b] : 0.0;
+                PA_TRY(o.upload(coef, w.coef));
+                PA_HIP(launch_axpy(B, n, w.coef, 1.0, w.S + sl * SP, w.dv, nullptr, c->stream));
+            }
+            // d = -H g (members without pairs had zero coefficients and gamma = 1: H g = g)
+            for (int b = 0; b < B; ++b) coef[b] = -1.0;
+            PA_TRY(o.upload(coef, w.coef));
+            PA_HIP(launch_scal_copy(B, n, w.coef, w.dv, w.dv, c->stream));
+        } else {
+            for (int b = 0; b < B; ++b) coef[b] = -1.0;
+            PA_TRY(o.upload(coef, w.coef));
+            PA_HIP(launch_scal_copy(B, n, w.coef, w.g, w.dv, c->stream));
+        }
+        PA_TRY(o.dot(w.g, w.dv, gd));
+        PA_TRY(o.dot(w.g, w.g, gg));
+        std::vector<int> reset(B, 0);
+        bool any_reset = false;
+        for (int b = 0; b < B; ++b) {
+            if (mem[b] && gd[b] >= 0.0) {
+                reset[b] = 1;
+                any_reset = true;
+                for (int s2 = 0; s2 < m; ++s2) ok[s2][b] = 0;
+                mem[b] = 0;
+                gd[b] = -gg[b];
+            }
+        }
+        if (any_reset) {
+            for (int b = 0; b < B; ++b) coef[b] = -1.0;
+            PA_TRY(o.upload(coef, w.coef));
+            PA_TRY(o.upload_mask(reset));
+            PA_HIP(launch_axpby(B, n, w.coef, 1.0, w.g, nullptr, 0.0, w.g, w.dv, w.active, c->stream));
+        }
+        for (int b = 0; b < B; ++b) alpha[b] = mem[b] ? 1.0 : J[b] / gg[b];
+        // ---- backtracking Armijo line search, per member
+        PA_HIP(launch_copy(w.xt, w.x, SP, c->stream));
+        for (int b = 0; b < B; ++b) {
+            pend[b] = running[b];
+            acc[b] = 0;
+        }
+        for (int trial = 0; trial < 30; ++trial) {
+            bool anyp = false;
+            for (int b = 0; b < B; ++b) anyp = anyp || pend[b];
+            if (!anyp) break;
+            PA_TRY(o.upload(alpha, w.coef));
+            PA_TRY(o.upload_mask(pend));
+            PA_HIP(launch_axpby(B, n, nullptr, 1.0, w.x, w.coef, 1.0, w.dv, w.xt, w.active, c->stream));
+            PA_TRY(eval_J(w.xt));
+            PA_TRY(o.read_J(tmp));
+            for (int b = 0; b < B; ++b) {
+                if (!pend[b]) continue;
+                if (tmp[b] <= J[b] + 1e-4 * alpha[b] * gd[b]) {
+                    pend[b] = 0;
+                    acc[b] = 1;
+                    Jt[b] = tmp[b];
+                } else {
+                    alpha[b] *= 0.5;
+                }
+            }
+        }
+        bool any_acc = false;
+        for (int b = 0; b < B; ++b) {
+            if (pend[b]) {   // step size collapsed
+                running[b] = 0;
+                iters_done[b] = -(done[b] + 1);
+            }
+            any_acc = any_acc || acc[b];
+        }
+        if (!any_acc) break;
+        const bool last = it == max_iter - 1;
+        if (!last) {
+            // the last trial's forward sweep holds valid checkpoints for every accepted member
+            PA_TRY(eval_grad(w.gt));
+            if (method == 0) {
+                const int sl = head % m;
+                PA_HIP(launch_axpby(B, n, nullptr, 1.0, w.xt, nullptr, -1.0, w.x, w.S + sl * SP, nullptr, c->stream));
+                PA_HIP(launch_axpby(B, n, nullptr, 1.0, w.gt, nullptr, -1.0, w.g, w.Yv + sl * SP, nullptr, c->stream));
+                std::vector<double> sy, ss, yy;
+                PA_TRY(o.dot(w.S + sl * SP, w.Yv + sl * SP, sy));
+                PA_TRY(o.dot(w.S + sl * SP, w.S + sl * SP, ss));
+                PA_TRY(o.dot(w.Yv + sl * SP, w.Yv + sl * SP, yy));
+                for (int b = 0; b < B; ++b) {
+                    ok[sl][b] = acc[b] && sy[b] > 1e-10 * std::sqrt(ss[b]) * std::sqrt(yy[b]);
+                    rho[sl][b] = ok[sl][b] ? 1.0 / sy[b] : 0.0;
+                    gam[sl][b] = ok[sl][b] ? sy[b] / yy[b] : 1.0;
+                }
+                ++head;
+            }
+            PA_TRY(o.upload_mask(acc));
+            PA_HIP(launch_axpby(B, n, nullptr, 1.0, w.gt, nullptr, 0.0, w.gt, w.g, w.active, c->stream));
+        }
+        PA_TRY(o.upload_mask(acc));
+        PA_HIP(launch_axpby(B, n, nullptr, 1.0, w.xt, nullptr, 0.0, w.xt, w.x, w.active, c->stream));
+        for (int b = 0; b < B; ++b) {
+            if (!acc[b]) continue;
+            J[b] = Jt[b];
+            done[b] = it + 1;
+            J_hist[(size_t)b * (max_iter + 1) + it + 1] = J[b];
+        }
+        if (last) break;
+    }
+    for (int b = 0; b < B; ++b)
+        if (running[b]) iters_done[b] = done[b];
+    PA_TRY(apply_filter(c, w, mult_p, w.x, omega_inout));
+    PA_TRY(o.sync());
+    return PA_OK;
+}

@@ -1,0 +1,228 @@
+// fft.hpp -- FP64 complex FFT building blocks for gfx950 (CDNA4).
+//
+// A length-N transform is done by a "team" of T threads.  Thread t of a team
+// holds E = N / T elements in registers, element t + T*m in slot m (m < E).
+// The transform is a Stockham autosort sequence of radix-R stages (R in
+// {2, 4, 8, 16}); each stage does E/R butterflies per thread entirely in
+// registers and, between stages, the team exchanges data through its own LDS
+// region (one write + barrier + read per stage boundary).  The first stage's
+// inputs and the last stage's outputs are both in the register layout
+// "thread t holds index t + T*m", so a forward transform, a pointwise
+// operation and an inverse transform chain with no extra exchange, and global
+// loads/stores of a contiguous signal are coalesced across the team.
+//
+// Direction: forward uses exp(-2 pi i jk/N) (unnormalised), inverse
+// exp(+2 pi i jk/N) (unnormalised).  Inter-stage twiddles come from a table
+// tw[m] = exp(-2 pi i m / N), m < N, precomputed on the host.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace pa {
+
+struct cd { double x, y; };
+
+__device__ __forceinline__ cd mk(double x, double y) { cd r; r.x = x; r.y = y; return r; }
+__device__ __forceinline__ cd cadd(cd a, cd b) { return mk(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ cd csub(cd a, cd b) { return mk(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ cd cmul(cd a, cd b) { return mk(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
+__device__ __forceinline__ cd cmulc(cd a, cd b) { return mk(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y); }  // a*conj(b)
+__device__ __forceinline__ cd cconj(cd a) { return mk(a.x, -a.y); }
+__device__ __forceinline__ cd cscale(cd a, double s) { return mk(a.x * s, a.y * s); }
+__device__ __forceinline__ cd mul_i(cd a) { return mk(-a.y, a.x); }     //  i a
+__device__ __forceinline__ cd mul_mi(cd a) { return mk(a.y, -a.x); }    // -i a
+__device__ __forceinline__ cd czero() { return mk(0.0, 0.0); }
+
+// cos / sin of 2 pi k / 16, k = 0..15 (correctly rounded literals).
+#define PA_C1 0.92387953251128675613
+#define PA_S1 0.38268343236508977173
+#define PA_R2 0.70710678118654752440
+
+template <int K16>
+struct Unit16 {
+    static constexpr double c = (K16 % 16 == 0) ? 1.0 : (K16 % 16 == 1) ? PA_C1 : (K16 % 16 == 2) ? PA_R2
+        : (K16 % 16 == 3) ? PA_S1 : (K16 % 16 == 4) ? 0.0 : (K16 % 16 == 5) ? -PA_S1 : (K16 % 16 == 6) ? -PA_R2
+        : (K16 % 16 == 7) ? -PA_C1 : (K16 % 16 == 8) ? -1.0 : (K16 % 16 == 9) ? -PA_C1 : (K16 % 16 == 10) ? -PA_R2
+        : (K16 % 16 == 11) ? -PA_S1 : (K16 % 16 == 12) ? 0.0 : (K16 % 16 == 13) ? PA_S1 : (K16 % 16 == 14) ? PA_R2
+        : PA_C1;
+    static constexpr double s = (K16 % 16 == 0) ? 0.0 : (K16 % 16 == 1) ? PA_S1 : (K16 % 16 == 2) ? PA_R2
+        : (K16 % 16 == 3) ? PA_C1 : (K16 % 16 == 4) ? 1.0 : (K16 % 16 == 5) ? PA_C1 : (K16 % 16 == 6) ? PA_R2
+        : (K16 % 16 == 7) ? PA_S1 : (K16 % 16 == 8) ? 0.0 : (K16 % 16 == 9) ? -PA_S1 : (K16 % 16 == 10) ? -PA_R2
+        : (K16 % 16 == 11) ? -PA_C1 : (K16 % 16 == 12) ? -1.0 : (K16 % 16 == 13) ? -PA_C1 : (K16 % 16 == 14) ? -PA_R2
+        : -PA_S1;
+};
+
+// a * exp(-+ 2 pi i K / R) with R dividing 16; exact special cases.
+template <int K, int R, bool INV>
+__device__ __forceinline__ cd twc(cd a) {
+    constexpr int k16 = ((K * (16 / R)) % 16 + 16) % 16;
+    if constexpr (k16 == 0) return a;
+    else if constexpr (k16 == 8) return mk(-a.x, -a.y);
+    else if constexpr (k16 == 4) return INV ? mul_i(a) : mul_mi(a);
+    else if constexpr (k16 == 12) return INV ? mul_mi(a) : mul_i(a);
+    else {
+        constexpr double c = Unit16<k16>::c;
+        constexpr double s = INV ? Unit16<k16>::s : -Unit16<k16>::s;
+        return mk(a.x * c - a.y * s, a.x * s + a.y * c);
+    }
+}
+
+template <bool INV>
+__device__ __forceinline__ void dft2(cd& a, cd& b) {
+    cd t = a;
+    a = cadd(t, b);
+    b = csub(t, b);
+}
+
+template <bool INV>
+__device__ __forceinline__ void dft4(cd& x0, cd& x1, cd& x2, cd& x3) {
+    cd a = cadd(x0, x2), b = csub(x0, x2), c = cadd(x1, x3), d = csub(x1, x3);
+    cd dd = INV ? mul_i(d) : mul_mi(d);
+    x0 = cadd(a, c);
+    x2 = csub(a, c);
+    x1 = cadd(b, dd);
+    x3 = csub(b, dd);
+}
+
+// In-place R-point DFT of v[0..R-1] with natural-order output.
+template <int R, bool INV>
+__device__ __forceinline__ void dft(cd* v);
+
+template <>
+__device__ __forceinline__ void dft<2, false>(cd* v) { dft2<false>(v[0], v[1]); }
+template <>
+__device__ __forceinline__ void dft<2, true>(cd* v) { dft2<true>(v[0], v[1]); }
+template <>
+__device__ __forceinline__ void dft<4, false>(cd* v) { dft4<false>(v[0], v[1], v[2], v[3]); }
+template <>
+__device__ __forceinline__ void dft<4, true>(cd* v) { dft4<true>(v[0], v[1], v[2], v[3]); }
+
+// 8 = 2 x 4:  X[k1 + 4 k2] = sum_p w8^{p k1} w2^{p k2} sum_m x[2m+p] w4^{m k1}
+template <bool INV>
+__device__ __forceinline__ void dft8(cd* v) {
+    dft4<INV>(v[0], v[2], v[4], v[6]);
+    dft4<INV>(v[1], v[3], v[5], v[7]);
+    v[3] = twc<1, 8, INV>(v[3]);
+    v[5] = twc<2, 8, INV>(v[5]);
+    v[7] = twc<3, 8, INV>(v[7]);
+    dft2<INV>(v[0], v[1]);
+    dft2<INV>(v[2], v[3]);
+    dft2<INV>(v[4], v[5]);
+    dft2<INV>(v[6], v[7]);
+    // v[2 k1 + k2] holds X[k1 + 4 k2]
+    cd o[8];
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1)
+#pragma unroll
+        for (int k2 = 0; k2 < 2; ++k2) o[k1 + 4 * k2] = v[2 * k1 + k2];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) v[i] = o[i];
+}
+template <>
+__device__ __forceinline__ void dft<8, false>(cd* v) { dft8<false>(v); }
+template <>
+__device__ __forceinline__ void dft<8, true>(cd* v) { dft8<true>(v); }
+
+// 16 = 4 x 4:  X[k1 + 4 k2] = sum_p w16^{p k1} w4^{p k2} sum_m x[4m+p] w4^{m k1}
+template <bool INV>
+__device__ __forceinline__ void dft16(cd* v) {
+#pragma unroll
+    for (int p = 0; p < 4; ++p) dft4<INV>(v[p], v[4 + p], v[8 + p], v[12 + p]);
+    // v[p + 4 k1] = Y_p[k1]; twiddle by w16^{p k1}
+    v[5] = twc<1, 16, INV>(v[5]);
+    v[6] = twc<2, 16, INV>(v[6]);
+    v[7] = twc<3, 16, INV>(v[7]);
+    v[9] = twc<2, 16, INV>(v[9]);
+    v[10] = twc<4, 16, INV>(v[10]);
+    v[11] = twc<6, 16, INV>(v[11]);
+    v[13] = twc<3, 16, INV>(v[13]);
+    v[14] = twc<6, 16, INV>(v[14]);
+    v[15] = twc<9, 16, INV>(v[15]);
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) dft4<INV>(v[4 * k1], v[4 * k1 + 1], v[4 * k1 + 2], v[4 * k1 + 3]);
+    // v[4 k1 + k2] holds X[k1 + 4 k2]
+    cd o[16];
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1)
+#pragma unroll
+        for (int k2 = 0; k2 < 4; ++k2) o[k1 + 4 * k2] = v[4 * k1 + k2];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) v[i] = o[i];
+}
+template <>
+__device__ __forceinline__ void dft<16, false>(cd* v) { dft16<false>(v); }
+template <>
+__device__ __forceinline__ void dft<16, true>(cd* v) { dft16<true>(v); }
+
+// ---------------------------------------------------------------- plans --
+// Radix sequence per length; T threads per transform, E elements per thread.
+template <int N> struct Plan;
+template <> struct Plan<8>    { static constexpr int NS = 1, T = 1,  E = 8;  static constexpr int R[3] = {8, 1, 1}; };
+template <> struct Plan<16>   { static constexpr int NS = 2, T = 4,  E = 4;  static constexpr int R[3] = {4, 4, 1}; };
+template <> struct Plan<32>   { static constexpr int NS = 2, T = 4,  E = 8;  static constexpr int R[3] = {8, 4, 1}; };
+template <> struct Plan<64>   { static constexpr int NS = 2, T = 8,  E = 8;  static constexpr int R[3] = {8, 8, 1}; };
+template <> struct Plan<128>  { static constexpr int NS = 2, T = 8,  E = 16; static constexpr int R[3] = {16, 8, 1}; };
+template <> struct Plan<256>  { static constexpr int NS = 2, T = 16, E = 16; static constexpr int R[3] = {16, 16, 1}; };
+template <> struct Plan<512>  { static constexpr int NS = 3, T = 64, E = 8;  static constexpr int R[3] = {8, 8, 8}; };
+template <> struct Plan<1024> { static constexpr int NS = 3, T = 64, E = 16; static constexpr int R[3] = {16, 16, 4}; };
+
+// LDS footprint of one team's exchange area (one padding slot per 16 entries).
+template <int N>
+__host__ __device__ constexpr int lds_team() { return N + N / 16 + 1; }
+__device__ __forceinline__ int lpad(int i) { return i + (i >> 4); }
+
+// One Stockham stage: radix R, span S (product of the radices already done).
+template <int N, int R, int S, bool INV, bool LAST>
+__device__ __forceinline__ void fft_stage(cd* v, int t, cd* lds, const cd* __restrict__ tw) {
+    constexpr int T = Plan<N>::T, E = Plan<N>::E, NB = E / R;
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        const int j = t + T * b;
+        cd u[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) u[r] = v[b + r * NB];
+        if constexpr (S > 1) {
+            const int k = j % S;
+            constexpr int step = N / (S * R);
+#pragma unroll
+            for (int r = 1; r < R; ++r) {
+                const cd w = tw[r * k * step];
+                u[r] = INV ? cmulc(u[r], w) : cmul(u[r], w);
+            }
+        }
+        dft<R, INV>(u);
+        if constexpr (LAST) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[b + r * NB] = u[r];
+        } else {
+            const int base = (j / S) * S * R + (j % S);
+#pragma unroll
+            for (int r = 0; r < R; ++r) lds[lpad(base + r * S)] = u[r];
+        }
+    }
+    if constexpr (!LAST) {
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < E; ++m) v[m] = lds[lpad(t + T * m)];
+        __syncthreads();
+    }
+}
+
+// Full transform of the team's register signal v (layout t + T*m).
+// Every thread of the workgroup must call this (it contains barriers when the
+// plan has more than one stage).
+template <int N, bool INV>
+__device__ __forceinline__ void fft(cd* v, int t, cd* lds, const cd* __restrict__ tw) {
+    using P = Plan<N>;
+    if constexpr (P::NS == 1) {
+        fft_stage<N, P::R[0], 1, INV, true>(v, t, lds, tw);
+    } else if constexpr (P::NS == 2) {
+        fft_stage<N, P::R[0], 1, INV, false>(v, t, lds, tw);
+        fft_stage<N, P::R[1], P::R[0], INV, true>(v, t, lds, tw);
+    } else {
+        fft_stage<N, P::R[0], 1, INV, false>(v, t, lds, tw);
+        fft_stage<N, P::R[1], P::R[0], INV, false>(v, t, lds, tw);
+        fft_stage<N, P::R[2], P::R[0] * P::R[1], INV, true>(v, t, lds, tw);
+    }
+}
+
+}  // namespace pa

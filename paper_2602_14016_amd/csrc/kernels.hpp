@@ -1,0 +1,120 @@
+// kernels.hpp -- data layout, kernel argument blocks and launcher declarations.
+//
+// Layout in HBM (per context: N grid, B members, Kc = largest integer < N/3):
+//   physical field   double [B][N][N]                f[b][y][x]
+//   spectral state   cd     [B][KY][KXP]  ("compact") only the de-aliased band:
+//                    row r <-> ky = r (r <= Kc) or r - KY (r > Kc), KY = 2 Kc + 1,
+//                    column kx = 0..Kc, padded to KXP (multiple of 8) columns.
+//                    Unnormalised DFT coefficients of the real field (the
+//                    conjugate half kx < 0 is implied).
+//   y-field          cd     [B][N][KXP]   ("Y")  a field after the x-direction
+//                    real transform, kx = 0..Kc kept: the hand-off between the
+//                    row pass (physical space, x contiguous) and the column
+//                    pass (spectral space, transform along y).
+// Every 2D transform is a row pass + a column pass over Y; pointwise spectral
+// work (projection, Poisson inversion, velocity, derivatives, Lawson RK4
+// combine, adjoint transposes) is fused into the column pass, products of
+// fields into the row pass.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+#include "fft.hpp"
+
+namespace pa {
+
+struct Dims {
+    int N, B, K, KX, KXP, KY;
+    int cb;    // kx columns per column-pass workgroup
+    int tpb;   // row teams per row-pass workgroup
+};
+
+enum FieldKind : int { F_OMEGA = 0, F_U = 1, F_V = 2, F_WX = 3, F_WY = 4 };
+
+enum ColMode : int {
+    COL_INIT = 0,     // Y -> P omega0 -> state (+checkpoint) -> derived fields
+    COL_A = 1, COL_B = 2, COL_C = 3, COL_D = 4,   // Lawson RK4 stages
+    COL_FILTER = 5,   // Y -> multiplier * 1_S -> Y   (precondition)
+    COL_FROM_STATE = 6,   // compact state -> derived fields (no input transform)
+    COL_ADJ_C = 7, COL_ADJ_B = 8, COL_ADJ_A = 9, COL_ADJ_N = 10,  // adjoint stages
+    COL_ADJ_SRC = 11  // terminal source -> lambda_H
+};
+
+struct ColArgs {
+    const cd* yin[4];        // inputs (Y layout)
+    cd* yout[4];             // derived outputs (Y layout)
+    int nout;
+    int fields[4];           // FieldKind per output
+    cd* omega;               // compact state (rw)
+    cd* acc;                 // compact RK4 accumulator (rw)
+    cd* lam;                 // compact adjoint lambda_{n+1} / lambda_n
+    cd* omb;                 // compact adjoint accumulator omega-bar
+    cd* ckpt;                // optional compact checkpoint (write)
+    const cd* state_in;      // COL_FROM_STATE input
+    const double* invk2;     // [KY][KXP] 1/|k|^2 on S, 0 elsewhere
+    const double* ex2;       // [KXP] exp(-(nu kx^2 + mu) h/2)
+    const double* ey2;       // [KY]  exp(-nu ky^2 h/2)
+    const double* mult;      // [B?][KY][KXP] real multiplier (COL_FILTER)
+    const double* scale;     // [B] gradient scale (final adjoint output) or null
+    const cd* tw;            // twiddles exp(-2 pi i m/N)
+    double h;                // time step
+    double forcing;          // value of the curl-force spectrum at (0, +-n_f)
+    int nf;                  // n_f (0 = none or outside the band)
+    int final_out;           // adjoint: emit the gradient field instead of Lambda
+    int mult_per_member;     // COL_FILTER: multiplier table per member
+};
+
+struct RowObs {
+    int slot;                // observation slot, -1 = none
+    int stride, M, n_times;
+    const double* values;    // [B][n_times][2][M][M] or null
+    double* obs_out;         // [B][n_times][2][M][M] or null
+    double* jpart;           // [B][n_times][M] or null
+    int imp_x, imp_y;        // impulse source (row_src mode 1)
+};
+
+struct RowArgs {
+    const cd* yin[5];
+    cd* yout[4];
+    const double* phys_in;
+    double* phys_out;
+    const cd* tw;
+    RowObs obs;
+};
+
+// launchers (kernels.hip)
+hipError_t launch_row_r2c(const Dims& d, const double* in, cd* out, const cd* tw, hipStream_t s);
+hipError_t launch_row_c2r(const Dims& d, const cd* in, double* out, const cd* tw, hipStream_t s);
+hipError_t launch_row_nl(const Dims& d, const RowArgs& a, hipStream_t s);
+hipError_t launch_row_obs(const Dims& d, const RowArgs& a, hipStream_t s);
+hipError_t launch_row_adj(const Dims& d, const RowArgs& a, hipStream_t s);
+hipError_t launch_row_src(const Dims& d, const RowArgs& a, int impulse, hipStream_t s);
+hipError_t launch_col(const Dims& d, int mode, const ColArgs& a, hipStream_t s);
+
+// small kernels (misc.hip)
+hipError_t launch_reduce_j(int B, int n_rows, const double* jpart, double* J, hipStream_t s);
+hipError_t launch_fill(double* p, double v, size_t n, hipStream_t s);
+hipError_t launch_copy(double* dst, const double* src, size_t n, hipStream_t s);
+hipError_t launch_make_mult(const Dims& d, int kind, int metric, double param, double power,
+                            double* mult, hipStream_t s);
+hipError_t launch_init_spectrum(const Dims& d, const uint64_t* seeds, int kind, double k0,
+                                cd* state, hipStream_t s);
+hipError_t launch_state_norm(const Dims& d, const cd* state, int kind, double* out, hipStream_t s);
+hipError_t launch_state_scale(const Dims& d, cd* state, int kind, double target, const double* norm,
+                              hipStream_t s);
+hipError_t launch_shells(const Dims& d, const cd* lam, const int* shell_start, const int* shell_modes,
+                         int n_shells, double* out, size_t out_stride, hipStream_t s);
+// batched vector algebra over B members of length n (deterministic reductions)
+hipError_t launch_dot(int B, size_t n, const double* x, const double* y, double* out, double* partial,
+                      hipStream_t s);
+hipError_t launch_axpy(int B, size_t n, const double* alpha, double alpha_scale, const double* x,
+                       double* y, const int* active, hipStream_t s);
+hipError_t launch_axpby(int B, size_t n, const double* alpha, double alpha_scale, const double* x,
+                        const double* beta, double beta_scale, const double* y, double* z,
+                        const int* active, hipStream_t s);
+hipError_t launch_scal_copy(int B, size_t n, const double* alpha, const double* x, double* y,
+                            hipStream_t s);
+hipError_t launch_nonfinite(int B, size_t n, const double* x, int* flags, hipStream_t s);
+
+constexpr int DOT_BLOCKS = 64;   // partial sums per member in launch_dot
+
+}  // namespace pa

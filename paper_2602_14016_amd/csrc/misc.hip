@@ -1,0 +1,321 @@
+// misc.hip -- small kernels: deterministic reductions, batched vector algebra
+// for the optimiser, preconditioner multipliers, seeded initial spectra and
+// adjoint shell energies.  Every reduction runs in a fixed order (no atomics),
+// so results are bitwise reproducible and independent of the batch size.
+#include "kernels.hpp"
+
+namespace pa {
+
+__global__ void reduce_j_kernel(int B, int n_rows, const double* __restrict__ jpart, double* __restrict__ J) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    double s = 0.0;
+    const double* p = jpart + (size_t)b * n_rows;
+    for (int i = 0; i < n_rows; ++i) s += p[i];
+    J[b] = s;
+}
+hipError_t launch_reduce_j(int B, int n_rows, const double* jpart, double* J, hipStream_t s) {
+    hipLaunchKernelGGL(reduce_j_kernel, dim3((B + 63) / 64), dim3(64), 0, s, B, n_rows, jpart, J);
+    return hipGetLastError();
+}
+
+__global__ void fill_kernel(double* __restrict__ p, double v, size_t n) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+hipError_t launch_fill(double* p, double v, size_t n, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    size_t blocks = (n + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(fill_kernel, dim3((unsigned)blocks), dim3(256), 0, s, p, v, n);
+    return hipGetLastError();
+}
+
+__global__ void copy_kernel(double* __restrict__ dst, const double* __restrict__ src, size_t n) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+hipError_t launch_copy(double* dst, const double* src, size_t n, hipStream_t s) {
+    if (n == 0 || dst == src) return hipSuccess;
+    size_t blocks = (n + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(copy_kernel, dim3((unsigned)blocks), dim3(256), 0, s, dst, src, n);
+    return hipGetLastError();
+}
+
+// (m^2 W)^power on the band, 0 elsewhere.  kind: 0 identity, 1 exp(-p|k|),
+// 2 |k|^(-2p), 3 exp(-p|k|^2); metric 0 velocity (m^2 = |k|^2), 1 vorticity.
+__global__ void make_mult_kernel(Dims d, int kind, int metric, double param, double power,
+                                 double* __restrict__ mult) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= d.KY * d.KXP) return;
+    const int r = i / d.KXP, kx = i % d.KXP;
+    const int ky = (r <= d.K) ? r : r - d.KY;
+    const double k2 = (double)kx * kx + (double)ky * ky;
+    if (kx > d.K || k2 == 0.0) { mult[i] = 0.0; return; }
+    const double kap = sqrt(k2);
+    double W = 1.0;
+    if (kind == 1) W = exp(-param * kap);
+    else if (kind == 2) W = pow(kap, -2.0 * param);
+    else if (kind == 3) W = exp(-param * k2);
+    const double base = (metric == 0 ? k2 : 1.0) * W;
+    mult[i] = pow(base, power);
+}
+hipError_t launch_make_mult(const Dims& d, int kind, int metric, double param, double power, double* mult,
+                            hipStream_t s) {
+    const int n = d.KY * d.KXP;
+    hipLaunchKernelGGL(make_mult_kernel, dim3((n + 255) / 256), dim3(256), 0, s, d, kind, metric, param,
+                       power, mult);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- fields --
+// SplitMix64 (Steele, Lea & Flood 2014): n-th output of the stream seeded
+// with `seed` is mix64(seed + n * 0x9E3779B97F4A7C15).
+__device__ __forceinline__ uint64_t splitmix64(uint64_t seed, uint64_t n) {
+    uint64_t z = seed + n * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+__device__ __forceinline__ double unit_draw(uint64_t seed, int kx, int ky, int stream) {
+    const uint64_t n = 1ull + (uint64_t)stream + 4ull * ((uint64_t)(kx + 2048) + 4096ull * (uint64_t)(ky + 2048));
+    return (double)(splitmix64(seed, n) >> 11) * 0x1.0p-53;
+}
+
+__global__ void init_spectrum_kernel(Dims d, const uint64_t* __restrict__ seeds, int kind, double k0,
+                                     cd* __restrict__ state) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int b = blockIdx.y;
+    if (i >= d.KY * d.KXP) return;
+    const int r = i / d.KXP, kx = i % d.KXP;
+    const int ky = (r <= d.K) ? r : r - d.KY;
+    cd out = czero();
+    if (kx <= d.K && !(kx == 0 && ky == 0)) {
+        const bool inside = (ky > 0) || (ky == 0 && kx > 0);
+        const int rx = inside ? kx : -kx, ry = inside ? ky : -ky;
+        const uint64_t seed = seeds[b];
+        const double kap = sqrt((double)kx * kx + (double)ky * ky);
+        const double twopi = 6.283185307179586476925286766559;
+        double zr, zi, amp;
+        if (kind == 0) {
+            const double U = unit_draw(seed, rx, ry, 0);
+            zr = cos(twopi * U);
+            zi = sin(twopi * U);
+        } else {
+            const double U1 = unit_draw(seed, rx, ry, 1);
+            const double U2 = unit_draw(seed, rx, ry, 2);
+            const double rad = sqrt(-2.0 * log(1.0 - U1));
+            zr = rad * cos(twopi * U2) / sqrt(2.0);
+            zi = rad * sin(twopi * U2) / sqrt(2.0);
+        }
+        if (kind == 2) {
+            amp = 1.0;
+        } else {
+            const double q = kap / k0;
+            amp = sqrt(kap * (kap * kap * kap * kap * exp(-2.0 * q * q)));
+        }
+        out = mk(amp * zr, inside ? amp * zi : -amp * zi);
+    }
+    state[(size_t)b * d.KY * d.KXP + i] = out;
+}
+hipError_t launch_init_spectrum(const Dims& d, const uint64_t* seeds, int kind, double k0, cd* state,
+                                hipStream_t s) {
+    const int n = d.KY * d.KXP;
+    hipLaunchKernelGGL(init_spectrum_kernel, dim3((n + 255) / 256, d.B), dim3(256), 0, s, d, seeds, kind, k0,
+                       state);
+    return hipGetLastError();
+}
+
+// kind 0/1: sum over the full spectrum of |w|^2 / |k|^2; kind 2: of |w|^2.
+// One block per member, fixed-order tree.
+__global__ void state_norm_kernel(Dims d, const cd* __restrict__ state, int kind, double* __restrict__ out) {
+    __shared__ double sh[256];
+    const int b = blockIdx.x;
+    const cd* st = state + (size_t)b * d.KY * d.KXP;
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < d.KY * d.KXP; i += blockDim.x) {
+        const int r = i / d.KXP, kx = i % d.KXP;
+        if (kx > d.K) continue;
+        const int ky = (r <= d.K) ? r : r - d.KY;
+        const double k2 = (double)kx * kx + (double)ky * ky;
+        if (k2 == 0.0) continue;
+        const double wgt = kx > 0 ? 2.0 : 1.0;
+        const double a2 = st[i].x * st[i].x + st[i].y * st[i].y;
+        acc += wgt * (kind == 2 ? a2 : a2 / k2);
+    }
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[b] = sh[0];
+}
+hipError_t launch_state_norm(const Dims& d, const cd* state, int kind, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(state_norm_kernel, dim3(d.B), dim3(256), 0, s, d, state, kind, out);
+    return hipGetLastError();
+}
+
+__global__ void state_scale_kernel(Dims d, cd* __restrict__ state, int kind, double target,
+                                   const double* __restrict__ norm) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int b = blockIdx.y;
+    if (i >= d.KY * d.KXP) return;
+    const double n4 = (double)d.N * d.N * (double)d.N * d.N;
+    double f;
+    if (kind == 2) f = target / (sqrt(norm[b]) / ((double)d.N * d.N));
+    else f = sqrt(target / (0.5 * norm[b] / n4));
+    cd& v = state[(size_t)b * d.KY * d.KXP + i];
+    v = cscale(v, f);
+}
+hipError_t launch_state_scale(const Dims& d, cd* state, int kind, double target, const double* norm,
+                              hipStream_t s) {
+    const int n = d.KY * d.KXP;
+    hipLaunchKernelGGL(state_scale_kernel, dim3((n + 255) / 256, d.B), dim3(256), 0, s, d, state, kind,
+                       target, norm);
+    return hipGetLastError();
+}
+
+// Shell energies 1/2 |k|^2 |lam|^2 / N^4 per unit-width shell k = 1..n_shells.
+// shell_modes lists compact indices r*KXP + kx grouped by shell (CSR with
+// shell_start); one thread per (member, shell), fixed order.
+__global__ void shells_kernel(Dims d, const cd* __restrict__ lam, const int* __restrict__ start,
+                              const int* __restrict__ modes, int n_shells, double* __restrict__ out,
+                              size_t out_stride) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    const int b = blockIdx.y;
+    if (k >= n_shells) return;
+    const cd* l = lam + (size_t)b * d.KY * d.KXP;
+    const double n4 = (double)d.N * d.N * (double)d.N * d.N;
+    double s = 0.0;
+    for (int i = start[k]; i < start[k + 1]; ++i) {
+        const int idx = modes[i];
+        const int r = idx / d.KXP, kx = idx % d.KXP;
+        const int ky = (r <= d.K) ? r : r - d.KY;
+        const double k2 = (double)kx * kx + (double)ky * ky;
+        const double wgt = kx > 0 ? 2.0 : 1.0;
+        s += wgt * 0.5 * k2 * (l[idx].x * l[idx].x + l[idx].y * l[idx].y);
+    }
+    out[(size_t)b * out_stride + k] = s / n4;
+}
+hipError_t launch_shells(const Dims& d, const cd* lam, const int* shell_start, const int* shell_modes,
+                         int n_shells, double* out, size_t out_stride, hipStream_t s) {
+    hipLaunchKernelGGL(shells_kernel, dim3((n_shells + 127) / 128, d.B), dim3(128), 0, s, d, lam, shell_start,
+                       shell_modes, n_shells, out, out_stride);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------- vector algebra --
+
+__global__ void dot_partial_kernel(size_t n, const double* __restrict__ x, const double* __restrict__ y,
+                                   double* __restrict__ partial) {
+    __shared__ double sh[256];
+    const int b = blockIdx.y;
+    const size_t chunk = (n + DOT_BLOCKS - 1) / DOT_BLOCKS;
+    const size_t lo = blockIdx.x * chunk;
+    const size_t hi = (lo + chunk < n) ? lo + chunk : n;
+    const double* xb = x + (size_t)b * n;
+    const double* yb = y + (size_t)b * n;
+    double acc = 0.0;
+    for (size_t i = lo + threadIdx.x; i < hi; i += blockDim.x) acc += xb[i] * yb[i];
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[(size_t)b * DOT_BLOCKS + blockIdx.x] = sh[0];
+}
+__global__ void dot_final_kernel(int B, const double* __restrict__ partial, double* __restrict__ out) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    double s = 0.0;
+    for (int i = 0; i < DOT_BLOCKS; ++i) s += partial[(size_t)b * DOT_BLOCKS + i];
+    out[b] = s;
+}
+hipError_t launch_dot(int B, size_t n, const double* x, const double* y, double* out, double* partial,
+                      hipStream_t s) {
+    hipLaunchKernelGGL(dot_partial_kernel, dim3(DOT_BLOCKS, B), dim3(256), 0, s, n, x, y, partial);
+    hipLaunchKernelGGL(dot_final_kernel, dim3((B + 63) / 64), dim3(64), 0, s, B, partial, out);
+    return hipGetLastError();
+}
+
+// y[b] += alpha[b] * alpha_scale * x[b]  (members with active[b] == 0 untouched)
+__global__ void axpy_kernel(size_t n, const double* __restrict__ alpha, double alpha_scale,
+                            const double* __restrict__ x, double* __restrict__ y, const int* __restrict__ active) {
+    const int b = blockIdx.y;
+    if (active && !active[b]) return;
+    const double a = (alpha ? alpha[b] : 1.0) * alpha_scale;
+    const double* xb = x + (size_t)b * n;
+    double* yb = y + (size_t)b * n;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        yb[i] += a * xb[i];
+}
+hipError_t launch_axpy(int B, size_t n, const double* alpha, double alpha_scale, const double* x, double* y,
+                       const int* active, hipStream_t s) {
+    size_t blocks = (n + 255) / 256;
+    if (blocks > 1024) blocks = 1024;
+    hipLaunchKernelGGL(axpy_kernel, dim3((unsigned)blocks, B), dim3(256), 0, s, n, alpha, alpha_scale, x, y,
+                       active);
+    return hipGetLastError();
+}
+
+// z[b] = alpha[b]*as * x[b] + beta[b]*bs * y[b]   (null alpha/beta read as 1)
+__global__ void axpby_kernel(size_t n, const double* __restrict__ alpha, double as, const double* __restrict__ x,
+                             const double* __restrict__ beta, double bs, const double* __restrict__ y,
+                             double* __restrict__ z, const int* __restrict__ active) {
+    const int b = blockIdx.y;
+    if (active && !active[b]) return;
+    const double a = (alpha ? alpha[b] : 1.0) * as;
+    const double c = (beta ? beta[b] : 1.0) * bs;
+    const double* xb = x + (size_t)b * n;
+    const double* yb = y + (size_t)b * n;
+    double* zb = z + (size_t)b * n;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        zb[i] = a * xb[i] + c * yb[i];
+}
+hipError_t launch_axpby(int B, size_t n, const double* alpha, double alpha_scale, const double* x,
+                        const double* beta, double beta_scale, const double* y, double* z, const int* active,
+                        hipStream_t s) {
+    size_t blocks = (n + 255) / 256;
+    if (blocks > 1024) blocks = 1024;
+    hipLaunchKernelGGL(axpby_kernel, dim3((unsigned)blocks, B), dim3(256), 0, s, n, alpha, alpha_scale, x, beta,
+                       beta_scale, y, z, active);
+    return hipGetLastError();
+}
+
+// y[b] = alpha[b] * x[b]
+__global__ void scal_copy_kernel(size_t n, const double* __restrict__ alpha, const double* __restrict__ x,
+                                 double* __restrict__ y) {
+    const int b = blockIdx.y;
+    const double a = alpha[b];
+    const double* xb = x + (size_t)b * n;
+    double* yb = y + (size_t)b * n;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        yb[i] = a * xb[i];
+}
+hipError_t launch_scal_copy(int B, size_t n, const double* alpha, const double* x, double* y, hipStream_t s) {
+    size_t blocks = (n + 255) / 256;
+    if (blocks > 1024) blocks = 1024;
+    hipLaunchKernelGGL(scal_copy_kernel, dim3((unsigned)blocks, B), dim3(256), 0, s, n, alpha, x, y);
+    return hipGetLastError();
+}
+
+// flags[b] = 1 if any entry of member b is not finite (flags must start at 0).
+__global__ void nonfinite_kernel(size_t n, const double* __restrict__ x, int* __restrict__ flags) {
+    const int b = blockIdx.y;
+    const double* xb = x + (size_t)b * n;
+    int bad = 0;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        if (!isfinite(xb[i])) bad = 1;
+    if (bad) flags[b] = 1;
+}
+hipError_t launch_nonfinite(int B, size_t n, const double* x, int* flags, hipStream_t s) {
+    size_t blocks = (n + 255) / 256;
+    if (blocks > 256) blocks = 256;
+    hipLaunchKernelGGL(nonfinite_kernel, dim3((unsigned)blocks, B), dim3(256), 0, s, n, x, flags);
+    return hipGetLastError();
+}
+
+}  // namespace pa

@@ -1,0 +1,216 @@
+"""Torch-facing wrapper of the C ABI: device memory and streams from PyTorch,
+all computation in the HIP library.
+
+A Solver owns one library context (grid N, batch B, physics) and a cached
+workspace tensor.  Fields are float64 CUDA tensors of shape [B, N, N].
+"""
+
+import ctypes
+from ctypes import byref, c_double, c_int32, c_size_t, c_uint64, c_void_p
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import torch
+
+from . import native as nv
+
+IDENTITY, EXP_ABS, FRACTIONAL, HEAT = 0, 1, 2, 3
+VELOCITY, VORTICITY = 0, 1
+
+
+@dataclass(frozen=True)
+class KernelSpec:
+    """W(|k|): 0 identity, 1 exp(-param|k|), 2 |k|^(-2 param), 3 exp(-param|k|^2)."""
+    kind: int = IDENTITY
+    param: float = 0.0
+    metric: int = VELOCITY
+
+    def c(self):
+        return nv.Kernel(self.kind, self.metric, float(self.param))
+
+
+@dataclass
+class Observations:
+    """Probe stride, increasing step indices, values [B, n_times, 2, M, M] (device) or None."""
+    stride: int
+    steps: Sequence[int]
+    values: Optional[torch.Tensor] = None
+
+    def c(self):
+        arr = (c_int32 * len(self.steps))(*[int(s) for s in self.steps])
+        vals = self.values.data_ptr() if self.values is not None else None
+        o = nv.Obs(int(self.stride), len(self.steps), ctypes.cast(arr, ctypes.POINTER(c_int32)), vals)
+        return o, arr   # keep arr alive while o is used
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _need(t, shape, name):
+    if not (isinstance(t, torch.Tensor) and t.dtype == torch.float64 and t.is_cuda):
+        raise TypeError(f"{name} must be a float64 CUDA tensor")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+class Solver:
+    def __init__(self, N, B=1, nu=1e-3, dt=5e-3, mu=0.0, forcing_amp=0.0, forcing_k=4,
+                 device="cuda", stream: Optional[torch.cuda.Stream] = None):
+        self.lib = nv.load()
+        self.N, self.B = int(N), int(B)
+        self.phys = nv.Physics(float(nu), float(mu), float(dt), float(forcing_amp), int(forcing_k), 0)
+        self.device = torch.device(device)
+        self.stream = stream
+        ctx = c_void_p()
+        with torch.cuda.device(self.device):
+            nv.check(self.lib.pa_create(byref(self.phys), self.N, self.B, self._stream_handle(), byref(ctx)))
+        self.ctx = ctx
+        kc = c_int32()
+        nv.check(self.lib.pa_get_shape(self.ctx, None, None, byref(kc)))
+        self.Kc = kc.value
+        self._ws = None
+
+    # ------------------------------------------------------------- plumbing
+    def _stream_handle(self):
+        s = self.stream if self.stream is not None else torch.cuda.current_stream(self.device)
+        return c_void_p(s.cuda_stream)
+
+    def _sync_stream(self):
+        nv.check(self.lib.pa_set_stream(self.ctx, self._stream_handle()))
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            self.lib.pa_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def workspace_bytes(self, n_steps=0, ckpt_every=1, n_obs=0, lbfgs_m=0):
+        b = c_size_t()
+        nv.check(self.lib.pa_workspace_bytes(self.ctx, int(n_steps), int(ckpt_every), int(n_obs), int(lbfgs_m),
+                                             byref(b)))
+        return b.value
+
+    def checkpoint_bytes(self, n_steps, ckpt_every):
+        b = c_size_t()
+        nv.check(self.lib.pa_checkpoint_bytes(self.ctx, int(n_steps), int(ckpt_every), byref(b)))
+        return b.value
+
+    def workspace(self, n_steps=0, ckpt_every=1, n_obs=0, lbfgs_m=0):
+        need = self.workspace_bytes(n_steps, ckpt_every, n_obs, lbfgs_m)
+        if self._ws is None or self._ws.numel() < need + 256:
+            self._ws = None
+            self._ws = torch.empty(need + 256, dtype=torch.uint8, device=self.device)
+        base = self._ws.data_ptr()
+        off = (-base) % 256
+        return c_void_p(base + off), c_size_t(self._ws.numel() - off)
+
+    def empty(self):
+        return torch.empty((self.B, self.N, self.N), dtype=torch.float64, device=self.device)
+
+    def set_tiles(self, col_block=0, row_teams=0):
+        nv.check(self.lib.pa_set_tiles(self.ctx, int(col_block), int(row_teams)))
+
+    # ---------------------------------------------------------------- calls
+    def init_field(self, seeds, kind=0, k0=4.0, target=0.5, out=None):
+        seeds = [int(s) for s in seeds]
+        if len(seeds) != self.B:
+            raise ValueError("need one seed per member")
+        out = self.empty() if out is None else out
+        _need(out, (self.B, self.N, self.N), "out")
+        arr = (c_uint64 * self.B)(*seeds)
+        self._sync_stream()
+        ws, wb = self.workspace()
+        nv.check(self.lib.pa_init_field(self.ctx, arr, int(kind), float(k0), float(target), _ptr(out), ws, wb))
+        return out
+
+    def forward(self, omega0, n_steps, obs: Optional[Observations] = None, want_obs=False, want_J=None,
+                ckpt_every=1, ckpt: Optional[torch.Tensor] = None, want_final=True):
+        _need(omega0, (self.B, self.N, self.N), "omega0")
+        self._sync_stream()
+        res = {}
+        o_c = None
+        keep = None
+        if obs is not None:
+            o_c, keep = obs.c()
+        if want_J is None:
+            want_J = obs is not None and obs.values is not None
+        J = torch.empty(self.B, dtype=torch.float64, device=self.device) if want_J else None
+        M = self.N // obs.stride if obs is not None else 0
+        oo = (torch.empty((self.B, len(obs.steps), 2, M, M), dtype=torch.float64, device=self.device)
+              if want_obs else None)
+        wT = self.empty() if want_final else None
+        ws, wb = self.workspace(0, ckpt_every, len(obs.steps) if obs else 0)
+        nv.check(self.lib.pa_forward(self.ctx, _ptr(omega0), int(n_steps), byref(o_c) if o_c else None,
+                                     _ptr(J), _ptr(oo), _ptr(wT), int(ckpt_every), _ptr(ckpt), ws, wb))
+        del keep
+        res["omega_T"] = wT
+        res["J"] = J
+        res["obs"] = oo
+        return res
+
+    def adjoint_gradient(self, omega0, n_steps, obs: Observations, ckpt_every=50):
+        _need(omega0, (self.B, self.N, self.N), "omega0")
+        self._sync_stream()
+        o_c, keep = obs.c()
+        J = torch.empty(self.B, dtype=torch.float64, device=self.device)
+        g = self.empty()
+        ws, wb = self.workspace(n_steps, ckpt_every, len(obs.steps))
+        nv.check(self.lib.pa_adjoint_gradient(self.ctx, _ptr(omega0), int(n_steps), byref(o_c), _ptr(J), _ptr(g),
+                                              int(ckpt_every), ws, wb))
+        del keep
+        return J, g
+
+    def adjoint_from_checkpoints(self, ckpt, n_steps, obs: Observations, ckpt_every, scale=None):
+        self._sync_stream()
+        o_c, keep = obs.c()
+        g = self.empty()
+        ws, wb = self.workspace(n_steps, ckpt_every, len(obs.steps))
+        nv.check(self.lib.pa_adjoint_from_checkpoints(self.ctx, _ptr(ckpt), int(n_steps), byref(o_c), _ptr(scale),
+                                                      _ptr(g), int(ckpt_every), ws, wb))
+        del keep
+        return g
+
+    def precondition(self, x, kernel: KernelSpec, power, out=None):
+        _need(x, (self.B, self.N, self.N), "x")
+        out = self.empty() if out is None else out
+        self._sync_stream()
+        k = kernel.c()
+        ws, wb = self.workspace()
+        nv.check(self.lib.pa_precondition(self.ctx, byref(k), float(power), _ptr(x), _ptr(out), ws, wb))
+        return out
+
+    def assimilate(self, omega_fg, n_steps, obs: Observations, kernel: KernelSpec, method="lbfgs",
+                   max_iter=10, lbfgs_m=10, ckpt_every=50):
+        _need(omega_fg, (self.B, self.N, self.N), "omega_fg")
+        self._sync_stream()
+        w = omega_fg.clone()
+        o_c, keep = obs.c()
+        k = kernel.c()
+        hist = (c_double * (self.B * (max_iter + 1)))()
+        iters = (c_int32 * self.B)()
+        m = int(lbfgs_m) if method == "lbfgs" else 1
+        ws, wb = self.workspace(n_steps, ckpt_every, len(obs.steps), max(m, 1))
+        nv.check(self.lib.pa_assimilate(self.ctx, _ptr(w), int(n_steps), byref(o_c), byref(k),
+                                        0 if method == "lbfgs" else 1, int(max_iter), m, int(ckpt_every),
+                                        hist, iters, ws, wb))
+        del keep
+        H = [[hist[b * (max_iter + 1) + i] for i in range(max_iter + 1)] for b in range(self.B)]
+        return w, H, [iters[b] for b in range(self.B)]
+
+    def adjoint_impulse(self, omega0, n_steps, ix, iy, n_shells, ckpt_every=50, want_field=False):
+        _need(omega0, (self.B, self.N, self.N), "omega0")
+        self._sync_stream()
+        sh = torch.empty((self.B, n_steps + 1, n_shells), dtype=torch.float64, device=self.device)
+        f = self.empty() if want_field else None
+        ws, wb = self.workspace(n_steps, ckpt_every, 0)
+        nv.check(self.lib.pa_adjoint_impulse(self.ctx, _ptr(omega0), int(n_steps), int(ix), int(iy), int(n_shells),
+                                             _ptr(sh), _ptr(f), int(ckpt_every), ws, wb))
+        return sh, f

@@ -1,0 +1,71 @@
+"""GPU parity of the preconditioned 4D-Var loop against the oracle."""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import synth
+from oracle.model import Obs, Physics
+from oracle.precond import Kernel
+
+pytestmark = pytest.mark.gpu
+
+ITER_TOL = 1e-9
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float64)).cuda()
+
+
+def _setup(N, steps, osteps, stride, seeds=(0,), ph=None):
+    ph = ph or Physics(N=N, nu=1e-3, dt=5e-3)
+    mo = []
+    for s in seeds:
+        truth = O.init_field(N, [s], kind=1, k0=4.0)[0]
+        mo.append(O.forward(truth, ph, steps, Obs(stride, osteps))[2])
+    return ph, np.stack(mo)
+
+
+def test_steepest_descent_c0_like_parity():
+    # BASELINE c0 shape at reduced size: SD with the exponential kernel, first guess 0
+    from paper_2602_14016_amd import KernelSpec, Observations, Solver
+    print("CASE sd", flush=True)
+    N, steps = 32, 40
+    osteps = [steps]
+    ph, mo = _setup(N, steps, osteps, 4)
+    fg = np.zeros((N, N))
+    kern = Kernel(1, 0.1, 0)
+    w_ref, h_ref, it_ref, st_ref = O.assimilate(fg, ph, steps, Obs(4, osteps, mo[0]), kern, "sd", 5)
+    s = Solver(N, 1, nu=ph.nu, dt=ph.dt)
+    w, H, iters = s.assimilate(dev(fg[None]), steps, Observations(4, osteps, dev(mo)), KernelSpec(1, 0.1, 0),
+                               method="sd", max_iter=5, ckpt_every=16)
+    torch.cuda.synchronize()
+    assert iters[0] == it_ref == 5 and st_ref == 0
+    assert np.allclose(H[0], h_ref, rtol=ITER_TOL, atol=0)
+    assert rel(w.cpu().numpy()[0], w_ref) < ITER_TOL
+
+
+@pytest.mark.parametrize("kern", [Kernel(0, 0.0, 0), Kernel(2, 0.5, 0)])
+def test_lbfgs_parity(kern):
+    from paper_2602_14016_amd import KernelSpec, Observations, Solver
+    print("CASE lbfgs", kern, flush=True)
+    N, steps = 32, 24
+    osteps = synth.evenly_spaced_steps(steps, 3)
+    ph, mo = _setup(N, steps, osteps, 4, seeds=(3, 4))
+    fg = 0.5 * O.init_field(N, [5, 6], kind=0, k0=4.0)
+    s = Solver(N, 2, nu=ph.nu, dt=ph.dt)
+    w, H, iters = s.assimilate(dev(fg), steps, Observations(4, osteps, dev(mo)),
+                               KernelSpec(kern.kind, kern.param, kern.metric), method="lbfgs", max_iter=4,
+                               lbfgs_m=3, ckpt_every=10)
+    torch.cuda.synchronize()
+    w = w.cpu().numpy()
+    for b in range(2):
+        w_ref, h_ref, it_ref, st_ref = O.assimilate(fg[b], ph, steps, Obs(4, osteps, mo[b]), kern, "lbfgs", 4, 3)
+        assert iters[b] == it_ref
+        assert np.allclose(H[b][: it_ref + 1], h_ref, rtol=ITER_TOL, atol=0)
+        assert rel(w[b], w_ref) < ITER_TOL
