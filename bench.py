@@ -1,0 +1,245 @@
+#!/usr/bin/env python
+"""Benchmark of the hot path on one MI355X.
+
+One step = one complete batched forward + adjoint solve of the ensemble
+workload: 64 independent realizations of 256^2 decaying 2D turbulence (k0 =
+10 random-phase spectrum, energy 0.5, seeds 0..63), nu = 1e-4, dt = 2e-3,
+500 forward steps with checkpoints every 50, segment recomputation, 500
+adjoint steps from a unit u-impulse at (128, 128), per-shell adjoint energy
+for |k| in 1..85 after every adjoint step.  Inputs are resident in HBM before
+the timed region.  value = members * N^2 * horizon * steps / seconds
+(grid-point-steps/s, each unit one point advanced one forward and one adjoint
+step).  Beside it: the plain path (one member per solve, same kernels),
+p50/p99 solve latency, the roofline of the dominant kernel measured with HIP
+events on its stream, and the CPU oracle timed on a bounded sample.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+
+import argparse
+import hashlib
+import json
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "grid-point-steps/s fwd+adj FP64, batched vs plain at 256²; p50/p99 solve latency"
+HBM_PEAK_GBS = 8000.0
+
+# Kernel classes (pa_profile_start) and their algorithmic bytes per member.
+# Yb: one field's band-limited y-transform N*(Kc+1) complex; Cb: one compact
+# spectral state (2Kc+1)*(Kc+1) complex.
+CLASS_NAMES = {0: "row_nl_kernel", 1: "col_kernel (forward stages)", 2: "row_adj_kernel",
+               3: "col_kernel (adjoint stages)"}
+
+
+def algorithmic_bytes(cls, N):
+    Kc = (N - 1) // 3
+    Yb = N * (Kc + 1) * 16
+    Cb = (2 * Kc + 1) * (Kc + 1) * 16
+    return {0: 5 * Yb,                 # read U,V,Wx,Wy; write q
+            1: 5 * Yb + 2.75 * Cb,     # read q; write 4 fields; state/accumulator (mean of stages A-D)
+            2: 8 * Yb,                 # read U,V,Wx,Wy,Lambda,Lambda_y; write 2 products
+            3: 4 * Yb + 2.5 * Cb}[cls]  # read 2 products; write Lambda, Lambda_y; adjoint accumulators
+
+
+def percentile(xs, p):
+    xs = sorted(xs)
+    if not xs:
+        return None
+    k = (len(xs) - 1) * p / 100.0
+    lo = int(k)
+    hi = min(lo + 1, len(xs) - 1)
+    return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
+
+
+def kernel_source_sha():
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2602_14016_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".hpp")):
+            h.update(open(os.path.join(csrc, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(cls, N, members):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic_counters.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("source_sha") != kernel_source_sha():
+        return None
+    if int(kv.get("class", -1)) != cls or int(kv.get("N", -1)) != N or int(kv.get("members", -1)) != members:
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(N, nu, dt, steps_sample, k0):
+    """The oracle as written (NumPy, its own DFT), one member, a short horizon."""
+    import numpy as np
+    import oracle as O
+    from oracle.model import Physics
+    threads = None
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max((p.get("num_threads", 0) for p in threadpool_info()), default=None)
+    except Exception:
+        pass
+    ph = Physics(N=N, nu=nu, dt=dt)
+    w0 = O.init_field(N, [0], kind=0, k0=k0, target=0.5)[0]
+    t0 = time.perf_counter()
+    O.impulse_adjoint(w0, ph, steps_sample, N // 2, N // 2, (N - 1) // 3)
+    t = time.perf_counter() - t0
+    return {"value": N * N * steps_sample / t, "unit": "grid-point-steps/s", "cores": threads or os.cpu_count(),
+            "kind": "oracle",
+            "sample": f"1 member, {N}^2, {steps_sample} forward + {steps_sample} adjoint steps of the same "
+                      f"impulse-response solve (NumPy oracle with exact-twiddle DFT matrices), {t:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--members", type=int, default=64)
+    ap.add_argument("--N", type=int, default=256)
+    ap.add_argument("--horizon", type=int, default=500)
+    ap.add_argument("--ckpt-every", type=int, default=50)
+    ap.add_argument("--plain-solves", type=int, default=4)
+    ap.add_argument("--roofline-class", type=int, default=2)
+    ap.add_argument("--sample-every", type=int, default=8)
+    ap.add_argument("--cpu-steps", type=int, default=100)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--col-block", type=int, default=0)
+    ap.add_argument("--row-teams", type=int, default=0)
+    ap.add_argument("--fft-variant", type=int, default=-1)
+    ap.add_argument("--no-autotune", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(members and requests would shard across GPUs with no exchange). Run with --gpus 1.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2602_14016_amd import Solver
+
+    N, B, H, K = args.N, args.members, args.horizon, args.ckpt_every
+    nu, dt, k0 = 1e-4, 2e-3, 10.0
+    nshell = (N - 1) // 3
+    ix = iy = N // 2
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+
+    from paper_2602_14016_amd.autotune import autotune
+    s = Solver(N, B, nu=nu, dt=dt, device=dev)
+    w0 = s.init_field(list(range(B)), kind=0, k0=k0, target=0.5)
+    torch.cuda.synchronize()
+    manual = args.col_block or args.row_teams or args.fft_variant >= 0
+    if manual or args.no_autotune:
+        s.set_tiles(args.col_block, args.row_teams, args.fft_variant)
+        tiles = {"col_block": args.col_block, "row_teams": args.row_teams, "fft_variant": args.fft_variant,
+                 "autotuned": False}
+    else:
+        at = autotune(s, w0, n_steps=16, ckpt_every=8)
+        tiles = {k: at[k] for k in ("fft_variant", "col_block", "row_teams")}
+        tiles["autotuned"] = True
+        tiles["trials"] = [(r["fft_variant"], r["col_block"], r["row_teams"], round(r["ms"], 3)) for r in at["trials"]]
+        print("autotune", json.dumps(tiles), file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        s.adjoint_impulse(w0, H, ix, iy, nshell, ckpt_every=K)
+    torch.cuda.synchronize()
+
+    stream = torch.cuda.current_stream(dev)
+    lat = []
+    s.profile_start(args.roofline_class, args.sample_every)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        s.adjoint_impulse(w0, H, ix, iy, nshell, ckpt_every=K)
+        e1.record(stream)
+        lat.append((e0, e1))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = s.profile_stop()
+    lat_ms = [a.elapsed_time(b) for a, b in lat]
+    elapsed = t1 - t0
+    value = B * N * N * H * args.steps / elapsed
+
+    # plain path: one member per solve, same kernels, solved one after another
+    p = Solver(N, 1, nu=nu, dt=dt, device=dev)
+    if args.col_block or args.row_teams:
+        p.set_tiles(args.col_block, args.row_teams)
+    p.adjoint_impulse(w0[:1].contiguous(), H, ix, iy, nshell, ckpt_every=K)
+    torch.cuda.synchronize()
+    plain_lat = []
+    tp0 = time.perf_counter()
+    for m in range(args.plain_solves):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        p.adjoint_impulse(w0[m:m + 1].contiguous(), H, ix, iy, nshell, ckpt_every=K)
+        e1.record(stream)
+        plain_lat.append((e0, e1))
+    torch.cuda.synchronize()
+    tp1 = time.perf_counter()
+    plain_ms = [a.elapsed_time(b) for a, b in plain_lat]
+    plain_value = N * N * H * args.plain_solves / (tp1 - tp0)
+
+    # roofline of the dominant kernel
+    cls = args.roofline_class
+    per_launch_ms = prof["total_ms"] / max(prof["timed_launches"], 1)
+    bytes_launch = algorithmic_bytes(cls, N) * B
+    achieved = bytes_launch / (per_launch_ms * 1e-3) / 1e9
+    traffic = read_traffic(cls, N, B)
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": CLASS_NAMES[cls], "avg_launch_ms": round(per_launch_ms, 4),
+                "algorithmic_bytes_per_launch": int(bytes_launch),
+                "timed_launches": prof["timed_launches"], "launches": prof["launches"]}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(N, nu, dt, args.cpu_steps, k0)
+
+    line = {
+        "metric": METRIC, "value": value, "unit": "grid-point-steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"ensemble of {B} realizations of {N}^2 decaying 2D turbulence "
+                               f"(k0={k0:g} random-phase spectrum, energy 0.5, seeds 0..{B - 1}), nu={nu:g}, "
+                               f"dt={dt:g}, {H} forward + {H} adjoint steps per member from a unit u-impulse "
+                               f"at ({ix},{iy}), checkpoints every {K}, shell energies |k|=1..{nshell}",
+                   "members": B, "grid": N, "horizon": H, "ckpt_every": K},
+        "latency_ms": {"batched_p50": percentile(lat_ms, 50), "batched_p99": percentile(lat_ms, 99),
+                       "plain_p50": percentile(plain_ms, 50), "plain_p99": percentile(plain_ms, 99)},
+        "plain": {"value": plain_value, "unit": "grid-point-steps/s", "solves": args.plain_solves,
+                  "speedup_batched_over_plain": value / plain_value},
+        "roofline": roofline,
+        "tiles": tiles,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

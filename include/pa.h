@@ -206,10 +206,25 @@ pa_status pa_adjoint_impulse(pa_ctx* ctx, const double* omega0, int32_t n_steps,
                              double* field_out, int32_t ckpt_every, void* workspace,
                              size_t workspace_bytes);
 
-/* FFT tile choice for this context (the autotuner's knob): col_block = kx
- * columns per column-pass workgroup (1, 2, 4 or 8), row_teams = rows per
- * row-pass workgroup (1, 2, 4 or 8).  0 keeps the current value. */
-pa_status pa_set_tiles(pa_ctx* ctx, int32_t col_block, int32_t row_teams);
+/* FFT tile choice for this context (the autotuner's knobs): col_block = kx
+ * columns per column-pass workgroup (1, 2, 4 or 8; 0 keeps the current value,
+ * reduced if the variant needs it), row_teams = rows per row-pass workgroup
+ * (1, 2, 4 or 8; 0 keeps), fft_variant = register plan of the 1D transforms
+ * (0: more elements per thread, 1: more threads per transform; -1 keeps).
+ * Results do not depend on the choice beyond rounding of the transforms. */
+pa_status pa_set_tiles(pa_ctx* ctx, int32_t col_block, int32_t row_teams, int32_t fft_variant);
+
+/* Launch timing for measurement: until pa_profile_stop, every sample_every-th
+ * launch of one kernel class is bracketed by HIP events recorded on the
+ * context stream (the stream the kernel runs on).  kernel_class 0: row pass
+ * of the right-hand side; 1: column pass of the forward RK4 stages; 2: row
+ * pass of the adjoint products; 3: column pass of the adjoint stages.
+ * pa_profile_stop synchronises the stream and returns the number of timed
+ * launches, the number of launches of that class seen, and the summed event
+ * time in milliseconds. */
+pa_status pa_profile_start(pa_ctx* ctx, int32_t kernel_class, int32_t sample_every);
+pa_status pa_profile_stop(pa_ctx* ctx, int64_t* timed_launches, int64_t* seen_launches,
+                          double* total_ms);
 
 #ifdef __cplusplus
 }

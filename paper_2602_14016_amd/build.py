@@ -38,9 +38,11 @@ def _run(cmd):
     return time.time() - t0, r.stdout
 
 
-def build(verbose=True, jobs=4):
+def build(verbose=True, jobs=None):
     """Compile every source and link libpadjoint.so (always rebuilds)."""
     os.makedirs(BUILD_DIR, exist_ok=True)
+    if jobs is None:
+        jobs = max(1, min(8, os.cpu_count() or 1))
     objs = []
     procs = []
     for src in sources():

@@ -41,18 +41,6 @@ pa_status fail(pa_status code, const std::string& msg) {
 
 bool is_pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
 
-int threads_per_fft(int N) {
-    switch (N) {
-        case 8: return Plan<8>::T;
-        case 16: return Plan<16>::T;
-        case 32: return Plan<32>::T;
-        case 64: return Plan<64>::T;
-        case 128: return Plan<128>::T;
-        case 256: return Plan<256>::T;
-        case 512: return Plan<512>::T;
-        default: return Plan<1024>::T;
-    }
-}
 bool finite_nonneg(double v) { return std::isfinite(v) && v >= 0.0; }
 
 }  // namespace
@@ -71,6 +59,12 @@ struct pa_ctx {
     int n_shell_max;
     double forcing;     // curl-force spectrum value at (0, +-n_f)
     int nf;             // n_f if inside the band, else 0
+    // launch timing of one kernel class with HIP events on the context stream
+    int prof_class = -1;
+    int prof_every = 1;
+    long prof_seen = 0;
+    size_t prof_used = 0;
+    std::vector<hipEvent_t> prof_ev;   // pairs (start, stop)
 };
 
 namespace {
@@ -81,7 +75,7 @@ struct WS {
     cd* Y0;
     cd* Yf[4];
     cd* Yp[4];
-    cd* YL;
+    cd* YL[2];          // Lambda and Lambda_y (adjoint cotangent fields)
     cd* omega;
     cd* acc;
     cd* lam;
@@ -132,7 +126,8 @@ WS carve(const pa_ctx* c, int n_steps, int ckpt_every, int n_obs, int m, void* b
     w.Y0 = cv.take<cd>(SY);
     for (int i = 0; i < 4; ++i) w.Yf[i] = cv.take<cd>(SY);
     for (int i = 0; i < 4; ++i) w.Yp[i] = cv.take<cd>(SY);
-    w.YL = cv.take<cd>(SY);
+    w.YL[0] = cv.take<cd>(SY);
+    w.YL[1] = cv.take<cd>(SY);
     w.omega = cv.take<cd>(SC);
     w.acc = cv.take<cd>(SC);
     w.lam = cv.take<cd>(SC);
@@ -223,6 +218,33 @@ pa_status check_ws(const pa_ctx* c, void* ws, size_t bytes, int n_steps, int K, 
     return PA_OK;
 }
 
+// ------------------------------------------------------------- timing --
+// Kernel classes that pa_profile_start can time.
+enum { PROF_ROW_NL = 0, PROF_COL_FWD = 1, PROF_ROW_ADJ = 2, PROF_COL_ADJ = 3 };
+
+template <class F>
+hipError_t timed(pa_ctx* c, int cls, F&& launch) {
+    if (c->prof_class != cls) return launch();
+    const bool take = (c->prof_seen++ % c->prof_every) == 0;
+    if (!take) return launch();
+    if (c->prof_used + 2 > c->prof_ev.size()) {
+        for (int i = 0; i < 64; ++i) {
+            hipEvent_t e;
+            hipError_t r = hipEventCreate(&e);
+            if (r != hipSuccess) return r;
+            c->prof_ev.push_back(e);
+        }
+    }
+    hipEvent_t e0 = c->prof_ev[c->prof_used], e1 = c->prof_ev[c->prof_used + 1];
+    hipError_t r = hipEventRecord(e0, c->stream);
+    if (r != hipSuccess) return r;
+    r = launch();
+    if (r != hipSuccess) return r;
+    r = hipEventRecord(e1, c->stream);
+    c->prof_used += 2;
+    return r;
+}
+
 // -------------------------------------------------------------- sweeps --
 
 RowObs row_obs_args(const ObsPlan& op, int slot, double* obs_out, double* jpart) {
@@ -298,7 +320,7 @@ pa_status run_steps(pa_ctx* c, WS& w, int n0, int n1, int n_total, int K, bool s
             ra.tw = c->tw;
             const int slot = (s == 0 && op) ? op->slot_of[(size_t)n] : -1;
             ra.obs = op ? row_obs_args(*op, slot, obs_out, w.jpart) : row_obs_args(ObsPlan(), -1, nullptr, nullptr);
-            PA_HIP(launch_row_nl(c->d, ra, c->stream));
+            PA_HIP(timed(c, PROF_ROW_NL, [&] { return launch_row_nl(c->d, ra, c->stream); }));
             ColArgs a = col_base(c);
             a.yin[0] = w.Yp[0];
             a.omega = w.omega;
@@ -309,7 +331,7 @@ pa_status run_steps(pa_ctx* c, WS& w, int n0, int n1, int n_total, int K, bool s
                 if (ckpt && (nn % K == 0 || nn == n_total)) a.ckpt = ckpt_slot(c, ckpt, nn == n_total ? nseg : nn / K);
                 if (nn == n1 && !final_fields) a.nout = 0;
             }
-            PA_HIP(launch_col(c->d, COL_A + s, a, c->stream));
+            PA_HIP(timed(c, PROF_COL_FWD, [&] { return launch_col(c->d, COL_A + s, a, c->stream); }));
         }
     }
     return PA_OK;
@@ -352,26 +374,55 @@ pa_status forward_sweep(pa_ctx* c, WS& w, const double* omega0, int n_steps, con
     return PA_OK;
 }
 
-// Adjoint stage: row products + column transposes for stage `mode`.
+// Adjoint stage: row products + column transposes for stage `mode`.  At an
+// observed step (stage n) the residual source rows are formed from the same
+// stage fields and enter the column pass as two extra inputs.
 pa_status adj_stage(pa_ctx* c, WS& w, cd* const fields[4], int mode, const ObsPlan* op, int obs_slot,
-                    int final_out, const double* scale, cd* yl_out) {
+                    int final_out, const double* scale) {
     RowArgs ra{};
     for (int i = 0; i < 4; ++i) ra.yin[i] = fields[i];
-    ra.yin[4] = w.YL;
-    for (int i = 0; i < 4; ++i) ra.yout[i] = w.Yp[i];
+    ra.yin[4] = w.YL[0];
+    ra.yin[5] = w.YL[1];
+    ra.yout[0] = w.Yp[0];
+    ra.yout[1] = w.Yp[1];
     ra.tw = c->tw;
-    ra.obs = op ? row_obs_args(*op, obs_slot, nullptr, nullptr) : row_obs_args(ObsPlan(), -1, nullptr, nullptr);
-    PA_HIP(launch_row_adj(c->d, ra, c->stream));
+    ra.obs = row_obs_args(ObsPlan(), -1, nullptr, nullptr);
+    PA_HIP(timed(c, PROF_ROW_ADJ, [&] { return launch_row_adj(c->d, ra, c->stream); }));
     ColArgs a = col_base(c);
-    for (int i = 0; i < 4; ++i) a.yin[i] = w.Yp[i];
+    a.yin[0] = w.Yp[0];
+    a.yin[1] = w.Yp[1];
+    a.nin = 2;
+    a.inmul[0] = IN_INVK2;
+    a.inmul[1] = IN_ONE;
+    if (op && obs_slot >= 0) {
+        RowArgs rs{};
+        rs.yin[0] = fields[0];
+        rs.yin[1] = fields[1];
+        rs.yout[0] = w.Yp[2];
+        rs.yout[1] = w.Yp[3];
+        rs.tw = c->tw;
+        rs.obs = row_obs_args(*op, obs_slot, nullptr, nullptr);
+        PA_HIP(launch_row_src(c->d, rs, 0, c->stream));
+        a.yin[2] = w.Yp[2];
+        a.yin[3] = w.Yp[3];
+        a.nin = 4;
+        a.inmul[2] = IN_IKY_INVK2;
+        a.inmul[3] = IN_MIKX_INVK2;
+    }
     a.lam = w.lam;
     a.omb = w.omb;
     a.final_out = final_out;
     a.scale = scale;
-    a.nout = 1;
+    a.yout[0] = w.YL[0];
     a.fields[0] = F_OMEGA;
-    a.yout[0] = yl_out;
-    PA_HIP(launch_col(c->d, mode, a, c->stream));
+    if (final_out) {
+        a.nout = 1;
+    } else {
+        a.nout = 2;
+        a.yout[1] = w.YL[1];
+        a.fields[1] = F_WY;
+    }
+    PA_HIP(timed(c, PROF_COL_ADJ, [&] { return launch_col(c->d, mode, a, c->stream); }));
     return PA_OK;
 }
 
@@ -396,7 +447,8 @@ pa_status terminal(pa_ctx* c, WS& w, const ObsPlan* op, int n_steps, cd* const f
     const int slot = op ? op->slot_of[(size_t)n_steps] : -1;
     if (!impulse && slot < 0) {
         PA_HIP(launch_fill(reinterpret_cast<double*>(w.lam), 0.0, 2 * SC, c->stream));
-        PA_HIP(launch_fill(reinterpret_cast<double*>(w.YL), 0.0, 2 * SY, c->stream));
+        PA_HIP(launch_fill(reinterpret_cast<double*>(w.YL[0]), 0.0, 2 * SY, c->stream));
+        PA_HIP(launch_fill(reinterpret_cast<double*>(w.YL[1]), 0.0, 2 * SY, c->stream));
         return PA_OK;
     }
     RowArgs ra{};
@@ -412,12 +464,21 @@ pa_status terminal(pa_ctx* c, WS& w, const ObsPlan* op, int n_steps, cd* const f
     ColArgs a = col_base(c);
     a.yin[0] = w.Yp[0];
     a.yin[1] = w.Yp[1];
+    a.nin = 2;
+    a.inmul[0] = IN_IKY_INVK2;
+    a.inmul[1] = IN_MIKX_INVK2;
     a.lam = w.lam;
     a.final_out = final_out ? 1 : 0;
     a.scale = scale;
-    a.nout = 1;
+    a.yout[0] = w.YL[0];
     a.fields[0] = F_OMEGA;
-    a.yout[0] = w.YL;
+    if (final_out) {
+        a.nout = 1;
+    } else {
+        a.nout = 2;
+        a.yout[1] = w.YL[1];
+        a.fields[1] = F_WY;
+    }
     PA_HIP(launch_col(c->d, COL_ADJ_SRC, a, c->stream));
     return PA_OK;
 }
@@ -443,7 +504,7 @@ pa_status backward_sweep(pa_ctx* c, WS& w, const cd* ckpt, int n_steps, int K, c
         }
         PA_TRY(terminal(c, w, op, 0, f0, impulse, ix, iy, true, scale));
         PA_TRY(record_shells(c, w, sh, 0));
-        if (grad_out) PA_HIP(launch_row_c2r(c->d, w.YL, grad_out, c->tw, c->stream));
+        if (grad_out) PA_HIP(launch_row_c2r(c->d, w.YL[0], grad_out, c->tw, c->stream));
         return PA_OK;
     }
     if (!w.seg) return fail(PA_EINVAL, "workspace carved without a segment buffer");
@@ -468,18 +529,18 @@ pa_status backward_sweep(pa_ctx* c, WS& w, const cd* ckpt, int n_steps, int K, c
             const int n = n0 + j;
             cd* fs[4];
             seg_fields(c, w, j, 3, fs);
-            PA_TRY(adj_stage(c, w, fs, COL_ADJ_C, nullptr, -1, 0, nullptr, w.YL));
+            PA_TRY(adj_stage(c, w, fs, COL_ADJ_C, nullptr, -1, 0, nullptr));
             seg_fields(c, w, j, 2, fs);
-            PA_TRY(adj_stage(c, w, fs, COL_ADJ_B, nullptr, -1, 0, nullptr, w.YL));
+            PA_TRY(adj_stage(c, w, fs, COL_ADJ_B, nullptr, -1, 0, nullptr));
             seg_fields(c, w, j, 1, fs);
-            PA_TRY(adj_stage(c, w, fs, COL_ADJ_A, nullptr, -1, 0, nullptr, w.YL));
+            PA_TRY(adj_stage(c, w, fs, COL_ADJ_A, nullptr, -1, 0, nullptr));
             seg_fields(c, w, j, 0, fs);
             const int slot = (op && !impulse) ? op->slot_of[(size_t)n] : -1;
-            PA_TRY(adj_stage(c, w, fs, COL_ADJ_N, op, slot, n == 0 ? 1 : 0, scale, w.YL));
+            PA_TRY(adj_stage(c, w, fs, COL_ADJ_N, op, slot, n == 0 ? 1 : 0, scale));
             PA_TRY(record_shells(c, w, sh, n_steps - n));
         }
     }
-    if (grad_out) PA_HIP(launch_row_c2r(c->d, w.YL, grad_out, c->tw, c->stream));
+    if (grad_out) PA_HIP(launch_row_c2r(c->d, w.YL[0], grad_out, c->tw, c->stream));
     return PA_OK;
 }
 
@@ -565,9 +626,10 @@ pa_status pa_create(const pa_physics* phys, int32_t N, int32_t B, void* hip_stre
     d.KX = d.K + 1;
     d.KXP = (d.KX + 7) / 8 * 8;
     d.KY = 2 * d.K + 1;
+    d.var = 0;
     d.cb = 8;
-    while (d.cb > 1 && (d.cb * threads_per_fft(N) > 256 ||
-                        (size_t)d.cb * (N + N / 16 + 1) * sizeof(cd) > 65536)) d.cb >>= 1;
+    while (d.cb > 1 && (d.cb * fft_threads(N, d.var) > 256 ||
+                        ((size_t)d.cb * (N + N / 16 + 1) + N) * sizeof(cd) > 65536)) d.cb >>= 1;
     d.tpb = 4;
 
     std::vector<cd> tw;
@@ -629,6 +691,7 @@ pa_status pa_create(const pa_physics* phys, int32_t N, int32_t B, void* hip_stre
 pa_status pa_destroy(pa_ctx* c) {
     if (!c) return PA_OK;
     (void)hipStreamSynchronize(c->stream);
+    for (hipEvent_t e : c->prof_ev) (void)hipEventDestroy(e);
     (void)hipFree(c->tw);
     (void)hipFree(c->invk2);
     (void)hipFree(c->ex2);
@@ -653,21 +716,53 @@ pa_status pa_get_shape(const pa_ctx* c, int32_t* N, int32_t* B, int32_t* Kc) {
     return PA_OK;
 }
 
-pa_status pa_set_tiles(pa_ctx* c, int32_t col_block, int32_t row_teams) {
+pa_status pa_set_tiles(pa_ctx* c, int32_t col_block, int32_t row_teams, int32_t fft_variant) {
     if (!c) return fail(PA_EINVAL, "ctx is NULL");
-    const int T = threads_per_fft(c->d.N);
-    if (col_block) {
-        if (col_block != 1 && col_block != 2 && col_block != 4 && col_block != 8)
-            return fail(PA_EINVAL, "col_block must be 1, 2, 4 or 8");
-        if (col_block * T > 256 || (size_t)col_block * (c->d.N + c->d.N / 16 + 1) * sizeof(cd) > 65536)
-            return fail(PA_EINVAL, "col_block too large for this N");
-        c->d.cb = col_block;
+    if (fft_variant < -1 || fft_variant > 1) return fail(PA_EINVAL, "fft_variant must be -1, 0 or 1");
+    const int var = fft_variant >= 0 ? fft_variant : c->d.var;
+    const int T = fft_threads(c->d.N, var);
+    int cb = col_block ? col_block : c->d.cb;
+    if (cb != 1 && cb != 2 && cb != 4 && cb != 8) return fail(PA_EINVAL, "col_block must be 1, 2, 4 or 8");
+    if (!col_block) {
+        while (cb > 1 && (cb * T > 256 || ((size_t)cb * (c->d.N + c->d.N / 16 + 1) + c->d.N) * sizeof(cd) > 65536))
+            cb >>= 1;
+    } else if (cb * T > 256 || ((size_t)cb * (c->d.N + c->d.N / 16 + 1) + c->d.N) * sizeof(cd) > 65536) {
+        return fail(PA_EINVAL, "col_block too large for this N and FFT variant");
     }
-    if (row_teams) {
-        if (row_teams != 1 && row_teams != 2 && row_teams != 4 && row_teams != 8)
-            return fail(PA_EINVAL, "row_teams must be 1, 2, 4 or 8");
-        c->d.tpb = row_teams;
+    if (row_teams && row_teams != 1 && row_teams != 2 && row_teams != 4 && row_teams != 8)
+        return fail(PA_EINVAL, "row_teams must be 1, 2, 4 or 8");
+    c->d.var = var;
+    c->d.cb = cb;
+    if (row_teams) c->d.tpb = row_teams;
+    return PA_OK;
+}
+
+pa_status pa_profile_start(pa_ctx* c, int32_t kernel_class, int32_t sample_every) {
+    if (!c) return fail(PA_EINVAL, "ctx is NULL");
+    if (kernel_class < 0 || kernel_class > 3) return fail(PA_EINVAL, "kernel_class must be 0..3");
+    if (sample_every < 1) return fail(PA_EINVAL, "sample_every must be >= 1");
+    c->prof_class = kernel_class;
+    c->prof_every = sample_every;
+    c->prof_seen = 0;
+    c->prof_used = 0;
+    return PA_OK;
+}
+
+pa_status pa_profile_stop(pa_ctx* c, int64_t* timed_launches, int64_t* seen_launches, double* total_ms) {
+    if (!c) return fail(PA_EINVAL, "ctx is NULL");
+    PA_HIP(hipStreamSynchronize(c->stream));
+    double tot = 0.0;
+    for (size_t i = 0; i < c->prof_used; i += 2) {
+        float ms = 0.f;
+        PA_HIP(hipEventElapsedTime(&ms, c->prof_ev[i], c->prof_ev[i + 1]));
+        tot += ms;
     }
+    if (timed_launches) *timed_launches = (int64_t)(c->prof_used / 2);
+    if (seen_launches) *seen_launches = c->prof_seen;
+    if (total_ms) *total_ms = tot;
+    c->prof_class = -1;
+    c->prof_used = 0;
+    c->prof_seen = 0;
     return PA_OK;
 }
 

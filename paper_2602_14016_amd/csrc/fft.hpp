@@ -21,6 +21,12 @@ namespace pa {
 
 struct cd { double x, y; };
 
+// Workgroup barrier for LDS hand-offs only: waits for this wave's LDS
+// operations, then meets the other waves.  Unlike __syncthreads() it does not
+// drain outstanding global loads, so loads issued before a transform stay in
+// flight across its exchanges.
+__device__ __forceinline__ void lds_sync() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
 __device__ __forceinline__ cd mk(double x, double y) { cd r; r.x = x; r.y = y; return r; }
 __device__ __forceinline__ cd cadd(cd a, cd b) { return mk(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ cd csub(cd a, cd b) { return mk(a.x - b.x, a.y - b.y); }
@@ -154,16 +160,23 @@ template <>
 __device__ __forceinline__ void dft<16, true>(cd* v) { dft16<true>(v); }
 
 // ---------------------------------------------------------------- plans --
-// Radix sequence per length; T threads per transform, E elements per thread.
-template <int N> struct Plan;
-template <> struct Plan<8>    { static constexpr int NS = 1, T = 1,  E = 8;  static constexpr int R[3] = {8, 1, 1}; };
-template <> struct Plan<16>   { static constexpr int NS = 2, T = 4,  E = 4;  static constexpr int R[3] = {4, 4, 1}; };
-template <> struct Plan<32>   { static constexpr int NS = 2, T = 4,  E = 8;  static constexpr int R[3] = {8, 4, 1}; };
-template <> struct Plan<64>   { static constexpr int NS = 2, T = 8,  E = 8;  static constexpr int R[3] = {8, 8, 1}; };
-template <> struct Plan<128>  { static constexpr int NS = 2, T = 8,  E = 16; static constexpr int R[3] = {16, 8, 1}; };
-template <> struct Plan<256>  { static constexpr int NS = 2, T = 16, E = 16; static constexpr int R[3] = {16, 16, 1}; };
-template <> struct Plan<512>  { static constexpr int NS = 3, T = 64, E = 8;  static constexpr int R[3] = {8, 8, 8}; };
-template <> struct Plan<1024> { static constexpr int NS = 3, T = 64, E = 16; static constexpr int R[3] = {16, 16, 4}; };
+// Radix sequence per length and variant; T threads per transform, E elements
+// per thread.  Variant 0 keeps more elements per thread (fewer LDS exchanges,
+// more registers); variant 1 spreads a transform over more threads (fewer
+// registers per thread, one more exchange).  The autotuner picks per context.
+template <int N, int V> struct Plan;
+template <int V> struct Plan<8, V>    { static constexpr int NS = 1, T = 1,  E = 8;  static constexpr int R[4] = {8, 1, 1, 1}; };
+template <int V> struct Plan<16, V>   { static constexpr int NS = 2, T = 4,  E = 4;  static constexpr int R[4] = {4, 4, 1, 1}; };
+template <int V> struct Plan<32, V>   { static constexpr int NS = 2, T = 4,  E = 8;  static constexpr int R[4] = {8, 4, 1, 1}; };
+template <> struct Plan<64, 0>   { static constexpr int NS = 2, T = 8,   E = 8;  static constexpr int R[4] = {8, 8, 1, 1}; };
+template <> struct Plan<64, 1>   { static constexpr int NS = 3, T = 16,  E = 4;  static constexpr int R[4] = {4, 4, 4, 1}; };
+template <> struct Plan<128, 0>  { static constexpr int NS = 2, T = 8,   E = 16; static constexpr int R[4] = {16, 8, 1, 1}; };
+template <> struct Plan<128, 1>  { static constexpr int NS = 3, T = 16,  E = 8;  static constexpr int R[4] = {8, 4, 4, 1}; };
+template <> struct Plan<256, 0>  { static constexpr int NS = 2, T = 16,  E = 16; static constexpr int R[4] = {16, 16, 1, 1}; };
+template <> struct Plan<256, 1>  { static constexpr int NS = 3, T = 32,  E = 8;  static constexpr int R[4] = {8, 8, 4, 1}; };
+template <int V> struct Plan<512, V>  { static constexpr int NS = 3, T = 64, E = 8; static constexpr int R[4] = {8, 8, 8, 1}; };
+template <> struct Plan<1024, 0> { static constexpr int NS = 3, T = 64,  E = 16; static constexpr int R[4] = {16, 16, 4, 1}; };
+template <> struct Plan<1024, 1> { static constexpr int NS = 4, T = 128, E = 8;  static constexpr int R[4] = {8, 8, 4, 4}; };
 
 // LDS footprint of one team's exchange area (one padding slot per 16 entries).
 template <int N>
@@ -171,9 +184,9 @@ __host__ __device__ constexpr int lds_team() { return N + N / 16 + 1; }
 __device__ __forceinline__ int lpad(int i) { return i + (i >> 4); }
 
 // One Stockham stage: radix R, span S (product of the radices already done).
-template <int N, int R, int S, bool INV, bool LAST>
+template <int N, int V, int R, int S, bool INV, bool LAST>
 __device__ __forceinline__ void fft_stage(cd* v, int t, cd* lds, const cd* __restrict__ tw) {
-    constexpr int T = Plan<N>::T, E = Plan<N>::E, NB = E / R;
+    constexpr int T = Plan<N, V>::T, E = Plan<N, V>::E, NB = E / R;
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
         const int j = t + T * b;
@@ -200,28 +213,34 @@ __device__ __forceinline__ void fft_stage(cd* v, int t, cd* lds, const cd* __res
         }
     }
     if constexpr (!LAST) {
-        __syncthreads();
+        lds_sync();
 #pragma unroll
         for (int m = 0; m < E; ++m) v[m] = lds[lpad(t + T * m)];
-        __syncthreads();
+        lds_sync();
     }
 }
 
 // Full transform of the team's register signal v (layout t + T*m).
 // Every thread of the workgroup must call this (it contains barriers when the
 // plan has more than one stage).
-template <int N, bool INV>
+template <int N, int V, bool INV>
 __device__ __forceinline__ void fft(cd* v, int t, cd* lds, const cd* __restrict__ tw) {
-    using P = Plan<N>;
+    using P = Plan<N, V>;
+    constexpr int R0 = P::R[0], R1 = P::R[1], R2 = P::R[2], R3 = P::R[3];
     if constexpr (P::NS == 1) {
-        fft_stage<N, P::R[0], 1, INV, true>(v, t, lds, tw);
+        fft_stage<N, V, R0, 1, INV, true>(v, t, lds, tw);
     } else if constexpr (P::NS == 2) {
-        fft_stage<N, P::R[0], 1, INV, false>(v, t, lds, tw);
-        fft_stage<N, P::R[1], P::R[0], INV, true>(v, t, lds, tw);
+        fft_stage<N, V, R0, 1, INV, false>(v, t, lds, tw);
+        fft_stage<N, V, R1, R0, INV, true>(v, t, lds, tw);
+    } else if constexpr (P::NS == 3) {
+        fft_stage<N, V, R0, 1, INV, false>(v, t, lds, tw);
+        fft_stage<N, V, R1, R0, INV, false>(v, t, lds, tw);
+        fft_stage<N, V, R2, R0 * R1, INV, true>(v, t, lds, tw);
     } else {
-        fft_stage<N, P::R[0], 1, INV, false>(v, t, lds, tw);
-        fft_stage<N, P::R[1], P::R[0], INV, false>(v, t, lds, tw);
-        fft_stage<N, P::R[2], P::R[0] * P::R[1], INV, true>(v, t, lds, tw);
+        fft_stage<N, V, R0, 1, INV, false>(v, t, lds, tw);
+        fft_stage<N, V, R1, R0, INV, false>(v, t, lds, tw);
+        fft_stage<N, V, R2, R0 * R1, INV, false>(v, t, lds, tw);
+        fft_stage<N, V, R3, R0 * R1 * R2, INV, true>(v, t, lds, tw);
     }
 }
 

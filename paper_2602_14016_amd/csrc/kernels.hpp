@@ -26,9 +26,13 @@ struct Dims {
     int N, B, K, KX, KXP, KY;
     int cb;    // kx columns per column-pass workgroup
     int tpb;   // row teams per row-pass workgroup
+    int var;   // FFT plan variant (0 or 1)
 };
 
 enum FieldKind : int { F_OMEGA = 0, F_U = 1, F_V = 2, F_WX = 3, F_WY = 4 };
+
+// Multiplier applied to an adjoint column input after its y-transform.
+enum InMul : int { IN_INVK2 = 0, IN_ONE = 1, IN_IKY_INVK2 = 2, IN_MIKX_INVK2 = 3 };
 
 enum ColMode : int {
     COL_INIT = 0,     // Y -> P omega0 -> state (+checkpoint) -> derived fields
@@ -41,6 +45,8 @@ enum ColMode : int {
 
 struct ColArgs {
     const cd* yin[4];        // inputs (Y layout)
+    int nin;                 // adjoint modes: number of inputs
+    int inmul[4];            // adjoint modes: InMul per input
     cd* yout[4];             // derived outputs (Y layout)
     int nout;
     int fields[4];           // FieldKind per output
@@ -73,13 +79,29 @@ struct RowObs {
 };
 
 struct RowArgs {
-    const cd* yin[5];
+    const cd* yin[6];
     cd* yout[4];
     const double* phys_in;
     double* phys_out;
     const cd* tw;
     RowObs obs;
 };
+
+// Per-grid-size launchers, instantiated in kern_<N>.hip.
+template <int N>
+struct Launch {
+    static hipError_t row_r2c(const Dims& d, const double* in, cd* out, const cd* tw, hipStream_t s);
+    static hipError_t row_c2r(const Dims& d, const cd* in, double* out, const cd* tw, hipStream_t s);
+    static hipError_t row_nl(const Dims& d, const RowArgs& a, hipStream_t s);
+    static hipError_t row_obs(const Dims& d, const RowArgs& a, hipStream_t s);
+    static hipError_t row_adj(const Dims& d, const RowArgs& a, hipStream_t s);
+    static hipError_t row_src(const Dims& d, const RowArgs& a, int impulse, hipStream_t s);
+    static hipError_t col(const Dims& d, int mode, const ColArgs& a, hipStream_t s);
+    static int threads(int var);
+};
+
+// Threads per transform for grid size N and plan variant var.
+int fft_threads(int N, int var);
 
 // launchers (kernels.hip)
 hipError_t launch_row_r2c(const Dims& d, const double* in, cd* out, const cd* tw, hipStream_t s);

@@ -1,0 +1,631 @@
+// kernels_impl.hpp -- row (physical-space) and column (spectral-space) passes.
+//
+// Row pass: a team of T threads owns one grid row (or a pair of rows) of one
+// member.  It rebuilds full complex rows from the stored half spectra
+// (Hermitian extension, two real fields packed as re + i im), inverse
+// transforms along x, forms the pointwise products of the method in
+// registers, and forward transforms the products back, keeping kx <= Kc.
+// Column pass: a team owns one kx column of one member; a workgroup holds CB
+// adjacent columns so that every global access is a run of CB contiguous
+// complex values.  It transforms along y, applies the spectral operators of
+// the step mode by mode, and transforms the derived fields back along y.
+//
+// Included once per grid size by kern_<N>.hip, which instantiates Launch<N>.
+#pragma once
+#include "kernels.hpp"
+
+namespace pa {
+
+// Global accesses as uniform base + 32-bit byte offset (element index << 4),
+// so the backend can address with a scalar base and one 32-bit lane offset.
+__device__ __forceinline__ cd ldc(const cd* base, unsigned i) {
+    return *reinterpret_cast<const cd*>(reinterpret_cast<const char*>(base) + (i << 4));
+}
+__device__ __forceinline__ void stc(cd* base, unsigned i, cd v) {
+    *reinterpret_cast<cd*>(reinterpret_cast<char*>(base) + (i << 4)) = v;
+}
+
+// The twiddle table is copied into LDS at kernel start: reads after a
+// barrier are not hoisted out of loops, so they do not pin registers across
+// the successive transforms of a kernel.
+template <int N>
+__device__ __forceinline__ const cd* stage_twiddles(cd* lds_tw, const cd* __restrict__ tw) {
+    for (int i = threadIdx.x; i < N; i += blockDim.x) lds_tw[i] = tw[i];
+    lds_sync();
+    return lds_tw;
+}
+
+// z = A_full[e] + i B_full[e] for the Hermitian extensions of half-spectrum
+// rows A, B (only kx = 0..K stored, zero beyond).  The kx = 0 entry of a real
+// field's half spectrum is real; its imaginary round-off is discarded.
+__device__ __forceinline__ cd herm_pair(const cd* __restrict__ A, const cd* __restrict__ B, int e, int N, int K) {
+    if (e == 0) return mk(A[0].x, B[0].x);
+    if (e <= K) {
+        const cd a = A[e], b = B[e];
+        return mk(a.x - b.y, a.y + b.x);
+    }
+    if (e >= N - K) {
+        const cd a = A[N - e], b = B[N - e];
+        return mk(a.x + b.y, b.x - a.y);
+    }
+    return czero();
+}
+
+// Same with A replaced by its x-derivative i kx A (kx = 0 gives zero).
+__device__ __forceinline__ cd herm_pair_dxA(const cd* __restrict__ A, const cd* __restrict__ B, int e, int N, int K) {
+    if (e == 0) return mk(0.0, B[0].x);
+    if (e <= K) {
+        const cd a = mul_i(cscale(A[e], (double)e)), b = B[e];
+        return mk(a.x - b.y, a.y + b.x);
+    }
+    if (e >= N - K) {
+        const int k = N - e;
+        const cd a = mul_i(cscale(A[k], (double)k)), b = B[k];
+        return mk(a.x + b.y, b.x - a.y);
+    }
+    return czero();
+}
+
+// Forward transform z of a + i b (a, b real) is split into the half spectra
+// of a and b:  Ahat[k] = (Z[k] + conj Z[N-k]) / 2,  Bhat[k] = (Z[k] - conj Z[N-k]) / (2i).
+// Stores kx = 0..K of both.  Called by every thread of the workgroup.
+template <int N, int V>
+__device__ __forceinline__ void split_store(const cd* z, int t, cd* lds, cd* __restrict__ outA,
+                                            cd* __restrict__ outB, int K) {
+    constexpr int T = Plan<N, V>::T, E = Plan<N, V>::E;
+#pragma unroll
+    for (int m = 0; m < E; ++m) lds[lpad(t + T * m)] = z[m];
+    lds_sync();
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+        const int k = t + T * m;
+        if (k <= K) {
+            const cd zk = z[m];
+            const cd zn = lds[lpad((N - k) & (N - 1))];
+            outA[k] = mk(0.5 * (zk.x + zn.x), 0.5 * (zk.y - zn.y));
+            outB[k] = mk(0.5 * (zk.y + zn.y), -0.5 * (zk.x - zn.x));
+        }
+    }
+    lds_sync();
+}
+
+// Team sum (fixed order) of one double per thread; result valid in thread t == 0.
+template <int N, int V>
+__device__ __forceinline__ double team_sum(double v, int t, cd* lds) {
+    constexpr int T = Plan<N, V>::T;
+    lds[t] = mk(v, 0.0);
+    lds_sync();
+    double s = 0.0;
+    if (t == 0)
+        for (int i = 0; i < T; ++i) s += lds[i].x;
+    lds_sync();
+    return s;
+}
+
+// Observation of one velocity component c (0 = u, 1 = v) at (x, y): writes the
+// model observation and returns the squared residual (0 off the probes).
+__device__ __forceinline__ double observe_comp(const RowObs& o, int b, int y, int x, int comp, double val) {
+    if ((y % o.stride) != 0 || (x % o.stride) != 0) return 0.0;
+    const int i = x / o.stride, j = y / o.stride, M = o.M;
+    const size_t idx = ((((size_t)b * o.n_times + o.slot) * 2) + comp) * M * M + (size_t)j * M + i;
+    if (o.obs_out) o.obs_out[idx] = val;
+    if (!o.values) return 0.0;
+    const double r = val - o.values[idx];
+    return r * r;
+}
+
+__device__ __forceinline__ void store_jpart(const RowObs& o, int b, int y, double s) {
+    if (o.jpart && o.values && (y % o.stride) == 0)
+        o.jpart[((size_t)b * o.n_times + o.slot) * o.M + y / o.stride] = 0.5 * s;
+}
+
+// A workgroup holds `tpb` teams; the launcher guarantees tpb divides the
+// teams per member, so the member index is uniform over the workgroup and
+// member base pointers live in scalar registers (32-bit lane offsets).
+#define PA_TEAM_SETUP(N, V, TEAMS_PER_MEMBER)                           \
+    constexpr int T = Plan<N, V>::T, E = Plan<N, V>::E;                 \
+    extern __shared__ cd smem[];                                        \
+    const int team = threadIdx.x / T, t = threadIdx.x % T;              \
+    cd* lds = smem + team * lds_team<N>();                              \
+    const int tpb_ = blockDim.x / T;                                    \
+    cd* const tw_lds = smem + tpb_ * lds_team<N>();                     \
+    const int g0 = blockIdx.x * tpb_;                                   \
+    const int b = g0 / (TEAMS_PER_MEMBER);                              \
+    const int w0 = g0 % (TEAMS_PER_MEMBER);                             \
+    const int wi = w0 + team;
+
+// ------------------------------------------------------------ row passes --
+
+// physical rows (y0, y0+1) -> Y rows; team per row pair.
+template <int N, int V>
+__global__ void __launch_bounds__(256) row_r2c_kernel(Dims d, const double* __restrict__ in,
+                                                      cd* __restrict__ out, const cd* __restrict__ tw_g) {
+    PA_TEAM_SETUP(N, V, N / 2)
+    const double* r0 = in + ((size_t)b * N + 2 * w0) * N;     // block base (uniform)
+    const int ro = 2 * team * N;                               // this team's row pair
+    cd z[E];
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+        const int x = t + T * m;
+        z[m] = mk(r0[ro + x], r0[ro + N + x]);
+    }
+    const cd* twl = stage_twiddles<N>(tw_lds, tw_g);
+    fft<N, V, false>(z, t, lds, twl);
+    cd* o0 = out + ((size_t)b * N + 2 * wi) * d.KXP;
+    split_store<N, V>(z, t, lds, o0, o0 + d.KXP, d.K);
+}
+
+// Y rows (y0, y0+1) -> physical rows.
+template <int N, int V>
+__global__ void __launch_bounds__(256) row_c2r_kernel(Dims d, const cd* __restrict__ in,
+                                                      double* __restrict__ out, const cd* __restrict__ tw_g) {
+    PA_TEAM_SETUP(N, V, N / 2)
+    const cd* i0 = in + ((size_t)b * N + 2 * wi) * d.KXP;
+    cd z[E];
+#pragma unroll
+    for (int m = 0; m < E; ++m) z[m] = herm_pair(i0, i0 + d.KXP, t + T * m, N, d.K);
+    const cd* twl = stage_twiddles<N>(tw_lds, tw_g);
+    fft<N, V, true>(z, t, lds, twl);
+    double* r0 = out + ((size_t)b * N + 2 * w0) * N;
+    const int ro = 2 * team * N;
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+        const int x = t + T * m;
+        r0[ro + x] = z[m].x;
+        r0[ro + N + x] = z[m].y;
+    }
+}
+
+// Right-hand side products of one row:  q = u w_x + v w_y  (+ observation).
+// Inputs yin[0..3] = U, V, Wx, Wy (Y layout), output yout[0] = row transform
+// of q.  Every input load is issued before the first transform, so the
+// memory latency is paid once per kernel rather than once per transform.
+template <int N, int V>
+__global__ void __launch_bounds__(256) row_nl_kernel(Dims d, RowArgs a) {
+    const cd* __restrict__ tw_g = a.tw;
+    PA_TEAM_SETUP(N, V, N)
+    const int y = wi;
+    const size_t roff = ((size_t)b * N + y) * d.KXP;
+    const bool obs = a.obs.slot >= 0;
+    cd z1[E], z2[E];
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+        z1[m] = herm_pair(a.yin[0] + roff, a.yin[2] + roff, t + T * m, N, d.K);   // u + i w_x
+        z2[m] = herm_pair(a.yin[1] + roff, a.yin[3] + roff, t + T * m, N, d.K);   // v + i w_y
+    }
+    const cd* twl = stage_twiddles<N>(tw_lds, tw_g);
+    double part = 0.0;
+    fft<N, V, true>(z1, t, lds, twl);
+    fft<N, V, true>(z2, t, lds, twl);
+    cd z[E];
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+        if (obs) {
+            part += observe_comp(a.obs, b, y, t + T * m, 0, z1[m].x);
+            part += observe_comp(a.obs, b, y, t + T * m, 1, z2[m].x);
+        }
+        z[m] = mk(z1[m].x * z1[m].y + z2[m].x * z2[m].y, 0.0);
+    }
+    if (obs) {
+        const double s = team_sum<N, V>(part, t, lds);
+        if (t == 0) store_jpart(a.obs, b, y, s);
+    }
+    fft<N, V, false>(z, t, lds, twl);
+    cd* o = a.yout[0] + roff;
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+        const int k = t + T * m;
+        if (k <= d.K) o[k] = z[m];
+    }
+}
+
+// Observation only (final time): team per observed row; yin[0..1] = U, V.
+template <int N, int V>
+__global__ void __launch_bounds__(256) row_obs_kernel(Dims d, RowArgs a) {
+    const cd* __restrict__ tw_g = a.tw;
+    PA_TEAM_SETUP(N, V, a.obs.M)
+    const int y = wi * a.obs.stride;
+    const size_t roff = ((size_t)b * N + y) * d.KXP;
+    cd z[E];
+#pragma unroll
+    for (int m = 0; m < E; ++m) z[m] = herm_pair(a.yin[0] + roff, a.yin[1] + roff, t + T * m, N, d.K);
+    const cd* twl = stage_twiddles<N>(tw_lds, tw_g);
+    fft<N, V, true>(z, t, lds, twl);
+    double part = 0.0;
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+        part += observe_comp(a.obs, b, y, t + T * m, 0, z[m].x);
+        part += observe_comp(a.obs, b, y, t + T * m, 1, z[m].y);
+    }
+    const double s = team_sum<N, V>(part, t, lds);
+    if (t == 0) store_jpart(a.obs, b, y, s);
+}
+
+// Adjoint products of one row.  The transpose of the tangent right-hand side
+// applied to lambda, with Lam = P lambda, is on the de-aliased band
+//   (1/|k|^2) F[w_x Lam_y - w_y Lam_x] + F[u Lam_x + v Lam_y]
+// (the product rule holds on the band because the 2/3 rule keeps every alias
+// outside it, and u_x + v_y = 0).  Inputs yin[0..3] = U, V, Wx, Wy of the stage
+// state, yin[4] = Lam, yin[5] = Lam_y (Y layout).  Outputs: yout[0] = row
+// transform of G1 = w_x Lam_y - w_y Lam_x, yout[1] = of G2 = u Lam_x + v Lam_y.
+template <int N, int V>
+__global__ void __launch_bounds__(256) row_adj_kernel(Dims d, RowArgs a) {
+    const cd* __restrict__ tw_g = a.tw;
+    PA_TEAM_SETUP(N, V, N)
+    const int y = wi;
+    const size_t roff = ((size_t)b * N + y) * d.KXP;
+    cd L[E], z1[E], z2[E];   // (Lam_x, Lam_y), (u, w_x), (v, w_y)
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+        L[m] = herm_pair_dxA(a.yin[4] + roff, a.yin[5] + roff, t + T * m, N, d.K);
+        z1[m] = herm_pair(a.yin[0] + roff, a.yin[2] + roff, t + T * m, N, d.K);
+        z2[m] = herm_pair(a.yin[1] + roff, a.yin[3] + roff, t + T * m, N, d.K);
+    }
+    const cd* twl = stage_twiddles<N>(tw_lds, tw_g);
+    fft<N, V, true>(L, t, lds, twl);
+    fft<N, V, true>(z1, t, lds, twl);
+    fft<N, V, true>(z2, t, lds, twl);
+    cd G[E];   // (G1, G2)
+#pragma unroll
+    for (int m = 0; m < E; ++m)
+        G[m] = mk(z1[m].y * L[m].y - z2[m].y * L[m].x, z1[m].x * L[m].x + z2[m].x * L[m].y);
+    fft<N, V, false>(G, t, lds, twl);
+    split_store<N, V>(G, t, lds, a.yout[0] + roff, a.yout[1] + roff, d.K);
+}
+
+// Adjoint source rows.  mode 0: observation residual at one observed step
+// (yin[0..1] = U, V of that state); mode 1: unit u-impulse at (imp_x, imp_y).
+// Outputs yout[0] = row transform of -S^T r_u, yout[1] = of -S^T r_v.
+template <int N, int V>
+__global__ void __launch_bounds__(256) row_src_kernel(Dims d, RowArgs a, int impulse) {
+    const cd* __restrict__ tw_g = a.tw;
+    PA_TEAM_SETUP(N, V, N)
+    const int y = wi;
+    const size_t roff = ((size_t)b * N + y) * d.KXP;
+    const RowObs& o = a.obs;
+    cd z[E];
+    if (!impulse) {
+#pragma unroll
+        for (int m = 0; m < E; ++m) z[m] = herm_pair(a.yin[0] + roff, a.yin[1] + roff, t + T * m, N, d.K);
+    }
+    const cd* twl = stage_twiddles<N>(tw_lds, tw_g);
+    if (!impulse) fft<N, V, true>(z, t, lds, twl);
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+        const int x = t + T * m;
+        double A = 0.0, Bv = 0.0;
+        if (impulse) {
+            if (x == o.imp_x && y == o.imp_y) A = -1.0;
+        } else if (o.values && (y % o.stride) == 0 && (x % o.stride) == 0) {
+            const int i = x / o.stride, j = y / o.stride, M = o.M;
+            const size_t base = (((size_t)b * o.n_times + o.slot) * 2) * M * M + (size_t)j * M + i;
+            A = -(z[m].x - o.values[base]);
+            Bv = -(z[m].y - o.values[base + (size_t)M * M]);
+        }
+        z[m] = mk(A, Bv);
+    }
+    fft<N, V, false>(z, t, lds, twl);
+    split_store<N, V>(z, t, lds, a.yout[0] + roff, a.yout[1] + roff, d.K);
+}
+
+// ---------------------------------------------------------- column pass --
+
+__device__ __forceinline__ int band_row(int q, int N, int K, int KY) {
+    if (q <= K) return q;
+    if (q >= N - K) return q - N + KY;
+    return -1;
+}
+
+template <int N, int V, int MODE>
+__global__ void __launch_bounds__(256) col_kernel(Dims d, ColArgs a) {
+    constexpr int T = Plan<N, V>::T, E = Plan<N, V>::E;
+    constexpr bool FWD_STAGE = MODE >= COL_A && MODE <= COL_D;
+    constexpr bool ADJ = MODE >= COL_ADJ_C;
+    extern __shared__ cd smem[];
+    const int CB = d.cb;
+    const int c = threadIdx.x % CB, t = threadIdx.x / CB;
+    cd* lds = smem + c * lds_team<N>();
+    const int b = blockIdx.y;
+    const int kx0 = blockIdx.x * CB;           // uniform first column of the block
+    const int kx = kx0 + c;
+    const int K = d.K, KXP = d.KXP, KY = d.KY;
+    const bool colok = kx <= K;
+    // uniform bases (scalar registers) + 32-bit lane offsets
+    const size_t ymem = (size_t)b * N * KXP + kx0;
+    const size_t cmem = (size_t)b * KY * KXP + kx0;
+    const unsigned ylane = (unsigned)c;         // + y * KXP
+    const double* __restrict__ ik2t = a.invk2 + kx0;
+    const double dkx = (double)kx;
+    const double ex = a.ex2[kx];
+    const double h = a.h;
+    auto yoff = [&](int m) { return ylane + (unsigned)(t + T * m) * (unsigned)KXP; };
+    auto rowof = [&](int m) { return colok ? band_row(t + T * m, N, K, KY) : -1; };
+    auto inS = [&](int r) { return r >= 0 && !(kx == 0 && r == 0); };
+    auto cidx = [&](int r) { return (unsigned)c + (unsigned)r * (unsigned)KXP; };
+
+    // ---- issue every global load first: input column(s) and compact operands
+    cd v0[E];          // first input column
+    cd v1[E];          // second input column (adjoint)
+    cd s0[E], s1[E];   // compact operands: (omega_n, acc) forward, (lambda, omega-bar) adjoint
+    if constexpr (MODE != COL_FROM_STATE) {
+        const cd* __restrict__ src = a.yin[0] + ymem;
+#pragma unroll
+        for (int m = 0; m < E; ++m) v0[m] = colok ? ldc(src, yoff(m)) : czero();
+    }
+    if constexpr (ADJ) {
+        const cd* __restrict__ src = a.yin[1] + ymem;
+#pragma unroll
+        for (int m = 0; m < E; ++m) v1[m] = colok ? ldc(src, yoff(m)) : czero();
+    }
+    if constexpr (FWD_STAGE || ADJ || MODE == COL_FROM_STATE) {
+        const cd* __restrict__ p0 = FWD_STAGE ? a.omega + cmem : ADJ ? a.lam + cmem : a.state_in + cmem;
+        const cd* __restrict__ p1 = FWD_STAGE ? a.acc + cmem : (ADJ && MODE != COL_ADJ_SRC) ? a.omb + cmem : nullptr;
+        const bool need1 = (FWD_STAGE && MODE != COL_A) || (ADJ && MODE != COL_ADJ_C && MODE != COL_ADJ_SRC);
+        const bool need0 = !(ADJ && (MODE == COL_ADJ_N || MODE == COL_ADJ_SRC));
+#pragma unroll
+        for (int m = 0; m < E; ++m) {
+            const int r = rowof(m);
+            s0[m] = (need0 && r >= 0) ? ldc(p0, cidx(r)) : czero();
+            s1[m] = (need1 && r >= 0) ? ldc(p1, cidx(r)) : czero();
+        }
+    }
+    const cd* twl = stage_twiddles<N>(smem + CB * lds_team<N>(), a.tw);
+
+    cd w[E];   // spectral values handed to the output transforms
+
+    if constexpr (MODE <= COL_FILTER) {
+        fft<N, V, false>(v0, t, lds, twl);
+        cd* __restrict__ om = a.omega ? a.omega + cmem : nullptr;
+        cd* __restrict__ ac = a.acc ? a.acc + cmem : nullptr;
+        cd* __restrict__ ck = a.ckpt ? a.ckpt + cmem : nullptr;
+#pragma unroll
+        for (int m = 0; m < E; ++m) {
+            const int r = rowof(m);
+            if (r < 0) { w[m] = czero(); continue; }
+            const unsigned ci = cidx(r);
+            const bool ins = inS(r);
+            if constexpr (MODE == COL_INIT) {
+                const cd s = ins ? v0[m] : czero();
+                stc(om, ci, s);
+                if (ck) stc(ck, ci, s);
+                w[m] = s;
+            } else if constexpr (MODE == COL_FILTER) {
+                const size_t mi = (a.mult_per_member ? (size_t)b * KY * KXP : 0) + (size_t)r * KXP + kx;
+                w[m] = ins ? cscale(v0[m], a.mult[mi]) : czero();
+            } else {
+                const int ky = (r <= K) ? r : r - KY;
+                cd nl = ins ? mk(-v0[m].x, -v0[m].y) : czero();
+                if (a.nf > 0 && kx == 0 && (ky == a.nf || ky == -a.nf)) nl.x += a.forcing;
+                const double e2 = ex * a.ey2[r];
+                const double e1 = e2 * e2;
+                const cd wn = s0[m];
+                if constexpr (MODE == COL_A) {
+                    stc(ac, ci, cscale(nl, e1));
+                    w[m] = cscale(mk(wn.x + 0.5 * h * nl.x, wn.y + 0.5 * h * nl.y), e2);
+                } else if constexpr (MODE == COL_B) {
+                    const cd q = s1[m];
+                    stc(ac, ci, mk(q.x + 2.0 * e2 * nl.x, q.y + 2.0 * e2 * nl.y));
+                    w[m] = mk(e2 * wn.x + 0.5 * h * nl.x, e2 * wn.y + 0.5 * h * nl.y);
+                } else if constexpr (MODE == COL_C) {
+                    const cd q = s1[m];
+                    stc(ac, ci, mk(q.x + 2.0 * e2 * nl.x, q.y + 2.0 * e2 * nl.y));
+                    w[m] = mk(e1 * wn.x + h * e2 * nl.x, e1 * wn.y + h * e2 * nl.y);
+                } else {   // COL_D
+                    const cd q = s1[m];
+                    const double h6 = h / 6.0;
+                    const cd s = mk(e1 * wn.x + h6 * (q.x + nl.x), e1 * wn.y + h6 * (q.y + nl.y));
+                    stc(om, ci, s);
+                    if (ck) stc(ck, ci, s);
+                    w[m] = s;
+                }
+            }
+        }
+    } else if constexpr (MODE == COL_FROM_STATE) {
+        cd* __restrict__ om = a.omega ? a.omega + cmem : nullptr;
+#pragma unroll
+        for (int m = 0; m < E; ++m) {
+            const int r = rowof(m);
+            if (r < 0) { w[m] = czero(); continue; }
+            const cd s = inS(r) ? s0[m] : czero();
+            if (om) stc(om, cidx(r), s);
+            w[m] = s;
+        }
+    } else {
+        // adjoint: wbar = 1_S sum_p mult_p F_y(yin[p]), mult_p selected by inmul[p]
+        auto accumulate = [&](cd* v, int mk_) {
+#pragma unroll
+            for (int m = 0; m < E; ++m) {
+                const int r = rowof(m);
+                if (!inS(r)) continue;
+                const double ky = (double)((r <= K) ? r : r - KY);
+                const double ik2 = ik2t[cidx(r)];
+                if (mk_ == IN_INVK2) {
+                    w[m].x += ik2 * v[m].x;
+                    w[m].y += ik2 * v[m].y;
+                } else if (mk_ == IN_ONE) {
+                    w[m].x += v[m].x;
+                    w[m].y += v[m].y;
+                } else {
+                    const double f = (mk_ == IN_IKY_INVK2) ? ky * ik2 : -dkx * ik2;   // i f v
+                    w[m].x -= f * v[m].y;
+                    w[m].y += f * v[m].x;
+                }
+            }
+        };
+#pragma unroll
+        for (int m = 0; m < E; ++m) w[m] = czero();
+        fft<N, V, false>(v0, t, lds, twl);
+        accumulate(v0, a.inmul[0]);
+        fft<N, V, false>(v1, t, lds, twl);
+        accumulate(v1, a.inmul[1]);
+        for (int p = 2; p < a.nin; ++p) {
+            const cd* __restrict__ src = a.yin[p] + ymem;
+#pragma unroll
+            for (int m = 0; m < E; ++m) v0[m] = colok ? ldc(src, yoff(m)) : czero();
+            fft<N, V, false>(v0, t, lds, twl);
+            accumulate(v0, a.inmul[p]);
+        }
+        const double sc = a.scale ? a.scale[b] : 1.0;
+        cd* __restrict__ lm_p = a.lam + cmem;
+        cd* __restrict__ ob_p = a.omb ? a.omb + cmem : nullptr;
+#pragma unroll
+        for (int m = 0; m < E; ++m) {
+            const int r = rowof(m);
+            if (r < 0) { w[m] = czero(); continue; }
+            const unsigned ci = cidx(r);
+            const cd wb = w[m];   // zero off the band by construction
+            const double e2 = ex * a.ey2[r];
+            const double e1 = e2 * e2;
+            if constexpr (MODE == COL_ADJ_C) {
+                const cd lm = s0[m];
+                stc(ob_p, ci, mk(e1 * (lm.x + wb.x), e1 * (lm.y + wb.y)));
+                w[m] = mk((h / 3.0) * e2 * lm.x + h * e2 * wb.x, (h / 3.0) * e2 * lm.y + h * e2 * wb.y);
+            } else if constexpr (MODE == COL_ADJ_B) {
+                const cd lm = s0[m], ob = s1[m];
+                stc(ob_p, ci, mk(ob.x + e2 * wb.x, ob.y + e2 * wb.y));
+                w[m] = mk((h / 3.0) * e2 * lm.x + 0.5 * h * wb.x, (h / 3.0) * e2 * lm.y + 0.5 * h * wb.y);
+            } else if constexpr (MODE == COL_ADJ_A) {
+                const cd lm = s0[m], ob = s1[m];
+                stc(ob_p, ci, mk(ob.x + e2 * wb.x, ob.y + e2 * wb.y));
+                w[m] = mk((h / 6.0) * e1 * lm.x + 0.5 * h * e2 * wb.x, (h / 6.0) * e1 * lm.y + 0.5 * h * e2 * wb.y);
+            } else {   // COL_ADJ_N, COL_ADJ_SRC
+                cd ln = wb;
+                if constexpr (MODE == COL_ADJ_N) {
+                    const cd ob = s1[m];
+                    ln = mk(ob.x + wb.x, ob.y + wb.y);
+                }
+                stc(lm_p, ci, ln);
+                w[m] = a.final_out ? cscale(ln, sc) : cscale(ln, h / 6.0);
+            }
+        }
+    }
+
+    // derived fields: 1_S * multiplier * w / N^2, inverse transform along y
+    const double inv_n2 = 1.0 / ((double)N * (double)N);
+    for (int o = 0; o < a.nout; ++o) {
+        const int f = a.fields[o];
+        cd v[E];
+#pragma unroll
+        for (int m = 0; m < E; ++m) {
+            const int r = rowof(m);
+            if (!inS(r)) { v[m] = czero(); continue; }
+            const double ky = (double)((r <= K) ? r : r - KY);
+            const cd s = cscale(w[m], inv_n2);
+            if (f == F_OMEGA) v[m] = s;
+            else if (f == F_U) v[m] = cscale(mul_i(s), ky * ik2t[(unsigned)c + (unsigned)r * (unsigned)KXP]);
+            else if (f == F_V) v[m] = cscale(mul_i(s), -dkx * ik2t[(unsigned)c + (unsigned)r * (unsigned)KXP]);
+            else if (f == F_WX) v[m] = cscale(mul_i(s), dkx);
+            else v[m] = cscale(mul_i(s), ky);
+        }
+        fft<N, V, true>(v, t, lds, twl);
+        if (colok) {
+            cd* __restrict__ out = a.yout[o] + ymem;
+#pragma unroll
+            for (int m = 0; m < E; ++m) stc(out, yoff(m), v[m]);
+        }
+    }
+}
+
+// ------------------------------------------------------------- launchers --
+
+// Teams per workgroup: must divide the teams per member (the kernels take the
+// member index from the workgroup's first team), fit 256 threads and 64 KiB
+// of LDS.
+template <int N, int V>
+int row_tpb(const Dims& d, long teams_per_member) {
+    int tpb = d.tpb;
+    const int cap = 256 / Plan<N, V>::T;
+    if (tpb > cap) tpb = cap;
+    if (tpb < 1) tpb = 1;
+    while (tpb > 1 && ((size_t)tpb * lds_team<N>() + N) * sizeof(cd) > 65536) tpb >>= 1;
+    while (tpb > 1 && teams_per_member % tpb) tpb >>= 1;
+    return tpb;
+}
+
+template <int N, int V>
+size_t row_lds(int tpb) { return ((size_t)tpb * lds_team<N>() + N) * sizeof(cd); }
+
+#define PA_ROW_LAUNCH(KERNEL, TEAMS_PER_MEMBER, ...)                                           \
+    do {                                                                                       \
+        const long tpm_ = (TEAMS_PER_MEMBER);                                                  \
+        const long teams_ = tpm_ * d.B;                                                        \
+        if (d.var == 0) {                                                                      \
+            const int tpb = row_tpb<N, 0>(d, tpm_);                                            \
+            const dim3 grid_((unsigned)(teams_ / tpb));                                        \
+            const dim3 block_((unsigned)(tpb * Plan<N, 0>::T));                                \
+            const size_t lds_ = row_lds<N, 0>(tpb);                                            \
+            hipLaunchKernelGGL((KERNEL<N, 0>), grid_, block_, lds_, s, __VA_ARGS__);           \
+        } else {                                                                               \
+            const int tpb = row_tpb<N, 1>(d, tpm_);                                            \
+            const dim3 grid_((unsigned)(teams_ / tpb));                                        \
+            const dim3 block_((unsigned)(tpb * Plan<N, 1>::T));                                \
+            const size_t lds_ = row_lds<N, 1>(tpb);                                            \
+            hipLaunchKernelGGL((KERNEL<N, 1>), grid_, block_, lds_, s, __VA_ARGS__);           \
+        }                                                                                      \
+        return hipGetLastError();                                                              \
+    } while (0)
+
+template <int N>
+hipError_t Launch<N>::row_r2c(const Dims& d, const double* in, cd* out, const cd* tw, hipStream_t s) {
+    PA_ROW_LAUNCH(row_r2c_kernel, N / 2, d, in, out, tw);
+}
+template <int N>
+hipError_t Launch<N>::row_c2r(const Dims& d, const cd* in, double* out, const cd* tw, hipStream_t s) {
+    PA_ROW_LAUNCH(row_c2r_kernel, N / 2, d, in, out, tw);
+}
+template <int N>
+hipError_t Launch<N>::row_nl(const Dims& d, const RowArgs& a, hipStream_t s) {
+    PA_ROW_LAUNCH(row_nl_kernel, N, d, a);
+}
+template <int N>
+hipError_t Launch<N>::row_obs(const Dims& d, const RowArgs& a, hipStream_t s) {
+    PA_ROW_LAUNCH(row_obs_kernel, a.obs.M, d, a);
+}
+template <int N>
+hipError_t Launch<N>::row_adj(const Dims& d, const RowArgs& a, hipStream_t s) {
+    PA_ROW_LAUNCH(row_adj_kernel, N, d, a);
+}
+template <int N>
+hipError_t Launch<N>::row_src(const Dims& d, const RowArgs& a, int impulse, hipStream_t s) {
+    PA_ROW_LAUNCH(row_src_kernel, N, d, a, impulse);
+}
+
+template <int N, int V, int MODE>
+hipError_t col_mode(const Dims& d, const ColArgs& a, hipStream_t s) {
+    const dim3 grid((unsigned)(d.KXP / d.cb), (unsigned)d.B);
+    const dim3 block((unsigned)(d.cb * Plan<N, V>::T));
+    const size_t lds = ((size_t)d.cb * lds_team<N>() + N) * sizeof(cd);
+    hipLaunchKernelGGL((col_kernel<N, V, MODE>), grid, block, lds, s, d, a);
+    return hipGetLastError();
+}
+
+template <int N, int V>
+hipError_t col_variant(const Dims& d, int mode, const ColArgs& a, hipStream_t s) {
+    switch (mode) {
+        case COL_INIT: return col_mode<N, V, COL_INIT>(d, a, s);
+        case COL_A: return col_mode<N, V, COL_A>(d, a, s);
+        case COL_B: return col_mode<N, V, COL_B>(d, a, s);
+        case COL_C: return col_mode<N, V, COL_C>(d, a, s);
+        case COL_D: return col_mode<N, V, COL_D>(d, a, s);
+        case COL_FILTER: return col_mode<N, V, COL_FILTER>(d, a, s);
+        case COL_FROM_STATE: return col_mode<N, V, COL_FROM_STATE>(d, a, s);
+        case COL_ADJ_C: return col_mode<N, V, COL_ADJ_C>(d, a, s);
+        case COL_ADJ_B: return col_mode<N, V, COL_ADJ_B>(d, a, s);
+        case COL_ADJ_A: return col_mode<N, V, COL_ADJ_A>(d, a, s);
+        case COL_ADJ_N: return col_mode<N, V, COL_ADJ_N>(d, a, s);
+        case COL_ADJ_SRC: return col_mode<N, V, COL_ADJ_SRC>(d, a, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <int N>
+hipError_t Launch<N>::col(const Dims& d, int mode, const ColArgs& a, hipStream_t s) {
+    return d.var == 0 ? col_variant<N, 0>(d, mode, a, s) : col_variant<N, 1>(d, mode, a, s);
+}
+
+template <int N>
+int Launch<N>::threads(int var) {
+    return var == 0 ? Plan<N, 0>::T : Plan<N, 1>::T;
+}
+
+}  // namespace pa

@@ -179,17 +179,19 @@ hipError_t launch_state_scale(const Dims& d, cd* state, int kind, double target,
 
 // Shell energies 1/2 |k|^2 |lam|^2 / N^4 per unit-width shell k = 1..n_shells.
 // shell_modes lists compact indices r*KXP + kx grouped by shell (CSR with
-// shell_start); one thread per (member, shell), fixed order.
-__global__ void shells_kernel(Dims d, const cd* __restrict__ lam, const int* __restrict__ start,
-                              const int* __restrict__ modes, int n_shells, double* __restrict__ out,
-                              size_t out_stride) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+// shell_start).  One workgroup per (shell, member): threads stride over the
+// shell's modes, then a fixed-order tree sums the partials.
+constexpr int SHELL_THREADS = 64;
+__global__ void __launch_bounds__(SHELL_THREADS) shells_kernel(Dims d, const cd* __restrict__ lam,
+                                                               const int* __restrict__ start,
+                                                               const int* __restrict__ modes, int n_shells,
+                                                               double* __restrict__ out, size_t out_stride) {
+    __shared__ double sh[SHELL_THREADS];
+    const int k = blockIdx.x;
     const int b = blockIdx.y;
-    if (k >= n_shells) return;
     const cd* l = lam + (size_t)b * d.KY * d.KXP;
-    const double n4 = (double)d.N * d.N * (double)d.N * d.N;
     double s = 0.0;
-    for (int i = start[k]; i < start[k + 1]; ++i) {
+    for (int i = start[k] + threadIdx.x; i < start[k + 1]; i += SHELL_THREADS) {
         const int idx = modes[i];
         const int r = idx / d.KXP, kx = idx % d.KXP;
         const int ky = (r <= d.K) ? r : r - d.KY;
@@ -197,11 +199,21 @@ __global__ void shells_kernel(Dims d, const cd* __restrict__ lam, const int* __r
         const double wgt = kx > 0 ? 2.0 : 1.0;
         s += wgt * 0.5 * k2 * (l[idx].x * l[idx].x + l[idx].y * l[idx].y);
     }
-    out[(size_t)b * out_stride + k] = s / n4;
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = SHELL_THREADS / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double n4 = (double)d.N * d.N * (double)d.N * d.N;
+        out[(size_t)b * out_stride + k] = sh[0] / n4;
+    }
 }
 hipError_t launch_shells(const Dims& d, const cd* lam, const int* shell_start, const int* shell_modes,
                          int n_shells, double* out, size_t out_stride, hipStream_t s) {
-    hipLaunchKernelGGL(shells_kernel, dim3((n_shells + 127) / 128, d.B), dim3(128), 0, s, d, lam, shell_start,
+    if (!lam || !shell_start || !shell_modes || !out || n_shells < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(shells_kernel, dim3(n_shells, d.B), dim3(SHELL_THREADS), 0, s, d, lam, shell_start,
                        shell_modes, n_shells, out, out_stride);
     return hipGetLastError();
 }

@@ -115,8 +115,8 @@ class Solver:
     def empty(self):
         return torch.empty((self.B, self.N, self.N), dtype=torch.float64, device=self.device)
 
-    def set_tiles(self, col_block=0, row_teams=0):
-        nv.check(self.lib.pa_set_tiles(self.ctx, int(col_block), int(row_teams)))
+    def set_tiles(self, col_block=0, row_teams=0, fft_variant=-1):
+        nv.check(self.lib.pa_set_tiles(self.ctx, int(col_block), int(row_teams), int(fft_variant)))
 
     # ---------------------------------------------------------------- calls
     def init_field(self, seeds, kind=0, k0=4.0, target=0.5, out=None):
@@ -214,3 +214,18 @@ class Solver:
         nv.check(self.lib.pa_adjoint_impulse(self.ctx, _ptr(omega0), int(n_steps), int(ix), int(iy), int(n_shells),
                                              _ptr(sh), _ptr(f), int(ckpt_every), ws, wb))
         return sh, f
+
+    # ----------------------------------------------------------- measurement
+    def profile_start(self, kernel_class, sample_every=1):
+        """Time every sample_every-th launch of a kernel class with HIP events
+        on this solver's stream (0 row rhs, 1 column forward, 2 row adjoint,
+        3 column adjoint)."""
+        self._sync_stream()
+        nv.check(self.lib.pa_profile_start(self.ctx, int(kernel_class), int(sample_every)))
+
+    def profile_stop(self):
+        t = ctypes.c_int64()
+        seen = ctypes.c_int64()
+        ms = c_double()
+        nv.check(self.lib.pa_profile_stop(self.ctx, byref(t), byref(seen), byref(ms)))
+        return {"timed_launches": t.value, "launches": seen.value, "total_ms": ms.value}
