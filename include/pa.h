@@ -206,6 +206,23 @@ pa_status pa_adjoint_impulse(pa_ctx* ctx, const double* omega0, int32_t n_steps,
                              double* field_out, int32_t ckpt_every, void* workspace,
                              size_t workspace_bytes);
 
+/* First guess from the probe velocities at t = 0 (the paper's "initial
+ * interpolated state", Sec. III.A): spectral interpolation of the M x M probe
+ * grid (M = N / stride) -- the coarse Nyquist row and column are dropped --
+ * then omega_hat = i kx v_hat - i ky u_hat on the de-aliased band.
+ * probes: device [B][2][M][M] (u then v); omega_out: device [B][N][N];
+ * workspace: at least pa_workspace_bytes(ctx, 0, 1, 0, 0). */
+pa_status pa_first_guess(pa_ctx* ctx, int32_t stride, const double* probes, double* omega_out,
+                         void* workspace, size_t workspace_bytes);
+
+/* Ensemble statistics of pa_adjoint_impulse output (Sec. IV): shells is
+ * device [B][rows][n_shells]; mean_out (device [rows][n_shells], may be NULL)
+ * receives the member mean, rate_out (device [n_shells]) the least-squares
+ * slope of ln(mean) against backward time tau = row * dt over
+ * [tau_min, tau_max] (NaN where undefined). */
+pa_status pa_shell_growth(pa_ctx* ctx, const double* shells, int32_t rows, int32_t n_shells,
+                          double tau_min, double tau_max, double* mean_out, double* rate_out);
+
 /* FFT tile choice for this context (the autotuner's knobs): col_block = kx
  * columns per column-pass workgroup (1, 2, 4 or 8; 0 keeps the current value,
  * reduced if the variant needs it), row_teams = rows per row-pass workgroup

@@ -76,6 +76,8 @@ struct WS {
     cd* Yf[4];
     cd* Yp[4];
     cd* YL[2];          // Lambda and Lambda_y (adjoint cotangent fields)
+    double* P0;         // physical scratch [B][N][N]
+    double* P1;         // physical scratch [B][N][N]
     cd* omega;
     cd* acc;
     cd* lam;
@@ -128,6 +130,8 @@ WS carve(const pa_ctx* c, int n_steps, int ckpt_every, int n_obs, int m, void* b
     for (int i = 0; i < 4; ++i) w.Yp[i] = cv.take<cd>(SY);
     w.YL[0] = cv.take<cd>(SY);
     w.YL[1] = cv.take<cd>(SY);
+    w.P0 = cv.take<double>(SP);
+    w.P1 = cv.take<double>(SP);
     w.omega = cv.take<cd>(SC);
     w.acc = cv.take<cd>(SC);
     w.lam = cv.take<cd>(SC);
@@ -874,6 +878,43 @@ pa_status pa_adjoint_impulse(pa_ctx* c, const double* omega0, int32_t n_steps, i
     sh.n = n_shells;
     sh.stride = (size_t)(n_steps + 1) * n_shells;
     return backward_sweep(c, w, w.ckpt, n_steps, K, nullptr, 1, ix, iy, nullptr, field_out, sh);
+}
+
+pa_status pa_first_guess(pa_ctx* c, int32_t stride, const double* probes, double* omega_out, void* workspace,
+                         size_t wbytes) {
+    g_err.clear();
+    if (!c || !probes || !omega_out) return fail(PA_EINVAL, "NULL argument");
+    if (stride < 1 || stride > c->d.N || c->d.N % stride) return fail(PA_EINVAL, "stride must divide N");
+    WS w;
+    PA_TRY(check_ws(c, workspace, wbytes, 0, 1, 0, 0, &w));
+    double* gu = w.P0;
+    double* gv = w.P1;
+    const int M = c->d.N / stride;
+    PA_HIP(launch_scatter_probes(c->d.B, c->d.N, stride, probes, gu, gv, c->stream));
+    PA_HIP(launch_row_r2c(c->d, gu, w.Yf[0], c->tw, c->stream));
+    PA_HIP(launch_row_r2c(c->d, gv, w.Yf[1], c->tw, c->stream));
+    ColArgs a = col_base(c);
+    a.yin[0] = w.Yf[0];
+    a.yin[1] = w.Yf[1];
+    a.lowpass = (M % 2 == 0) ? M / 2 - 1 : (M - 1) / 2;
+    a.nout = 1;
+    a.fields[0] = F_OMEGA;
+    a.yout[0] = w.Y0;
+    PA_HIP(launch_col(c->d, COL_FIRST_GUESS, a, c->stream));
+    PA_HIP(launch_row_c2r(c->d, w.Y0, omega_out, c->tw, c->stream));
+    return PA_OK;
+}
+
+pa_status pa_shell_growth(pa_ctx* c, const double* shells, int32_t rows, int32_t n_shells, double tau_min,
+                          double tau_max, double* mean_out, double* rate_out) {
+    g_err.clear();
+    if (!c || !shells || !rate_out) return fail(PA_EINVAL, "NULL argument");
+    if (rows < 1 || n_shells < 1) return fail(PA_EINVAL, "bad sizes");
+    if (!std::isfinite(tau_min) || !std::isfinite(tau_max) || tau_max < tau_min)
+        return fail(PA_EINVAL, "bad growth window");
+    PA_HIP(launch_shell_growth(c->d.B, rows, n_shells, shells, c->ph.dt, tau_min, tau_max, mean_out, rate_out,
+                               c->stream));
+    return PA_OK;
 }
 
 pa_status pa_precondition(pa_ctx* c, const pa_kernel* k, double power, const double* in, double* out,

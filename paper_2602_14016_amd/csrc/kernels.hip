@@ -20,6 +20,7 @@ static bool col_ptrs_ok(int mode, const ColArgs& a) {
         case COL_A: case COL_B: case COL_C: case COL_D: return a.yin[0] && a.omega && a.acc;
         case COL_FILTER: return a.yin[0] && a.mult;
         case COL_FROM_STATE: return a.state_in != nullptr;
+        case COL_FIRST_GUESS: return a.yin[0] && a.yin[1] && a.lowpass >= 0;
         case COL_ADJ_C: case COL_ADJ_B: case COL_ADJ_A: case COL_ADJ_N: case COL_ADJ_SRC:
             if (a.nin < 2 || a.nin > 4 || !a.lam) return false;
             if (mode != COL_ADJ_SRC && !a.omb) return false;

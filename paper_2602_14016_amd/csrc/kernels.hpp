@@ -40,7 +40,8 @@ enum ColMode : int {
     COL_FILTER = 5,   // Y -> multiplier * 1_S -> Y   (precondition)
     COL_FROM_STATE = 6,   // compact state -> derived fields (no input transform)
     COL_ADJ_C = 7, COL_ADJ_B = 8, COL_ADJ_A = 9, COL_ADJ_N = 10,  // adjoint stages
-    COL_ADJ_SRC = 11  // terminal source -> lambda_H
+    COL_ADJ_SRC = 11, // terminal source -> lambda_H
+    COL_FIRST_GUESS = 12  // probe velocities (u, v grids) -> band-limited vorticity
 };
 
 struct ColArgs {
@@ -67,6 +68,7 @@ struct ColArgs {
     int nf;                  // n_f (0 = none or outside the band)
     int final_out;           // adjoint: emit the gradient field instead of Lambda
     int mult_per_member;     // COL_FILTER: multiplier table per member
+    int lowpass;             // COL_FIRST_GUESS: keep |kx|, |ky| <= lowpass
 };
 
 struct RowObs {
@@ -136,6 +138,10 @@ hipError_t launch_axpby(int B, size_t n, const double* alpha, double alpha_scale
 hipError_t launch_scal_copy(int B, size_t n, const double* alpha, const double* x, double* y,
                             hipStream_t s);
 hipError_t launch_nonfinite(int B, size_t n, const double* x, int* flags, hipStream_t s);
+hipError_t launch_scatter_probes(int B, int N, int stride, const double* probes, double* grid_u, double* grid_v,
+                                 hipStream_t s);
+hipError_t launch_shell_growth(int B, int rows, int n_shells, const double* shells, double dt, double tau_min,
+                               double tau_max, double* mean_out, double* rate_out, hipStream_t s);
 
 constexpr int DOT_BLOCKS = 64;   // partial sums per member in launch_dot
 

@@ -320,7 +320,7 @@ template <int N, int V, int MODE>
 __global__ void __launch_bounds__(256) col_kernel(Dims d, ColArgs a) {
     constexpr int T = Plan<N, V>::T, E = Plan<N, V>::E;
     constexpr bool FWD_STAGE = MODE >= COL_A && MODE <= COL_D;
-    constexpr bool ADJ = MODE >= COL_ADJ_C;
+    constexpr bool ADJ = MODE >= COL_ADJ_C && MODE <= COL_ADJ_SRC;
     extern __shared__ cd smem[];
     const int CB = d.cb;
     const int c = threadIdx.x % CB, t = threadIdx.x / CB;
@@ -352,7 +352,7 @@ __global__ void __launch_bounds__(256) col_kernel(Dims d, ColArgs a) {
 #pragma unroll
         for (int m = 0; m < E; ++m) v0[m] = colok ? ldc(src, yoff(m)) : czero();
     }
-    if constexpr (ADJ) {
+    if constexpr (ADJ || MODE == COL_FIRST_GUESS) {
         const cd* __restrict__ src = a.yin[1] + ymem;
 #pragma unroll
         for (int m = 0; m < E; ++m) v1[m] = colok ? ldc(src, yoff(m)) : czero();
@@ -419,6 +419,17 @@ __global__ void __launch_bounds__(256) col_kernel(Dims d, ColArgs a) {
                     w[m] = s;
                 }
             }
+        }
+    } else if constexpr (MODE == COL_FIRST_GUESS) {
+        // vorticity of the low-passed probe velocity: i kx v_hat - i ky u_hat on S
+        fft<N, V, false>(v0, t, lds, twl);
+        fft<N, V, false>(v1, t, lds, twl);
+#pragma unroll
+        for (int m = 0; m < E; ++m) {
+            const int r = rowof(m);
+            const int ky = (r <= K) ? r : r - KY;
+            const bool keep = inS(r) && kx <= a.lowpass && ky <= a.lowpass && -ky <= a.lowpass;
+            w[m] = keep ? mk(-dkx * v1[m].y + (double)ky * v0[m].y, dkx * v1[m].x - (double)ky * v0[m].x) : czero();
         }
     } else if constexpr (MODE == COL_FROM_STATE) {
         cd* __restrict__ om = a.omega ? a.omega + cmem : nullptr;
@@ -614,6 +625,7 @@ hipError_t col_variant(const Dims& d, int mode, const ColArgs& a, hipStream_t s)
         case COL_ADJ_A: return col_mode<N, V, COL_ADJ_A>(d, a, s);
         case COL_ADJ_N: return col_mode<N, V, COL_ADJ_N>(d, a, s);
         case COL_ADJ_SRC: return col_mode<N, V, COL_ADJ_SRC>(d, a, s);
+        case COL_FIRST_GUESS: return col_mode<N, V, COL_FIRST_GUESS>(d, a, s);
         default: return hipErrorInvalidValue;
     }
 }

@@ -330,4 +330,72 @@ hipError_t launch_nonfinite(int B, size_t n, const double* x, int* flags, hipStr
     return hipGetLastError();
 }
 
+// Probe velocities [B][2][M][M] scattered onto zero grids [B][N][N] at (i s, j s),
+// times s^2: the unnormalised transform of that grid restricted to |k| < M/2
+// is (N/M)^2 times the coarse transform of the probes.
+__global__ void scatter_probes_kernel(int N, int stride, const double* __restrict__ probes, double* __restrict__ gu,
+                                      double* __restrict__ gv) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int b = blockIdx.y;
+    if (i >= N * N) return;
+    const int y = i / N, x = i % N;
+    const int M = N / stride;
+    double u = 0.0, v = 0.0;
+    if (y % stride == 0 && x % stride == 0) {
+        const size_t base = (size_t)b * 2 * M * M + (size_t)(y / stride) * M + (x / stride);
+        const double s2 = (double)stride * stride;
+        u = s2 * probes[base];
+        v = s2 * probes[base + (size_t)M * M];
+    }
+    gu[(size_t)b * N * N + i] = u;
+    gv[(size_t)b * N * N + i] = v;
+}
+hipError_t launch_scatter_probes(int B, int N, int stride, const double* probes, double* grid_u, double* grid_v,
+                                 hipStream_t s) {
+    if (!probes || !grid_u || !grid_v || stride < 1 || N % stride) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(scatter_probes_kernel, dim3((N * N + 255) / 256, B), dim3(256), 0, s, N, stride, probes,
+                       grid_u, grid_v);
+    return hipGetLastError();
+}
+
+// Ensemble mean of shell energies and least-squares growth rate per shell:
+// mean[n][k] = (1/B) sum_b shells[b][n][k];  rate[k] = slope of ln mean[n][k]
+// against tau = n dt over tau in [tau_min, tau_max] (NaN when a value is not
+// positive or fewer than two rows fall in the window).  One thread per shell.
+__global__ void shell_growth_kernel(int B, int rows, int n_shells, const double* __restrict__ shells, double dt,
+                                    double tau_min, double tau_max, double* __restrict__ mean,
+                                    double* __restrict__ rate) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n_shells) return;
+    double st = 0.0, sy = 0.0, stt = 0.0, sty = 0.0;
+    int cnt = 0;
+    bool ok = true;
+    for (int n = 0; n < rows; ++n) {
+        double m = 0.0;
+        for (int b = 0; b < B; ++b) m += shells[((size_t)b * rows + n) * n_shells + k];
+        m /= (double)B;
+        if (mean) mean[(size_t)n * n_shells + k] = m;
+        const double tau = n * dt;
+        if (tau >= tau_min - 1e-12 && tau <= tau_max + 1e-12) {
+            if (!(m > 0.0)) { ok = false; continue; }
+            const double ly = log(m);
+            st += tau; sy += ly; stt += tau * tau; sty += tau * ly;
+            ++cnt;
+        }
+    }
+    double r = NAN;
+    if (ok && cnt >= 2) {
+        const double tm = st / cnt, ym = sy / cnt;
+        r = (sty - cnt * tm * ym) / (stt - cnt * tm * tm);
+    }
+    rate[k] = r;
+}
+hipError_t launch_shell_growth(int B, int rows, int n_shells, const double* shells, double dt, double tau_min,
+                               double tau_max, double* mean_out, double* rate_out, hipStream_t s) {
+    if (!shells || !rate_out || B < 1 || rows < 1 || n_shells < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(shell_growth_kernel, dim3((n_shells + 63) / 64), dim3(64), 0, s, B, rows, n_shells, shells, dt,
+                       tau_min, tau_max, mean_out, rate_out);
+    return hipGetLastError();
+}
+
 }  // namespace pa

@@ -61,6 +61,8 @@ EXPORTS = {
     "pa_adjoint_impulse": (c_int32, [c_void_p, c_void_p, c_int32, c_int32, c_int32, c_int32, c_void_p,
                                      c_void_p, c_int32, c_void_p, c_size_t]),
     "pa_set_tiles": (c_int32, [c_void_p, c_int32, c_int32, c_int32]),
+    "pa_first_guess": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_size_t]),
+    "pa_shell_growth": (c_int32, [c_void_p, c_void_p, c_int32, c_int32, c_double, c_double, c_void_p, c_void_p]),
     "pa_profile_start": (c_int32, [c_void_p, c_int32, c_int32]),
     "pa_profile_stop": (c_int32, [c_void_p, POINTER(ctypes.c_int64), POINTER(ctypes.c_int64), POINTER(c_double)]),
 }

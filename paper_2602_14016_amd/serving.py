@@ -1,0 +1,232 @@
+"""Continuous-batching request server for assimilation solves.
+
+Requests (grid size, flow, horizon, observation stride and steps, kernel,
+iteration count, observations) arrive over time.  The server keeps a queue
+and a fixed number of slots; each slot owns a HIP stream (default priority)
+and a worker thread.  Whenever a slot is free, queued requests are admitted in
+arrival order if their device footprint (workspace + fields + observations,
+from pa_workspace_bytes) fits in the remaining HBM budget; requests with the
+same shape (grid, physics, horizon, observation layout, kernel, iterations)
+that are waiting are admitted together as one batched solve.  A slot uploads
+its observations, forms the first guess, runs pa_assimilate on its stream and
+copies the result back; its memory is released for the next admission as soon
+as it finishes.  Solves on different slots overlap on the device.  Latency is
+stamped from arrival to result-ready.
+
+Results of a request are identical whether it runs alone, batched with
+others or concurrently with other slots: every member uses the same kernels
+with the same tiles, and no reduction crosses members.
+"""
+
+import heapq
+import queue
+import threading
+import time
+from dataclasses import dataclass, field
+from typing import List, Optional
+
+import numpy as np
+import torch
+
+from .solver import KernelSpec, Observations, Solver
+
+DECAYING = "decaying"
+KOLMOGOROV = "kolmogorov"
+
+
+def physics_for(flow, N):
+    """Per-flow physics: decaying HIT (nu = 1e-4) or Kolmogorov (nu = 1/40, drag 0.1, A = 1, n_f = 4),
+    with a time step that keeps the explicit nonlinear term stable at grid size N."""
+    if flow == DECAYING:
+        dt = 2e-3 if N <= 256 else (1e-3 if N == 512 else 5e-4)
+        return dict(nu=1e-4, mu=0.0, dt=dt, forcing_amp=0.0, forcing_k=4)
+    dt = 1e-3 if N <= 512 else 5e-4
+    return dict(nu=1.0 / 40, mu=0.1, dt=dt, forcing_amp=1.0, forcing_k=4)
+
+
+@dataclass
+class Request:
+    rid: int
+    N: int
+    flow: str
+    n_steps: int
+    stride: int
+    obs_steps: List[int]
+    obs_values: torch.Tensor          # host float64 [n_times, 2, M, M]
+    kernel: KernelSpec
+    iters: int = 10
+    lbfgs_m: int = 10
+    ckpt_every: int = 50
+    first_guess: str = "interp"       # "interp" (spectral interpolation of t=0 probes) or "zero"
+    arrival: float = 0.0              # seconds from trace start
+
+    def shape_key(self):
+        return (self.N, self.flow, self.n_steps, self.stride, tuple(self.obs_steps), self.kernel, self.iters,
+                self.lbfgs_m, self.ckpt_every, self.first_guess)
+
+
+@dataclass
+class Result:
+    rid: int
+    omega0: Optional[torch.Tensor]
+    J_hist: List[float]
+    iters: int
+    status: str
+    arrival: float
+    admitted: float
+    finished: float
+    batch: int
+
+    @property
+    def latency(self):
+        return self.finished - self.arrival
+
+
+def footprint_bytes(solver, req: Request):
+    n_obs = len(req.obs_steps)
+    M = req.N // req.stride
+    ws = solver.workspace_bytes(req.n_steps, req.ckpt_every, n_obs, max(req.lbfgs_m, 1))
+    fields = solver.B * (3 * req.N * req.N + n_obs * 2 * M * M) * 8
+    return ws + fields
+
+
+class Server:
+    def __init__(self, hbm_budget_bytes, slots=4, max_batch=8, device="cuda:0"):
+        self.device = torch.device(device)
+        self.budget = int(hbm_budget_bytes)
+        self.in_use = 0
+        self.slots = slots
+        self.max_batch = max_batch
+        self.lock = threading.Condition()
+        self.queue: List[Request] = []
+        self.results = {}
+        self.free_slots = list(range(slots))
+        self.streams = [torch.cuda.Stream(device=self.device) for _ in range(slots)]
+        self.t0 = None
+        self._solvers = {}   # (slot, N, flow, B) -> Solver
+
+    # ------------------------------------------------------------------ API
+    def now(self):
+        return time.perf_counter() - self.t0
+
+    def submit(self, req: Request):
+        with self.lock:
+            self.queue.append(req)
+            self.lock.notify_all()
+
+    def _solver(self, slot, N, flow, B):
+        key = (slot, N, flow, B)
+        if key not in self._solvers:
+            with torch.cuda.stream(self.streams[slot]):
+                self._solvers[key] = Solver(N, B, device=self.device, stream=self.streams[slot],
+                                            **physics_for(flow, N))
+        return self._solvers[key]
+
+    def _probe_solver(self, req, B):
+        # footprint query only (any slot's context of the same shape answers it)
+        return self._solver(0, req.N, req.flow, B)
+
+    def _admit_locked(self):
+        """Admit queued requests into free slots while memory allows (arrival order)."""
+        started = []
+        while self.free_slots and self.queue:
+            head = self.queue[0]
+            group = [r for r in self.queue if r.shape_key() == head.shape_key()][: self.max_batch]
+            solver = self._probe_solver(head, len(group))
+            need = footprint_bytes(solver, head)
+            while need > self.budget - self.in_use and len(group) > 1:
+                group = group[:-1]
+                need = footprint_bytes(self._probe_solver(head, len(group)), head)
+            if need > self.budget:
+                self.queue.remove(head)
+                self.results[head.rid] = Result(head.rid, None, [], 0, "rejected: exceeds HBM budget",
+                                                head.arrival, self.now(), self.now(), 0)
+                continue
+            if need > self.budget - self.in_use:
+                break   # wait for memory to free up
+            for r in group:
+                self.queue.remove(r)
+            slot = self.free_slots.pop(0)
+            self.in_use += need
+            started.append((slot, group, need))
+        return started
+
+    def _run_group(self, slot, group, need):
+        admitted = self.now()
+        try:
+            head = group[0]
+            B = len(group)
+            s = self._solver(slot, head.N, head.flow, B)
+            stream = self.streams[slot]
+            with torch.cuda.stream(stream):
+                vals = torch.stack([r.obs_values for r in group]).to(self.device, dtype=torch.float64,
+                                                                      non_blocking=False).contiguous()
+                obs = Observations(head.stride, head.obs_steps, vals)
+                if head.first_guess == "interp" and head.obs_steps and head.obs_steps[0] == 0:
+                    fg = s.first_guess(head.stride, vals[:, 0].contiguous())
+                else:
+                    fg = torch.zeros((B, head.N, head.N), dtype=torch.float64, device=self.device)
+                w, H, iters = s.assimilate(fg, head.n_steps, obs, head.kernel, "lbfgs", head.iters,
+                                           head.lbfgs_m, head.ckpt_every)
+                w_host = w.cpu()
+            fin = self.now()
+            for b, r in enumerate(group):
+                status = "ok" if iters[b] >= 0 else "line-search failure"
+                self.results[r.rid] = Result(r.rid, w_host[b].clone(), [h for h in H[b] if h == h],
+                                             iters[b] if iters[b] >= 0 else -iters[b] - 1, status, r.arrival,
+                                             admitted, fin, B)
+        except Exception as e:   # a failing request fails alone
+            fin = self.now()
+            for r in group:
+                self.results[r.rid] = Result(r.rid, None, [], 0, f"error: {e}", r.arrival, admitted, fin, len(group))
+        finally:
+            try:
+                s._ws = None     # return the workspace to the allocator before the budget is released
+            except NameError:
+                pass
+            with self.lock:
+                self.in_use -= need
+                self.free_slots.append(slot)
+                self.free_slots.sort()
+                self.lock.notify_all()
+
+    def run_trace(self, requests: List[Request], time_scale=1.0):
+        """Replay requests at their arrival times (seconds * time_scale); returns results by id."""
+        self.t0 = time.perf_counter()
+        pending = sorted(requests, key=lambda r: r.arrival)
+        threads = []
+        i = 0
+        while True:
+            now = self.now()
+            while i < len(pending) and pending[i].arrival * time_scale <= now:
+                self.submit(pending[i])
+                i += 1
+            with self.lock:
+                started = self._admit_locked()
+            for slot, group, need in started:
+                th = threading.Thread(target=self._run_group, args=(slot, group, need), daemon=True)
+                th.start()
+                threads.append(th)
+            with self.lock:
+                done = i == len(pending) and not self.queue and len(self.free_slots) == self.slots
+                if done:
+                    break
+                next_arrival = pending[i].arrival * time_scale - self.now() if i < len(pending) else None
+                timeout = 0.05 if next_arrival is None else max(0.0, min(0.05, next_arrival))
+                self.lock.wait(timeout=timeout)
+        for th in threads:
+            th.join()
+        return dict(self.results)
+
+
+def poisson_arrivals(n, rate, seed=0):
+    rng = np.random.default_rng(seed)
+    return np.cumsum(rng.exponential(1.0 / rate, size=n))
+
+
+def latency_stats(results):
+    lat = sorted(r.latency for r in results.values() if r.status == "ok")
+    if not lat:
+        return {}
+    q = lambda p: float(np.percentile(np.array(lat), p))
+    return {"n": len(lat), "p50_s": q(50), "p99_s": q(99), "mean_s": float(np.mean(lat)), "max_s": lat[-1]}

@@ -229,3 +229,26 @@ class Solver:
         ms = c_double()
         nv.check(self.lib.pa_profile_stop(self.ctx, byref(t), byref(seen), byref(ms)))
         return {"timed_launches": t.value, "launches": seen.value, "total_ms": ms.value}
+
+    # ---------------------------------------------------------- extra calls
+    def first_guess(self, stride, probes, out=None):
+        """Interpolated vorticity from probe velocities probes [B, 2, M, M] at t = 0."""
+        M = self.N // int(stride)
+        _need(probes, (self.B, 2, M, M), "probes")
+        out = self.empty() if out is None else out
+        self._sync_stream()
+        ws, wb = self.workspace()
+        nv.check(self.lib.pa_first_guess(self.ctx, int(stride), _ptr(probes), _ptr(out), ws, wb))
+        return out
+
+    def shell_growth(self, shells, tau_min=0.3, tau_max=1.0):
+        """Member mean of shells [B, rows, n] and per-shell growth rate of ln(mean) vs tau."""
+        B, rows, n = shells.shape
+        if B != self.B or shells.dtype != torch.float64 or not shells.is_cuda or not shells.is_contiguous():
+            raise ValueError("shells must be a contiguous float64 CUDA tensor [B, rows, n_shells]")
+        mean = torch.empty((rows, n), dtype=torch.float64, device=self.device)
+        rate = torch.empty(n, dtype=torch.float64, device=self.device)
+        self._sync_stream()
+        nv.check(self.lib.pa_shell_growth(self.ctx, _ptr(shells), int(rows), int(n), float(tau_min), float(tau_max),
+                                          _ptr(mean), _ptr(rate)))
+        return mean, rate

@@ -1,0 +1,63 @@
+"""GPU test of the continuous-batching server: every request's result is the
+same alone and in a mix, oversize requests are rejected alone, and latency is
+recorded."""
+
+import numpy as np
+import pytest
+import torch
+
+pytestmark = pytest.mark.gpu
+
+
+def _make_requests(seed=0):
+    from paper_2602_14016_amd import Solver, KernelSpec
+    from paper_2602_14016_amd.serving import Request, physics_for, poisson_arrivals
+    rng = np.random.default_rng(seed)
+    specs = [(32, "decaying", 40, 4), (64, "kolmogorov", 30, 8), (32, "decaying", 40, 4), (64, "decaying", 24, 4),
+             (32, "kolmogorov", 20, 2), (64, "decaying", 24, 4)]
+    kernels = [KernelSpec(0, 0.0), KernelSpec(1, 0.05), KernelSpec(2, 0.5)]
+    arrivals = poisson_arrivals(len(specs), rate=50.0, seed=seed)
+    reqs = []
+    for i, (N, flow, H, stride) in enumerate(specs):
+        ph = physics_for(flow, N)
+        truth_solver = Solver(N, 1, **ph)
+        truth = truth_solver.init_field([100 + i], kind=0 if flow == "decaying" else 2, k0=max(2.0, N / 25),
+                                        target=0.5 if flow == "decaying" else 1e-2)
+        steps = [0, H // 2, H]
+        from paper_2602_14016_amd import Observations
+        obs = truth_solver.forward(truth, H, Observations(stride, steps), want_obs=True)["obs"][0].cpu()
+        kern = kernels[i % 3] if i != 3 else kernels[2]
+        reqs.append(Request(rid=i, N=N, flow=flow, n_steps=H, stride=stride, obs_steps=steps, obs_values=obs,
+                            kernel=kern, iters=3, lbfgs_m=3, ckpt_every=10, arrival=float(arrivals[i])))
+    return reqs
+
+
+def test_alone_equals_mix_and_latency():
+    from paper_2602_14016_amd.serving import Server, latency_stats
+    print("CASE serving", flush=True)
+    reqs = _make_requests()
+    mix = Server(hbm_budget_bytes=8 << 30, slots=3).run_trace(reqs)
+    assert all(r.status == "ok" for r in mix.values()), {k: v.status for k, v in mix.items()}
+    # requests 3 and 5 share a shape: they may run as one batched solve
+    for r in reqs:
+        alone = Server(hbm_budget_bytes=8 << 30, slots=1).run_trace([r])[r.rid]
+        assert alone.status == "ok"
+        a, m = alone.omega0.numpy(), mix[r.rid].omega0.numpy()
+        assert np.array_equal(a, m), (r.rid, float(np.abs(a - m).max()))
+        assert alone.J_hist == mix[r.rid].J_hist
+        assert mix[r.rid].J_hist[-1] < mix[r.rid].J_hist[0]
+    st = latency_stats(mix)
+    assert st["n"] == len(reqs) and st["p99_s"] >= st["p50_s"] > 0
+
+
+def test_oversize_request_rejected_alone():
+    from paper_2602_14016_amd.serving import Server, footprint_bytes
+    print("CASE serving-reject", flush=True)
+    reqs = _make_requests()[:3]
+    probe = Server(hbm_budget_bytes=1 << 40, slots=1)
+    fp = [footprint_bytes(probe._probe_solver(r, 1), r) for r in reqs]
+    assert fp[1] > max(fp[0], fp[2])            # the 64^2 request is the largest
+    budget = (fp[1] + max(fp[0], fp[2])) // 2   # fits the 32^2 requests one at a time, never the 64^2 one
+    res = Server(hbm_budget_bytes=budget, slots=2).run_trace(reqs)
+    assert res[1].status.startswith("rejected")
+    assert res[0].status == "ok" and res[2].status == "ok"
