@@ -1,0 +1,147 @@
+"""Named workloads of the hot path and a runner.
+
+    python -m paper_2602_14016_amd.configs c0|c1|c2|c3 [--iters K] [--horizon H]
+
+c0  decaying turbulence, 64^2, nu = 1e-3, Gaussian random field (k0 = 4,
+    energy 0.5), 200 RK4 steps at dt = 5e-3, velocity at every 4th grid point
+    at the final time, first guess 0, 5 steepest-descent steps with
+    W = exp(-0.1 |k|).
+c1  decaying turbulence, 256^2, nu = 1e-4, random phases (k0 = 10), 1000
+    steps at dt = 2e-3, velocity at 8 x 8-stride probes at 5 evenly spaced
+    times, interpolated first guess, 50 L-BFGS iterations for each of W = 1,
+    exp(-0.05 |k|), |k|^-1; checkpoints every 50 steps.
+c2  forced Kolmogorov flow, 512^2, nu = 1/40, drag 0.1, f_x = sin 4y, spin-up
+    of 5000 steps from noise of RMS 1e-2, horizon 2000 at dt = 1e-3,
+    observations at 16 x 16 stride every 50 steps, W = |k|^(-2 beta) for beta
+    in {0.25, 0.5, 1.0}, 30 L-BFGS iterations.
+c3  ensemble of 64 realizations of the c1 spectrum (seeds 0..63), 500
+    forward + 500 adjoint steps from a unit u-impulse, shell energies and
+    growth rates for |k| = 1..85.
+
+Truth fields are seeded synthetic spectra (the paper's truth realizations are
+not available); observations are the model's own (twin experiment).
+"""
+
+import argparse
+import json
+import sys
+import time
+from dataclasses import dataclass, field
+from typing import List, Tuple
+
+import torch
+
+from .solver import KernelSpec, Observations, Solver
+
+
+def evenly_spaced(n_steps, n):
+    return sorted({int(round(i * n_steps / (n - 1))) for i in range(n)})
+
+
+@dataclass
+class Config:
+    name: str
+    N: int
+    nu: float
+    dt: float
+    n_steps: int
+    stride: int
+    obs_steps: List[int]
+    kernels: List[KernelSpec]
+    method: str = "lbfgs"
+    iters: int = 50
+    mu: float = 0.0
+    forcing_amp: float = 0.0
+    forcing_k: int = 4
+    truth_kind: int = 0
+    truth_k0: float = 10.0
+    truth_target: float = 0.5
+    truth_seed: int = 0
+    spinup: int = 0
+    first_guess: str = "interp"
+    ckpt_every: int = 50
+    lbfgs_m: int = 10
+
+    def physics(self):
+        return dict(nu=self.nu, dt=self.dt, mu=self.mu, forcing_amp=self.forcing_amp, forcing_k=self.forcing_k)
+
+
+def c0():
+    return Config("c0", 64, 1e-3, 5e-3, 200, 4, [200], [KernelSpec(1, 0.1)], method="sd", iters=5,
+                  truth_kind=1, truth_k0=4.0, first_guess="zero")
+
+
+def c1():
+    return Config("c1", 256, 1e-4, 2e-3, 1000, 8, evenly_spaced(1000, 5),
+                  [KernelSpec(0, 0.0), KernelSpec(1, 0.05), KernelSpec(2, 0.5)], iters=50, truth_k0=10.0)
+
+
+def c2():
+    return Config("c2", 512, 1.0 / 40, 1e-3, 2000, 16, list(range(0, 2001, 50)),
+                  [KernelSpec(2, 0.25), KernelSpec(2, 0.5), KernelSpec(2, 1.0)], iters=30, mu=0.1,
+                  forcing_amp=1.0, forcing_k=4, truth_kind=2, truth_target=1e-2, spinup=5000)
+
+
+CONFIGS = {"c0": c0, "c1": c1, "c2": c2}
+
+
+def truth_and_obs(cfg: Config, solver: Solver):
+    """Seeded truth (after spin-up) and its model observations [B, n_times, 2, M, M]."""
+    w = solver.init_field([cfg.truth_seed + b for b in range(solver.B)], kind=cfg.truth_kind, k0=cfg.truth_k0,
+                          target=cfg.truth_target)
+    if cfg.spinup:
+        w = solver.forward(w, cfg.spinup)["omega_T"]
+    obs = solver.forward(w, cfg.n_steps, Observations(cfg.stride, cfg.obs_steps), want_obs=True)["obs"]
+    return w, obs
+
+
+def run_config(cfg: Config, iters=None, verbose=True):
+    """Run the assimilation of cfg once per kernel; returns a list of result dicts."""
+    s = Solver(cfg.N, 1, **cfg.physics())
+    t0 = time.perf_counter()
+    truth, obs_vals = truth_and_obs(cfg, s)
+    obs = Observations(cfg.stride, cfg.obs_steps, obs_vals)
+    if cfg.first_guess == "interp" and cfg.obs_steps[0] == 0:
+        fg = s.first_guess(cfg.stride, obs_vals[:, 0].contiguous())
+    else:
+        fg = torch.zeros_like(truth)
+    setup_s = time.perf_counter() - t0
+    out = []
+    for kern in cfg.kernels:
+        t1 = time.perf_counter()
+        w, H, it = s.assimilate(fg, cfg.n_steps, obs, kern, cfg.method, iters or cfg.iters, cfg.lbfgs_m,
+                                cfg.ckpt_every)
+        torch.cuda.synchronize()
+        err = float(torch.linalg.norm(w - truth) / torch.linalg.norm(truth))
+        rec = {"config": cfg.name, "kernel": [kern.kind, kern.param, kern.metric], "iterations": it[0],
+               "J": [h for h in H[0] if h == h], "rel_err_omega0": err, "seconds": time.perf_counter() - t1,
+               "setup_seconds": setup_s}
+        out.append(rec)
+        if verbose:
+            print(json.dumps(rec), flush=True)
+    return out
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("config", choices=sorted(list(CONFIGS) + ["c3"]))
+    ap.add_argument("--iters", type=int, default=None)
+    ap.add_argument("--horizon", type=int, default=None)
+    args = ap.parse_args(argv)
+    if args.config == "c3":
+        from . import ensemble
+        t0 = time.perf_counter()
+        res = ensemble.run(n_steps=args.horizon or 500)
+        torch.cuda.synchronize()
+        print(json.dumps({"config": "c3", "seconds": time.perf_counter() - t0,
+                          "growth_rates": [float(x) for x in res.rates.cpu()]}))
+        return
+    cfg = CONFIGS[args.config]()
+    if args.horizon:
+        cfg.n_steps = args.horizon
+        cfg.obs_steps = [s for s in cfg.obs_steps if s <= args.horizon] or [args.horizon]
+    run_config(cfg, args.iters)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,103 @@
+"""GPU checks at the configurations' own sizes.
+
+c0 runs in full against the oracle; c1 and c2 are checked against the oracle
+at a shortened horizon on their full grids, and c1 in full (256^2, 1000
+steps) by central finite differences of the GPU's own cost on 20 directions.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import synth
+from oracle.model import Obs, Physics
+from oracle.precond import Kernel
+
+pytestmark = pytest.mark.gpu
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float64)).cuda()
+
+
+def test_c0_full_parity():
+    from paper_2602_14016_amd import KernelSpec, Observations, Solver
+    print("CASE c0", flush=True)
+    N, H = 64, 200
+    ph = Physics(N=N, nu=1e-3, dt=5e-3)
+    truth = O.init_field(N, [0], kind=1, k0=4.0, target=0.5)[0]
+    _, _, mo = O.forward(truth, ph, H, Obs(4, [H]))
+    fg = np.zeros((N, N))
+    w_ref, h_ref, it_ref, st_ref = O.assimilate(fg, ph, H, Obs(4, [H], mo), Kernel(1, 0.1, 0), "sd", 5)
+    s = Solver(N, 1, nu=ph.nu, dt=ph.dt)
+    w, Hh, it = s.assimilate(dev(fg[None]), H, Observations(4, [H], dev(mo[None])), KernelSpec(1, 0.1), "sd", 5,
+                             ckpt_every=50)
+    torch.cuda.synchronize()
+    assert it[0] == it_ref == 5
+    assert np.allclose(Hh[0], h_ref, rtol=1e-9, atol=0)
+    assert rel(w.cpu().numpy()[0], w_ref) < 1e-9
+    assert h_ref[-1] < h_ref[0]
+
+
+def test_c1_shortened_horizon_gradient_parity():
+    from paper_2602_14016_amd import Observations, Solver
+    print("CASE c1-100", flush=True)
+    N, H = 256, 100
+    ph = Physics(N=N, nu=1e-4, dt=2e-3)
+    osteps = synth.evenly_spaced_steps(H, 5)
+    truth = O.init_field(N, [0], kind=0, k0=10.0)[0]
+    _, _, mo = O.forward(truth, ph, H, Obs(8, osteps))
+    w0 = O.init_field(N, [1], kind=0, k0=10.0)[0]
+    J_ref, g_ref = O.adjoint_gradient(w0, ph, H, Obs(8, osteps, mo))
+    s = Solver(N, 1, nu=ph.nu, dt=ph.dt)
+    J, g = s.adjoint_gradient(dev(w0[None]), H, Observations(8, osteps, dev(mo[None])), ckpt_every=50)
+    torch.cuda.synchronize()
+    assert abs(float(J.cpu()[0]) - J_ref) <= 1e-11 * J_ref
+    assert rel(g.cpu().numpy()[0], g_ref) < 1e-9
+
+
+def test_c1_full_finite_differences():
+    from paper_2602_14016_amd import Observations, Solver
+    print("CASE c1-fd", flush=True)
+    N, H, ndir = 256, 1000, 20
+    s1 = Solver(N, 1, nu=1e-4, dt=2e-3)
+    osteps = synth.evenly_spaced_steps(H, 5)
+    truth = s1.init_field([0], kind=0, k0=10.0)
+    mo = s1.forward(truth, H, Observations(8, osteps), want_obs=True)["obs"]
+    fg = s1.first_guess(8, mo[:, 0].contiguous())
+    obs1 = Observations(8, osteps, mo)
+    J0, g = s1.adjoint_gradient(fg, H, obs1, ckpt_every=50)
+    rms = float(fg.pow(2).mean().sqrt())
+    d = torch.stack([torch.from_numpy(synth.normal_field((N, N), 1000 + i)) for i in range(ndir)]).cuda()
+    d = d * (rms / d.pow(2).mean(dim=(1, 2), keepdim=True).sqrt())
+    sB = Solver(N, ndir, nu=1e-4, dt=2e-3)
+    obsB = Observations(8, osteps, mo.expand(ndir, -1, -1, -1, -1).contiguous())
+    eps = 1e-6
+    Jp = sB.forward((fg + eps * d).contiguous(), H, obsB)["J"]
+    Jm = sB.forward((fg - eps * d).contiguous(), H, obsB)["J"]
+    fd = ((Jp - Jm) / (2 * eps)).cpu().numpy()
+    ad = (g * d).sum(dim=(1, 2)).cpu().numpy()
+    relerr = np.abs(fd - ad) / np.abs(ad)
+    print("c1 FD relative errors: max %.2e median %.2e" % (relerr.max(), np.median(relerr)), flush=True)
+    assert np.all(relerr < 1e-6), relerr
+
+
+def test_c2_grid_short_parity():
+    from paper_2602_14016_amd import Observations, Solver
+    print("CASE c2-512", flush=True)
+    N, H = 512, 3
+    ph = Physics(N=N, nu=1.0 / 40, dt=1e-3, mu=0.1, forcing_amp=1.0, forcing_k=4)
+    w0 = O.init_field(N, [0], kind=0, k0=6.0, target=0.5)[0]
+    truth = O.init_field(N, [1], kind=0, k0=6.0, target=0.5)[0]
+    _, _, mo = O.forward(truth, ph, H, Obs(16, [0, H]))
+    J_ref, g_ref = O.adjoint_gradient(w0, ph, H, Obs(16, [0, H], mo))
+    s = Solver(N, 1, nu=ph.nu, dt=ph.dt, mu=ph.mu, forcing_amp=1.0, forcing_k=4)
+    J, g = s.adjoint_gradient(dev(w0[None]), H, Observations(16, [0, H], dev(mo[None])), ckpt_every=2)
+    torch.cuda.synchronize()
+    assert abs(float(J.cpu()[0]) - J_ref) <= 1e-11 * J_ref
+    assert rel(g.cpu().numpy()[0], g_ref) < 1e-9
