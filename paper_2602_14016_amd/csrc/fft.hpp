@@ -27,6 +27,20 @@ struct cd { double x, y; };
 // flight across its exchanges.
 __device__ __forceinline__ void lds_sync() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
 
+// Hand-off inside one wavefront: a wave's LDS operations are executed in
+// issue order, so a team that lies within one wave only has to wait for its
+// own LDS operations (and keep the compiler from moving accesses across).
+// No other wave is stalled.
+__device__ __forceinline__ void wave_lds_sync() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
+
+// WL: the team lies within one wavefront (T divides 64 and teams are
+// consecutive threads), so its exchanges need no workgroup barrier.
+template <bool WL>
+__device__ __forceinline__ void team_sync() {
+    if constexpr (WL) wave_lds_sync();
+    else lds_sync();
+}
+
 __device__ __forceinline__ cd mk(double x, double y) { cd r; r.x = x; r.y = y; return r; }
 __device__ __forceinline__ cd cadd(cd a, cd b) { return mk(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ cd csub(cd a, cd b) { return mk(a.x - b.x, a.y - b.y); }
@@ -184,7 +198,7 @@ __host__ __device__ constexpr int lds_team() { return N + N / 16 + 1; }
 __device__ __forceinline__ int lpad(int i) { return i + (i >> 4); }
 
 // One Stockham stage: radix R, span S (product of the radices already done).
-template <int N, int V, int R, int S, bool INV, bool LAST>
+template <int N, int V, int R, int S, bool INV, bool LAST, bool WL>
 __device__ __forceinline__ void fft_stage(cd* v, int t, cd* lds, const cd* __restrict__ tw) {
     constexpr int T = Plan<N, V>::T, E = Plan<N, V>::E, NB = E / R;
 #pragma unroll
@@ -213,34 +227,34 @@ __device__ __forceinline__ void fft_stage(cd* v, int t, cd* lds, const cd* __res
         }
     }
     if constexpr (!LAST) {
-        lds_sync();
+        team_sync<WL>();
 #pragma unroll
         for (int m = 0; m < E; ++m) v[m] = lds[lpad(t + T * m)];
-        lds_sync();
+        team_sync<WL>();
     }
 }
 
 // Full transform of the team's register signal v (layout t + T*m).
-// Every thread of the workgroup must call this (it contains barriers when the
-// plan has more than one stage).
-template <int N, int V, bool INV>
+// Unless WL, every thread of the workgroup must call this (it contains
+// barriers when the plan has more than one stage).
+template <int N, int V, bool INV, bool WL = false>
 __device__ __forceinline__ void fft(cd* v, int t, cd* lds, const cd* __restrict__ tw) {
     using P = Plan<N, V>;
     constexpr int R0 = P::R[0], R1 = P::R[1], R2 = P::R[2], R3 = P::R[3];
     if constexpr (P::NS == 1) {
-        fft_stage<N, V, R0, 1, INV, true>(v, t, lds, tw);
+        fft_stage<N, V, R0, 1, INV, true, WL>(v, t, lds, tw);
     } else if constexpr (P::NS == 2) {
-        fft_stage<N, V, R0, 1, INV, false>(v, t, lds, tw);
-        fft_stage<N, V, R1, R0, INV, true>(v, t, lds, tw);
+        fft_stage<N, V, R0, 1, INV, false, WL>(v, t, lds, tw);
+        fft_stage<N, V, R1, R0, INV, true, WL>(v, t, lds, tw);
     } else if constexpr (P::NS == 3) {
-        fft_stage<N, V, R0, 1, INV, false>(v, t, lds, tw);
-        fft_stage<N, V, R1, R0, INV, false>(v, t, lds, tw);
-        fft_stage<N, V, R2, R0 * R1, INV, true>(v, t, lds, tw);
+        fft_stage<N, V, R0, 1, INV, false, WL>(v, t, lds, tw);
+        fft_stage<N, V, R1, R0, INV, false, WL>(v, t, lds, tw);
+        fft_stage<N, V, R2, R0 * R1, INV, true, WL>(v, t, lds, tw);
     } else {
-        fft_stage<N, V, R0, 1, INV, false>(v, t, lds, tw);
-        fft_stage<N, V, R1, R0, INV, false>(v, t, lds, tw);
-        fft_stage<N, V, R2, R0 * R1, INV, false>(v, t, lds, tw);
-        fft_stage<N, V, R3, R0 * R1 * R2, INV, true>(v, t, lds, tw);
+        fft_stage<N, V, R0, 1, INV, false, WL>(v, t, lds, tw);
+        fft_stage<N, V, R1, R0, INV, false, WL>(v, t, lds, tw);
+        fft_stage<N, V, R2, R0 * R1, INV, false, WL>(v, t, lds, tw);
+        fft_stage<N, V, R3, R0 * R1 * R2, INV, true, WL>(v, t, lds, tw);
     }
 }
 

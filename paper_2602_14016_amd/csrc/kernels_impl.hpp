@@ -35,70 +35,84 @@ __device__ __forceinline__ const cd* stage_twiddles(cd* lds_tw, const cd* __rest
     return lds_tw;
 }
 
+// Retained band of a grid of size N: the 2/3 rule keeps |kx|, |ky| <= (N-1)/3.
+template <int N>
+__host__ __device__ constexpr int band() { return (N - 1) / 3; }
+// Row pitch of the half-spectrum layouts: kx = 0..K padded to a multiple of 8.
+template <int N>
+__host__ __device__ constexpr int kx_pad() { return (band<N>() + 1 + 7) / 8 * 8; }
+
+// Whether register slot m of a T-thread team (elements t + T m, t < T) can
+// touch the band kx <= K or kx >= N - K; folded at compile time after
+// unrolling, so slots that only see the de-aliased gap issue no loads.
+template <int N, int V>
+__device__ constexpr bool slot_in_band(int m) {
+    constexpr int T = Plan<N, V>::T, K = band<N>();
+    return T * m <= K || T * m + T - 1 >= N - K;
+}
+template <int N, int V>
+__device__ constexpr bool slot_low(int m) { return Plan<N, V>::T * m <= band<N>(); }
+
 // z = A_full[e] + i B_full[e] for the Hermitian extensions of half-spectrum
 // rows A, B (only kx = 0..K stored, zero beyond).  The kx = 0 entry of a real
-// field's half spectrum is real; its imaginary round-off is discarded.
-__device__ __forceinline__ cd herm_pair(const cd* __restrict__ A, const cd* __restrict__ B, int e, int N, int K) {
-    if (e == 0) return mk(A[0].x, B[0].x);
-    if (e <= K) {
-        const cd a = A[e], b = B[e];
-        return mk(a.x - b.y, a.y + b.x);
-    }
-    if (e >= N - K) {
-        const cd a = A[N - e], b = B[N - e];
-        return mk(a.x + b.y, b.x - a.y);
-    }
-    return czero();
+// field's half spectrum is real; its imaginary round-off is discarded.  With
+// DX, A is replaced by its x-derivative i kx A.  Branch-free: the load index
+// is clamped to 0 off the band and the result selected, so the loads of all
+// slots issue back to back instead of each waiting inside a divergent branch.
+template <int N, bool DX = false>
+__device__ __forceinline__ cd herm_pair(const cd* __restrict__ A, const cd* __restrict__ B, int e) {
+    constexpr int K = band<N>();
+    const bool lo = e <= K, hi = e >= N - K;
+    const unsigned k = lo ? (unsigned)e : (hi ? (unsigned)(N - e) : 0u);
+    cd a = ldc(A, k), bb = ldc(B, k);
+    if (DX) a = mul_i(cscale(a, (double)k));
+    if (e == 0) { a.y = 0.0; bb.y = 0.0; }
+    if (hi) { a.y = -a.y; bb.y = -bb.y; }
+    const cd z = mk(a.x - bb.y, a.y + bb.x);
+    return (lo || hi) ? z : czero();
 }
 
-// Same with A replaced by its x-derivative i kx A (kx = 0 gives zero).
-__device__ __forceinline__ cd herm_pair_dxA(const cd* __restrict__ A, const cd* __restrict__ B, int e, int N, int K) {
-    if (e == 0) return mk(0.0, B[0].x);
-    if (e <= K) {
-        const cd a = mul_i(cscale(A[e], (double)e)), b = B[e];
-        return mk(a.x - b.y, a.y + b.x);
-    }
-    if (e >= N - K) {
-        const int k = N - e;
-        const cd a = mul_i(cscale(A[k], (double)k)), b = B[k];
-        return mk(a.x + b.y, b.x - a.y);
-    }
-    return czero();
+// Fills the E register slots of a team with the extension of (A, B).
+template <int N, int V, bool DX = false>
+__device__ __forceinline__ void herm_load(cd* z, const cd* __restrict__ A, const cd* __restrict__ B, int t) {
+    constexpr int T = Plan<N, V>::T, E = Plan<N, V>::E;
+#pragma unroll
+    for (int m = 0; m < E; ++m) z[m] = slot_in_band<N, V>(m) ? herm_pair<N, DX>(A, B, t + T * m) : czero();
 }
 
 // Forward transform z of a + i b (a, b real) is split into the half spectra
 // of a and b:  Ahat[k] = (Z[k] + conj Z[N-k]) / 2,  Bhat[k] = (Z[k] - conj Z[N-k]) / (2i).
 // Stores kx = 0..K of both.  Called by every thread of the workgroup.
-template <int N, int V>
+template <int N, int V, bool WL>
 __device__ __forceinline__ void split_store(const cd* z, int t, cd* lds, cd* __restrict__ outA,
-                                            cd* __restrict__ outB, int K) {
-    constexpr int T = Plan<N, V>::T, E = Plan<N, V>::E;
+                                            cd* __restrict__ outB) {
+    constexpr int T = Plan<N, V>::T, E = Plan<N, V>::E, K = band<N>();
 #pragma unroll
     for (int m = 0; m < E; ++m) lds[lpad(t + T * m)] = z[m];
-    lds_sync();
+    team_sync<WL>();
 #pragma unroll
     for (int m = 0; m < E; ++m) {
         const int k = t + T * m;
-        if (k <= K) {
+        if (slot_low<N, V>(m) && k <= K) {
             const cd zk = z[m];
             const cd zn = lds[lpad((N - k) & (N - 1))];
             outA[k] = mk(0.5 * (zk.x + zn.x), 0.5 * (zk.y - zn.y));
             outB[k] = mk(0.5 * (zk.y + zn.y), -0.5 * (zk.x - zn.x));
         }
     }
-    lds_sync();
+    team_sync<WL>();
 }
 
 // Team sum (fixed order) of one double per thread; result valid in thread t == 0.
-template <int N, int V>
+template <int N, int V, bool WL>
 __device__ __forceinline__ double team_sum(double v, int t, cd* lds) {
     constexpr int T = Plan<N, V>::T;
     lds[t] = mk(v, 0.0);
-    lds_sync();
+    team_sync<WL>();
     double s = 0.0;
     if (t == 0)
         for (int i = 0; i < T; ++i) s += lds[i].x;
-    lds_sync();
+    team_sync<WL>();
     return s;
 }
 
@@ -121,9 +135,13 @@ __device__ __forceinline__ void store_jpart(const RowObs& o, int b, int y, doubl
 
 // A workgroup holds `tpb` teams; the launcher guarantees tpb divides the
 // teams per member, so the member index is uniform over the workgroup and
-// member base pointers live in scalar registers (32-bit lane offsets).
+// member base pointers live in scalar registers (32-bit lane offsets).  A
+// team of at most 64 threads lies within one wavefront (WL): its exchanges
+// synchronise the wave only, and the one workgroup barrier is the twiddle
+// staging.
 #define PA_TEAM_SETUP(N, V, TEAMS_PER_MEMBER)                           \
     constexpr int T = Plan<N, V>::T, E = Plan<N, V>::E;                 \
+    constexpr bool WL = T <= 64 && 64 % T == 0;                         \
     extern __shared__ cd smem[];                                        \
     const int team = threadIdx.x / T, t = threadIdx.x % T;              \
     cd* lds = smem + team * lds_team<N>();                              \
@@ -150,9 +168,9 @@ __global__ void __launch_bounds__(256) row_r2c_kernel(Dims d, const double* __re
         z[m] = mk(r0[ro + x], r0[ro + N + x]);
     }
     const cd* twl = stage_twiddles<N>(tw_lds, tw_g);
-    fft<N, V, false>(z, t, lds, twl);
-    cd* o0 = out + ((size_t)b * N + 2 * wi) * d.KXP;
-    split_store<N, V>(z, t, lds, o0, o0 + d.KXP, d.K);
+    fft<N, V, false, WL>(z, t, lds, twl);
+    cd* o0 = out + ((size_t)b * N + 2 * wi) * kx_pad<N>();
+    split_store<N, V, WL>(z, t, lds, o0, o0 + kx_pad<N>());
 }
 
 // Y rows (y0, y0+1) -> physical rows.
@@ -160,12 +178,11 @@ template <int N, int V>
 __global__ void __launch_bounds__(256) row_c2r_kernel(Dims d, const cd* __restrict__ in,
                                                       double* __restrict__ out, const cd* __restrict__ tw_g) {
     PA_TEAM_SETUP(N, V, N / 2)
-    const cd* i0 = in + ((size_t)b * N + 2 * wi) * d.KXP;
+    const cd* i0 = in + ((size_t)b * N + 2 * wi) * kx_pad<N>();
     cd z[E];
-#pragma unroll
-    for (int m = 0; m < E; ++m) z[m] = herm_pair(i0, i0 + d.KXP, t + T * m, N, d.K);
+    herm_load<N, V>(z, i0, i0 + kx_pad<N>(), t);
     const cd* twl = stage_twiddles<N>(tw_lds, tw_g);
-    fft<N, V, true>(z, t, lds, twl);
+    fft<N, V, true, WL>(z, t, lds, twl);
     double* r0 = out + ((size_t)b * N + 2 * w0) * N;
     const int ro = 2 * team * N;
 #pragma unroll
@@ -176,48 +193,51 @@ __global__ void __launch_bounds__(256) row_c2r_kernel(Dims d, const cd* __restri
     }
 }
 
-// Right-hand side products of one row:  q = u w_x + v w_y  (+ observation).
-// Inputs yin[0..3] = U, V, Wx, Wy (Y layout), output yout[0] = row transform
-// of q.  Every input load is issued before the first transform, so the
-// memory latency is paid once per kernel rather than once per transform.
-template <int N, int V>
-__global__ void __launch_bounds__(256) row_nl_kernel(Dims d, RowArgs a) {
+// Right-hand side products of one row:  q = u w_x + v w_y  (+ observation
+// when OBS).  Inputs yin[0..3] = U, V, Wx, Wy (Y layout), output yout[0] =
+// row transform of q.  Every input load is issued before the first transform,
+// so the memory latency is paid once per kernel rather than once per
+// transform.  The observing variant is a separate instantiation so that the
+// plain one carries none of its index arithmetic or registers.
+template <int N, int V, bool OBS>
+__device__ __forceinline__ void row_nl_body(const Dims& d, const RowArgs& a) {
     const cd* __restrict__ tw_g = a.tw;
     PA_TEAM_SETUP(N, V, N)
     const int y = wi;
-    const size_t roff = ((size_t)b * N + y) * d.KXP;
-    const bool obs = a.obs.slot >= 0;
+    const size_t roff = ((size_t)b * N + y) * kx_pad<N>();
     cd z1[E], z2[E];
-#pragma unroll
-    for (int m = 0; m < E; ++m) {
-        z1[m] = herm_pair(a.yin[0] + roff, a.yin[2] + roff, t + T * m, N, d.K);   // u + i w_x
-        z2[m] = herm_pair(a.yin[1] + roff, a.yin[3] + roff, t + T * m, N, d.K);   // v + i w_y
-    }
+    herm_load<N, V>(z1, a.yin[0] + roff, a.yin[2] + roff, t);   // u + i w_x
+    herm_load<N, V>(z2, a.yin[1] + roff, a.yin[3] + roff, t);   // v + i w_y
     const cd* twl = stage_twiddles<N>(tw_lds, tw_g);
     double part = 0.0;
-    fft<N, V, true>(z1, t, lds, twl);
-    fft<N, V, true>(z2, t, lds, twl);
+    fft<N, V, true, WL>(z1, t, lds, twl);
+    fft<N, V, true, WL>(z2, t, lds, twl);
     cd z[E];
 #pragma unroll
     for (int m = 0; m < E; ++m) {
-        if (obs) {
+        if (OBS) {
             part += observe_comp(a.obs, b, y, t + T * m, 0, z1[m].x);
             part += observe_comp(a.obs, b, y, t + T * m, 1, z2[m].x);
         }
         z[m] = mk(z1[m].x * z1[m].y + z2[m].x * z2[m].y, 0.0);
     }
-    if (obs) {
-        const double s = team_sum<N, V>(part, t, lds);
+    if (OBS) {
+        const double s = team_sum<N, V, WL>(part, t, lds);
         if (t == 0) store_jpart(a.obs, b, y, s);
     }
-    fft<N, V, false>(z, t, lds, twl);
+    fft<N, V, false, WL>(z, t, lds, twl);
     cd* o = a.yout[0] + roff;
 #pragma unroll
     for (int m = 0; m < E; ++m) {
         const int k = t + T * m;
-        if (k <= d.K) o[k] = z[m];
+        if (slot_low<N, V>(m) && k <= band<N>()) o[k] = z[m];
     }
 }
+
+template <int N, int V>
+__global__ void __launch_bounds__(256) row_nl_kernel(Dims d, RowArgs a) { row_nl_body<N, V, false>(d, a); }
+template <int N, int V>
+__global__ void __launch_bounds__(256) row_nl_obs_kernel(Dims d, RowArgs a) { row_nl_body<N, V, true>(d, a); }
 
 // Observation only (final time): team per observed row; yin[0..1] = U, V.
 template <int N, int V>
@@ -225,21 +245,26 @@ __global__ void __launch_bounds__(256) row_obs_kernel(Dims d, RowArgs a) {
     const cd* __restrict__ tw_g = a.tw;
     PA_TEAM_SETUP(N, V, a.obs.M)
     const int y = wi * a.obs.stride;
-    const size_t roff = ((size_t)b * N + y) * d.KXP;
+    const size_t roff = ((size_t)b * N + y) * kx_pad<N>();
     cd z[E];
-#pragma unroll
-    for (int m = 0; m < E; ++m) z[m] = herm_pair(a.yin[0] + roff, a.yin[1] + roff, t + T * m, N, d.K);
+    herm_load<N, V>(z, a.yin[0] + roff, a.yin[1] + roff, t);
     const cd* twl = stage_twiddles<N>(tw_lds, tw_g);
-    fft<N, V, true>(z, t, lds, twl);
+    fft<N, V, true, WL>(z, t, lds, twl);
     double part = 0.0;
 #pragma unroll
     for (int m = 0; m < E; ++m) {
         part += observe_comp(a.obs, b, y, t + T * m, 0, z[m].x);
         part += observe_comp(a.obs, b, y, t + T * m, 1, z[m].y);
     }
-    const double s = team_sum<N, V>(part, t, lds);
+    const double s = team_sum<N, V, WL>(part, t, lds);
     if (t == 0) store_jpart(a.obs, b, y, s);
 }
+
+// Occupancy hint for the adjoint row pass: with 8 register slots per thread
+// its three input signals fit the 168 VGPRs of three waves per SIMD (a couple
+// of spilled values at most); with 16 slots the hint would spill heavily.
+template <int N, int V>
+constexpr int adj_waves() { return Plan<N, V>::E <= 8 ? 3 : 1; }
 
 // Adjoint products of one row.  The transpose of the tangent right-hand side
 // applied to lambda, with Lam = P lambda, is on the de-aliased band
@@ -249,28 +274,26 @@ __global__ void __launch_bounds__(256) row_obs_kernel(Dims d, RowArgs a) {
 // state, yin[4] = Lam, yin[5] = Lam_y (Y layout).  Outputs: yout[0] = row
 // transform of G1 = w_x Lam_y - w_y Lam_x, yout[1] = of G2 = u Lam_x + v Lam_y.
 template <int N, int V>
-__global__ void __launch_bounds__(256) row_adj_kernel(Dims d, RowArgs a) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(adj_waves<N, V>())))
+row_adj_kernel(Dims d, RowArgs a) {
     const cd* __restrict__ tw_g = a.tw;
     PA_TEAM_SETUP(N, V, N)
     const int y = wi;
-    const size_t roff = ((size_t)b * N + y) * d.KXP;
+    const size_t roff = ((size_t)b * N + y) * kx_pad<N>();
     cd L[E], z1[E], z2[E];   // (Lam_x, Lam_y), (u, w_x), (v, w_y)
-#pragma unroll
-    for (int m = 0; m < E; ++m) {
-        L[m] = herm_pair_dxA(a.yin[4] + roff, a.yin[5] + roff, t + T * m, N, d.K);
-        z1[m] = herm_pair(a.yin[0] + roff, a.yin[2] + roff, t + T * m, N, d.K);
-        z2[m] = herm_pair(a.yin[1] + roff, a.yin[3] + roff, t + T * m, N, d.K);
-    }
+    herm_load<N, V, true>(L, a.yin[4] + roff, a.yin[5] + roff, t);
+    herm_load<N, V>(z1, a.yin[0] + roff, a.yin[2] + roff, t);
+    herm_load<N, V>(z2, a.yin[1] + roff, a.yin[3] + roff, t);
     const cd* twl = stage_twiddles<N>(tw_lds, tw_g);
-    fft<N, V, true>(L, t, lds, twl);
-    fft<N, V, true>(z1, t, lds, twl);
-    fft<N, V, true>(z2, t, lds, twl);
+    fft<N, V, true, WL>(L, t, lds, twl);
+    fft<N, V, true, WL>(z1, t, lds, twl);
+    fft<N, V, true, WL>(z2, t, lds, twl);
     cd G[E];   // (G1, G2)
 #pragma unroll
     for (int m = 0; m < E; ++m)
         G[m] = mk(z1[m].y * L[m].y - z2[m].y * L[m].x, z1[m].x * L[m].x + z2[m].x * L[m].y);
-    fft<N, V, false>(G, t, lds, twl);
-    split_store<N, V>(G, t, lds, a.yout[0] + roff, a.yout[1] + roff, d.K);
+    fft<N, V, false, WL>(G, t, lds, twl);
+    split_store<N, V, WL>(G, t, lds, a.yout[0] + roff, a.yout[1] + roff);
 }
 
 // Adjoint source rows.  mode 0: observation residual at one observed step
@@ -281,15 +304,14 @@ __global__ void __launch_bounds__(256) row_src_kernel(Dims d, RowArgs a, int imp
     const cd* __restrict__ tw_g = a.tw;
     PA_TEAM_SETUP(N, V, N)
     const int y = wi;
-    const size_t roff = ((size_t)b * N + y) * d.KXP;
+    const size_t roff = ((size_t)b * N + y) * kx_pad<N>();
     const RowObs& o = a.obs;
     cd z[E];
     if (!impulse) {
-#pragma unroll
-        for (int m = 0; m < E; ++m) z[m] = herm_pair(a.yin[0] + roff, a.yin[1] + roff, t + T * m, N, d.K);
+        herm_load<N, V>(z, a.yin[0] + roff, a.yin[1] + roff, t);
     }
     const cd* twl = stage_twiddles<N>(tw_lds, tw_g);
-    if (!impulse) fft<N, V, true>(z, t, lds, twl);
+    if (!impulse) fft<N, V, true, WL>(z, t, lds, twl);
 #pragma unroll
     for (int m = 0; m < E; ++m) {
         const int x = t + T * m;
@@ -304,8 +326,8 @@ __global__ void __launch_bounds__(256) row_src_kernel(Dims d, RowArgs a, int imp
         }
         z[m] = mk(A, Bv);
     }
-    fft<N, V, false>(z, t, lds, twl);
-    split_store<N, V>(z, t, lds, a.yout[0] + roff, a.yout[1] + roff, d.K);
+    fft<N, V, false, WL>(z, t, lds, twl);
+    split_store<N, V, WL>(z, t, lds, a.yout[0] + roff, a.yout[1] + roff);
 }
 
 // ---------------------------------------------------------- column pass --
@@ -328,7 +350,7 @@ __global__ void __launch_bounds__(256) col_kernel(Dims d, ColArgs a) {
     const int b = blockIdx.y;
     const int kx0 = blockIdx.x * CB;           // uniform first column of the block
     const int kx = kx0 + c;
-    const int K = d.K, KXP = d.KXP, KY = d.KY;
+    constexpr int K = band<N>(), KXP = kx_pad<N>(), KY = 2 * K + 1;
     const bool colok = kx <= K;
     // uniform bases (scalar registers) + 32-bit lane offsets
     const size_t ymem = (size_t)b * N * KXP + kx0;
@@ -339,23 +361,33 @@ __global__ void __launch_bounds__(256) col_kernel(Dims d, ColArgs a) {
     const double ex = a.ex2[kx];
     const double h = a.h;
     auto yoff = [&](int m) { return ylane + (unsigned)(t + T * m) * (unsigned)KXP; };
-    auto rowof = [&](int m) { return colok ? band_row(t + T * m, N, K, KY) : -1; };
+    // compact row of slot m, -1 off the band (gap slots fold to -1 at compile time)
+    auto rowof = [&](int m) { return (slot_in_band<N, V>(m) && colok) ? band_row(t + T * m, N, K, KY) : -1; };
     auto inS = [&](int r) { return r >= 0 && !(kx == 0 && r == 0); };
     auto cidx = [&](int r) { return (unsigned)c + (unsigned)r * (unsigned)KXP; };
 
-    // ---- issue every global load first: input column(s) and compact operands
+    // ---- issue every global load first: input column(s) and compact operands.
+    // Loads are unconditional at in-bounds addresses (padding columns kx < KXP,
+    // compact row 0 for rows off the band) and their results selected, so no
+    // load sits in a branch.
     cd v0[E];          // first input column
     cd v1[E];          // second input column (adjoint)
     cd s0[E], s1[E];   // compact operands: (omega_n, acc) forward, (lambda, omega-bar) adjoint
     if constexpr (MODE != COL_FROM_STATE) {
         const cd* __restrict__ src = a.yin[0] + ymem;
 #pragma unroll
-        for (int m = 0; m < E; ++m) v0[m] = colok ? ldc(src, yoff(m)) : czero();
+        for (int m = 0; m < E; ++m) {
+            const cd x = ldc(src, yoff(m));
+            v0[m] = colok ? x : czero();
+        }
     }
     if constexpr (ADJ || MODE == COL_FIRST_GUESS) {
         const cd* __restrict__ src = a.yin[1] + ymem;
 #pragma unroll
-        for (int m = 0; m < E; ++m) v1[m] = colok ? ldc(src, yoff(m)) : czero();
+        for (int m = 0; m < E; ++m) {
+            const cd x = ldc(src, yoff(m));
+            v1[m] = colok ? x : czero();
+        }
     }
     if constexpr (FWD_STAGE || ADJ || MODE == COL_FROM_STATE) {
         const cd* __restrict__ p0 = FWD_STAGE ? a.omega + cmem : ADJ ? a.lam + cmem : a.state_in + cmem;
@@ -364,9 +396,19 @@ __global__ void __launch_bounds__(256) col_kernel(Dims d, ColArgs a) {
         const bool need0 = !(ADJ && (MODE == COL_ADJ_N || MODE == COL_ADJ_SRC));
 #pragma unroll
         for (int m = 0; m < E; ++m) {
+            s0[m] = czero();
+            s1[m] = czero();
+            if (!slot_in_band<N, V>(m)) continue;
             const int r = rowof(m);
-            s0[m] = (need0 && r >= 0) ? ldc(p0, cidx(r)) : czero();
-            s1[m] = (need1 && r >= 0) ? ldc(p1, cidx(r)) : czero();
+            const unsigned ci = cidx(r >= 0 ? r : 0);
+            if (need0) {
+                const cd x = ldc(p0, ci);
+                s0[m] = r >= 0 ? x : czero();
+            }
+            if (need1) {
+                const cd x = ldc(p1, ci);
+                s1[m] = r >= 0 ? x : czero();
+            }
         }
     }
     const cd* twl = stage_twiddles<N>(smem + CB * lds_team<N>(), a.tw);
@@ -472,7 +514,10 @@ __global__ void __launch_bounds__(256) col_kernel(Dims d, ColArgs a) {
         for (int p = 2; p < a.nin; ++p) {
             const cd* __restrict__ src = a.yin[p] + ymem;
 #pragma unroll
-            for (int m = 0; m < E; ++m) v0[m] = colok ? ldc(src, yoff(m)) : czero();
+            for (int m = 0; m < E; ++m) {
+                const cd x = ldc(src, yoff(m));
+                v0[m] = colok ? x : czero();
+            }
             fft<N, V, false>(v0, t, lds, twl);
             accumulate(v0, a.inmul[p]);
         }
@@ -586,6 +631,7 @@ hipError_t Launch<N>::row_c2r(const Dims& d, const cd* in, double* out, const cd
 }
 template <int N>
 hipError_t Launch<N>::row_nl(const Dims& d, const RowArgs& a, hipStream_t s) {
+    if (a.obs.slot >= 0) PA_ROW_LAUNCH(row_nl_obs_kernel, N, d, a);
     PA_ROW_LAUNCH(row_nl_kernel, N, d, a);
 }
 template <int N>
