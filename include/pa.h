@@ -150,8 +150,9 @@ pa_status pa_init_field(pa_ctx* ctx, const uint64_t* seeds, int32_t kind, double
  *   obs      observation set; with obs->values the cost J is computed
  *   J_out    device [B]         cost per member (needs obs->values)
  *   obs_out  device [B][n_times][2][M][M]  model observations M u
- *   ckpt     device, pa_checkpoint_bytes: spectral states every ckpt_every
- *            steps, the input of pa_adjoint_from_checkpoints. */
+ *   ckpt     device, pa_checkpoint_bytes, 16-byte aligned (PA_EINVAL
+ *            otherwise): spectral states every ckpt_every steps, the input
+ *            of pa_adjoint_from_checkpoints. */
 pa_status pa_forward(pa_ctx* ctx, const double* omega0, int32_t n_steps,
                      const pa_obs* obs, double* J_out, double* obs_out, double* omega_T,
                      int32_t ckpt_every, void* ckpt, void* workspace, size_t workspace_bytes);
@@ -164,8 +165,9 @@ pa_status pa_adjoint_gradient(pa_ctx* ctx, const double* omega0, int32_t n_steps
                               int32_t ckpt_every, void* workspace, size_t workspace_bytes);
 
 /* Same gradient from the checkpoints a previous pa_forward wrote (same
- * n_steps, ckpt_every, obs steps).  scale: device [B] or NULL; the gradient of
- * member b is multiplied by scale[b] (the autograd backward's grad_output). */
+ * n_steps, ckpt_every, obs steps; ckpt 16-byte aligned).  scale: device [B]
+ * or NULL; the gradient of member b is multiplied by scale[b] (the autograd
+ * backward's grad_output). */
 pa_status pa_adjoint_from_checkpoints(pa_ctx* ctx, const void* ckpt, int32_t n_steps,
                                       const pa_obs* obs, const double* scale,
                                       double* grad_out, int32_t ckpt_every,

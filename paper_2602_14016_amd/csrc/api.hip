@@ -809,6 +809,7 @@ pa_status pa_forward(pa_ctx* c, const double* omega0, int32_t n_steps, const pa_
     if (!c || !omega0) return fail(PA_EINVAL, "NULL argument");
     if (n_steps < 0) return fail(PA_EINVAL, "n_steps must be >= 0");
     if (ckpt_every < 1) return fail(PA_EINVAL, "ckpt_every must be >= 1");
+    if (reinterpret_cast<uintptr_t>(ckpt) % 16) return fail(PA_EINVAL, "checkpoint buffer must be 16-byte aligned");
     if (J_out && (!obs || !obs->values)) return fail(PA_EINVAL, "J_out needs observation values");
     if (obs_out && !obs) return fail(PA_EINVAL, "obs_out needs observations");
     ObsPlan op;
@@ -830,6 +831,7 @@ pa_status pa_adjoint_from_checkpoints(pa_ctx* c, const void* ckpt, int32_t n_ste
                                       size_t wbytes) {
     g_err.clear();
     if (!c || !ckpt || !grad_out) return fail(PA_EINVAL, "NULL argument");
+    if (reinterpret_cast<uintptr_t>(ckpt) % 16) return fail(PA_EINVAL, "checkpoint buffer must be 16-byte aligned");
     if (n_steps < 0 || ckpt_every < 1) return fail(PA_EINVAL, "bad sizes");
     ObsPlan op;
     PA_TRY(make_obs_plan(c, obs, n_steps, true, &op));

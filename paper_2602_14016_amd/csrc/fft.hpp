@@ -12,14 +12,17 @@
 // loads/stores of a contiguous signal are coalesced across the team.
 //
 // Direction: forward uses exp(-2 pi i jk/N) (unnormalised), inverse
-// exp(+2 pi i jk/N) (unnormalised).  Inter-stage twiddles come from a table
-// tw[m] = exp(-2 pi i m / N), m < N, precomputed on the host.
+// exp(+2 pi i jk/N) (unnormalised).  Inter-stage twiddles come from a
+// stage-ordered table in LDS (see twiddle_source) filled from the natural
+// table exp(-2 pi i m / N), m < N, precomputed on the host.
 #pragma once
 #include <hip/hip_runtime.h>
 
 namespace pa {
 
-struct cd { double x, y; };
+// 16-byte aligned so that LDS and global accesses of one value are single
+// 128-bit operations (ds_read_b128: a lane covers four consecutive banks).
+struct alignas(16) cd { double x, y; };
 
 // Workgroup barrier for LDS hand-offs only: waits for this wave's LDS
 // operations, then meets the other waves.  Unlike __syncthreads() it does not
@@ -197,6 +200,24 @@ template <int N>
 __host__ __device__ constexpr int lds_team() { return N + N / 16 + 1; }
 __device__ __forceinline__ int lpad(int i) { return i + (i >> 4); }
 
+// Stage-ordered twiddle table.  The factor exp(-2 pi i r k / (S R)) of the
+// stage with span S and radix R (1 <= r < R, 0 <= k < S) sits at r S + k - 1;
+// the stages' ranges [S - 1, S R - 1) tile [0, N - 1).  Lanes of a stage hold
+// consecutive k, so they read consecutive entries (no bank conflicts), where
+// the natural table indexed by r k N / (S R) puts them on a few banks.
+// Returns the natural-table index of stage-ordered entry n.
+template <int N, int V>
+__host__ __device__ constexpr int twiddle_source(int n) {
+    using P = Plan<N, V>;
+    int S = 1;
+    for (int s = 0; s < P::NS; ++s) {
+        const int R = P::R[s];
+        if (n + 1 < S * R) return ((n + 1) / S) * ((n + 1) % S) * (N / (S * R));
+        S *= R;
+    }
+    return 0;
+}
+
 // One Stockham stage: radix R, span S (product of the radices already done).
 template <int N, int V, int R, int S, bool INV, bool LAST, bool WL>
 __device__ __forceinline__ void fft_stage(cd* v, int t, cd* lds, const cd* __restrict__ tw) {
@@ -209,10 +230,9 @@ __device__ __forceinline__ void fft_stage(cd* v, int t, cd* lds, const cd* __res
         for (int r = 0; r < R; ++r) u[r] = v[b + r * NB];
         if constexpr (S > 1) {
             const int k = j % S;
-            constexpr int step = N / (S * R);
 #pragma unroll
             for (int r = 1; r < R; ++r) {
-                const cd w = tw[r * k * step];
+                const cd w = tw[r * S + k - 1];
                 u[r] = INV ? cmulc(u[r], w) : cmul(u[r], w);
             }
         }

@@ -25,12 +25,12 @@ __device__ __forceinline__ void stc(cd* base, unsigned i, cd v) {
     *reinterpret_cast<cd*>(reinterpret_cast<char*>(base) + (i << 4)) = v;
 }
 
-// The twiddle table is copied into LDS at kernel start: reads after a
-// barrier are not hoisted out of loops, so they do not pin registers across
-// the successive transforms of a kernel.
-template <int N>
+// The twiddle table is copied into LDS at kernel start, in the stage order of
+// the plan: reads after a barrier are not hoisted out of loops, so they do
+// not pin registers across the successive transforms of a kernel.
+template <int N, int V>
 __device__ __forceinline__ const cd* stage_twiddles(cd* lds_tw, const cd* __restrict__ tw) {
-    for (int i = threadIdx.x; i < N; i += blockDim.x) lds_tw[i] = tw[i];
+    for (int i = threadIdx.x; i < N; i += blockDim.x) lds_tw[i] = tw[twiddle_source<N, V>(i)];
     lds_sync();
     return lds_tw;
 }
@@ -167,7 +167,7 @@ __global__ void __launch_bounds__(256) row_r2c_kernel(Dims d, const double* __re
         const int x = t + T * m;
         z[m] = mk(r0[ro + x], r0[ro + N + x]);
     }
-    const cd* twl = stage_twiddles<N>(tw_lds, tw_g);
+    const cd* twl = stage_twiddles<N, V>(tw_lds, tw_g);
     fft<N, V, false, WL>(z, t, lds, twl);
     cd* o0 = out + ((size_t)b * N + 2 * wi) * kx_pad<N>();
     split_store<N, V, WL>(z, t, lds, o0, o0 + kx_pad<N>());
@@ -181,7 +181,7 @@ __global__ void __launch_bounds__(256) row_c2r_kernel(Dims d, const cd* __restri
     const cd* i0 = in + ((size_t)b * N + 2 * wi) * kx_pad<N>();
     cd z[E];
     herm_load<N, V>(z, i0, i0 + kx_pad<N>(), t);
-    const cd* twl = stage_twiddles<N>(tw_lds, tw_g);
+    const cd* twl = stage_twiddles<N, V>(tw_lds, tw_g);
     fft<N, V, true, WL>(z, t, lds, twl);
     double* r0 = out + ((size_t)b * N + 2 * w0) * N;
     const int ro = 2 * team * N;
@@ -208,7 +208,7 @@ __device__ __forceinline__ void row_nl_body(const Dims& d, const RowArgs& a) {
     cd z1[E], z2[E];
     herm_load<N, V>(z1, a.yin[0] + roff, a.yin[2] + roff, t);   // u + i w_x
     herm_load<N, V>(z2, a.yin[1] + roff, a.yin[3] + roff, t);   // v + i w_y
-    const cd* twl = stage_twiddles<N>(tw_lds, tw_g);
+    const cd* twl = stage_twiddles<N, V>(tw_lds, tw_g);
     double part = 0.0;
     fft<N, V, true, WL>(z1, t, lds, twl);
     fft<N, V, true, WL>(z2, t, lds, twl);
@@ -248,7 +248,7 @@ __global__ void __launch_bounds__(256) row_obs_kernel(Dims d, RowArgs a) {
     const size_t roff = ((size_t)b * N + y) * kx_pad<N>();
     cd z[E];
     herm_load<N, V>(z, a.yin[0] + roff, a.yin[1] + roff, t);
-    const cd* twl = stage_twiddles<N>(tw_lds, tw_g);
+    const cd* twl = stage_twiddles<N, V>(tw_lds, tw_g);
     fft<N, V, true, WL>(z, t, lds, twl);
     double part = 0.0;
 #pragma unroll
@@ -284,7 +284,7 @@ row_adj_kernel(Dims d, RowArgs a) {
     herm_load<N, V, true>(L, a.yin[4] + roff, a.yin[5] + roff, t);
     herm_load<N, V>(z1, a.yin[0] + roff, a.yin[2] + roff, t);
     herm_load<N, V>(z2, a.yin[1] + roff, a.yin[3] + roff, t);
-    const cd* twl = stage_twiddles<N>(tw_lds, tw_g);
+    const cd* twl = stage_twiddles<N, V>(tw_lds, tw_g);
     fft<N, V, true, WL>(L, t, lds, twl);
     fft<N, V, true, WL>(z1, t, lds, twl);
     fft<N, V, true, WL>(z2, t, lds, twl);
@@ -310,7 +310,7 @@ __global__ void __launch_bounds__(256) row_src_kernel(Dims d, RowArgs a, int imp
     if (!impulse) {
         herm_load<N, V>(z, a.yin[0] + roff, a.yin[1] + roff, t);
     }
-    const cd* twl = stage_twiddles<N>(tw_lds, tw_g);
+    const cd* twl = stage_twiddles<N, V>(tw_lds, tw_g);
     if (!impulse) fft<N, V, true, WL>(z, t, lds, twl);
 #pragma unroll
     for (int m = 0; m < E; ++m) {
@@ -411,7 +411,7 @@ __global__ void __launch_bounds__(256) col_kernel(Dims d, ColArgs a) {
             }
         }
     }
-    const cd* twl = stage_twiddles<N>(smem + CB * lds_team<N>(), a.tw);
+    const cd* twl = stage_twiddles<N, V>(smem + CB * lds_team<N>(), a.tw);
 
     cd w[E];   // spectral values handed to the output transforms
 
