@@ -4,14 +4,17 @@
 One step = one complete batched forward + adjoint solve of the ensemble
 workload: 64 independent realizations of 256^2 decaying 2D turbulence (k0 =
 10 random-phase spectrum, energy 0.5, seeds 0..63), nu = 1e-4, dt = 2e-3,
-500 forward steps with checkpoints every 50, segment recomputation, 500
-adjoint steps from a unit u-impulse at (128, 128), per-shell adjoint energy
-for |k| in 1..85 after every adjoint step.  Inputs are resident in HBM before
-the timed region.  value = members * N^2 * horizon * steps / seconds
+500 forward steps, 500 adjoint steps from a unit u-impulse at (128, 128),
+per-shell adjoint energy for |k| in 1..85 after every adjoint step.  The
+checkpoint interval defaults to the largest whose workspace fits in free HBM:
+on a 288 GB device the whole stage trajectory of the 64 members (about 185 GB)
+stays resident, so the adjoint needs no recomputation (--ckpt-every 50 gives
+the checkpointed form).  Inputs are resident in HBM before the timed region.  value = members * N^2 * horizon * steps / seconds
 (grid-point-steps/s, each unit one point advanced one forward and one adjoint
 step).  Beside it: the plain path (one member per solve, same kernels),
 p50/p99 solve latency, the roofline of the dominant kernel measured with HIP
-events on its stream, and the CPU oracle timed on a bounded sample.
+events on its stream, the solve replayed from a captured HIP graph, and the
+CPU oracle timed on a bounded sample.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -117,15 +120,19 @@ def main():
     ap.add_argument("--members", type=int, default=64)
     ap.add_argument("--N", type=int, default=256)
     ap.add_argument("--horizon", type=int, default=500)
-    ap.add_argument("--ckpt-every", type=int, default=50)
+    ap.add_argument("--ckpt-every", type=int, default=0,
+                    help="checkpoint interval; 0 = the largest that fits in free HBM (the whole horizon if possible)")
     ap.add_argument("--plain-solves", type=int, default=4)
     ap.add_argument("--roofline-class", type=int, default=2)
     ap.add_argument("--sample-every", type=int, default=8)
     ap.add_argument("--cpu-steps", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--graph-replays", type=int, default=3,
+                    help="also capture the batched solve in a HIP graph and time this many replays (0: skip)")
     ap.add_argument("--col-block", type=int, default=0)
     ap.add_argument("--row-teams", type=int, default=0)
-    ap.add_argument("--fft-variant", type=int, default=-1)
+    ap.add_argument("--row-variant", type=int, default=-1)
+    ap.add_argument("--col-variant", type=int, default=-1)
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one torch copy of this many MiB first (HBM counter calibration)")
@@ -141,7 +148,7 @@ def main():
     import torch
     from paper_2602_14016_amd import Solver
 
-    N, B, H, K = args.N, args.members, args.horizon, args.ckpt_every
+    N, B, H = args.N, args.members, args.horizon
     nu, dt, k0 = 1e-4, 2e-3, 10.0
     nshell = (N - 1) // 3
     ix = iy = N // 2
@@ -161,17 +168,32 @@ def main():
     s = Solver(N, B, nu=nu, dt=dt, device=dev)
     w0 = s.init_field(list(range(B)), kind=0, k0=k0, target=0.5)
     torch.cuda.synchronize()
-    manual = args.col_block or args.row_teams or args.fft_variant >= 0
-    if manual or args.no_autotune:
-        s.set_tiles(args.col_block, args.row_teams, args.fft_variant)
-        tiles = {"col_block": args.col_block, "row_teams": args.row_teams, "fft_variant": args.fft_variant,
-                 "autotuned": False}
-    else:
-        at = autotune(s, w0, n_steps=16, ckpt_every=8)
-        tiles = {k: at[k] for k in ("fft_variant", "col_block", "row_teams")}
-        tiles["autotuned"] = True
-        tiles["trials"] = [(r["fft_variant"], r["col_block"], r["row_teams"], round(r["ms"], 3)) for r in at["trials"]]
-        print("autotune", json.dumps(tiles), file=sys.stderr, flush=True)
+    knobs = ("row_variant", "row_teams", "col_variant", "col_block")
+    manual = args.col_block or args.row_teams or args.row_variant >= 0 or args.col_variant >= 0
+
+    def tune(solver, omega0):
+        if manual or args.no_autotune:
+            solver.set_tiles(args.col_block, args.row_teams, args.row_variant, args.col_variant)
+            return {k: getattr(args, k) for k in knobs} | {"autotuned": False}
+        at = autotune(solver, omega0, n_steps=16, ckpt_every=8)
+        out = {k: at[k] for k in knobs} | {"autotuned": True}
+        out["trials"] = [[r[k] for k in knobs] + [round(r["ms"], 3)] for r in at["trials"]]
+        print("autotune", json.dumps(out), file=sys.stderr, flush=True)
+        return out
+
+    tiles = tune(s, w0)
+
+    def ckpt_interval(solver):
+        if args.ckpt_every:
+            return args.ckpt_every
+        torch.cuda.empty_cache()
+        k = solver.fit_ckpt_every(H)
+        if k < 1:
+            print("workload does not fit in device memory", file=sys.stderr)
+            sys.exit(1)
+        return k
+
+    K = ckpt_interval(s)
     for _ in range(args.warmup):
         s.adjoint_impulse(w0, H, ix, iy, nshell, ckpt_every=K)
     torch.cuda.synchronize()
@@ -195,11 +217,34 @@ def main():
     elapsed = t1 - t0
     value = B * N * N * H * args.steps / elapsed
 
+    # the same solve captured once into a HIP graph and replayed
+    graph = None
+    if args.graph_replays:
+        from paper_2602_14016_amd.graph import CapturedSolve
+        cap = CapturedSolve(lambda: s.adjoint_impulse(w0, H, ix, iy, nshell, ckpt_every=K))
+        g0 = torch.cuda.Event(enable_timing=True)
+        g1 = torch.cuda.Event(enable_timing=True)
+        g0.record(stream)
+        for _ in range(args.graph_replays):
+            cap.replay()
+        g1.record(stream)
+        torch.cuda.synchronize()
+        gms = g0.elapsed_time(g1) / args.graph_replays
+        graph = {"ms_per_step": gms, "replays": args.graph_replays,
+                 "grid_point_steps_per_s": B * N * N * H / (gms * 1e-3)}
+        del cap
+
     # plain path: one member per solve, same kernels, solved one after another
     p = Solver(N, 1, nu=nu, dt=dt, device=dev)
-    if args.col_block or args.row_teams:
-        p.set_tiles(args.col_block, args.row_teams)
-    p.adjoint_impulse(w0[:1].contiguous(), H, ix, iy, nshell, ckpt_every=K)
+    plain_tiles = None
+    if args.plain_solves:
+        plain_tiles = tune(p, w0[:1].contiguous())
+        plain_tiles.pop("trials", None)
+        s.close()
+        del s
+        Kp = ckpt_interval(p)
+        plain_tiles["ckpt_every"] = Kp
+        p.adjoint_impulse(w0[:1].contiguous(), H, ix, iy, nshell, ckpt_every=Kp)
     torch.cuda.synchronize()
     plain_lat = []
     tp0 = time.perf_counter()
@@ -207,7 +252,7 @@ def main():
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record(stream)
-        p.adjoint_impulse(w0[m:m + 1].contiguous(), H, ix, iy, nshell, ckpt_every=K)
+        p.adjoint_impulse(w0[m:m + 1].contiguous(), H, ix, iy, nshell, ckpt_every=Kp)
         e1.record(stream)
         plain_lat.append((e0, e1))
     torch.cuda.synchronize()
@@ -239,13 +284,16 @@ def main():
         "config": {"workload": f"ensemble of {B} realizations of {N}^2 decaying 2D turbulence "
                                f"(k0={k0:g} random-phase spectrum, energy 0.5, seeds 0..{B - 1}), nu={nu:g}, "
                                f"dt={dt:g}, {H} forward + {H} adjoint steps per member from a unit u-impulse "
-                               f"at ({ix},{iy}), checkpoints every {K}, shell energies |k|=1..{nshell}",
+                               f"at ({ix},{iy}), "
+                               + (f"checkpoints every {K}" if K < H else "whole stage trajectory kept in HBM (no recomputation)")
+                               + f", shell energies |k|=1..{nshell}",
                    "members": B, "grid": N, "horizon": H, "ckpt_every": K},
         "latency_ms": {"batched_p50": percentile(lat_ms, 50), "batched_p99": percentile(lat_ms, 99),
                        "plain_p50": percentile(plain_ms, 50), "plain_p99": percentile(plain_ms, 99)},
-        "plain": {"value": plain_value, "unit": "grid-point-steps/s", "solves": args.plain_solves,
+        "plain": {"value": plain_value, "unit": "grid-point-steps/s", "solves": args.plain_solves, "tiles": plain_tiles,
                   "speedup_batched_over_plain": value / plain_value if plain_value else None},
         "roofline": roofline,
+        "graph": graph,
         "tiles": tiles,
         "cpu_baseline": cpu,
     }

@@ -227,11 +227,16 @@ pa_status pa_shell_growth(pa_ctx* ctx, const double* shells, int32_t rows, int32
 
 /* FFT tile choice for this context (the autotuner's knobs): col_block = kx
  * columns per column-pass workgroup (1, 2, 4 or 8; 0 keeps the current value,
- * reduced if the variant needs it), row_teams = rows per row-pass workgroup
- * (1, 2, 4 or 8; 0 keeps), fft_variant = register plan of the 1D transforms
- * (0: more elements per thread, 1: more threads per transform; -1 keeps).
+ * reduced if the column variant needs it), row_teams = rows per row-pass
+ * workgroup (1, 2, 4 or 8; 0 keeps; capped at 256 threads per workgroup),
+ * row_variant / col_variant = register plan of the 1D transforms of the row
+ * and column passes (0: more elements per thread, 1: more threads per
+ * transform, 2: four elements per thread where the length allows; -1 keeps).
+ * PA_EINVAL for values outside these sets or an explicit col_block that does
+ * not fit (col_block * threads per transform <= 512, LDS <= 64 KiB).
  * Results do not depend on the choice beyond rounding of the transforms. */
-pa_status pa_set_tiles(pa_ctx* ctx, int32_t col_block, int32_t row_teams, int32_t fft_variant);
+pa_status pa_set_tiles(pa_ctx* ctx, int32_t col_block, int32_t row_teams, int32_t row_variant,
+                       int32_t col_variant);
 
 /* Launch timing for measurement: until pa_profile_stop, every sample_every-th
  * launch of one kernel class is bracketed by HIP events recorded on the

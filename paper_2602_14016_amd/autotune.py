@@ -1,15 +1,18 @@
 """Autotuner for the FFT tile shapes of a Solver.
 
-Knobs (pa_set_tiles): the register plan of the 1D transforms (variant 0:
-more elements per thread; 1: more threads per transform), the number of kx
-columns per column-pass workgroup, and the number of rows per row-pass
-workgroup.  Each candidate is timed with HIP events on a short batched
-forward + adjoint solve of the solver's own shape (the same kernels the real
-solve runs); the fastest is applied and returned.  Results depend on the
+Knobs (pa_set_tiles): the register plan of the 1D transforms of the row
+passes and of the column pass (variant 0: more elements per thread; 1: more
+threads per transform; 2: four elements per thread where the length allows),
+the number of rows per row-pass workgroup and the number of kx columns per
+column-pass workgroup.  Each candidate is timed with HIP events on a short
+batched forward + adjoint solve of the solver's own shape (the same kernels
+the real solve runs).  The row and column passes are separate kernels, so the
+search is coordinate-wise: row plan and rows per workgroup first (column
+tiles at their defaults), then column plan and columns per workgroup with the
+best row tiles.  The fastest is applied and returned.  Results depend on the
 choice only through the rounding of the transforms.
 """
 
-import itertools
 import time
 
 import torch
@@ -29,51 +32,47 @@ def _time_solve(solver, omega0, n_steps, ckpt_every, reps):
     return e0.elapsed_time(e1) / reps
 
 
-def candidates(N):
-    variants = [0, 1]
-    cbs = [1, 2, 4, 8]
-    tpbs = [1, 2, 4, 8]
-    return variants, cbs, tpbs
+VARIANTS = (0, 1, 2)
+BLOCKS = (1, 2, 4, 8)
 
 
 def autotune(solver, omega0=None, n_steps=16, ckpt_every=8, reps=2, verbose=False):
-    """Pick (fft_variant, col_block, row_teams) for `solver`; returns a dict."""
+    """Pick (row_variant, row_teams, col_variant, col_block) for `solver`; returns a dict."""
     if omega0 is None:
         omega0 = solver.init_field(list(range(solver.B)), kind=0, k0=max(2.0, solver.N / 25), target=0.5)
-    variants, cbs, tpbs = candidates(solver.N)
     results = []
-    best = None
     t_start = time.perf_counter()
-    for var in variants:
-        # column block first (row teams at 4), then row teams with the best column block
-        local = None
-        for cb in cbs:
-            try:
-                solver.set_tiles(cb, 4, var)
-            except Exception:
+
+    def trial(rv, tpb, cv, cb):
+        try:
+            solver.set_tiles(cb, tpb, rv, cv)
+        except Exception:
+            return None
+        ms = _time_solve(solver, omega0, n_steps, ckpt_every, reps)
+        results.append({"row_variant": rv, "row_teams": tpb, "col_variant": cv, "col_block": cb, "ms": ms})
+        return ms
+
+    best = None
+    for rv in VARIANTS:
+        for tpb in BLOCKS:
+            ms = trial(rv, tpb, 1, 8)
+            if ms is not None and (best is None or ms < best[0]):
+                best = (ms, rv, tpb, 1, 8)
+    _, rv, tpb, _, _ = best
+    for cv in VARIANTS:
+        for cb in BLOCKS:
+            if (cv, cb) == (best[3], best[4]):
                 continue
-            ms = _time_solve(solver, omega0, n_steps, ckpt_every, reps)
-            results.append({"fft_variant": var, "col_block": cb, "row_teams": 4, "ms": ms})
-            if local is None or ms < local[0]:
-                local = (ms, cb, 4)
-        if local is None:
-            continue
-        for tpb in tpbs:
-            if tpb == 4:
-                continue
-            solver.set_tiles(local[1], tpb, var)
-            ms = _time_solve(solver, omega0, n_steps, ckpt_every, reps)
-            results.append({"fft_variant": var, "col_block": local[1], "row_teams": tpb, "ms": ms})
-            if ms < local[0]:
-                local = (ms, local[1], tpb)
-        if best is None or local[0] < best[0]:
-            best = (local[0], local[1], local[2], var)
-    solver.set_tiles(best[1], best[2], best[3])
-    out = {"fft_variant": best[3], "col_block": best[1], "row_teams": best[2], "ms": best[0],
+            ms = trial(rv, tpb, cv, cb)
+            if ms is not None and ms < best[0]:
+                best = (ms, rv, tpb, cv, cb)
+    ms, rv, tpb, cv, cb = best
+    solver.set_tiles(cb, tpb, rv, cv)
+    out = {"row_variant": rv, "row_teams": tpb, "col_variant": cv, "col_block": cb, "ms": ms,
            "trials": results, "seconds": time.perf_counter() - t_start,
            "probe": f"{solver.B} x {solver.N}^2, {n_steps} forward + {n_steps} adjoint steps"}
     if verbose:
         for r in results:
             print("autotune", r)
-        print("autotune best", {k: out[k] for k in ("fft_variant", "col_block", "row_teams", "ms")})
+        print("autotune best", {k: out[k] for k in ("row_variant", "row_teams", "col_variant", "col_block", "ms")})
     return out

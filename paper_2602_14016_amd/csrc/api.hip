@@ -367,12 +367,38 @@ pa_status state_to_phys(pa_ctx* c, WS& w, const cd* state, double* out) {
 }
 
 // Forward sweep with checkpoints into `ckpt` and J into w.J (if values).
+// With store_last (and a segment buffer), the last checkpoint segment runs in
+// store mode: its stage fields go straight to the segment slots, so a
+// backward sweep that follows (last_ready) starts that segment without
+// recomputing it.  With ckpt_every >= n_steps the whole trajectory is kept
+// and the gradient needs no recomputation at all.  The stage fields are the
+// same either way (same kernels, only their output addresses differ).
 pa_status forward_sweep(pa_ctx* c, WS& w, const double* omega0, int n_steps, const ObsPlan& op,
-                        double* obs_out, cd* ckpt, int K) {
-    PA_TRY(start_state(c, w, omega0, ckpt ? ckpt_slot(c, ckpt, 0) : nullptr, w.Yf));
+                        double* obs_out, cd* ckpt, int K, bool store_last) {
+    const bool store = store_last && w.seg && n_steps > 0;
+    const int n_last = store ? (n_segments(n_steps, K) - 1) * K : n_steps;   // first step of the stored segment
     const bool final_obs = op.slot_of[(size_t)n_steps] >= 0;
-    PA_TRY(run_steps(c, w, 0, n_steps, n_steps, K, false, &op, obs_out, ckpt, final_obs));
-    if (final_obs) PA_TRY(observe_final(c, w, op, n_steps, w.Yf, obs_out));
+    cd* f0[4] = {w.Yf[0], w.Yf[1], w.Yf[2], w.Yf[3]};
+    if (store && n_last == 0) seg_fields(c, w, 0, 0, f0);
+    PA_TRY(start_state(c, w, omega0, ckpt ? ckpt_slot(c, ckpt, 0) : nullptr, f0));
+    if (n_last > 0) {
+        PA_TRY(run_steps(c, w, 0, n_last, n_steps, K, false, &op, obs_out, ckpt, !store && final_obs));
+        if (store) {
+            // stage-a fields of the state at n_last (in w.omega) into segment slot (0, 0)
+            cd* s0[4];
+            seg_fields(c, w, 0, 0, s0);
+            ColArgs a = col_base(c);
+            a.state_in = w.omega;
+            set_stage_fields(a, s0);
+            PA_HIP(launch_col(c->d, COL_FROM_STATE, a, c->stream));
+        }
+    }
+    cd* fH[4] = {w.Yf[0], w.Yf[1], w.Yf[2], w.Yf[3]};
+    if (store) {
+        PA_TRY(run_steps(c, w, n_last, n_steps, n_steps, K, true, &op, obs_out, ckpt, true));
+        seg_fields(c, w, n_steps - n_last, 0, fH);
+    }
+    if (final_obs) PA_TRY(observe_final(c, w, op, n_steps, fH, obs_out));
     if (op.values && op.n_times > 0)
         PA_HIP(launch_reduce_j(c->d.B, op.n_times * op.M, w.jpart, w.J, c->stream));
     return PA_OK;
@@ -488,10 +514,13 @@ pa_status terminal(pa_ctx* c, WS& w, const ObsPlan* op, int n_steps, cd* const f
 }
 
 // Backward sweep from checkpoints: recompute each segment storing every
-// stage's fields, then run the adjoint steps of the segment in reverse.  The
-// final field (P lambda_0 times scale) is written to grad_out (physical).
+// stage's fields, then run the adjoint steps of the segment in reverse.  With
+// last_ready the last segment's fields are already in the segment slots (a
+// forward sweep with store_last just ran in this workspace).  The final
+// field (P lambda_0 times scale) is written to grad_out (physical).
 pa_status backward_sweep(pa_ctx* c, WS& w, const cd* ckpt, int n_steps, int K, const ObsPlan* op, int impulse,
-                         int ix, int iy, const double* scale, double* grad_out, const Shells& sh) {
+                         int ix, int iy, const double* scale, double* grad_out, const Shells& sh,
+                         bool last_ready) {
     const int nseg = n_segments(n_steps, K);
     if (n_steps == 0) {
         // no segment buffer exists for a zero horizon: the stage fields of omega_0 go to w.Yf
@@ -514,15 +543,17 @@ pa_status backward_sweep(pa_ctx* c, WS& w, const cd* ckpt, int n_steps, int K, c
     if (!w.seg) return fail(PA_EINVAL, "workspace carved without a segment buffer");
     for (int seg = nseg - 1; seg >= 0; --seg) {
         const int n0 = seg * K, n1 = std::min(n_steps, n0 + K), L = n1 - n0;
-        cd* f0[4];
-        seg_fields(c, w, 0, 0, f0);
-        ColArgs a = col_base(c);
-        a.state_in = ckpt_slot(c, const_cast<cd*>(ckpt), seg);
-        a.omega = w.omega;
-        set_stage_fields(a, f0);
-        PA_HIP(launch_col(c->d, COL_FROM_STATE, a, c->stream));
         const bool last = seg == nseg - 1;
-        PA_TRY(run_steps(c, w, n0, n1, n_steps, K, true, nullptr, nullptr, nullptr, last));
+        if (!(last && last_ready)) {
+            cd* f0[4];
+            seg_fields(c, w, 0, 0, f0);
+            ColArgs a = col_base(c);
+            a.state_in = ckpt_slot(c, const_cast<cd*>(ckpt), seg);
+            a.omega = w.omega;
+            set_stage_fields(a, f0);
+            PA_HIP(launch_col(c->d, COL_FROM_STATE, a, c->stream));
+            PA_TRY(run_steps(c, w, n0, n1, n_steps, K, true, nullptr, nullptr, nullptr, last));
+        }
         if (last) {
             cd* fH[4];
             seg_fields(c, w, L, 0, fH);
@@ -631,8 +662,9 @@ pa_status pa_create(const pa_physics* phys, int32_t N, int32_t B, void* hip_stre
     d.KXP = (d.KX + 7) / 8 * 8;
     d.KY = 2 * d.K + 1;
     d.var = 0;
+    d.cvar = 0;
     d.cb = 8;
-    while (d.cb > 1 && (d.cb * fft_threads(N, d.var) > 256 ||
+    while (d.cb > 1 && (d.cb * fft_threads(N, d.cvar) > 512 ||
                         ((size_t)d.cb * (N + N / 16 + 1) + N) * sizeof(cd) > 65536)) d.cb >>= 1;
     d.tpb = 4;
 
@@ -720,22 +752,28 @@ pa_status pa_get_shape(const pa_ctx* c, int32_t* N, int32_t* B, int32_t* Kc) {
     return PA_OK;
 }
 
-pa_status pa_set_tiles(pa_ctx* c, int32_t col_block, int32_t row_teams, int32_t fft_variant) {
+pa_status pa_set_tiles(pa_ctx* c, int32_t col_block, int32_t row_teams, int32_t row_variant,
+                       int32_t col_variant) {
     if (!c) return fail(PA_EINVAL, "ctx is NULL");
-    if (fft_variant < -1 || fft_variant > 1) return fail(PA_EINVAL, "fft_variant must be -1, 0 or 1");
-    const int var = fft_variant >= 0 ? fft_variant : c->d.var;
-    const int T = fft_threads(c->d.N, var);
+    if (row_variant < -1 || row_variant > 2 || col_variant < -1 || col_variant > 2)
+        return fail(PA_EINVAL, "FFT variants must be -1, 0, 1 or 2");
+    const int rvar = row_variant >= 0 ? row_variant : c->d.var;
+    const int cvar = col_variant >= 0 ? col_variant : c->d.cvar;
+    const int T = fft_threads(c->d.N, cvar);
+    auto col_fits = [&](int cb) {
+        return cb * T <= 512 && ((size_t)cb * (c->d.N + c->d.N / 16 + 1) + c->d.N) * sizeof(cd) <= 65536;
+    };
     int cb = col_block ? col_block : c->d.cb;
     if (cb != 1 && cb != 2 && cb != 4 && cb != 8) return fail(PA_EINVAL, "col_block must be 1, 2, 4 or 8");
     if (!col_block) {
-        while (cb > 1 && (cb * T > 256 || ((size_t)cb * (c->d.N + c->d.N / 16 + 1) + c->d.N) * sizeof(cd) > 65536))
-            cb >>= 1;
-    } else if (cb * T > 256 || ((size_t)cb * (c->d.N + c->d.N / 16 + 1) + c->d.N) * sizeof(cd) > 65536) {
-        return fail(PA_EINVAL, "col_block too large for this N and FFT variant");
+        while (cb > 1 && !col_fits(cb)) cb >>= 1;
+    } else if (!col_fits(cb)) {
+        return fail(PA_EINVAL, "col_block too large for this N and column FFT variant");
     }
     if (row_teams && row_teams != 1 && row_teams != 2 && row_teams != 4 && row_teams != 8)
         return fail(PA_EINVAL, "row_teams must be 1, 2, 4 or 8");
-    c->d.var = var;
+    c->d.var = rvar;
+    c->d.cvar = cvar;
     c->d.cb = cb;
     if (row_teams) c->d.tpb = row_teams;
     return PA_OK;
@@ -817,7 +855,7 @@ pa_status pa_forward(pa_ctx* c, const double* omega0, int32_t n_steps, const pa_
     WS w;
     PA_TRY(check_ws(c, workspace, wbytes, 0, ckpt_every, op.n_times, 0, &w));
     const int K = seg_len(n_steps, ckpt_every);
-    PA_TRY(forward_sweep(c, w, omega0, n_steps, op, obs_out, reinterpret_cast<cd*>(ckpt), K));
+    PA_TRY(forward_sweep(c, w, omega0, n_steps, op, obs_out, reinterpret_cast<cd*>(ckpt), K, false));
     if (J_out) {
         if (op.n_times > 0) PA_HIP(launch_copy(J_out, w.J, c->d.B, c->stream));
         else PA_HIP(launch_fill(J_out, 0.0, c->d.B, c->stream));
@@ -839,7 +877,7 @@ pa_status pa_adjoint_from_checkpoints(pa_ctx* c, const void* ckpt, int32_t n_ste
     PA_TRY(check_ws(c, workspace, wbytes, n_steps, ckpt_every, op.n_times, 0, &w));
     const int K = seg_len(n_steps, ckpt_every);
     return backward_sweep(c, w, reinterpret_cast<const cd*>(ckpt), n_steps, K, &op, 0, -1, -1, scale, grad_out,
-                          Shells());
+                          Shells(), false);
 }
 
 pa_status pa_adjoint_gradient(pa_ctx* c, const double* omega0, int32_t n_steps, const pa_obs* obs, double* J_out,
@@ -852,12 +890,12 @@ pa_status pa_adjoint_gradient(pa_ctx* c, const double* omega0, int32_t n_steps, 
     WS w;
     PA_TRY(check_ws(c, workspace, wbytes, n_steps, ckpt_every, op.n_times, 0, &w));
     const int K = seg_len(n_steps, ckpt_every);
-    PA_TRY(forward_sweep(c, w, omega0, n_steps, op, nullptr, w.ckpt, K));
+    PA_TRY(forward_sweep(c, w, omega0, n_steps, op, nullptr, w.ckpt, K, true));
     if (J_out) {
         if (op.n_times > 0) PA_HIP(launch_copy(J_out, w.J, c->d.B, c->stream));
         else PA_HIP(launch_fill(J_out, 0.0, c->d.B, c->stream));
     }
-    return backward_sweep(c, w, w.ckpt, n_steps, K, &op, 0, -1, -1, nullptr, grad_out, Shells());
+    return backward_sweep(c, w, w.ckpt, n_steps, K, &op, 0, -1, -1, nullptr, grad_out, Shells(), true);
 }
 
 pa_status pa_adjoint_impulse(pa_ctx* c, const double* omega0, int32_t n_steps, int32_t ix, int32_t iy,
@@ -874,12 +912,12 @@ pa_status pa_adjoint_impulse(pa_ctx* c, const double* omega0, int32_t n_steps, i
     const int K = seg_len(n_steps, ckpt_every);
     ObsPlan none;
     none.slot_of.assign((size_t)n_steps + 1, -1);
-    PA_TRY(forward_sweep(c, w, omega0, n_steps, none, nullptr, w.ckpt, K));
+    PA_TRY(forward_sweep(c, w, omega0, n_steps, none, nullptr, w.ckpt, K, true));
     Shells sh;
     sh.out = shells_out;
     sh.n = n_shells;
     sh.stride = (size_t)(n_steps + 1) * n_shells;
-    return backward_sweep(c, w, w.ckpt, n_steps, K, nullptr, 1, ix, iy, nullptr, field_out, sh);
+    return backward_sweep(c, w, w.ckpt, n_steps, K, nullptr, 1, ix, iy, nullptr, field_out, sh, true);
 }
 
 pa_status pa_first_guess(pa_ctx* c, int32_t stride, const double* probes, double* omega_out, void* workspace,
@@ -1001,11 +1039,11 @@ extern "C" pa_status pa_assimilate(pa_ctx* c, double* omega_inout, int32_t n_ste
 
     auto eval_J = [&](const double* x) -> pa_status {
         PA_TRY(apply_filter(c, w, mult_p, x, w.w));
-        return forward_sweep(c, w, w.w, n_steps, op, nullptr, w.ckpt, K);
+        return forward_sweep(c, w, w.w, n_steps, op, nullptr, w.ckpt, K, true);
     };
     // gradient at the point whose forward sweep last filled w.ckpt
     auto eval_grad = [&](double* gout) -> pa_status {
-        PA_TRY(backward_sweep(c, w, w.ckpt, n_steps, K, &op, 0, -1, -1, nullptr, w.gw, Shells()));
+        PA_TRY(backward_sweep(c, w, w.ckpt, n_steps, K, &op, 0, -1, -1, nullptr, w.gw, Shells(), true));
         return apply_filter(c, w, mult_p, w.gw, gout);
     };
 

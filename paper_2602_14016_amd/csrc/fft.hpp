@@ -178,22 +178,28 @@ __device__ __forceinline__ void dft<16, true>(cd* v) { dft16<true>(v); }
 
 // ---------------------------------------------------------------- plans --
 // Radix sequence per length and variant; T threads per transform, E elements
-// per thread.  Variant 0 keeps more elements per thread (fewer LDS exchanges,
-// more registers); variant 1 spreads a transform over more threads (fewer
-// registers per thread, one more exchange).  The autotuner picks per context.
+// per thread (every radix divides E).  Variant 0 keeps more elements per
+// thread (fewer LDS exchanges, more registers); variant 1 spreads a transform
+// over more threads; variant 2 uses four elements per thread where the
+// length allows it (twice the threads of variant 1 at 128 and 256, the same
+// plan as variant 1 elsewhere).  The autotuner picks per context and pass.
 template <int N, int V> struct Plan;
 template <int V> struct Plan<8, V>    { static constexpr int NS = 1, T = 1,  E = 8;  static constexpr int R[4] = {8, 1, 1, 1}; };
 template <int V> struct Plan<16, V>   { static constexpr int NS = 2, T = 4,  E = 4;  static constexpr int R[4] = {4, 4, 1, 1}; };
 template <int V> struct Plan<32, V>   { static constexpr int NS = 2, T = 4,  E = 8;  static constexpr int R[4] = {8, 4, 1, 1}; };
 template <> struct Plan<64, 0>   { static constexpr int NS = 2, T = 8,   E = 8;  static constexpr int R[4] = {8, 8, 1, 1}; };
 template <> struct Plan<64, 1>   { static constexpr int NS = 3, T = 16,  E = 4;  static constexpr int R[4] = {4, 4, 4, 1}; };
+template <> struct Plan<64, 2>   { static constexpr int NS = 3, T = 16,  E = 4;  static constexpr int R[4] = {4, 4, 4, 1}; };
 template <> struct Plan<128, 0>  { static constexpr int NS = 2, T = 8,   E = 16; static constexpr int R[4] = {16, 8, 1, 1}; };
 template <> struct Plan<128, 1>  { static constexpr int NS = 3, T = 16,  E = 8;  static constexpr int R[4] = {8, 4, 4, 1}; };
+template <> struct Plan<128, 2>  { static constexpr int NS = 4, T = 32,  E = 4;  static constexpr int R[4] = {4, 4, 4, 2}; };
 template <> struct Plan<256, 0>  { static constexpr int NS = 2, T = 16,  E = 16; static constexpr int R[4] = {16, 16, 1, 1}; };
 template <> struct Plan<256, 1>  { static constexpr int NS = 3, T = 32,  E = 8;  static constexpr int R[4] = {8, 8, 4, 1}; };
+template <> struct Plan<256, 2>  { static constexpr int NS = 4, T = 64,  E = 4;  static constexpr int R[4] = {4, 4, 4, 4}; };
 template <int V> struct Plan<512, V>  { static constexpr int NS = 3, T = 64, E = 8; static constexpr int R[4] = {8, 8, 8, 1}; };
 template <> struct Plan<1024, 0> { static constexpr int NS = 3, T = 64,  E = 16; static constexpr int R[4] = {16, 16, 4, 1}; };
 template <> struct Plan<1024, 1> { static constexpr int NS = 4, T = 128, E = 8;  static constexpr int R[4] = {8, 8, 4, 4}; };
+template <> struct Plan<1024, 2> { static constexpr int NS = 4, T = 128, E = 8;  static constexpr int R[4] = {8, 8, 4, 4}; };
 
 // LDS footprint of one team's exchange area (one padding slot per 16 entries).
 template <int N>

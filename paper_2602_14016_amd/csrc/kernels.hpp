@@ -26,7 +26,8 @@ struct Dims {
     int N, B, K, KX, KXP, KY;
     int cb;    // kx columns per column-pass workgroup
     int tpb;   // row teams per row-pass workgroup
-    int var;   // FFT plan variant (0 or 1)
+    int var;   // FFT plan variant of the row passes (0, 1 or 2)
+    int cvar;  // FFT plan variant of the column pass (0, 1 or 2)
 };
 
 enum FieldKind : int { F_OMEGA = 0, F_U = 1, F_V = 2, F_WX = 3, F_WY = 4 };

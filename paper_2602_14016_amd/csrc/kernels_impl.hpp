@@ -338,8 +338,9 @@ __device__ __forceinline__ int band_row(int q, int N, int K, int KY) {
     return -1;
 }
 
+// Up to 512 threads: CB columns of T threads each (CB * T <= 512).
 template <int N, int V, int MODE>
-__global__ void __launch_bounds__(256) col_kernel(Dims d, ColArgs a) {
+__global__ void __launch_bounds__(512) col_kernel(Dims d, ColArgs a) {
     constexpr int T = Plan<N, V>::T, E = Plan<N, V>::E;
     constexpr bool FWD_STAGE = MODE >= COL_A && MODE <= COL_D;
     constexpr bool ADJ = MODE >= COL_ADJ_C && MODE <= COL_ADJ_SRC;
@@ -601,23 +602,22 @@ int row_tpb(const Dims& d, long teams_per_member) {
 template <int N, int V>
 size_t row_lds(int tpb) { return ((size_t)tpb * lds_team<N>() + N) * sizeof(cd); }
 
+#define PA_ROW_LAUNCH_V(V, KERNEL, ...)                                                        \
+    do {                                                                                       \
+        const int tpb = row_tpb<N, V>(d, tpm_);                                                \
+        const dim3 grid_((unsigned)(teams_ / tpb));                                            \
+        const dim3 block_((unsigned)(tpb * Plan<N, V>::T));                                    \
+        const size_t lds_ = row_lds<N, V>(tpb);                                                \
+        hipLaunchKernelGGL((KERNEL<N, V>), grid_, block_, lds_, s, __VA_ARGS__);               \
+    } while (0)
+
 #define PA_ROW_LAUNCH(KERNEL, TEAMS_PER_MEMBER, ...)                                           \
     do {                                                                                       \
         const long tpm_ = (TEAMS_PER_MEMBER);                                                  \
         const long teams_ = tpm_ * d.B;                                                        \
-        if (d.var == 0) {                                                                      \
-            const int tpb = row_tpb<N, 0>(d, tpm_);                                            \
-            const dim3 grid_((unsigned)(teams_ / tpb));                                        \
-            const dim3 block_((unsigned)(tpb * Plan<N, 0>::T));                                \
-            const size_t lds_ = row_lds<N, 0>(tpb);                                            \
-            hipLaunchKernelGGL((KERNEL<N, 0>), grid_, block_, lds_, s, __VA_ARGS__);           \
-        } else {                                                                               \
-            const int tpb = row_tpb<N, 1>(d, tpm_);                                            \
-            const dim3 grid_((unsigned)(teams_ / tpb));                                        \
-            const dim3 block_((unsigned)(tpb * Plan<N, 1>::T));                                \
-            const size_t lds_ = row_lds<N, 1>(tpb);                                            \
-            hipLaunchKernelGGL((KERNEL<N, 1>), grid_, block_, lds_, s, __VA_ARGS__);           \
-        }                                                                                      \
+        if (d.var == 0) PA_ROW_LAUNCH_V(0, KERNEL, __VA_ARGS__);                               \
+        else if (d.var == 1) PA_ROW_LAUNCH_V(1, KERNEL, __VA_ARGS__);                          \
+        else PA_ROW_LAUNCH_V(2, KERNEL, __VA_ARGS__);                                          \
         return hipGetLastError();                                                              \
     } while (0)
 
@@ -678,12 +678,14 @@ hipError_t col_variant(const Dims& d, int mode, const ColArgs& a, hipStream_t s)
 
 template <int N>
 hipError_t Launch<N>::col(const Dims& d, int mode, const ColArgs& a, hipStream_t s) {
-    return d.var == 0 ? col_variant<N, 0>(d, mode, a, s) : col_variant<N, 1>(d, mode, a, s);
+    if (d.cvar == 0) return col_variant<N, 0>(d, mode, a, s);
+    if (d.cvar == 1) return col_variant<N, 1>(d, mode, a, s);
+    return col_variant<N, 2>(d, mode, a, s);
 }
 
 template <int N>
 int Launch<N>::threads(int var) {
-    return var == 0 ? Plan<N, 0>::T : Plan<N, 1>::T;
+    return var == 0 ? Plan<N, 0>::T : var == 1 ? Plan<N, 1>::T : Plan<N, 2>::T;
 }
 
 }  // namespace pa

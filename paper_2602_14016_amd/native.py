@@ -60,7 +60,7 @@ EXPORTS = {
                                 c_size_t]),
     "pa_adjoint_impulse": (c_int32, [c_void_p, c_void_p, c_int32, c_int32, c_int32, c_int32, c_void_p,
                                      c_void_p, c_int32, c_void_p, c_size_t]),
-    "pa_set_tiles": (c_int32, [c_void_p, c_int32, c_int32, c_int32]),
+    "pa_set_tiles": (c_int32, [c_void_p, c_int32, c_int32, c_int32, c_int32]),
     "pa_first_guess": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_size_t]),
     "pa_shell_growth": (c_int32, [c_void_p, c_void_p, c_int32, c_int32, c_double, c_double, c_void_p, c_void_p]),
     "pa_profile_start": (c_int32, [c_void_p, c_int32, c_int32]),

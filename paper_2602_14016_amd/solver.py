@@ -103,6 +103,27 @@ class Solver:
         nv.check(self.lib.pa_checkpoint_bytes(self.ctx, int(n_steps), int(ckpt_every), byref(b)))
         return b.value
 
+    def fit_ckpt_every(self, n_steps, n_obs=0, lbfgs_m=0, budget_bytes=None, reserve=0.1):
+        """Largest checkpoint interval K <= n_steps whose workspace fits in budget_bytes.
+
+        The default budget is the device's free memory (plus this solver's
+        current workspace, which would be released) less a `reserve` fraction.
+        K = n_steps keeps every stage field of the trajectory, so a gradient
+        needs no recomputation; smaller K trade recomputation for memory.
+        Returns 0 if not even K = 1 fits.
+        """
+        if budget_bytes is None:
+            free, _ = torch.cuda.mem_get_info(self.device)
+            held = self._ws.numel() if self._ws is not None else 0
+            budget_bytes = int((free + held) * (1.0 - reserve))
+        if n_steps <= 1:
+            return 1 if self.workspace_bytes(n_steps, 1, n_obs, lbfgs_m) + 256 <= budget_bytes else 0
+        for m in range(1, n_steps + 1):
+            K = -(-n_steps // m)
+            if self.workspace_bytes(n_steps, K, n_obs, lbfgs_m) + 256 <= budget_bytes:
+                return K
+        return 0
+
     def workspace(self, n_steps=0, ckpt_every=1, n_obs=0, lbfgs_m=0):
         need = self.workspace_bytes(n_steps, ckpt_every, n_obs, lbfgs_m)
         if self._ws is None or self._ws.numel() < need + 256:
@@ -115,8 +136,10 @@ class Solver:
     def empty(self):
         return torch.empty((self.B, self.N, self.N), dtype=torch.float64, device=self.device)
 
-    def set_tiles(self, col_block=0, row_teams=0, fft_variant=-1):
-        nv.check(self.lib.pa_set_tiles(self.ctx, int(col_block), int(row_teams), int(fft_variant)))
+    def set_tiles(self, col_block=0, row_teams=0, row_variant=-1, col_variant=-1):
+        """Tile shapes of the FFT passes (0 / -1 keep the current value); see pa_set_tiles."""
+        nv.check(self.lib.pa_set_tiles(self.ctx, int(col_block), int(row_teams), int(row_variant),
+                                       int(col_variant)))
 
     # ---------------------------------------------------------------- calls
     def init_field(self, seeds, kind=0, k0=4.0, target=0.5, out=None):

@@ -146,6 +146,49 @@ def test_gradient_parity(N, steps, K, flow):
     assert rel(host(g)[0], gref) < GRAD_TOL, rel(host(g)[0], gref)
 
 
+@pytest.mark.parametrize("N", [64, 128, 256])
+def test_tile_variants_gradient_parity(N):
+    """Every (row plan, column plan) pair, with several workgroup shapes, against the oracle (B = 2)."""
+    from paper_2602_14016_amd import Observations
+    announce("tile-variants", N)
+    ph = _hit(N, nu=1e-3, dt=2e-3)
+    steps, osteps = 6, [0, 3, 6]
+    w0 = O.init_field(N, [2, 7], kind=0, k0=min(8.0, N / 8))
+    mo = np.stack([_twin(N, ph, steps, osteps, 8, seed=30 + b) for b in range(2)])
+    ref = [O.adjoint_gradient(w0[b], ph, steps, Obs(8, osteps, mo[b])) for b in range(2)]
+    s = solver(N, 2, ph)
+    obs = Observations(8, osteps, dev(mo))
+    shapes = [(1, 8), (2, 4), (4, 2), (8, 1)]
+    for rv in (0, 1, 2):
+        for cv in (0, 1, 2):
+            tpb, cb = shapes[(3 * rv + cv) % len(shapes)]
+            s.set_tiles(cb, tpb, rv, cv)
+            J, g = s.adjoint_gradient(dev(w0), steps, obs, ckpt_every=4)
+            Jh, gh = host(J), host(g)
+            for b in range(2):
+                assert abs(float(Jh[b]) - ref[b][0]) <= FIELD_TOL * ref[b][0], (rv, cv, tpb, cb, b)
+                assert rel(gh[b], ref[b][1]) < GRAD_TOL, (rv, cv, tpb, cb, b, rel(gh[b], ref[b][1]))
+
+
+def test_autotune_applies_valid_tiles():
+    from paper_2602_14016_amd import Observations
+    from paper_2602_14016_amd.autotune import autotune
+    announce("autotune")
+    N, steps = 64, 8
+    ph = _hit(N)
+    osteps = [0, 8]
+    mo = _twin(N, ph, steps, osteps, 4)
+    w0 = O.init_field(N, [6], kind=0, k0=4.0)[0]
+    Jref, gref = O.adjoint_gradient(w0, ph, steps, Obs(4, osteps, mo))
+    s = solver(N, 1, ph)
+    at = autotune(s, n_steps=4, ckpt_every=2, reps=1)
+    assert at["row_variant"] in (0, 1, 2) and at["col_variant"] in (0, 1, 2)
+    assert at["row_teams"] in (1, 2, 4, 8) and at["col_block"] in (1, 2, 4, 8)
+    assert len(at["trials"]) >= 12
+    J, g = s.adjoint_gradient(dev(w0[None]), steps, Observations(4, osteps, dev(mo[None])), ckpt_every=3)
+    assert rel(host(g)[0], gref) < GRAD_TOL
+
+
 def test_gradient_horizon_zero_and_unobserved_end():
     from paper_2602_14016_amd import Observations
     announce("gradient-degenerate")
