@@ -129,10 +129,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--graph-replays", type=int, default=3,
                     help="also capture the batched solve in a HIP graph and time this many replays (0: skip)")
-    ap.add_argument("--col-block", type=int, default=0)
-    ap.add_argument("--row-teams", type=int, default=0)
-    ap.add_argument("--row-variant", type=int, default=-1)
-    ap.add_argument("--col-variant", type=int, default=-1)
+    for knob in ("row-variant", "row-teams", "adj-variant", "adj-teams", "col-variant", "col-block"):
+        ap.add_argument("--" + knob, type=int, default=-1, help="FFT tile knob (pa_set_tiles); -1: autotuned")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one torch copy of this many MiB first (HBM counter calibration)")
@@ -168,16 +166,16 @@ def main():
     s = Solver(N, B, nu=nu, dt=dt, device=dev)
     w0 = s.init_field(list(range(B)), kind=0, k0=k0, target=0.5)
     torch.cuda.synchronize()
-    knobs = ("row_variant", "row_teams", "col_variant", "col_block")
-    manual = args.col_block or args.row_teams or args.row_variant >= 0 or args.col_variant >= 0
+    knobs = ("row_variant", "row_teams", "adj_variant", "adj_teams", "col_variant", "col_block")
+    manual = any(getattr(args, k) >= 0 for k in knobs)
 
     def tune(solver, omega0):
         if manual or args.no_autotune:
-            solver.set_tiles(args.col_block, args.row_teams, args.row_variant, args.col_variant)
-            return {k: getattr(args, k) for k in knobs} | {"autotuned": False}
-        at = autotune(solver, omega0, n_steps=16, ckpt_every=8)
+            solver.set_tiles(**{k: getattr(args, k) for k in knobs})
+            return solver.get_tiles() | {"autotuned": False}
+        at = autotune(solver, omega0, n_steps=8)
         out = {k: at[k] for k in knobs} | {"autotuned": True}
-        out["trials"] = [[r[k] for k in knobs] + [round(r["ms"], 3)] for r in at["trials"]]
+        out["trials"] = [[r["pass"], r["variant"], r["block"], round(r["ms"], 3)] for r in at["trials"]]
         print("autotune", json.dumps(out), file=sys.stderr, flush=True)
         return out
 

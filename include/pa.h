@@ -225,18 +225,30 @@ pa_status pa_first_guess(pa_ctx* ctx, int32_t stride, const double* probes, doub
 pa_status pa_shell_growth(pa_ctx* ctx, const double* shells, int32_t rows, int32_t n_shells,
                           double tau_min, double tau_max, double* mean_out, double* rate_out);
 
-/* FFT tile choice for this context (the autotuner's knobs): col_block = kx
- * columns per column-pass workgroup (1, 2, 4 or 8; 0 keeps the current value,
- * reduced if the column variant needs it), row_teams = rows per row-pass
- * workgroup (1, 2, 4 or 8; 0 keeps; capped at 256 threads per workgroup),
- * row_variant / col_variant = register plan of the 1D transforms of the row
- * and column passes (0: more elements per thread, 1: more threads per
- * transform, 2: four elements per thread where the length allows; -1 keeps).
- * PA_EINVAL for values outside these sets or an explicit col_block that does
- * not fit (col_block * threads per transform <= 512, LDS <= 64 KiB).
- * Results do not depend on the choice beyond rounding of the transforms. */
-pa_status pa_set_tiles(pa_ctx* ctx, int32_t col_block, int32_t row_teams, int32_t row_variant,
-                       int32_t col_variant);
+/* FFT tile choice of a context (the autotuner's knobs), per pass: the forward
+ * row passes (right-hand side products, observation, transforms of physical
+ * fields), the adjoint row passes (adjoint products, source rows) and the
+ * column pass.  variant = register plan of the 1D transforms (0: more
+ * elements per thread, 1: more threads per transform, 2: four elements per
+ * thread where the length allows); teams = rows per row-pass workgroup (1, 2,
+ * 4 or 8, capped at 256 threads and 64 KiB of LDS per workgroup); col_block =
+ * kx columns per column-pass workgroup (1, 2, 4 or 8, with col_block times
+ * threads per transform <= 512 and LDS <= 64 KiB).  Results do not depend on
+ * the choice beyond rounding of the transforms. */
+typedef struct pa_tiles {
+    int32_t row_variant, row_teams;
+    int32_t adj_variant, adj_teams;
+    int32_t col_variant, col_block;
+} pa_tiles;
+
+/* Sets the tiles; a negative field keeps its current value (a kept col_block
+ * is reduced if the column variant needs it).  PA_EINVAL for values outside
+ * the sets above or an explicit col_block that does not fit; nothing changes
+ * then. */
+pa_status pa_set_tiles(pa_ctx* ctx, const pa_tiles* tiles);
+
+/* Current tiles of the context. */
+pa_status pa_get_tiles(const pa_ctx* ctx, pa_tiles* tiles);
 
 /* Launch timing for measurement: until pa_profile_stop, every sample_every-th
  * launch of one kernel class is bracketed by HIP events recorded on the

@@ -662,11 +662,13 @@ pa_status pa_create(const pa_physics* phys, int32_t N, int32_t B, void* hip_stre
     d.KXP = (d.KX + 7) / 8 * 8;
     d.KY = 2 * d.K + 1;
     d.var = 0;
+    d.tpb = 4;
+    d.avar = 0;
+    d.atpb = 4;
     d.cvar = 0;
     d.cb = 8;
     while (d.cb > 1 && (d.cb * fft_threads(N, d.cvar) > 512 ||
                         ((size_t)d.cb * (N + N / 16 + 1) + N) * sizeof(cd) > 65536)) d.cb >>= 1;
-    d.tpb = 4;
 
     std::vector<cd> tw;
     host_twiddles(N, tw);
@@ -752,30 +754,42 @@ pa_status pa_get_shape(const pa_ctx* c, int32_t* N, int32_t* B, int32_t* Kc) {
     return PA_OK;
 }
 
-pa_status pa_set_tiles(pa_ctx* c, int32_t col_block, int32_t row_teams, int32_t row_variant,
-                       int32_t col_variant) {
-    if (!c) return fail(PA_EINVAL, "ctx is NULL");
-    if (row_variant < -1 || row_variant > 2 || col_variant < -1 || col_variant > 2)
-        return fail(PA_EINVAL, "FFT variants must be -1, 0, 1 or 2");
-    const int rvar = row_variant >= 0 ? row_variant : c->d.var;
-    const int cvar = col_variant >= 0 ? col_variant : c->d.cvar;
-    const int T = fft_threads(c->d.N, cvar);
+pa_status pa_set_tiles(pa_ctx* c, const pa_tiles* t) {
+    if (!c || !t) return fail(PA_EINVAL, "NULL argument");
+    auto variant_ok = [](int v) { return v < 0 || v <= 2; };
+    auto block_ok = [](int b) { return b < 0 || b == 1 || b == 2 || b == 4 || b == 8; };
+    if (!variant_ok(t->row_variant) || !variant_ok(t->adj_variant) || !variant_ok(t->col_variant))
+        return fail(PA_EINVAL, "FFT variants must be 0, 1 or 2 (negative keeps)");
+    if (!block_ok(t->row_teams) || !block_ok(t->adj_teams) || !block_ok(t->col_block))
+        return fail(PA_EINVAL, "row teams and col_block must be 1, 2, 4 or 8 (negative keeps)");
+    Dims d = c->d;
+    if (t->row_variant >= 0) d.var = t->row_variant;
+    if (t->row_teams > 0) d.tpb = t->row_teams;
+    if (t->adj_variant >= 0) d.avar = t->adj_variant;
+    if (t->adj_teams > 0) d.atpb = t->adj_teams;
+    if (t->col_variant >= 0) d.cvar = t->col_variant;
+    const int T = fft_threads(d.N, d.cvar);
     auto col_fits = [&](int cb) {
-        return cb * T <= 512 && ((size_t)cb * (c->d.N + c->d.N / 16 + 1) + c->d.N) * sizeof(cd) <= 65536;
+        return cb * T <= 512 && ((size_t)cb * (d.N + d.N / 16 + 1) + d.N) * sizeof(cd) <= 65536;
     };
-    int cb = col_block ? col_block : c->d.cb;
-    if (cb != 1 && cb != 2 && cb != 4 && cb != 8) return fail(PA_EINVAL, "col_block must be 1, 2, 4 or 8");
-    if (!col_block) {
-        while (cb > 1 && !col_fits(cb)) cb >>= 1;
-    } else if (!col_fits(cb)) {
-        return fail(PA_EINVAL, "col_block too large for this N and column FFT variant");
+    if (t->col_block > 0) {
+        if (!col_fits(t->col_block)) return fail(PA_EINVAL, "col_block too large for this N and column FFT variant");
+        d.cb = t->col_block;
+    } else {
+        while (d.cb > 1 && !col_fits(d.cb)) d.cb >>= 1;
     }
-    if (row_teams && row_teams != 1 && row_teams != 2 && row_teams != 4 && row_teams != 8)
-        return fail(PA_EINVAL, "row_teams must be 1, 2, 4 or 8");
-    c->d.var = rvar;
-    c->d.cvar = cvar;
-    c->d.cb = cb;
-    if (row_teams) c->d.tpb = row_teams;
+    c->d = d;
+    return PA_OK;
+}
+
+pa_status pa_get_tiles(const pa_ctx* c, pa_tiles* t) {
+    if (!c || !t) return fail(PA_EINVAL, "NULL argument");
+    t->row_variant = c->d.var;
+    t->row_teams = c->d.tpb;
+    t->adj_variant = c->d.avar;
+    t->adj_teams = c->d.atpb;
+    t->col_variant = c->d.cvar;
+    t->col_block = c->d.cb;
     return PA_OK;
 }
 

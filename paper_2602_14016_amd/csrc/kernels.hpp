@@ -24,10 +24,9 @@ namespace pa {
 
 struct Dims {
     int N, B, K, KX, KXP, KY;
-    int cb;    // kx columns per column-pass workgroup
-    int tpb;   // row teams per row-pass workgroup
-    int var;   // FFT plan variant of the row passes (0, 1 or 2)
-    int cvar;  // FFT plan variant of the column pass (0, 1 or 2)
+    int var, tpb;    // forward row passes: FFT plan variant (0, 1, 2), rows per workgroup
+    int avar, atpb;  // adjoint row passes: FFT plan variant, rows per workgroup
+    int cvar, cb;    // column pass: FFT plan variant, kx columns per workgroup
 };
 
 enum FieldKind : int { F_OMEGA = 0, F_U = 1, F_V = 2, F_WX = 3, F_WY = 4 };

@@ -589,8 +589,7 @@ __global__ void __launch_bounds__(512) col_kernel(Dims d, ColArgs a) {
 // member index from the workgroup's first team), fit 256 threads and 64 KiB
 // of LDS.
 template <int N, int V>
-int row_tpb(const Dims& d, long teams_per_member) {
-    int tpb = d.tpb;
+int row_tpb(int tpb, long teams_per_member) {
     const int cap = 256 / Plan<N, V>::T;
     if (tpb > cap) tpb = cap;
     if (tpb < 1) tpb = 1;
@@ -602,49 +601,51 @@ int row_tpb(const Dims& d, long teams_per_member) {
 template <int N, int V>
 size_t row_lds(int tpb) { return ((size_t)tpb * lds_team<N>() + N) * sizeof(cd); }
 
-#define PA_ROW_LAUNCH_V(V, KERNEL, ...)                                                        \
+#define PA_ROW_LAUNCH_V(V, TPB, KERNEL, ...)                                                   \
     do {                                                                                       \
-        const int tpb = row_tpb<N, V>(d, tpm_);                                                \
+        const int tpb = row_tpb<N, V>((TPB), tpm_);                                            \
         const dim3 grid_((unsigned)(teams_ / tpb));                                            \
         const dim3 block_((unsigned)(tpb * Plan<N, V>::T));                                    \
         const size_t lds_ = row_lds<N, V>(tpb);                                                \
         hipLaunchKernelGGL((KERNEL<N, V>), grid_, block_, lds_, s, __VA_ARGS__);               \
     } while (0)
 
-#define PA_ROW_LAUNCH(KERNEL, TEAMS_PER_MEMBER, ...)                                           \
+// VAR / TPB: the plan variant and rows per workgroup of the launching pass
+// (forward rows: d.var, d.tpb; adjoint rows: d.avar, d.atpb).
+#define PA_ROW_LAUNCH(VAR, TPB, KERNEL, TEAMS_PER_MEMBER, ...)                                 \
     do {                                                                                       \
         const long tpm_ = (TEAMS_PER_MEMBER);                                                  \
         const long teams_ = tpm_ * d.B;                                                        \
-        if (d.var == 0) PA_ROW_LAUNCH_V(0, KERNEL, __VA_ARGS__);                               \
-        else if (d.var == 1) PA_ROW_LAUNCH_V(1, KERNEL, __VA_ARGS__);                          \
-        else PA_ROW_LAUNCH_V(2, KERNEL, __VA_ARGS__);                                          \
+        if ((VAR) == 0) PA_ROW_LAUNCH_V(0, TPB, KERNEL, __VA_ARGS__);                          \
+        else if ((VAR) == 1) PA_ROW_LAUNCH_V(1, TPB, KERNEL, __VA_ARGS__);                     \
+        else PA_ROW_LAUNCH_V(2, TPB, KERNEL, __VA_ARGS__);                                     \
         return hipGetLastError();                                                              \
     } while (0)
 
 template <int N>
 hipError_t Launch<N>::row_r2c(const Dims& d, const double* in, cd* out, const cd* tw, hipStream_t s) {
-    PA_ROW_LAUNCH(row_r2c_kernel, N / 2, d, in, out, tw);
+    PA_ROW_LAUNCH(d.var, d.tpb, row_r2c_kernel, N / 2, d, in, out, tw);
 }
 template <int N>
 hipError_t Launch<N>::row_c2r(const Dims& d, const cd* in, double* out, const cd* tw, hipStream_t s) {
-    PA_ROW_LAUNCH(row_c2r_kernel, N / 2, d, in, out, tw);
+    PA_ROW_LAUNCH(d.var, d.tpb, row_c2r_kernel, N / 2, d, in, out, tw);
 }
 template <int N>
 hipError_t Launch<N>::row_nl(const Dims& d, const RowArgs& a, hipStream_t s) {
-    if (a.obs.slot >= 0) PA_ROW_LAUNCH(row_nl_obs_kernel, N, d, a);
-    PA_ROW_LAUNCH(row_nl_kernel, N, d, a);
+    if (a.obs.slot >= 0) PA_ROW_LAUNCH(d.var, d.tpb, row_nl_obs_kernel, N, d, a);
+    PA_ROW_LAUNCH(d.var, d.tpb, row_nl_kernel, N, d, a);
 }
 template <int N>
 hipError_t Launch<N>::row_obs(const Dims& d, const RowArgs& a, hipStream_t s) {
-    PA_ROW_LAUNCH(row_obs_kernel, a.obs.M, d, a);
+    PA_ROW_LAUNCH(d.var, d.tpb, row_obs_kernel, a.obs.M, d, a);
 }
 template <int N>
 hipError_t Launch<N>::row_adj(const Dims& d, const RowArgs& a, hipStream_t s) {
-    PA_ROW_LAUNCH(row_adj_kernel, N, d, a);
+    PA_ROW_LAUNCH(d.avar, d.atpb, row_adj_kernel, N, d, a);
 }
 template <int N>
 hipError_t Launch<N>::row_src(const Dims& d, const RowArgs& a, int impulse, hipStream_t s) {
-    PA_ROW_LAUNCH(row_src_kernel, N, d, a, impulse);
+    PA_ROW_LAUNCH(d.avar, d.atpb, row_src_kernel, N, d, a, impulse);
 }
 
 template <int N, int V, int MODE>

@@ -37,6 +37,13 @@ class Kernel(Structure):
     _fields_ = [("kind", c_int32), ("metric", c_int32), ("param", c_double)]
 
 
+TILE_FIELDS = ("row_variant", "row_teams", "adj_variant", "adj_teams", "col_variant", "col_block")
+
+
+class Tiles(Structure):
+    _fields_ = [(name, c_int32) for name in TILE_FIELDS]
+
+
 EXPORTS = {
     "pa_create": (c_int32, [POINTER(Physics), c_int32, c_int32, c_void_p, POINTER(c_void_p)]),
     "pa_destroy": (c_int32, [c_void_p]),
@@ -60,7 +67,8 @@ EXPORTS = {
                                 c_size_t]),
     "pa_adjoint_impulse": (c_int32, [c_void_p, c_void_p, c_int32, c_int32, c_int32, c_int32, c_void_p,
                                      c_void_p, c_int32, c_void_p, c_size_t]),
-    "pa_set_tiles": (c_int32, [c_void_p, c_int32, c_int32, c_int32, c_int32]),
+    "pa_set_tiles": (c_int32, [c_void_p, POINTER(Tiles)]),
+    "pa_get_tiles": (c_int32, [c_void_p, POINTER(Tiles)]),
     "pa_first_guess": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_size_t]),
     "pa_shell_growth": (c_int32, [c_void_p, c_void_p, c_int32, c_int32, c_double, c_double, c_void_p, c_void_p]),
     "pa_profile_start": (c_int32, [c_void_p, c_int32, c_int32]),

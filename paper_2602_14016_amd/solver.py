@@ -136,10 +136,18 @@ class Solver:
     def empty(self):
         return torch.empty((self.B, self.N, self.N), dtype=torch.float64, device=self.device)
 
-    def set_tiles(self, col_block=0, row_teams=0, row_variant=-1, col_variant=-1):
-        """Tile shapes of the FFT passes (0 / -1 keep the current value); see pa_set_tiles."""
-        nv.check(self.lib.pa_set_tiles(self.ctx, int(col_block), int(row_teams), int(row_variant),
-                                       int(col_variant)))
+    def set_tiles(self, **tiles):
+        """Tile shapes of the FFT passes (keys of native.TILE_FIELDS; omitted keys keep their value)."""
+        unknown = set(tiles) - set(nv.TILE_FIELDS)
+        if unknown:
+            raise ValueError(f"unknown tile keys {sorted(unknown)}")
+        t = nv.Tiles(*[int(tiles.get(k, -1)) for k in nv.TILE_FIELDS])
+        nv.check(self.lib.pa_set_tiles(self.ctx, byref(t)))
+
+    def get_tiles(self):
+        t = nv.Tiles()
+        nv.check(self.lib.pa_get_tiles(self.ctx, byref(t)))
+        return {k: getattr(t, k) for k in nv.TILE_FIELDS}
 
     # ---------------------------------------------------------------- calls
     def init_field(self, seeds, kind=0, k0=4.0, target=0.5, out=None):

@@ -85,7 +85,8 @@ def test_null_context_calls_are_rejected():
     assert lib.pa_adjoint_gradient(None, None, 1, None, None, None, 1, None, 0) == -1
     assert lib.pa_precondition(None, None, 0.5, None, None, None, 0) == -1
     assert lib.pa_assimilate(None, None, 1, None, None, 0, 1, 1, 1, None, None, None, 0) == -1
-    assert lib.pa_set_tiles(None, 8, 4, 0, 0) == -1
+    assert lib.pa_set_tiles(None, None) == -1
+    assert lib.pa_get_tiles(None, None) == -1
 
 
 def test_product_path_has_no_cpu_fallback():

