@@ -230,8 +230,11 @@ pa_status pa_shell_growth(pa_ctx* ctx, const double* shells, int32_t rows, int32
  * fields), the adjoint row passes (adjoint products, source rows) and the
  * column pass.  variant = register plan of the 1D transforms (0: more
  * elements per thread, 1: more threads per transform, 2: four elements per
- * thread where the length allows); teams = rows per row-pass workgroup (1, 2,
- * 4 or 8, capped at 256 threads and 64 KiB of LDS per workgroup); col_block =
+ * thread where the length allows; 3, row passes only: the plan of variant 2
+ * run by persistent wavefronts that prefetch their next rows from HBM into
+ * LDS, bitwise equal to variant 2); teams = rows per row-pass workgroup (1,
+ * 2, 4 or 8, capped at 256 threads and 64 KiB of LDS per workgroup; with
+ * variant 3, wavefronts per workgroup, capped at 4); col_block =
  * kx columns per column-pass workgroup (1, 2, 4 or 8, with col_block times
  * threads per transform <= 512 and LDS <= 64 KiB).  Results do not depend on
  * the choice beyond rounding of the transforms. */

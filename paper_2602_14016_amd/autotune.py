@@ -2,8 +2,9 @@
 
 Knobs (pa_set_tiles), one set per pass: the register plan of the 1D
 transforms (variant 0: more elements per thread; 1: more threads per
-transform; 2: four elements per thread where the length allows) and the
-workgroup shape (rows per workgroup for the forward and the adjoint row
+transform; 2: four elements per thread where the length allows; 3, row
+passes only: variant 2's plan in persistent wavefronts that prefetch their
+next rows into LDS) and the workgroup shape (rows per workgroup for the forward and the adjoint row
 passes, kx columns per workgroup for the column pass).  The three passes are
 separate kernels reading and writing fixed layouts, so each is tuned on its
 own: every candidate runs a short batched forward + adjoint solve of the
@@ -19,7 +20,8 @@ import time
 
 import torch
 
-VARIANTS = (0, 1, 2)
+ROW_VARIANTS = (0, 1, 2, 3)
+COL_VARIANTS = (0, 1, 2)
 BLOCKS = (1, 2, 4, 8)
 ROW_NL, COL_FWD, ROW_ADJ, COL_ADJ = 0, 1, 2, 3
 
@@ -61,13 +63,13 @@ def autotune(solver, omega0=None, n_steps=8, reps=2, verbose=False):
     trials = []
     chosen = {}
     searches = (
-        ("row", ROW_NL, "row_variant", "row_teams", (ROW_NL,)),
-        ("adj", ROW_ADJ, "adj_variant", "adj_teams", (ROW_ADJ,)),
-        ("col", COL_FWD, "col_variant", "col_block", (COL_FWD, COL_ADJ)),
+        ("row", ROW_VARIANTS, "row_variant", "row_teams", (ROW_NL,)),
+        ("adj", ROW_VARIANTS, "adj_variant", "adj_teams", (ROW_ADJ,)),
+        ("col", COL_VARIANTS, "col_variant", "col_block", (COL_FWD, COL_ADJ)),
     )
-    for name, _, vkey, bkey, classes in searches:
+    for name, variants, vkey, bkey, classes in searches:
         best = None
-        for v in VARIANTS:
+        for v in variants:
             for blk in BLOCKS:
                 try:
                     solver.set_tiles(**{vkey: v, bkey: blk})

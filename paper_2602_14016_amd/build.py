@@ -21,8 +21,13 @@ ARCH = os.environ.get("PA_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+# -ffp-contract=on: a multiply is fused into an add only within one source
+# expression, decided in the front end, so every copy of a piece of code
+# (a peeled loop iteration, a kernel variant) rounds identically; with "fast"
+# the backend fuses across statements where it finds the pattern, and two
+# copies of the same source can differ in the last bit.
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall",
-          "-Wno-unused-function", "-Wno-unused-variable", "-ffp-contract=fast"]
+          "-Wno-unused-function", "-Wno-unused-variable", "-ffp-contract=on"]
 
 
 def sources():

@@ -661,6 +661,9 @@ pa_status pa_create(const pa_physics* phys, int32_t N, int32_t B, void* hip_stre
     d.KX = d.K + 1;
     d.KXP = (d.KX + 7) / 8 * 8;
     d.KY = 2 * d.K + 1;
+    d.cus = 0;
+    if (hipDeviceGetAttribute(&d.cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || d.cus < 1)
+        d.cus = 1;
     d.var = 0;
     d.tpb = 4;
     d.avar = 0;
@@ -757,9 +760,10 @@ pa_status pa_get_shape(const pa_ctx* c, int32_t* N, int32_t* B, int32_t* Kc) {
 pa_status pa_set_tiles(pa_ctx* c, const pa_tiles* t) {
     if (!c || !t) return fail(PA_EINVAL, "NULL argument");
     auto variant_ok = [](int v) { return v < 0 || v <= 2; };
+    auto row_variant_ok = [](int v) { return v < 0 || v <= 3; };
     auto block_ok = [](int b) { return b < 0 || b == 1 || b == 2 || b == 4 || b == 8; };
-    if (!variant_ok(t->row_variant) || !variant_ok(t->adj_variant) || !variant_ok(t->col_variant))
-        return fail(PA_EINVAL, "FFT variants must be 0, 1 or 2 (negative keeps)");
+    if (!row_variant_ok(t->row_variant) || !row_variant_ok(t->adj_variant) || !variant_ok(t->col_variant))
+        return fail(PA_EINVAL, "row FFT variants must be 0..3, column variants 0..2 (negative keeps)");
     if (!block_ok(t->row_teams) || !block_ok(t->adj_teams) || !block_ok(t->col_block))
         return fail(PA_EINVAL, "row teams and col_block must be 1, 2, 4 or 8 (negative keeps)");
     Dims d = c->d;

@@ -24,9 +24,10 @@ namespace pa {
 
 struct Dims {
     int N, B, K, KX, KXP, KY;
-    int var, tpb;    // forward row passes: FFT plan variant (0, 1, 2), rows per workgroup
-    int avar, atpb;  // adjoint row passes: FFT plan variant, rows per workgroup
+    int var, tpb;    // forward row passes: FFT plan variant (0..3; 3 = pipelined), rows (waves) per workgroup
+    int avar, atpb;  // adjoint row passes: FFT plan variant (0..3), rows (waves) per workgroup
     int cvar, cb;    // column pass: FFT plan variant, kx columns per workgroup
+    int cus;         // compute units of the device (persistent grids)
 };
 
 enum FieldKind : int { F_OMEGA = 0, F_U = 1, F_V = 2, F_WX = 3, F_WY = 4 };

@@ -12,6 +12,9 @@
 //
 // Included once per grid size by kern_<N>.hip, which instantiates Launch<N>.
 #pragma once
+#include <algorithm>
+#include <atomic>
+
 #include "kernels.hpp"
 
 namespace pa {
@@ -583,6 +586,200 @@ __global__ void __launch_bounds__(512) col_kernel(Dims d, ColArgs a) {
     }
 }
 
+// ---------------------------------------- pipelined row passes (gfx950) --
+// Variant 3 of the row passes: the plan of variant 2 run by persistent
+// wavefronts.  A wavefront owns G = 64 / T consecutive rows of one member
+// (contiguous in the Y layout) at a time and loops over such row groups.
+// The half spectra of its next group stream from HBM straight into a
+// per-wave LDS stage buffer (global->LDS loads: no registers are held while
+// they are in flight) while it transforms the current group.  They are read
+// into registers, with the Hermitian extension, just before the current
+// group's outputs are stored, so the wait for them never waits on fresh
+// stores.  Only the twiddle staging synchronises the workgroup.
+
+constexpr int PIPE_V = 2;   // plan variant run by the pipelined kernels
+
+template <int N>
+struct Pipe {
+    static constexpr int T = Plan<N, PIPE_V>::T, E = Plan<N, PIPE_V>::E;
+    static constexpr int G = (T <= 64 && 64 % T == 0) ? 64 / T : 1;   // rows per wavefront
+    static constexpr bool OK = T <= 64 && 64 % T == 0 && G <= N;
+    static constexpr int KXP = kx_pad<N>();
+    static constexpr int SPAN = G * KXP;                   // elements of one field of a row group
+    static constexpr int LOADS = (SPAN + 63) / 64;         // 64-lane loads per field
+    template <int NF>
+    static constexpr int wave_lds() { return NF * SPAN + G * lds_team<N>(); }
+    static __host__ __device__ size_t offset(int group) {  // first element of a row group
+        constexpr int GPM = N / G;
+        return ((size_t)(group / GPM) * N + (size_t)(group % GPM) * G) * KXP;
+    }
+};
+
+__device__ __forceinline__ void vm_wait() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
+// Returns v unchanged, opaquely: index arithmetic derived from it inside a
+// loop is not hoisted out of the loop (where its results would occupy
+// registers for the loop's whole lifetime) but recomputed per iteration.
+__device__ __forceinline__ int opaque(int v) {
+    asm volatile("" : "+v"(v));
+    return v;
+}
+
+// Global->LDS loads of one row group of NF fields into the wave's stage
+// buffer (lane l of a load lands at the load's LDS base + l).  The LDS base
+// of these loads goes to M0 and must be uniform over the wavefront: the
+// full-wave loads are issued first with no condition, and the partial final
+// loads of all fields together in one conditional block, so that the compiler
+// never merges a masked load with a load of another LDS base (the merged
+// instruction would take one lane's base for every lane).
+template <int N, int NF>
+__device__ __forceinline__ void pipe_fetch(cd* stage, const cd* const (&src)[NF], size_t off, int lane) {
+    using P = Pipe<N>;
+    constexpr int FULL = P::SPAN / 64, TAIL = P::SPAN % 64;
+#pragma unroll
+    for (int f = 0; f < NF; ++f)
+#pragma unroll
+        for (int i = 0; i < FULL; ++i)
+            __builtin_amdgcn_global_load_lds(src[f] + off + i * 64 + lane,
+                                             (__attribute__((address_space(3))) void*)(stage + f * P::SPAN + i * 64),
+                                             16, 0, 0);
+    if constexpr (TAIL > 0) {
+        if (lane < TAIL) {
+#pragma unroll
+            for (int f = 0; f < NF; ++f)
+                __builtin_amdgcn_global_load_lds(src[f] + off + FULL * 64 + lane,
+                                                 (__attribute__((address_space(3))) void*)(stage + f * P::SPAN + FULL * 64),
+                                                 16, 0, 0);
+        }
+    }
+}
+
+template <int N>
+__global__ void __launch_bounds__(256) row_nl_pipe_kernel(Dims d, RowArgs a, int n_groups) {
+    using P = Pipe<N>;
+    constexpr int V = PIPE_V, T = P::T, E = P::E, KXP = P::KXP, NF = 4, WL_ = true;
+    extern __shared__ cd smem[];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, team = lane / T, t0 = lane % T;
+    const int wpg = blockDim.x >> 6;
+    cd* const stage = smem + wave * P::template wave_lds<NF>();
+    cd* const lds = stage + NF * P::SPAN + team * lds_team<N>();
+    const cd* twl = stage_twiddles<N, V>(smem + wpg * P::template wave_lds<NF>(), a.tw);
+    const int nw = gridDim.x * wpg;
+    int g = blockIdx.x * wpg + wave;
+    const cd* const src[NF] = {a.yin[0], a.yin[2], a.yin[1], a.yin[3]};   // (U, Wx), (V, Wy)
+    const cd* const row = stage + team * KXP;
+    cd z1[E], z2[E];
+    if (g < n_groups) {
+        pipe_fetch<N, NF>(stage, src, P::offset(g), lane);
+        vm_wait();
+        herm_load<N, V>(z1, row, row + P::SPAN, t0);
+        wave_lds_sync();
+        herm_load<N, V>(z2, row + 2 * P::SPAN, row + 3 * P::SPAN, t0);
+        wave_lds_sync();
+        if (g + nw < n_groups) pipe_fetch<N, NF>(stage, src, P::offset(g + nw), lane);
+    }
+    for (; g < n_groups; g += nw) {
+        const int t = opaque(t0);
+        fft<N, V, true, WL_>(z1, t, lds, twl);
+        fft<N, V, true, WL_>(z2, t, lds, twl);
+        cd z[E];
+#pragma unroll
+        for (int m = 0; m < E; ++m) z[m] = mk(z1[m].x * z1[m].y + z2[m].x * z2[m].y, 0.0);
+        fft<N, V, false, WL_>(z, t, lds, twl);
+        const int gn = g + nw;
+        if (gn < n_groups) {
+            vm_wait();
+            herm_load<N, V>(z1, row, row + P::SPAN, t);
+            wave_lds_sync();
+            herm_load<N, V>(z2, row + 2 * P::SPAN, row + 3 * P::SPAN, t);
+            wave_lds_sync();
+            if (gn + nw < n_groups) pipe_fetch<N, NF>(stage, src, P::offset(gn + nw), lane);
+        }
+        cd* o = a.yout[0] + P::offset(g) + team * KXP;
+#pragma unroll
+        for (int m = 0; m < E; ++m) {
+            const int k = t + T * m;
+            if (slot_low<N, V>(m) && k <= band<N>()) o[k] = z[m];
+        }
+    }
+}
+
+template <int N>
+__global__ void __launch_bounds__(256) row_adj_pipe_kernel(Dims d, RowArgs a, int n_groups) {
+    using P = Pipe<N>;
+    constexpr int V = PIPE_V, T = P::T, E = P::E, KXP = P::KXP, NF = 6, WL_ = true;
+    extern __shared__ cd smem[];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, team = lane / T, t0 = lane % T;
+    const int wpg = blockDim.x >> 6;
+    cd* const stage = smem + wave * P::template wave_lds<NF>();
+    cd* const lds = stage + NF * P::SPAN + team * lds_team<N>();
+    const cd* twl = stage_twiddles<N, V>(smem + wpg * P::template wave_lds<NF>(), a.tw);
+    const int nw = gridDim.x * wpg;
+    int g = blockIdx.x * wpg + wave;
+    // (Lam, Lam_y), (U, Wx), (V, Wy)
+    const cd* const src[NF] = {a.yin[4], a.yin[5], a.yin[0], a.yin[2], a.yin[1], a.yin[3]};
+    const cd* const row = stage + team * KXP;
+    cd L[E], z1[E], z2[E];
+    // one signal pair at a time: LDS latency is short, and the raw values of
+    // all three pairs in flight at once would double the registers held
+    auto read_inputs = [&](int t) {
+        herm_load<N, V, true>(L, row, row + P::SPAN, t);
+        wave_lds_sync();
+        herm_load<N, V>(z1, row + 2 * P::SPAN, row + 3 * P::SPAN, t);
+        wave_lds_sync();
+        herm_load<N, V>(z2, row + 4 * P::SPAN, row + 5 * P::SPAN, t);
+        wave_lds_sync();
+    };
+    if (g < n_groups) {
+        pipe_fetch<N, NF>(stage, src, P::offset(g), lane);
+        vm_wait();
+        read_inputs(t0);
+        if (g + nw < n_groups) pipe_fetch<N, NF>(stage, src, P::offset(g + nw), lane);
+    }
+    for (; g < n_groups; g += nw) {
+        const int t = opaque(t0);
+        fft<N, V, true, WL_>(L, t, lds, twl);
+        fft<N, V, true, WL_>(z1, t, lds, twl);
+        fft<N, V, true, WL_>(z2, t, lds, twl);
+        cd G[E];
+#pragma unroll
+        for (int m = 0; m < E; ++m)
+            G[m] = mk(z1[m].y * L[m].y - z2[m].y * L[m].x, z1[m].x * L[m].x + z2[m].x * L[m].y);
+        fft<N, V, false, WL_>(G, t, lds, twl);
+        const int gn = g + nw;
+        if (gn < n_groups) {
+            vm_wait();
+            read_inputs(t);
+            if (gn + nw < n_groups) pipe_fetch<N, NF>(stage, src, P::offset(gn + nw), lane);
+        }
+        const size_t ro = P::offset(g) + team * KXP;
+        split_store<N, V, WL_>(G, t, lds, a.yout[0] + ro, a.yout[1] + ro);
+    }
+}
+
+// Persistent grid: as many workgroups as can be resident (occupancy query,
+// cached per kernel and workgroup size), at most one row group per wave.
+template <int N, int NF, class Kern>
+hipError_t pipe_launch(Kern kernel, int teams, const Dims& d, const RowArgs& a, hipStream_t s) {
+    using P = Pipe<N>;
+    const int n_groups = d.B * (N / P::G);
+    const int wpg = teams >= 4 ? 4 : teams >= 2 ? 2 : 1;
+    const size_t lds = ((size_t)wpg * P::template wave_lds<NF>() + N) * sizeof(cd);
+    static std::atomic<int> per_cu_cache[3];
+    std::atomic<int>& slot = per_cu_cache[wpg == 1 ? 0 : wpg == 2 ? 1 : 2];
+    int per_cu = slot.load(std::memory_order_relaxed);
+    if (per_cu <= 0) {
+        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, wpg * 64, lds);
+        if (e != hipSuccess) return e;
+        if (per_cu < 1) return hipErrorInvalidConfiguration;
+        slot.store(per_cu, std::memory_order_relaxed);
+    }
+    const long want = (n_groups + wpg - 1) / wpg;
+    const long wgs = std::min<long>(want, (long)per_cu * std::max(d.cus, 1));
+    hipLaunchKernelGGL(kernel, dim3((unsigned)wgs), dim3((unsigned)(wpg * 64)), lds, s, d, a, n_groups);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------- launchers --
 
 // Teams per workgroup: must divide the teams per member (the kernels take the
@@ -611,7 +808,8 @@ size_t row_lds(int tpb) { return ((size_t)tpb * lds_team<N>() + N) * sizeof(cd);
     } while (0)
 
 // VAR / TPB: the plan variant and rows per workgroup of the launching pass
-// (forward rows: d.var, d.tpb; adjoint rows: d.avar, d.atpb).
+// (forward rows: d.var, d.tpb; adjoint rows: d.avar, d.atpb).  Variant 3
+// (pipelined) runs the plan of variant 2 in the kernels it does not cover.
 #define PA_ROW_LAUNCH(VAR, TPB, KERNEL, TEAMS_PER_MEMBER, ...)                                 \
     do {                                                                                       \
         const long tpm_ = (TEAMS_PER_MEMBER);                                                  \
@@ -633,6 +831,8 @@ hipError_t Launch<N>::row_c2r(const Dims& d, const cd* in, double* out, const cd
 template <int N>
 hipError_t Launch<N>::row_nl(const Dims& d, const RowArgs& a, hipStream_t s) {
     if (a.obs.slot >= 0) PA_ROW_LAUNCH(d.var, d.tpb, row_nl_obs_kernel, N, d, a);
+    if constexpr (Pipe<N>::OK)
+        if (d.var == 3) return pipe_launch<N, 4>(row_nl_pipe_kernel<N>, d.tpb, d, a, s);
     PA_ROW_LAUNCH(d.var, d.tpb, row_nl_kernel, N, d, a);
 }
 template <int N>
@@ -641,6 +841,8 @@ hipError_t Launch<N>::row_obs(const Dims& d, const RowArgs& a, hipStream_t s) {
 }
 template <int N>
 hipError_t Launch<N>::row_adj(const Dims& d, const RowArgs& a, hipStream_t s) {
+    if constexpr (Pipe<N>::OK)
+        if (d.avar == 3) return pipe_launch<N, 6>(row_adj_pipe_kernel<N>, d.atpb, d, a, s);
     PA_ROW_LAUNCH(d.avar, d.atpb, row_adj_kernel, N, d, a);
 }
 template <int N>

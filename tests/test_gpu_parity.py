@@ -161,8 +161,8 @@ def test_tile_variants_gradient_parity(N):
     obs = Observations(8, osteps, dev(mo))
     blocks = (1, 2, 4, 8)
     i = 0
-    for rv in (0, 1, 2):
-        for av in (0, 1, 2):
+    for rv in (0, 1, 2, 3):
+        for av in (0, 1, 2, 3):
             for cv in (0, 1, 2):
                 tiles = dict(row_variant=rv, row_teams=blocks[i % 4], adj_variant=av, adj_teams=blocks[(i + 1) % 4],
                              col_variant=cv, col_block=blocks[(i + 2) % 4] if cv == 0 else blocks[(i + 3) % 4])
@@ -178,6 +178,32 @@ def test_tile_variants_gradient_parity(N):
                     assert rel(gh[b], ref[b][1]) < GRAD_TOL, (tiles, b, rel(gh[b], ref[b][1]))
 
 
+@pytest.mark.parametrize("N,B", [(64, 64), (128, 48), (256, 24)])
+def test_pipelined_rows_bitwise_equal_plain_rows(N, B):
+    """Variant 3 (persistent wavefronts, next row group prefetched into LDS) runs the arithmetic of
+    variant 2: the gradient must be bitwise identical.  The batch makes every wavefront loop over
+    several row groups, so the prefetch path is exercised; member 0 is also checked against the oracle."""
+    from paper_2602_14016_amd import Observations
+    announce("pipelined-rows", N, B)
+    ph = _hit(N, nu=1e-3, dt=2e-3)
+    steps, osteps = 4, [0, 4]
+    w0 = np.stack([O.init_field(N, [40 + b % 3], kind=0, k0=min(8.0, N / 8))[0] * (1 + 0.01 * b) for b in range(B)])
+    mo0 = _twin(N, ph, steps, osteps, 8, seed=50)
+    mo = np.repeat(mo0[None], B, axis=0)
+    s = solver(N, B, ph)
+    obs = Observations(8, osteps, dev(mo))
+    res = {}
+    for v in (2, 3):
+        s.set_tiles(row_variant=v, adj_variant=v, row_teams=4, adj_teams=4, col_variant=1, col_block=8)
+        J, g = s.adjoint_gradient(dev(w0), steps, obs, ckpt_every=2)
+        res[v] = (host(J), host(g))
+    assert np.array_equal(res[2][0], res[3][0])
+    assert np.array_equal(res[2][1], res[3][1])
+    Jref, gref = O.adjoint_gradient(w0[0], ph, steps, Obs(8, osteps, mo0))
+    assert rel(res[3][1][0], gref) < GRAD_TOL
+    assert abs(float(res[3][0][0]) - Jref) <= FIELD_TOL * Jref
+
+
 def test_set_tiles_validation_and_readback():
     announce("tiles-api")
     from paper_2602_14016_amd.native import PaError
@@ -187,7 +213,7 @@ def test_set_tiles_validation_and_readback():
                                  col_block=4)
     s.set_tiles(adj_teams=4)   # others kept
     assert s.get_tiles()["adj_teams"] == 4 and s.get_tiles()["row_variant"] == 2
-    for bad in (dict(row_variant=3), dict(col_block=3), dict(adj_teams=16)):
+    for bad in (dict(row_variant=4), dict(col_variant=3), dict(col_block=3), dict(adj_teams=16)):
         with pytest.raises(PaError):
             s.set_tiles(**bad)
     assert s.get_tiles()["col_block"] == 4
@@ -205,8 +231,9 @@ def test_autotune_applies_valid_tiles():
     Jref, gref = O.adjoint_gradient(w0, ph, steps, Obs(4, osteps, mo))
     s = solver(N, 1, ph)
     at = autotune(s, n_steps=4, reps=1)
-    for k in ("row_variant", "adj_variant", "col_variant"):
-        assert at[k] in (0, 1, 2)
+    for k in ("row_variant", "adj_variant"):
+        assert at[k] in (0, 1, 2, 3)
+    assert at["col_variant"] in (0, 1, 2)
     for k in ("row_teams", "adj_teams", "col_block"):
         assert at[k] in (1, 2, 4, 8)
     assert s.get_tiles() == {k: at[k] for k in s.get_tiles()}
