@@ -20,10 +20,8 @@ CPU oracle timed on a bounded sample.
 """
 
 import argparse
-import hashlib
 import json
 import os
-import statistics
 import sys
 import time
 
@@ -31,24 +29,6 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "grid-point-steps/s fwd+adj FP64, batched vs plain at 256²; p50/p99 solve latency"
-HBM_PEAK_GBS = 8000.0
-
-# Kernel classes (pa_profile_start) and their algorithmic bytes per member.
-# Yb: one field's band-limited y-transform N*(Kc+1) complex; Cb: one compact
-# spectral state (2Kc+1)*(Kc+1) complex.
-CLASS_NAMES = {0: "row_nl_kernel", 1: "col_kernel (forward stages)", 2: "row_adj_kernel",
-               3: "col_kernel (adjoint stages)"}
-
-
-def algorithmic_bytes(cls, N):
-    Kc = (N - 1) // 3
-    Yb = N * (Kc + 1) * 16
-    Cb = (2 * Kc + 1) * (Kc + 1) * 16
-    return {0: 5 * Yb,                 # read U,V,Wx,Wy; write q
-            1: 5 * Yb + 2.75 * Cb,     # read q; write 4 fields; state/accumulator (mean of stages A-D)
-            2: 8 * Yb,                 # read U,V,Wx,Wy,Lambda,Lambda_y; write 2 products
-            3: 4 * Yb + 2.5 * Cb}[cls]  # read 2 products; write Lambda, Lambda_y; adjoint accumulators
-
 
 def percentile(xs, p):
     xs = sorted(xs)
@@ -58,36 +38,6 @@ def percentile(xs, p):
     lo = int(k)
     hi = min(lo + 1, len(xs) - 1)
     return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
-
-
-def kernel_source_sha():
-    h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_2602_14016_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
-        if f.endswith((".hip", ".hpp")):
-            h.update(open(os.path.join(csrc, f), "rb").read())
-    return h.hexdigest()[:16]
-
-
-def read_traffic(cls, N, members):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel sources; else None."""
-    path = os.path.join(ROOT, "profiles", "traffic_counters.txt")
-    if not os.path.exists(path):
-        return None
-    kv = {}
-    for line in open(path):
-        if ":" in line and not line.startswith("#"):
-            k, v = line.split(":", 1)
-            kv[k.strip()] = v.strip()
-    if kv.get("source_sha") != kernel_source_sha():
-        return None
-    if int(kv.get("class", -1)) != cls or int(kv.get("N", -1)) != N or int(kv.get("members", -1)) != members:
-        return None
-    try:
-        return float(kv["hbm_bytes_per_launch"])
-    except (KeyError, ValueError):
-        return None
 
 
 def cpu_baseline(N, nu, dt, steps_sample, k0):
@@ -145,6 +95,7 @@ def main():
 
     import torch
     from paper_2602_14016_amd import Solver
+    from paper_2602_14016_amd.roofline import CLASS_NAMES, HBM_PEAK_GBS, algorithmic_bytes, read_traffic
 
     N, B, H = args.N, args.members, args.horizon
     nu, dt, k0 = 1e-4, 2e-3, 10.0
@@ -263,7 +214,13 @@ def main():
     per_launch_ms = prof["total_ms"] / max(prof["timed_launches"], 1)
     bytes_launch = algorithmic_bytes(cls, N) * B
     achieved = bytes_launch / (per_launch_ms * 1e-3) / 1e9
-    traffic = read_traffic(cls, N, B)
+    variant = tiles["adj_variant"] if cls >= 2 else tiles["row_variant"] if cls == 0 else tiles["col_variant"]
+    kname = CLASS_NAMES[cls].split(" ")[0]
+    if cls in (0, 2):
+        kname = f"{kname.replace('_kernel', '_pipe_kernel')}<{N}>" if variant == 3 else f"{kname}<{N}, {variant}>"
+    else:
+        kname = None
+    traffic = read_traffic(cls, N, B, kernel=kname)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": CLASS_NAMES[cls], "avg_launch_ms": round(per_launch_ms, 4),
