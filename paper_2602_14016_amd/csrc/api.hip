@@ -452,7 +452,8 @@ pa_status adj_stage(pa_ctx* c, WS& w, cd* const fields[4], int mode, const ObsPl
         a.yout[1] = w.YL[1];
         a.fields[1] = F_WY;
     }
-    PA_HIP(timed(c, PROF_COL_ADJ, [&] { return launch_col(c->d, mode, a, c->stream); }));
+    const int cmode = (mode == COL_ADJ_N && a.nin > 2) ? COL_ADJ_NSRC : mode;
+    PA_HIP(timed(c, PROF_COL_ADJ, [&] { return launch_col(c->d, cmode, a, c->stream); }));
     return PA_OK;
 }
 

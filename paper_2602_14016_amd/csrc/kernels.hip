@@ -21,8 +21,9 @@ static bool col_ptrs_ok(int mode, const ColArgs& a) {
         case COL_FILTER: return a.yin[0] && a.mult;
         case COL_FROM_STATE: return a.state_in != nullptr;
         case COL_FIRST_GUESS: return a.yin[0] && a.yin[1] && a.lowpass >= 0;
-        case COL_ADJ_C: case COL_ADJ_B: case COL_ADJ_A: case COL_ADJ_N: case COL_ADJ_SRC:
-            if (a.nin < 2 || a.nin > 4 || !a.lam) return false;
+        case COL_ADJ_C: case COL_ADJ_B: case COL_ADJ_A: case COL_ADJ_N: case COL_ADJ_SRC: case COL_ADJ_NSRC:
+            // extra (observation source) inputs are read by COL_ADJ_NSRC only
+            if (a.nin < 2 || a.nin > (mode == COL_ADJ_NSRC ? 4 : 2) || !a.lam) return false;
             if (mode != COL_ADJ_SRC && !a.omb) return false;
             for (int p = 0; p < a.nin; ++p)
                 if (!a.yin[p] || a.inmul[p] < IN_INVK2 || a.inmul[p] > IN_MIKX_INVK2) return false;

@@ -42,7 +42,8 @@ enum ColMode : int {
     COL_FROM_STATE = 6,   // compact state -> derived fields (no input transform)
     COL_ADJ_C = 7, COL_ADJ_B = 8, COL_ADJ_A = 9, COL_ADJ_N = 10,  // adjoint stages
     COL_ADJ_SRC = 11, // terminal source -> lambda_H
-    COL_FIRST_GUESS = 12  // probe velocities (u, v grids) -> band-limited vorticity
+    COL_FIRST_GUESS = 12, // probe velocities (u, v grids) -> band-limited vorticity
+    COL_ADJ_NSRC = 13     // adjoint stage n at an observed step: two more inputs (residual sources)
 };
 
 struct ColArgs {

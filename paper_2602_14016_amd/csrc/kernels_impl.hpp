@@ -346,7 +346,8 @@ template <int N, int V, int MODE>
 __global__ void __launch_bounds__(512) col_kernel(Dims d, ColArgs a) {
     constexpr int T = Plan<N, V>::T, E = Plan<N, V>::E;
     constexpr bool FWD_STAGE = MODE >= COL_A && MODE <= COL_D;
-    constexpr bool ADJ = MODE >= COL_ADJ_C && MODE <= COL_ADJ_SRC;
+    constexpr bool ADJ = (MODE >= COL_ADJ_C && MODE <= COL_ADJ_SRC) || MODE == COL_ADJ_NSRC;
+    constexpr bool STAGE_N = MODE == COL_ADJ_N || MODE == COL_ADJ_NSRC;
     extern __shared__ cd smem[];
     const int CB = d.cb;
     const int c = threadIdx.x % CB, t = threadIdx.x / CB;
@@ -393,11 +394,14 @@ __global__ void __launch_bounds__(512) col_kernel(Dims d, ColArgs a) {
             v1[m] = colok ? x : czero();
         }
     }
-    if constexpr (FWD_STAGE || ADJ || MODE == COL_FROM_STATE) {
+    // compact operands; the adjoint modes issue them after their first input
+    // transform, which keeps two input columns, the accumulator and these
+    // operands from being live at once (the registers set the occupancy)
+    auto load_compact = [&]() {
         const cd* __restrict__ p0 = FWD_STAGE ? a.omega + cmem : ADJ ? a.lam + cmem : a.state_in + cmem;
         const cd* __restrict__ p1 = FWD_STAGE ? a.acc + cmem : (ADJ && MODE != COL_ADJ_SRC) ? a.omb + cmem : nullptr;
         const bool need1 = (FWD_STAGE && MODE != COL_A) || (ADJ && MODE != COL_ADJ_C && MODE != COL_ADJ_SRC);
-        const bool need0 = !(ADJ && (MODE == COL_ADJ_N || MODE == COL_ADJ_SRC));
+        const bool need0 = !(ADJ && (STAGE_N || MODE == COL_ADJ_SRC));
 #pragma unroll
         for (int m = 0; m < E; ++m) {
             s0[m] = czero();
@@ -414,7 +418,8 @@ __global__ void __launch_bounds__(512) col_kernel(Dims d, ColArgs a) {
                 s1[m] = r >= 0 ? x : czero();
             }
         }
-    }
+    };
+    if constexpr (FWD_STAGE || MODE == COL_FROM_STATE) load_compact();
     const cd* twl = stage_twiddles<N, V>(smem + CB * lds_team<N>(), a.tw);
 
     cd w[E];   // spectral values handed to the output transforms
@@ -515,6 +520,9 @@ __global__ void __launch_bounds__(512) col_kernel(Dims d, ColArgs a) {
         accumulate(v0, a.inmul[0]);
         fft<N, V, false>(v1, t, lds, twl);
         accumulate(v1, a.inmul[1]);
+        load_compact();
+        // observation sources enter at stage n of an observed step only (two more inputs)
+        if constexpr (MODE == COL_ADJ_NSRC)
         for (int p = 2; p < a.nin; ++p) {
             const cd* __restrict__ src = a.yin[p] + ymem;
 #pragma unroll
@@ -548,9 +556,9 @@ __global__ void __launch_bounds__(512) col_kernel(Dims d, ColArgs a) {
                 const cd lm = s0[m], ob = s1[m];
                 stc(ob_p, ci, mk(ob.x + e2 * wb.x, ob.y + e2 * wb.y));
                 w[m] = mk((h / 6.0) * e1 * lm.x + 0.5 * h * e2 * wb.x, (h / 6.0) * e1 * lm.y + 0.5 * h * e2 * wb.y);
-            } else {   // COL_ADJ_N, COL_ADJ_SRC
+            } else {   // stage n (with or without sources), COL_ADJ_SRC
                 cd ln = wb;
-                if constexpr (MODE == COL_ADJ_N) {
+                if constexpr (STAGE_N) {
                     const cd ob = s1[m];
                     ln = mk(ob.x + wb.x, ob.y + wb.y);
                 }
@@ -873,6 +881,7 @@ hipError_t col_variant(const Dims& d, int mode, const ColArgs& a, hipStream_t s)
         case COL_ADJ_B: return col_mode<N, V, COL_ADJ_B>(d, a, s);
         case COL_ADJ_A: return col_mode<N, V, COL_ADJ_A>(d, a, s);
         case COL_ADJ_N: return col_mode<N, V, COL_ADJ_N>(d, a, s);
+        case COL_ADJ_NSRC: return col_mode<N, V, COL_ADJ_NSRC>(d, a, s);
         case COL_ADJ_SRC: return col_mode<N, V, COL_ADJ_SRC>(d, a, s);
         case COL_FIRST_GUESS: return col_mode<N, V, COL_FIRST_GUESS>(d, a, s);
         default: return hipErrorInvalidValue;
