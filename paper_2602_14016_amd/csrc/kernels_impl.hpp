@@ -237,8 +237,14 @@ __device__ __forceinline__ void row_nl_body(const Dims& d, const RowArgs& a) {
     }
 }
 
+// Occupancy hint for the right-hand-side row pass: with at most 8 register
+// slots per thread it fits the 128 VGPRs of four waves per SIMD.
 template <int N, int V>
-__global__ void __launch_bounds__(256) row_nl_kernel(Dims d, RowArgs a) { row_nl_body<N, V, false>(d, a); }
+constexpr int nl_waves() { return Plan<N, V>::E <= 8 ? 4 : 1; }
+
+template <int N, int V>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(nl_waves<N, V>())))
+row_nl_kernel(Dims d, RowArgs a) { row_nl_body<N, V, false>(d, a); }
 template <int N, int V>
 __global__ void __launch_bounds__(256) row_nl_obs_kernel(Dims d, RowArgs a) { row_nl_body<N, V, true>(d, a); }
 
