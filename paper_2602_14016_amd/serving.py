@@ -15,7 +15,16 @@ stamped from arrival to result-ready.
 
 Results of a request are identical whether it runs alone, batched with
 others or concurrently with other slots: every member uses the same kernels
-with the same tiles, and no reduction crosses members.
+with the same tiles (a fixed table per grid size, never chosen per batch),
+and no reduction crosses members.
+
+    python -m paper_2602_14016_amd.serving --requests R --rate HZ [--load F] --out FILE
+
+replays a seeded Poisson trace of the mixed workload (grids 128..1024,
+decaying and Kolmogorov flow, horizons 200..2000, strides 4..16, mixed
+kernels, 10 L-BFGS iterations each) and prints p50/p99 latency and
+throughput; with --load F a second trace runs at F times the capacity the
+first one measured.
 """
 
 import heapq
@@ -91,8 +100,12 @@ def footprint_bytes(solver, req: Request):
 
 
 class Server:
-    def __init__(self, hbm_budget_bytes, slots=4, max_batch=8, device="cuda:0"):
+    def __init__(self, hbm_budget_bytes, slots=4, max_batch=8, device="cuda:0", tiles=None, verbose=False):
+        """tiles: optional {N: pa_tiles dict} applied to every solver of grid size N;
+        verbose: print one line per finished group."""
         self.device = torch.device(device)
+        self.tiles = dict(tiles or {})
+        self.verbose = verbose
         self.budget = int(hbm_budget_bytes)
         self.in_use = 0
         self.slots = slots
@@ -118,8 +131,10 @@ class Server:
         key = (slot, N, flow, B)
         if key not in self._solvers:
             with torch.cuda.stream(self.streams[slot]):
-                self._solvers[key] = Solver(N, B, device=self.device, stream=self.streams[slot],
-                                            **physics_for(flow, N))
+                sv = Solver(N, B, device=self.device, stream=self.streams[slot], **physics_for(flow, N))
+                if N in self.tiles:
+                    sv.set_tiles(**self.tiles[N])
+                self._solvers[key] = sv
         return self._solvers[key]
 
     def _probe_solver(self, req, B):
@@ -170,6 +185,9 @@ class Server:
                                            head.lbfgs_m, head.ckpt_every)
                 w_host = w.cpu()
             fin = self.now()
+            if self.verbose:
+                print(f"[serving] slot {slot}: {B} x {head.N}^2 {head.flow} H={head.n_steps} done at {fin:.2f} s "
+                      f"(admitted {admitted:.2f} s)", flush=True)
             for b, r in enumerate(group):
                 status = "ok" if iters[b] >= 0 else "line-search failure"
                 self.results[r.rid] = Result(r.rid, w_host[b].clone(), [h for h in H[b] if h == h],
@@ -230,3 +248,100 @@ def latency_stats(results):
         return {}
     q = lambda p: float(np.percentile(np.array(lat), p))
     return {"n": len(lat), "p50_s": q(50), "p99_s": q(99), "mean_s": float(np.mean(lat)), "max_s": lat[-1]}
+
+
+# ------------------------------------------------------------ trace CLI --
+
+GRIDS = (128, 256, 512, 1024)
+KERNELS = (KernelSpec(0, 0.0), KernelSpec(1, 0.05), KernelSpec(2, 0.5))
+
+
+def make_trace(n, rate, seed=0, iters=10, grids=GRIDS, h_range=(200, 2000), strides=(4, 8, 16), device="cuda:0"):
+    """Seeded mixed requests with Poisson arrivals; observations (5 evenly spaced
+    times from step 0) come from a truth run of another seed, computed here,
+    before the trace, and kept on the host."""
+    rng = np.random.default_rng(seed)
+    arrivals = poisson_arrivals(n, rate, seed=seed + 1)
+    reqs = []
+    for i in range(n):
+        N = int(rng.choice(grids))
+        flow = DECAYING if rng.random() < 0.5 else KOLMOGOROV
+        H = int(rng.integers(h_range[0], h_range[1] + 1))
+        stride = int(rng.choice(strides))
+        kern = KERNELS[int(rng.integers(len(KERNELS)))]
+        steps = sorted({int(round(j * H / 4)) for j in range(5)})
+        truth_solver = Solver(N, 1, device=device, **physics_for(flow, N))
+        truth = truth_solver.init_field([1000 + i], kind=0 if flow == DECAYING else 2, k0=max(2.0, N / 25),
+                                        target=0.5 if flow == DECAYING else 1e-2)
+        obs = truth_solver.forward(truth, H, Observations(stride, steps), want_obs=True)["obs"][0].cpu()
+        truth_solver.close()
+        reqs.append(Request(rid=i, N=N, flow=flow, n_steps=H, stride=stride, obs_steps=steps, obs_values=obs,
+                            kernel=kern, iters=iters, arrival=float(arrivals[i])))
+    return reqs
+
+
+def tile_table(grids=GRIDS, device="cuda:0"):
+    """One autotuned tile set per grid size (at B = 1), fixed for the whole trace."""
+    from .autotune import autotune
+    table = {}
+    for N in grids:
+        sv = Solver(N, 1, device=device, **physics_for(DECAYING, N))
+        at = autotune(sv, n_steps=4)
+        table[N] = sv.get_tiles()
+        sv.close()
+    return table
+
+
+def trace_report(results, requests, t_wall):
+    ok = [r for r in results.values() if r.status == "ok"]
+    work = sum(q.N * q.N * q.n_steps for q in requests if results[q.rid].status == "ok")
+    out = latency_stats(results)
+    out.update({"requests": len(requests), "completed": len(ok), "wall_s": t_wall,
+                "throughput_req_per_s": len(ok) / t_wall if t_wall > 0 else None,
+                "grid_point_steps_per_iteration_per_s": work * (requests[0].iters if requests else 0) / t_wall,
+                "batched_solves": sum(1 for r in ok if r.batch > 1)})
+    return out
+
+
+def main(argv=None):
+    import argparse
+    import json
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--requests", type=int, default=40)
+    ap.add_argument("--rate", type=float, default=20.0, help="arrivals per second")
+    ap.add_argument("--load", type=float, default=0.0, help="also replay at this fraction of measured capacity")
+    ap.add_argument("--iters", type=int, default=10)
+    ap.add_argument("--slots", type=int, default=4)
+    ap.add_argument("--max-batch", type=int, default=8)
+    ap.add_argument("--budget-gb", type=float, default=200.0)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--out", default=None)
+    args = ap.parse_args(argv)
+    tiles = tile_table()
+    print("tiles", json.dumps({str(k): v for k, v in tiles.items()}), flush=True)
+    report = {"tiles": {str(k): v for k, v in tiles.items()}, "traces": []}
+    rate = args.rate
+    for label in ("offered", "capacity") if args.load > 0 else ("offered",):
+        reqs = make_trace(args.requests, rate, seed=args.seed, iters=args.iters)
+        print(f"trace {label}: {len(reqs)} requests at {rate:.2f}/s", flush=True)
+        srv = Server(int(args.budget_gb * (1 << 30)), slots=args.slots, max_batch=args.max_batch, tiles=tiles,
+                     verbose=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = srv.run_trace(reqs)
+        t_wall = time.perf_counter() - t0
+        rep = trace_report(res, reqs, t_wall)
+        rep.update({"trace": label, "rate_per_s": rate})
+        print(json.dumps(rep), flush=True)
+        report["traces"].append(rep)
+        if label == "offered" and args.load > 0:
+            busy = max(r.finished for r in res.values()) - min(r.admitted for r in res.values())
+            capacity = rep["completed"] / busy if busy > 0 else rate
+            rate = args.load * capacity
+    if args.out:
+        with open(args.out, "w") as fh:
+            json.dump(report, fh, indent=1)
+
+
+if __name__ == "__main__":
+    main()
