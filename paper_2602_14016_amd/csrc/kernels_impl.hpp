@@ -237,14 +237,46 @@ __device__ __forceinline__ void row_nl_body(const Dims& d, const RowArgs& a) {
     }
 }
 
-// Occupancy hint for the right-hand-side row pass: with at most 8 register
-// slots per thread it fits the 128 VGPRs of four waves per SIMD.
+// Occupancy hint for the right-hand-side row pass: with 8 register slots per
+// thread (one row per team) it fits the 128 VGPRs of four waves per SIMD; the
+// two-row kernel of the 4-slot plan holds both rows' loads and gets three.
 template <int N, int V>
-constexpr int nl_waves() { return Plan<N, V>::E <= 8 ? 4 : 1; }
+constexpr int nl_waves() { return V == 2 ? 3 : Plan<N, V>::E <= 8 ? 4 : 1; }
+
+// Two rows per team: q of both rows is real, so one complex transform of
+// q_a + i q_b, split into the two half spectra, replaces two transforms of
+// real signals (2.5 transforms per row instead of 3).  Used with the
+// four-values-per-thread plan, where both rows' signals fit in registers.
+template <int N, int V>
+__device__ __forceinline__ void row_nl_pair_body(const Dims& d, const RowArgs& a) {
+    const cd* __restrict__ tw_g = a.tw;
+    PA_TEAM_SETUP(N, V, N / 2)
+    constexpr int KXP = kx_pad<N>();
+    const size_t ra = ((size_t)b * N + 2 * wi) * KXP, rb = ra + KXP;
+    cd z1[E], z2[E], y1[E], y2[E];
+    herm_load<N, V>(z1, a.yin[0] + ra, a.yin[2] + ra, t);   // row a: u + i w_x
+    herm_load<N, V>(z2, a.yin[1] + ra, a.yin[3] + ra, t);   //        v + i w_y
+    herm_load<N, V>(y1, a.yin[0] + rb, a.yin[2] + rb, t);   // row b
+    herm_load<N, V>(y2, a.yin[1] + rb, a.yin[3] + rb, t);
+    const cd* twl = stage_twiddles<N, V>(tw_lds, tw_g);
+    fft<N, V, true, WL>(z1, t, lds, twl);
+    fft<N, V, true, WL>(z2, t, lds, twl);
+    fft<N, V, true, WL>(y1, t, lds, twl);
+    fft<N, V, true, WL>(y2, t, lds, twl);
+    cd z[E];
+#pragma unroll
+    for (int m = 0; m < E; ++m)
+        z[m] = mk(z1[m].x * z1[m].y + z2[m].x * z2[m].y, y1[m].x * y1[m].y + y2[m].x * y2[m].y);
+    fft<N, V, false, WL>(z, t, lds, twl);
+    split_store<N, V, WL>(z, t, lds, a.yout[0] + ra, a.yout[0] + rb);
+}
 
 template <int N, int V>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(nl_waves<N, V>())))
-row_nl_kernel(Dims d, RowArgs a) { row_nl_body<N, V, false>(d, a); }
+row_nl_kernel(Dims d, RowArgs a) {
+    if constexpr (V == 2) row_nl_pair_body<N, V>(d, a);
+    else row_nl_body<N, V, false>(d, a);
+}
 template <int N, int V>
 __global__ void __launch_bounds__(256) row_nl_obs_kernel(Dims d, RowArgs a) { row_nl_body<N, V, true>(d, a); }
 
@@ -847,6 +879,7 @@ hipError_t Launch<N>::row_nl(const Dims& d, const RowArgs& a, hipStream_t s) {
     if (a.obs.slot >= 0) PA_ROW_LAUNCH(d.var, d.tpb, row_nl_obs_kernel, N, d, a);
     if constexpr (Pipe<N>::OK)
         if (d.var == 3) return pipe_launch<N, 4>(row_nl_pipe_kernel<N>, d.tpb, d, a, s);
+    if (d.var == 2) PA_ROW_LAUNCH(d.var, d.tpb, row_nl_kernel, N / 2, d, a);   // two rows per team
     PA_ROW_LAUNCH(d.var, d.tpb, row_nl_kernel, N, d, a);
 }
 template <int N>
