@@ -197,16 +197,56 @@ pa_status pa_assimilate(pa_ctx* ctx, double* omega_inout, int32_t n_steps, const
                         int32_t lbfgs_m, int32_t ckpt_every, double* J_hist,
                         int32_t* iters_done, void* workspace, size_t workspace_bytes);
 
+/* Running sums of an ensemble of impulse responses, accumulated by
+ * pa_adjoint_impulse over any number of calls (batches of members), for the
+ * ensemble statistics of Sec. IV.  The caller allocates the device buffers
+ * (sizes from pa_ensemble_acc_bytes), zeroes them and sets count = 0 before
+ * the first batch; each call adds its B members, one at a time in member
+ * order, and adds B to count, so any split of an ensemble into batches gives
+ * bitwise the same sums.
+ *   lambda_sum  device, complex [n_steps + 1][2Kc + 1][KXP] (the compact
+ *               spectral layout: kx = 0..Kc of each ky row, padded to KXP =
+ *               8 * ceil((Kc + 1) / 8); padding is never written): sum over
+ *               members of the adjoint state at each backward step
+ *   energy_sum  device [n_steps + 1]: sum over members of the total adjoint
+ *               energy sum_k 1/2 |k|^2 |lambda_hat|^2 / N^4
+ *   shell_sum   device [n_steps + 1][n_shells]: sum over members of the
+ *               shell energies (the n_shells of the accumulating calls) */
+typedef struct pa_ensemble_acc {
+    void* lambda_sum;
+    double* energy_sum;
+    double* shell_sum;
+    int64_t count;
+} pa_ensemble_acc;
+
+pa_status pa_ensemble_acc_bytes(const pa_ctx* ctx, int32_t n_steps, int32_t n_shells, size_t* lambda_bytes,
+                                size_t* energy_bytes, size_t* shell_bytes);
+
 /* Adjoint impulse response (Sec. IV): forward n_steps from omega0, then the
  * adjoint from a unit u-impulse at grid point (ix, iy) at the final step.
  * shells_out: device [B][n_steps + 1][n_shells], row r = backward step r
  * (tau = r dt, row 0 the terminal field), entry k-1 = sum over
  * k <= |k| < k+1 of 1/2 |k|^2 |lambda_hat|^2 / N^4 (Eq. (20) with unit shell
- * width).  field_out: device [B][N][N] or NULL, P lambda at step 0. */
+ * width).  field_out: device [B][N][N] or NULL, P lambda at step 0.
+ * acc: NULL, or ensemble sums to add this batch to (see pa_ensemble_acc;
+ * its shell_sum has n_shells columns). */
 pa_status pa_adjoint_impulse(pa_ctx* ctx, const double* omega0, int32_t n_steps,
                              int32_t ix, int32_t iy, int32_t n_shells, double* shells_out,
-                             double* field_out, int32_t ckpt_every, void* workspace,
-                             size_t workspace_bytes);
+                             double* field_out, pa_ensemble_acc* acc, int32_t ckpt_every,
+                             void* workspace, size_t workspace_bytes);
+
+/* Ensemble statistics from accumulated sums (Sec. IV), per backward step
+ * r < rows (rows <= n_steps + 1 of the accumulation), all device outputs:
+ *   mean_energy      [rows][n_shells]  mean over members of the shell energy
+ *   energy_of_mean   [rows][n_shells]  shell energy of the ensemble-mean adjoint
+ *   total_mean       [rows]            mean over members of the total adjoint energy
+ *   total_of_mean    [rows]            total energy of the ensemble-mean adjoint
+ *   snr              [rows]            total_of_mean / total_mean
+ * n_shells must equal the accumulating calls' n_shells.  PA_EINVAL if
+ * acc->count < 1 or a pointer is NULL. */
+pa_status pa_ensemble_stats(pa_ctx* ctx, const pa_ensemble_acc* acc, int32_t rows, int32_t n_shells,
+                            double* mean_energy, double* energy_of_mean, double* total_mean,
+                            double* total_of_mean, double* snr);
 
 /* First guess from the probe velocities at t = 0 (the paper's "initial
  * interpolated state", Sec. III.A): spectral interpolation of the M x M probe

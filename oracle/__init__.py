@@ -24,7 +24,7 @@ precond    weighting kernels W(k), metric, precondition (Sec. II.B-C,
            Eqs. (13)-(19); Sec. III.B)
 optim      steepest descent and L-BFGS in the latent variable (Sec. II.C)
 fields     counter-based RNG, initial fields, first guess (Sec. III)
-ensemble   adjoint impulse response, shell energies, growth rates (Sec. IV)
+ensemble   adjoint impulse response, shell energies, growth rates, ensemble statistics (Sec. IV)
 """
 
 from .dft import twiddles, dft_matrix, fft2, ifft2
@@ -33,7 +33,7 @@ from .adjoint import adjoint_gradient, tlm_step, adjoint_step, tlm_trajectory
 from .precond import Kernel, weight, precondition
 from .optim import lbfgs_two_loop, assimilate
 from .fields import splitmix64, uniform01, init_field, first_guess
-from .ensemble import impulse_adjoint, shell_energy, growth_rates
+from .ensemble import impulse_adjoint, impulse_lambdas, shell_energy, total_energy, growth_rates, ensemble_statistics
 
 __all__ = [
     "twiddles", "dft_matrix", "fft2", "ifft2",
@@ -42,5 +42,6 @@ __all__ = [
     "Kernel", "weight", "precondition",
     "lbfgs_two_loop", "assimilate",
     "splitmix64", "uniform01", "init_field", "first_guess",
-    "impulse_adjoint", "shell_energy", "growth_rates",
+    "impulse_adjoint", "impulse_lambdas", "shell_energy", "total_energy", "growth_rates",
+    "ensemble_statistics",
 ]

@@ -13,6 +13,11 @@ lambda_hat, so the shell energy is sum 1/2 |k|^2 |lambda_hat|^2 / N^4.  Shell
 membership uses the exact integer square root of kx^2 + ky^2.  The growth rate
 of a shell is the least-squares slope of ln(mean energy) against backward time
 tau after the initial transient (the paper reports about 0.3, Sec. IV).
+
+Ensemble statistics (Sec. IV): the energy of the ensemble-mean adjoint (its
+reproducible part), the mean over members of the adjoint energy (mean plus
+fluctuations), per shell and in total, and their ratio, the signal-to-noise
+ratio of the adjoint sensitivity.
 """
 
 import math
@@ -40,13 +45,14 @@ def shell_energy(g, lam_hat, n_shells):
     return out
 
 
-def impulse_adjoint(omega0, phys, n_steps, ix, iy, n_shells):
-    """Backward adjoint from a unit u-impulse at grid point (x = ix, y = iy) at the final step.
+def total_energy(g, lam_hat):
+    """Adjoint velocity energy over the whole spectrum: sum 1/2 |k|^2 |lam_hat|^2 / N^4."""
+    return float(np.sum(0.5 * g.k2 * np.abs(lam_hat) ** 2)) / float(g.N) ** 4
 
-    Returns (shell energies [n_steps + 1][n_shells] indexed by backward step
-    tau_n = (n_steps - n) dt, i.e. row 0 is the terminal field; gradient-like
-    final field P lambda_0 (physical)).
-    """
+
+def impulse_lambdas(omega0, phys, n_steps, ix, iy):
+    """Adjoint spectra lambda_hat (full N x N) of the impulse response, one per
+    backward step (index 0 = terminal field, index r = step n_steps - r)."""
     g = grid(phys.N)
     fh = forcing_hat(g, phys)
     E1 = lin_factor(g, phys, phys.dt)
@@ -59,11 +65,52 @@ def impulse_adjoint(omega0, phys, n_steps, ix, iy, n_shells):
     e = np.zeros((g.N, g.N))
     e[iy, ix] = 1.0
     lam = np.conj(g.m_u) * fft2(e)
-    rows = [shell_energy(g, lam, n_shells)]
+    out = [lam]
     for n in range(n_steps - 1, -1, -1):
         lam = adjoint_step(g, phys, traj[n], lam, E1, E2)
-        rows.append(shell_energy(g, lam, n_shells))
-    return np.array(rows), g.to_phys(g.mask, lam)
+        out.append(lam)
+    return out
+
+
+def ensemble_statistics(omega0s, phys, n_steps, ix, iy, n_shells):
+    """Ensemble adjoint statistics of Sec. IV over the members omega0s.
+
+    Per backward step (rows as in impulse_adjoint):
+      mean_energy[r][k-1]       mean over members of the shell energy,
+      energy_of_mean[r][k-1]    shell energy of the ensemble-mean adjoint,
+      total_mean_energy[r]      mean over members of the total adjoint energy,
+      total_energy_of_mean[r]   total energy of the ensemble-mean adjoint,
+      snr[r]                    total_energy_of_mean / total_mean_energy.
+    """
+    g = grid(phys.N)
+    B = len(omega0s)
+    lam_sum = None
+    mean_e, tot_e = None, None
+    for w0 in omega0s:
+        lams = impulse_lambdas(w0, phys, n_steps, ix, iy)
+        se = np.array([shell_energy(g, l, n_shells) for l in lams])
+        te = np.array([total_energy(g, l) for l in lams])
+        mean_e = se if mean_e is None else mean_e + se
+        tot_e = te if tot_e is None else tot_e + te
+        lam_sum = list(lams) if lam_sum is None else [a + l for a, l in zip(lam_sum, lams)]
+    mean_lam = [l / B for l in lam_sum]
+    eom = np.array([shell_energy(g, l, n_shells) for l in mean_lam])
+    teom = np.array([total_energy(g, l) for l in mean_lam])
+    tme = tot_e / B
+    return {"mean_energy": mean_e / B, "energy_of_mean": eom, "total_mean_energy": tme,
+            "total_energy_of_mean": teom, "snr": teom / tme}
+
+
+def impulse_adjoint(omega0, phys, n_steps, ix, iy, n_shells):
+    """Backward adjoint from a unit u-impulse at grid point (x = ix, y = iy) at the final step.
+
+    Returns (shell energies [n_steps + 1][n_shells] indexed by backward step
+    tau_n = (n_steps - n) dt, i.e. row 0 is the terminal field; gradient-like
+    final field P lambda_0 (physical)).
+    """
+    g = grid(phys.N)
+    lams = impulse_lambdas(omega0, phys, n_steps, ix, iy)
+    return np.array([shell_energy(g, l, n_shells) for l in lams]), g.to_phys(g.mask, lams[-1])
 
 
 def growth_rates(mean_energy, dt, tau_min=0.3, tau_max=1.0):

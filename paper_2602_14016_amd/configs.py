@@ -127,14 +127,33 @@ def main(argv=None):
     ap.add_argument("config", choices=sorted(list(CONFIGS) + ["c3"]))
     ap.add_argument("--iters", type=int, default=None)
     ap.add_argument("--horizon", type=int, default=None)
+    ap.add_argument("--members", type=int, default=64, help="c3: ensemble size (statistics in batches beyond 64)")
+    ap.add_argument("--batch", type=int, default=64, help="c3: members per batched solve")
     args = ap.parse_args(argv)
     if args.config == "c3":
         from . import ensemble
         t0 = time.perf_counter()
-        res = ensemble.run(n_steps=args.horizon or 500)
+        H = args.horizon or 500
+        res = ensemble.run(n_steps=H, members=min(args.members, args.batch))
         torch.cuda.synchronize()
-        print(json.dumps({"config": "c3", "seconds": time.perf_counter() - t0,
-                          "growth_rates": [float(x) for x in res.rates.cpu()]}))
+        out = {"config": "c3", "seconds": time.perf_counter() - t0,
+               "growth_rates": [float(x) for x in res.rates.cpu()]}
+        if args.members > args.batch:
+            from .autotune import autotune
+            probe = Solver(256, args.batch, nu=1e-4, dt=2e-3)
+            tiles = {k: v for k, v in autotune(probe, n_steps=8).items() if k in probe.get_tiles()}
+            probe.close()
+            del probe
+            st = ensemble.statistics(members=args.members, batch=args.batch, n_steps=H, tiles=tiles, verbose=True)
+            every = max(1, H // 20)
+            out["statistics"] = {
+                "members": st.members, "seconds": st.seconds, "tau": [float(x) for x in st.tau[::every].cpu()],
+                "snr": [float(x) for x in st.snr[::every].cpu()],
+                "total_mean": [float(x) for x in st.total_mean[::every].cpu()],
+                "total_of_mean": [float(x) for x in st.total_of_mean[::every].cpu()],
+                "subsets": {str(n): {"snr_at_tau_1": float(v["snr"][min(int(round(1.0 / 2e-3)), H)].cpu())}
+                            for n, v in st.subsets.items()}}
+        print(json.dumps(out))
         return
     cfg = CONFIGS[args.config]()
     if args.horizon:

@@ -461,12 +461,20 @@ struct Shells {
     double* out = nullptr;
     int n = 0;
     size_t stride = 0;
+    pa_ensemble_acc* acc = nullptr;   // ensemble sums to add each row to
 };
 
 pa_status record_shells(pa_ctx* c, WS& w, const Shells& sh, int row) {
     if (!sh.out) return PA_OK;
     PA_HIP(launch_shells(c->d, w.lam, c->shell_start, c->shell_modes, sh.n, sh.out + (size_t)row * sh.n,
                          sh.stride, c->stream));
+    if (sh.acc) {
+        const size_t SC = (size_t)c->d.KY * c->d.KXP;
+        PA_HIP(launch_ens_accumulate(c->d, w.lam, static_cast<cd*>(sh.acc->lambda_sum) + (size_t)row * SC,
+                                     sh.out + (size_t)row * sh.n, sh.stride, sh.n,
+                                     sh.acc->shell_sum + (size_t)row * sh.n, w.dots, sh.acc->energy_sum + row,
+                                     c->stream));
+    }
     return PA_OK;
 }
 
@@ -917,15 +925,30 @@ pa_status pa_adjoint_gradient(pa_ctx* c, const double* omega0, int32_t n_steps, 
     return backward_sweep(c, w, w.ckpt, n_steps, K, &op, 0, -1, -1, nullptr, grad_out, Shells(), true);
 }
 
+pa_status pa_ensemble_acc_bytes(const pa_ctx* c, int32_t n_steps, int32_t n_shells, size_t* lambda_bytes,
+                                size_t* energy_bytes, size_t* shell_bytes) {
+    if (!c || !lambda_bytes || !energy_bytes || !shell_bytes) return fail(PA_EINVAL, "NULL argument");
+    if (n_steps < 0 || n_shells < 1) return fail(PA_EINVAL, "bad sizes");
+    const size_t rows = (size_t)n_steps + 1;
+    *lambda_bytes = rows * c->d.KY * c->d.KXP * sizeof(cd);
+    *energy_bytes = rows * sizeof(double);
+    *shell_bytes = rows * n_shells * sizeof(double);
+    return PA_OK;
+}
+
 pa_status pa_adjoint_impulse(pa_ctx* c, const double* omega0, int32_t n_steps, int32_t ix, int32_t iy,
-                             int32_t n_shells, double* shells_out, double* field_out, int32_t ckpt_every,
-                             void* workspace, size_t wbytes) {
+                             int32_t n_shells, double* shells_out, double* field_out, pa_ensemble_acc* acc,
+                             int32_t ckpt_every, void* workspace, size_t wbytes) {
     g_err.clear();
     if (!c || !omega0 || !shells_out) return fail(PA_EINVAL, "NULL argument");
     if (n_steps < 0 || ckpt_every < 1) return fail(PA_EINVAL, "bad sizes");
     if (ix < 0 || iy < 0 || ix >= c->d.N || iy >= c->d.N) return fail(PA_EINVAL, "impulse point outside the grid");
     if (n_shells < 1 || n_shells > c->n_shell_max)
         return fail(PA_EINVAL, "n_shells must be in [1, floor(sqrt(2) Kc)]");
+    if (acc && (!acc->lambda_sum || !acc->energy_sum || !acc->shell_sum || acc->count < 0))
+        return fail(PA_EINVAL, "ensemble accumulator has a NULL buffer or a negative count");
+    if (acc && reinterpret_cast<uintptr_t>(acc->lambda_sum) % 16)
+        return fail(PA_EINVAL, "lambda_sum must be 16-byte aligned");
     WS w;
     PA_TRY(check_ws(c, workspace, wbytes, n_steps, ckpt_every, 0, 0, &w));
     const int K = seg_len(n_steps, ckpt_every);
@@ -936,7 +959,25 @@ pa_status pa_adjoint_impulse(pa_ctx* c, const double* omega0, int32_t n_steps, i
     sh.out = shells_out;
     sh.n = n_shells;
     sh.stride = (size_t)(n_steps + 1) * n_shells;
-    return backward_sweep(c, w, w.ckpt, n_steps, K, nullptr, 1, ix, iy, nullptr, field_out, sh, true);
+    sh.acc = acc;
+    PA_TRY(backward_sweep(c, w, w.ckpt, n_steps, K, nullptr, 1, ix, iy, nullptr, field_out, sh, true));
+    if (acc) acc->count += c->d.B;
+    return PA_OK;
+}
+
+pa_status pa_ensemble_stats(pa_ctx* c, const pa_ensemble_acc* acc, int32_t rows, int32_t n_shells,
+                            double* mean_energy, double* energy_of_mean, double* total_mean, double* total_of_mean,
+                            double* snr) {
+    g_err.clear();
+    if (!c || !acc || !acc->lambda_sum || !acc->energy_sum || !acc->shell_sum || !mean_energy || !energy_of_mean ||
+        !total_mean || !total_of_mean || !snr)
+        return fail(PA_EINVAL, "NULL argument");
+    if (acc->count < 1) return fail(PA_EINVAL, "no members accumulated");
+    if (rows < 1 || n_shells < 1 || n_shells > c->n_shell_max) return fail(PA_EINVAL, "bad sizes");
+    PA_HIP(launch_ens_stats(c->d, rows, n_shells, 1.0 / (double)acc->count, static_cast<const cd*>(acc->lambda_sum),
+                            acc->shell_sum, acc->energy_sum, c->shell_start, c->shell_modes, mean_energy,
+                            energy_of_mean, total_mean, total_of_mean, snr, c->stream));
+    return PA_OK;
 }
 
 pa_status pa_first_guess(pa_ctx* c, int32_t stride, const double* probes, double* omega_out, void* workspace,

@@ -142,6 +142,14 @@ hipError_t launch_scal_copy(int B, size_t n, const double* alpha, const double* 
 hipError_t launch_nonfinite(int B, size_t n, const double* x, int* flags, hipStream_t s);
 hipError_t launch_scatter_probes(int B, int N, int stride, const double* probes, double* grid_u, double* grid_v,
                                  hipStream_t s);
+// ensemble statistics: add one batch at one row (adjoint step), and the final statistics
+hipError_t launch_ens_accumulate(const Dims& d, const cd* lam, cd* lambda_sum_row, const double* shells_row,
+                                 size_t shells_stride, int n_shells, double* shell_sum_row, double* etot_scratch,
+                                 double* energy_sum_row, hipStream_t s);
+hipError_t launch_ens_stats(const Dims& d, int rows, int n_shells, double inv_count, const cd* lambda_sum,
+                            const double* shell_sum, const double* energy_sum, const int* shell_start,
+                            const int* shell_modes, double* mean_energy, double* energy_of_mean, double* total_mean,
+                            double* total_of_mean, double* snr, hipStream_t s);
 hipError_t launch_shell_growth(int B, int rows, int n_shells, const double* shells, double dt, double tau_min,
                                double tau_max, double* mean_out, double* rate_out, hipStream_t s);
 

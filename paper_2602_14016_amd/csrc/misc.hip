@@ -218,6 +218,119 @@ hipError_t launch_shells(const Dims& d, const cd* lam, const int* shell_start, c
     return hipGetLastError();
 }
 
+// ------------------------------------------------- ensemble statistics --
+// Accumulators over an ensemble split into batches: members are added one at
+// a time in member order onto the running sum, so any split into batches
+// gives bitwise the same sums.  Padding columns kx > Kc are never touched.
+
+__global__ void ens_lambda_sum_kernel(Dims d, const cd* __restrict__ lam, cd* __restrict__ sum) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;   // compact index r * KXP + kx
+    if (i >= d.KY * d.KXP || i % d.KXP > d.K) return;
+    const size_t SC = (size_t)d.KY * d.KXP;
+    cd acc = sum[i];
+    for (int b = 0; b < d.B; ++b) {
+        const cd v = lam[(size_t)b * SC + i];
+        acc.x += v.x;
+        acc.y += v.y;
+    }
+    sum[i] = acc;
+}
+
+// acc[k] += v[0 * stride + k] + v[1 * stride + k] + ... (member order), k < n
+__global__ void ens_scalar_sum_kernel(int B, const double* __restrict__ v, size_t stride, int n,
+                                      double* __restrict__ acc) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    double a = acc[k];
+    for (int b = 0; b < B; ++b) a += v[(size_t)b * stride + k];
+    acc[k] = a;
+}
+
+// Total adjoint velocity energy sum_k 1/2 |k|^2 |lam_hat|^2 / N^4 of each of
+// d.B compact states (kx > 0 counted twice for the Hermitian half), times
+// scale; one workgroup per state, fixed-order tree.
+constexpr int ETOT_THREADS = 256;
+__global__ void __launch_bounds__(ETOT_THREADS) energy_total_kernel(Dims d, const cd* __restrict__ lam, double scale,
+                                                                    double* __restrict__ out) {
+    __shared__ double sh[ETOT_THREADS];
+    const int b = blockIdx.x;
+    const size_t SC = (size_t)d.KY * d.KXP;
+    const cd* l = lam + (size_t)b * SC;
+    double s = 0.0;
+    for (int i = threadIdx.x; i < (int)SC; i += ETOT_THREADS) {
+        const int r = i / d.KXP, kx = i % d.KXP;
+        if (kx > d.K) continue;
+        const int ky = (r <= d.K) ? r : r - d.KY;
+        const double k2 = (double)kx * kx + (double)ky * ky;
+        const double wgt = kx > 0 ? 2.0 : 1.0;
+        s += wgt * 0.5 * k2 * (l[i].x * l[i].x + l[i].y * l[i].y);
+    }
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = ETOT_THREADS / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double n4 = (double)d.N * d.N * (double)d.N * d.N;
+        out[b] = scale * sh[0] / n4;
+    }
+}
+
+// Per row: mean shell energy, energy of the mean (from the shells of the
+// member sum), their totals and the ratio of the totals.
+__global__ void ens_finish_kernel(int rows, int n_shells, double inv_count, const double* __restrict__ shell_sum,
+                                  const double* __restrict__ energy_sum, double* __restrict__ mean_energy,
+                                  double* __restrict__ energy_of_mean, double* __restrict__ total_mean,
+                                  double* __restrict__ total_of_mean, double* __restrict__ snr) {
+    const int row = blockIdx.x;
+    const double c2 = inv_count * inv_count;
+    for (int k = threadIdx.x; k < n_shells; k += blockDim.x) {
+        const size_t i = (size_t)row * n_shells + k;
+        mean_energy[i] = shell_sum[i] * inv_count;
+        energy_of_mean[i] *= c2;
+    }
+    if (threadIdx.x == 0) {
+        const double tm = energy_sum[row] * inv_count;
+        const double te = total_of_mean[row] * c2;
+        total_mean[row] = tm;
+        total_of_mean[row] = te;
+        snr[row] = tm > 0.0 ? te / tm : NAN;
+    }
+}
+
+hipError_t launch_ens_accumulate(const Dims& d, const cd* lam, cd* lambda_sum_row, const double* shells_row,
+                                 size_t shells_stride, int n_shells, double* shell_sum_row, double* etot_scratch,
+                                 double* energy_sum_row, hipStream_t s) {
+    if (!lam || !lambda_sum_row || !shells_row || !shell_sum_row || !etot_scratch || !energy_sum_row)
+        return hipErrorInvalidValue;
+    const int n = d.KY * d.KXP;
+    hipLaunchKernelGGL(ens_lambda_sum_kernel, dim3((n + 255) / 256), dim3(256), 0, s, d, lam, lambda_sum_row);
+    hipLaunchKernelGGL(ens_scalar_sum_kernel, dim3((n_shells + 63) / 64), dim3(64), 0, s, d.B, shells_row,
+                       shells_stride, n_shells, shell_sum_row);
+    hipLaunchKernelGGL(energy_total_kernel, dim3(d.B), dim3(ETOT_THREADS), 0, s, d, lam, 1.0, etot_scratch);
+    hipLaunchKernelGGL(ens_scalar_sum_kernel, dim3(1), dim3(64), 0, s, d.B, etot_scratch, (size_t)1, 1,
+                       energy_sum_row);
+    return hipGetLastError();
+}
+
+hipError_t launch_ens_stats(const Dims& d, int rows, int n_shells, double inv_count, const cd* lambda_sum,
+                            const double* shell_sum, const double* energy_sum, const int* shell_start,
+                            const int* shell_modes, double* mean_energy, double* energy_of_mean, double* total_mean,
+                            double* total_of_mean, double* snr, hipStream_t s) {
+    if (!lambda_sum || !shell_sum || !energy_sum || !mean_energy || !energy_of_mean || !total_mean ||
+        !total_of_mean || !snr || rows < 1 || n_shells < 1)
+        return hipErrorInvalidValue;
+    Dims dr = d;
+    dr.B = rows;   // the rows of the member sum take the place of members
+    hipLaunchKernelGGL(shells_kernel, dim3(n_shells, rows), dim3(SHELL_THREADS), 0, s, dr, lambda_sum, shell_start,
+                       shell_modes, n_shells, energy_of_mean, (size_t)n_shells);
+    hipLaunchKernelGGL(energy_total_kernel, dim3(rows), dim3(ETOT_THREADS), 0, s, dr, lambda_sum, 1.0, total_of_mean);
+    hipLaunchKernelGGL(ens_finish_kernel, dim3(rows), dim3(64), 0, s, rows, n_shells, inv_count, shell_sum,
+                       energy_sum, mean_energy, energy_of_mean, total_mean, total_of_mean, snr);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------- vector algebra --
 
 __global__ void dot_partial_kernel(size_t n, const double* __restrict__ x, const double* __restrict__ y,

@@ -37,6 +37,11 @@ class Kernel(Structure):
     _fields_ = [("kind", c_int32), ("metric", c_int32), ("param", c_double)]
 
 
+class EnsembleAcc(Structure):
+    _fields_ = [("lambda_sum", c_void_p), ("energy_sum", c_void_p), ("shell_sum", c_void_p),
+                ("count", ctypes.c_int64)]
+
+
 TILE_FIELDS = ("row_variant", "row_teams", "adj_variant", "adj_teams", "col_variant", "col_block")
 
 
@@ -66,7 +71,11 @@ EXPORTS = {
                                 c_int32, c_int32, c_int32, POINTER(c_double), POINTER(c_int32), c_void_p,
                                 c_size_t]),
     "pa_adjoint_impulse": (c_int32, [c_void_p, c_void_p, c_int32, c_int32, c_int32, c_int32, c_void_p,
-                                     c_void_p, c_int32, c_void_p, c_size_t]),
+                                     c_void_p, POINTER(EnsembleAcc), c_int32, c_void_p, c_size_t]),
+    "pa_ensemble_acc_bytes": (c_int32, [c_void_p, c_int32, c_int32, POINTER(c_size_t), POINTER(c_size_t),
+                                        POINTER(c_size_t)]),
+    "pa_ensemble_stats": (c_int32, [c_void_p, POINTER(EnsembleAcc), c_int32, c_int32, c_void_p, c_void_p,
+                                    c_void_p, c_void_p, c_void_p]),
     "pa_set_tiles": (c_int32, [c_void_p, POINTER(Tiles)]),
     "pa_get_tiles": (c_int32, [c_void_p, POINTER(Tiles)]),
     "pa_first_guess": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_size_t]),

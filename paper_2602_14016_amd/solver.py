@@ -236,15 +236,36 @@ class Solver:
         H = [[hist[b * (max_iter + 1) + i] for i in range(max_iter + 1)] for b in range(self.B)]
         return w, H, [iters[b] for b in range(self.B)]
 
-    def adjoint_impulse(self, omega0, n_steps, ix, iy, n_shells, ckpt_every=50, want_field=False):
+    def adjoint_impulse(self, omega0, n_steps, ix, iy, n_shells, ckpt_every=50, want_field=False, acc=None):
+        """Impulse response shells [B][n_steps + 1][n_shells] (and P lambda_0 if want_field);
+        with acc (an EnsembleAccumulator), the batch is added to its ensemble sums."""
         _need(omega0, (self.B, self.N, self.N), "omega0")
         self._sync_stream()
         sh = torch.empty((self.B, n_steps + 1, n_shells), dtype=torch.float64, device=self.device)
         f = self.empty() if want_field else None
         ws, wb = self.workspace(n_steps, ckpt_every, 0)
+        if acc is not None:
+            acc.check(self, n_steps, n_shells)
         nv.check(self.lib.pa_adjoint_impulse(self.ctx, _ptr(omega0), int(n_steps), int(ix), int(iy), int(n_shells),
-                                             _ptr(sh), _ptr(f), int(ckpt_every), ws, wb))
+                                             _ptr(sh), _ptr(f), byref(acc.c) if acc is not None else None,
+                                             int(ckpt_every), ws, wb))
         return sh, f
+
+    def ensemble_accumulator(self, n_steps, n_shells):
+        return EnsembleAccumulator(self, n_steps, n_shells)
+
+    def ensemble_stats(self, acc, rows=None):
+        """Ensemble statistics (pa_ensemble_stats) of the members accumulated in acc, per backward step."""
+        rows = acc.rows if rows is None else int(rows)
+        z = lambda *shape: torch.empty(shape, dtype=torch.float64, device=self.device)
+        out = {"mean_energy": z(rows, acc.n_shells), "energy_of_mean": z(rows, acc.n_shells),
+               "total_mean": z(rows), "total_of_mean": z(rows), "snr": z(rows)}
+        self._sync_stream()
+        nv.check(self.lib.pa_ensemble_stats(self.ctx, byref(acc.c), rows, acc.n_shells, _ptr(out["mean_energy"]),
+                                            _ptr(out["energy_of_mean"]), _ptr(out["total_mean"]),
+                                            _ptr(out["total_of_mean"]), _ptr(out["snr"])))
+        out["members"] = acc.count
+        return out
 
     # ----------------------------------------------------------- measurement
     def profile_start(self, kernel_class, sample_every=1):
@@ -283,3 +304,30 @@ class Solver:
         nv.check(self.lib.pa_shell_growth(self.ctx, _ptr(shells), int(rows), int(n), float(tau_min), float(tau_max),
                                           _ptr(mean), _ptr(rate)))
         return mean, rate
+
+
+class EnsembleAccumulator:
+    """Device running sums of an ensemble of impulse responses (pa_ensemble_acc):
+    member sum of the adjoint state per backward step, of the total adjoint energy
+    and of the shell energies.  Add batches with Solver.adjoint_impulse(..., acc=...)
+    (any solver of the same grid size), read statistics with Solver.ensemble_stats."""
+
+    def __init__(self, solver, n_steps, n_shells):
+        lb, eb, sb = c_size_t(), c_size_t(), c_size_t()
+        nv.check(solver.lib.pa_ensemble_acc_bytes(solver.ctx, int(n_steps), int(n_shells), byref(lb), byref(eb),
+                                                  byref(sb)))
+        dev = solver.device
+        self.N, self.n_steps, self.n_shells, self.rows = solver.N, int(n_steps), int(n_shells), int(n_steps) + 1
+        self.lambda_sum = torch.zeros(lb.value, dtype=torch.uint8, device=dev)
+        self.energy_sum = torch.zeros(eb.value // 8, dtype=torch.float64, device=dev)
+        self.shell_sum = torch.zeros(sb.value // 8, dtype=torch.float64, device=dev)
+        self.c = nv.EnsembleAcc(self.lambda_sum.data_ptr(), self.energy_sum.data_ptr(), self.shell_sum.data_ptr(), 0)
+
+    @property
+    def count(self):
+        return self.c.count
+
+    def check(self, solver, n_steps, n_shells):
+        if solver.N != self.N or int(n_steps) != self.n_steps or int(n_shells) != self.n_shells:
+            raise ValueError("accumulator made for another grid size, horizon or shell count")
+

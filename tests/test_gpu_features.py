@@ -125,3 +125,49 @@ def test_fit_ckpt_every_respects_budget():
     assert m == 1 or s.workspace_bytes(H, -(-H // (m - 1))) + 256 > budget
     assert s.fit_ckpt_every(H, budget_bytes=1000) == 0
     assert s.fit_ckpt_every(H) == H          # a few MB: fits in free device memory
+
+
+def test_ensemble_statistics_parity_and_batch_split_invariance():
+    import oracle as O
+    from oracle.model import Physics
+    from paper_2602_14016_amd import Solver
+    print("CASE ensemble-stats", flush=True)
+    N, H, nsh, M = 32, 8, 10, 4
+    ph = Physics(N=N, nu=1e-3, dt=5e-3)
+    w = O.init_field(N, list(range(M)), kind=0, k0=4.0)
+    ref = O.ensemble_statistics(list(w), ph, H, 7, 20, nsh)
+    results = []
+    for split in ((4,), (1, 3), (2, 2), (3, 1)):
+        acc = None
+        done = 0
+        for b in split:
+            s = Solver(N, b, nu=ph.nu, dt=ph.dt)
+            if acc is None:
+                acc = s.ensemble_accumulator(H, nsh)
+            x = torch.from_numpy(np.ascontiguousarray(w[done:done + b])).cuda()
+            s.adjoint_impulse(x, H, 7, 20, nsh, ckpt_every=3, acc=acc)
+            done += b
+        st = s.ensemble_stats(acc)
+        assert st["members"] == M
+        results.append({k: st[k].cpu().numpy() for k in ("mean_energy", "energy_of_mean", "total_mean",
+                                                          "total_of_mean", "snr")})
+    for r in results[1:]:
+        for k in r:
+            assert np.array_equal(r[k], results[0][k]), k
+    got = results[0]
+    pairs = (("mean_energy", "mean_energy"), ("energy_of_mean", "energy_of_mean"), ("total_mean", "total_mean_energy"),
+             ("total_of_mean", "total_energy_of_mean"), ("snr", "snr"))
+    for gk, ok in pairs:
+        a, b = got[gk], ref[ok]
+        assert np.linalg.norm(a - b) <= 1e-9 * np.linalg.norm(b), (gk, np.linalg.norm(a - b) / np.linalg.norm(b))
+    assert abs(got["snr"][0] - 1.0) < 1e-12 and np.all(got["snr"][1:] < 1)
+
+
+def test_ensemble_stats_rejects_empty_accumulator():
+    from paper_2602_14016_amd import Solver
+    from paper_2602_14016_amd.native import PaError
+    print("CASE ensemble-empty", flush=True)
+    s = Solver(32, 1, nu=1e-3, dt=5e-3)
+    acc = s.ensemble_accumulator(4, 5)
+    with pytest.raises(PaError):
+        s.ensemble_stats(acc)

@@ -464,3 +464,39 @@ def test_growth_rate_fit_exact_exponentials():
     E = np.exp(np.outer(tau, rates)) * np.array([2.0, 1e-3, 7.0])
     got = ensemble.growth_rates(E, dt)
     assert np.allclose(got, rates, rtol=1e-10)
+
+
+def test_total_adjoint_energy_parseval_against_physical_velocity():
+    # 1/2 sum_k |k|^2 |lam_hat|^2 / N^4 equals the grid mean of 1/2 (u^2 + v^2) of the adjoint
+    # velocity u = d_y lam, v = -d_x lam, formed in physical space by the inverse DFT
+    N = 16
+    g = model.grid(N)
+    lam = g.mask * dft.fft2(np.random.default_rng(3).standard_normal((N, N)))
+    u = dft.ifft2(1j * g.iky * lam).real
+    v = dft.ifft2(-1j * g.ikx * lam).real
+    assert ensemble.total_energy(g, lam) == pytest.approx(float(np.mean(0.5 * (u * u + v * v))), rel=1e-13)
+    # every mode with |k| >= 1 lies in one shell: the shells partition the total
+    nmax = int(math.isqrt(2 * (N // 2) ** 2)) + 1
+    assert np.sum(ensemble.shell_energy(g, lam, nmax)) == pytest.approx(ensemble.total_energy(g, lam), rel=1e-13)
+
+
+def test_ensemble_statistics_single_member_and_jensen():
+    N, H = 16, 6
+    ph = Physics(N=N, nu=1e-3, dt=5e-3)
+    w = O.init_field(N, [1, 2, 3], kind=0, k0=3.0)
+    one = ensemble.ensemble_statistics([w[0]], ph, H, 5, 9, 8)
+    assert np.array_equal(one["energy_of_mean"], one["mean_energy"])
+    assert np.allclose(one["snr"], 1.0, rtol=0, atol=1e-15)
+    # identical members: the mean is the member
+    two = ensemble.ensemble_statistics([w[0], w[0]], ph, H, 5, 9, 8)
+    assert np.allclose(two["energy_of_mean"], one["energy_of_mean"], rtol=1e-14, atol=0)
+    # different members: the energy of the mean never exceeds the mean energy (Jensen), per shell and total
+    st = ensemble.ensemble_statistics(list(w), ph, H, 5, 9, 8)
+    assert np.all(st["energy_of_mean"] <= st["mean_energy"] * (1 + 1e-12))
+    assert np.all(st["snr"] <= 1 + 1e-12) and np.all(st["snr"] > 0)
+    # at the terminal step every member holds the same impulse: the mean is that impulse
+    assert st["snr"][0] == pytest.approx(1.0, rel=1e-14)
+    assert np.all(st["snr"][1:] < 1)
+    # mean energy is the average of the single-member rows
+    rows = [ensemble.impulse_adjoint(x, ph, H, 5, 9, 8)[0] for x in w]
+    assert np.allclose(st["mean_energy"], np.mean(rows, axis=0), rtol=1e-14, atol=0)
