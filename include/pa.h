@@ -197,6 +197,16 @@ pa_status pa_assimilate(pa_ctx* ctx, double* omega_inout, int32_t n_steps, const
                         int32_t lbfgs_m, int32_t ckpt_every, double* J_hist,
                         int32_t* iters_done, void* workspace, size_t workspace_bytes);
 
+/* pa_assimilate with one kernel per member (kernels: host array of B): a
+ * sweep over preconditioners (kernel families and parameters) as one batched
+ * solve, e.g. the fractional exponent or the heat-kernel parameter across
+ * members (Sec. III.B-C).  Member b follows exactly the iterations
+ * pa_assimilate would run for it alone with kernels[b]. */
+pa_status pa_assimilate_kernels(pa_ctx* ctx, double* omega_inout, int32_t n_steps, const pa_obs* obs,
+                                const pa_kernel* kernels, int32_t method, int32_t max_iter,
+                                int32_t lbfgs_m, int32_t ckpt_every, double* J_hist,
+                                int32_t* iters_done, void* workspace, size_t workspace_bytes);
+
 /* Running sums of an ensemble of impulse responses, accumulated by
  * pa_adjoint_impulse over any number of calls (batches of members), for the
  * ensemble statistics of Sec. IV.  The caller allocates the device buffers

@@ -1,6 +1,6 @@
 """Named workloads of the hot path and a runner.
 
-    python -m paper_2602_14016_amd.configs c0|c1|c2|c3 [--iters K] [--horizon H]
+    python -m paper_2602_14016_amd.configs c0|c1|c2|c3|sweep [--iters K] [--horizon H]
 
 c0  decaying turbulence, 64^2, nu = 1e-3, Gaussian random field (k0 = 4,
     energy 0.5), 200 RK4 steps at dt = 5e-3, velocity at every 4th grid point
@@ -16,7 +16,11 @@ c2  forced Kolmogorov flow, 512^2, nu = 1/40, drag 0.1, f_x = sin 4y, spin-up
     in {0.25, 0.5, 1.0}, 30 L-BFGS iterations.
 c3  ensemble of 64 realizations of the c1 spectrum (seeds 0..63), 500
     forward + 500 adjoint steps from a unit u-impulse, shell energies and
-    growth rates for |k| = 1..85.
+    growth rates for |k| = 1..85; with --members M > 64 the ensemble
+    statistics of M realizations in batches.
+sweep  the c1 problem assimilated under 14 preconditioners at once (fractional
+    |k|^(-2 alpha), alpha = -2..2, and heat exp(-nu beta |k|^2), beta = -0.1..0.8)
+    as one batched solve, timed against one solve per kernel.
 
 Truth fields are seeded synthetic spectra (the paper's truth realizations are
 not available); observations are the model's own (twin experiment).
@@ -85,6 +89,45 @@ def c2():
 CONFIGS = {"c0": c0, "c1": c1, "c2": c2}
 
 
+def sweep_kernels(nu=1e-4, alphas=(-2.0, -1.5, -1.0, -0.5, 0.0, 0.5, 1.0, 1.5, 2.0),
+                  betas=(-0.1, 0.1, 0.3, 0.5, 0.8)):
+    """Fractional kernels |k|^(-2 alpha) and heat kernels exp(-nu beta |k|^2) (Sec. III.B-C)."""
+    return [KernelSpec(2, a) for a in alphas] + [KernelSpec(3, nu * b) for b in betas]
+
+
+def run_sweep(cfg: Config, kernels, iters, sequential=True, verbose=True):
+    """Assimilate cfg once per kernel: all kernels as one batched solve, then (if
+    sequential) one solve per kernel; returns timings and per-kernel results."""
+    B = len(kernels)
+    s1 = Solver(cfg.N, 1, **cfg.physics())
+    truth, obs_vals = truth_and_obs(cfg, s1)
+    fg = s1.first_guess(cfg.stride, obs_vals[:, 0].contiguous())
+    sb = Solver(cfg.N, B, **cfg.physics())
+    obs_b = Observations(cfg.stride, cfg.obs_steps, obs_vals.expand(B, -1, -1, -1, -1).contiguous())
+    fg_b = fg.expand(B, -1, -1).contiguous()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    w, H, it = sb.assimilate(fg_b, cfg.n_steps, obs_b, kernels, "lbfgs", iters, cfg.lbfgs_m, cfg.ckpt_every)
+    torch.cuda.synchronize()
+    t_batched = time.perf_counter() - t0
+    err = (torch.linalg.norm((w - truth).reshape(B, -1), dim=1) / torch.linalg.norm(truth)).cpu().tolist()
+    out = {"config": cfg.name + "-sweep", "kernels": [[k.kind, k.param] for k in kernels], "iterations": it,
+           "J_final": [h[it_b] if it_b >= 0 else None for h, it_b in zip(H, it)], "rel_err_omega0": err,
+           "batched_seconds": t_batched}
+    if sequential:
+        obs1 = Observations(cfg.stride, cfg.obs_steps, obs_vals)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in kernels:
+            s1.assimilate(fg, cfg.n_steps, obs1, k, "lbfgs", iters, cfg.lbfgs_m, cfg.ckpt_every)
+        torch.cuda.synchronize()
+        out["sequential_seconds"] = time.perf_counter() - t0
+        out["speedup"] = out["sequential_seconds"] / t_batched
+    if verbose:
+        print(json.dumps(out), flush=True)
+    return out
+
+
 def truth_and_obs(cfg: Config, solver: Solver):
     """Seeded truth (after spin-up) and its model observations [B, n_times, 2, M, M]."""
     w = solver.init_field([cfg.truth_seed + b for b in range(solver.B)], kind=cfg.truth_kind, k0=cfg.truth_k0,
@@ -124,7 +167,7 @@ def run_config(cfg: Config, iters=None, verbose=True):
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("config", choices=sorted(list(CONFIGS) + ["c3"]))
+    ap.add_argument("config", choices=sorted(list(CONFIGS) + ["c3", "sweep"]))
     ap.add_argument("--iters", type=int, default=None)
     ap.add_argument("--horizon", type=int, default=None)
     ap.add_argument("--members", type=int, default=64, help="c3: ensemble size (statistics in batches beyond 64)")
@@ -154,6 +197,13 @@ def main(argv=None):
                 "subsets": {str(n): {"snr_at_tau_1": float(v["snr"][min(int(round(1.0 / 2e-3)), H)].cpu())}
                             for n, v in st.subsets.items()}}
         print(json.dumps(out))
+        return
+    if args.config == "sweep":
+        cfg = c1()
+        if args.horizon:
+            cfg.n_steps = args.horizon
+            cfg.obs_steps = evenly_spaced(args.horizon, 5)
+        run_sweep(cfg, sweep_kernels(cfg.nu), args.iters or 10)
         return
     cfg = CONFIGS[args.config]()
     if args.horizon:

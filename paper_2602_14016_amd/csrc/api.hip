@@ -87,7 +87,7 @@ struct WS {
     double* jpart;      // [B][n_obs][N]
     double* J;          // [B]
     double* J2;         // [B]
-    double* mult;       // [KY][KXP] (two tables)
+    double* mult;       // two tables of [B][KY][KXP] (member-major; one kernel per member)
     double* norm;       // [B]
     uint64_t* seeds;    // [B]
     double* partial;    // [B][DOT_BLOCKS]
@@ -141,7 +141,7 @@ WS carve(const pa_ctx* c, int n_steps, int ckpt_every, int n_obs, int m, void* b
     w.jpart = cv.take<double>((size_t)d.B * std::max(n_obs, 1) * d.N);
     w.J = cv.take<double>(d.B);
     w.J2 = cv.take<double>(d.B);
-    w.mult = cv.take<double>((size_t)2 * d.KY * d.KXP);
+    w.mult = cv.take<double>((size_t)2 * d.B * d.KY * d.KXP);
     w.norm = cv.take<double>(d.B);
     w.seeds = cv.take<uint64_t>(d.B);
     w.partial = cv.take<double>((size_t)d.B * DOT_BLOCKS);
@@ -588,12 +588,15 @@ pa_status backward_sweep(pa_ctx* c, WS& w, const cd* ckpt, int n_steps, int K, c
     return PA_OK;
 }
 
-// precondition with the multiplier table mult (per context, computed before)
-pa_status apply_filter(pa_ctx* c, WS& w, const double* mult, const double* in, double* out) {
+// precondition with the multiplier table mult (computed before): one table
+// for every member, or with per_member one table per member ([B][KY][KXP])
+pa_status apply_filter(pa_ctx* c, WS& w, const double* mult, const double* in, double* out,
+                       bool per_member = false) {
     PA_HIP(launch_row_r2c(c->d, in, w.Y0, c->tw, c->stream));
     ColArgs a = col_base(c);
     a.yin[0] = w.Y0;
     a.mult = mult;
+    a.mult_per_member = per_member ? 1 : 0;
     a.nout = 1;
     a.fields[0] = F_OMEGA;
     a.yout[0] = w.Yf[0];
@@ -1070,13 +1073,15 @@ struct Opt {
 
 }  // namespace
 
-extern "C" pa_status pa_assimilate(pa_ctx* c, double* omega_inout, int32_t n_steps, const pa_obs* obs,
-                                   const pa_kernel* kernel, int32_t method, int32_t max_iter, int32_t lbfgs_m,
-                                   int32_t ckpt_every, double* J_hist, int32_t* iters_done, void* workspace,
-                                   size_t wbytes) {
+// kernels: host array of B kernels (one per member) when per_member, else one kernel for all
+static pa_status assimilate_impl(pa_ctx* c, double* omega_inout, int32_t n_steps, const pa_obs* obs,
+                                 const pa_kernel* kernels, bool per_member, int32_t method, int32_t max_iter,
+                                 int32_t lbfgs_m, int32_t ckpt_every, double* J_hist, int32_t* iters_done,
+                                 void* workspace, size_t wbytes) {
     g_err.clear();
     if (!c || !omega_inout || !J_hist || !iters_done) return fail(PA_EINVAL, "NULL argument");
-    PA_TRY(valid_kernel(kernel));
+    if (!kernels) return fail(PA_EINVAL, "kernel is NULL");
+    for (int b = 0; b < (per_member ? c->d.B : 1); ++b) PA_TRY(valid_kernel(&kernels[b]));
     if (method != 0 && method != 1) return fail(PA_EINVAL, "method must be 0 (L-BFGS) or 1 (steepest descent)");
     if (max_iter < 0 || n_steps < 0 || ckpt_every < 1) return fail(PA_EINVAL, "bad sizes");
     if (method == 0 && lbfgs_m < 1) return fail(PA_EINVAL, "lbfgs_m must be >= 1");
@@ -1091,20 +1096,24 @@ extern "C" pa_status pa_assimilate(pa_ctx* c, double* omega_inout, int32_t n_ste
     const size_t n = (size_t)c->d.N * c->d.N;
     const size_t SP = (size_t)B * n;
     const size_t MT = (size_t)c->d.KY * c->d.KXP;
-    double* mult_p = w.mult;        // (m^2 W)^(+1/2)
-    double* mult_m = w.mult + MT;   // (m^2 W)^(-1/2)
-    PA_HIP(launch_make_mult(c->d, kernel->kind, kernel->metric, kernel->param, 0.5, mult_p, c->stream));
-    PA_HIP(launch_make_mult(c->d, kernel->kind, kernel->metric, kernel->param, -0.5, mult_m, c->stream));
+    const size_t MTB = per_member ? (size_t)B * MT : MT;
+    double* mult_p = w.mult;         // (m^2 W)^(+1/2), one table per member when per_member
+    double* mult_m = w.mult + MTB;   // (m^2 W)^(-1/2)
+    for (int b = 0; b < (per_member ? B : 1); ++b) {
+        const pa_kernel* k = &kernels[b];
+        PA_HIP(launch_make_mult(c->d, k->kind, k->metric, k->param, 0.5, mult_p + b * MT, c->stream));
+        PA_HIP(launch_make_mult(c->d, k->kind, k->metric, k->param, -0.5, mult_m + b * MT, c->stream));
+    }
     Opt o{c, w, n, B, {}};
 
     auto eval_J = [&](const double* x) -> pa_status {
-        PA_TRY(apply_filter(c, w, mult_p, x, w.w));
+        PA_TRY(apply_filter(c, w, mult_p, x, w.w, per_member));
         return forward_sweep(c, w, w.w, n_steps, op, nullptr, w.ckpt, K, true);
     };
     // gradient at the point whose forward sweep last filled w.ckpt
     auto eval_grad = [&](double* gout) -> pa_status {
         PA_TRY(backward_sweep(c, w, w.ckpt, n_steps, K, &op, 0, -1, -1, nullptr, w.gw, Shells(), true));
-        return apply_filter(c, w, mult_p, w.gw, gout);
+        return apply_filter(c, w, mult_p, w.gw, gout, per_member);
     };
 
     for (int i = 0; i < B * (max_iter + 1); ++i) J_hist[i] = NAN;
@@ -1116,7 +1125,7 @@ extern "C" pa_status pa_assimilate(pa_ctx* c, double* omega_inout, int32_t n_ste
     std::vector<std::vector<double>> al(m, std::vector<double>(B, 0.0));
     int head = 0;
 
-    PA_TRY(apply_filter(c, w, mult_m, omega_inout, w.x));
+    PA_TRY(apply_filter(c, w, mult_m, omega_inout, w.x, per_member));
     PA_TRY(eval_J(w.x));
     PA_TRY(eval_grad(w.g));
     PA_TRY(o.read_J(J));
@@ -1260,7 +1269,23 @@ extern "C" pa_status pa_assimilate(pa_ctx* c, double* omega_inout, int32_t n_ste
     }
     for (int b = 0; b < B; ++b)
         if (running[b]) iters_done[b] = done[b];
-    PA_TRY(apply_filter(c, w, mult_p, w.x, omega_inout));
+    PA_TRY(apply_filter(c, w, mult_p, w.x, omega_inout, per_member));
     PA_TRY(o.sync());
     return PA_OK;
+}
+
+extern "C" pa_status pa_assimilate(pa_ctx* c, double* omega_inout, int32_t n_steps, const pa_obs* obs,
+                                   const pa_kernel* kernel, int32_t method, int32_t max_iter, int32_t lbfgs_m,
+                                   int32_t ckpt_every, double* J_hist, int32_t* iters_done, void* workspace,
+                                   size_t wbytes) {
+    return assimilate_impl(c, omega_inout, n_steps, obs, kernel, false, method, max_iter, lbfgs_m, ckpt_every,
+                           J_hist, iters_done, workspace, wbytes);
+}
+
+extern "C" pa_status pa_assimilate_kernels(pa_ctx* c, double* omega_inout, int32_t n_steps, const pa_obs* obs,
+                                           const pa_kernel* kernels, int32_t method, int32_t max_iter,
+                                           int32_t lbfgs_m, int32_t ckpt_every, double* J_hist,
+                                           int32_t* iters_done, void* workspace, size_t wbytes) {
+    return assimilate_impl(c, omega_inout, n_steps, obs, kernels, true, method, max_iter, lbfgs_m, ckpt_every,
+                           J_hist, iters_done, workspace, wbytes);
 }

@@ -218,20 +218,31 @@ class Solver:
         nv.check(self.lib.pa_precondition(self.ctx, byref(k), float(power), _ptr(x), _ptr(out), ws, wb))
         return out
 
-    def assimilate(self, omega_fg, n_steps, obs: Observations, kernel: KernelSpec, method="lbfgs",
+    def assimilate(self, omega_fg, n_steps, obs: Observations, kernel, method="lbfgs",
                    max_iter=10, lbfgs_m=10, ckpt_every=50):
+        """4D-Var from the first guess omega_fg [B, N, N].  kernel: one KernelSpec for every
+        member, or a sequence of B KernelSpecs (one preconditioner per member: a kernel sweep
+        as one batched solve).  Returns (omega0 [B, N, N], J history per member, iterations)."""
         _need(omega_fg, (self.B, self.N, self.N), "omega_fg")
+        per_member = not isinstance(kernel, KernelSpec)
+        if per_member and len(kernel) != self.B:
+            raise ValueError(f"{len(kernel)} kernels for {self.B} members")
         self._sync_stream()
         w = omega_fg.clone()
         o_c, keep = obs.c()
-        k = kernel.c()
         hist = (c_double * (self.B * (max_iter + 1)))()
         iters = (c_int32 * self.B)()
         m = int(lbfgs_m) if method == "lbfgs" else 1
         ws, wb = self.workspace(n_steps, ckpt_every, len(obs.steps), max(m, 1))
-        nv.check(self.lib.pa_assimilate(self.ctx, _ptr(w), int(n_steps), byref(o_c), byref(k),
-                                        0 if method == "lbfgs" else 1, int(max_iter), m, int(ckpt_every),
-                                        hist, iters, ws, wb))
+        meth = 0 if method == "lbfgs" else 1
+        if per_member:
+            ks = (nv.Kernel * self.B)(*[k.c() for k in kernel])
+            nv.check(self.lib.pa_assimilate_kernels(self.ctx, _ptr(w), int(n_steps), byref(o_c), ks, meth,
+                                                    int(max_iter), m, int(ckpt_every), hist, iters, ws, wb))
+        else:
+            k = kernel.c()
+            nv.check(self.lib.pa_assimilate(self.ctx, _ptr(w), int(n_steps), byref(o_c), byref(k), meth,
+                                            int(max_iter), m, int(ckpt_every), hist, iters, ws, wb))
         del keep
         H = [[hist[b * (max_iter + 1) + i] for i in range(max_iter + 1)] for b in range(self.B)]
         return w, H, [iters[b] for b in range(self.B)]

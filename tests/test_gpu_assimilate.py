@@ -32,7 +32,7 @@ def _setup(N, steps, osteps, stride, seeds=(0,), ph=None):
 
 
 def test_steepest_descent_c0_like_parity():
-    # BASELINE c0 shape at reduced size: SD with the exponential kernel, first guess 0
+    # the 64^2 decaying-turbulence workload at reduced size: SD with the exponential kernel, first guess 0
     from paper_2602_14016_amd import KernelSpec, Observations, Solver
     print("CASE sd", flush=True)
     N, steps = 32, 40
@@ -69,3 +69,31 @@ def test_lbfgs_parity(kern):
         assert iters[b] == it_ref
         assert np.allclose(H[b][: it_ref + 1], h_ref, rtol=ITER_TOL, atol=0)
         assert rel(w[b], w_ref) < ITER_TOL
+
+
+def test_kernel_sweep_one_batch_equals_separate_solves():
+    """A preconditioner sweep as one batched solve (one kernel per member): every member equals its own
+    single-kernel solve bitwise, and the heat-kernel member matches the oracle."""
+    from paper_2602_14016_amd import KernelSpec, Observations, Solver
+    print("CASE kernel-sweep", flush=True)
+    N, steps = 32, 24
+    osteps = synth.evenly_spaced_steps(steps, 3)
+    ph, mo = _setup(N, steps, osteps, 4, seeds=(7,))
+    fg = 0.5 * O.init_field(N, [8], kind=0, k0=4.0)[0]
+    kernels = [KernelSpec(0, 0.0), KernelSpec(1, 0.05), KernelSpec(2, -0.5), KernelSpec(3, 0.01)]
+    B = len(kernels)
+    obs_b = Observations(4, osteps, dev(np.repeat(mo, B, axis=0)))
+    sweep = Solver(N, B, nu=ph.nu, dt=ph.dt)
+    w, H, iters = sweep.assimilate(dev(np.repeat(fg[None], B, axis=0)), steps, obs_b, kernels, "lbfgs",
+                                   max_iter=4, lbfgs_m=3, ckpt_every=10)
+    w = w.cpu().numpy()
+    one = Solver(N, 1, nu=ph.nu, dt=ph.dt)
+    for b, k in enumerate(kernels):
+        w1, H1, it1 = one.assimilate(dev(fg[None]), steps, Observations(4, osteps, dev(mo)), k, "lbfgs",
+                                     max_iter=4, lbfgs_m=3, ckpt_every=10)
+        assert np.array_equal(w[b], w1.cpu().numpy()[0]), b
+        assert H[b] == H1[0] and iters[b] == it1[0]
+    w_ref, h_ref, it_ref, _ = O.assimilate(fg, ph, steps, Obs(4, osteps, mo[0]), Kernel(3, 0.01, 0), "lbfgs", 4, 3)
+    assert iters[3] == it_ref
+    assert np.allclose(H[3][: it_ref + 1], h_ref, rtol=ITER_TOL, atol=0)
+    assert rel(w[3], w_ref) < ITER_TOL
