@@ -26,7 +26,7 @@ import numpy as np
 
 from .dft import fft2
 from .model import (grid, forcing_hat, lin_factor, lawson_step, observe,
-                    initial_spectrum, velocity_and_gradient, Obs)
+                    initial_spectrum, velocity_and_gradient, Obs, sobolev_term)
 
 
 def nl_tangent(g, w_hat, d_hat):
@@ -98,8 +98,12 @@ def obs_source(g, w_hat, stride, values):
     return src, 0.5 * float(np.sum(r * r))
 
 
-def adjoint_gradient(omega0, phys, n_steps, obs: Obs):
-    """Return (J, dJ/d omega0) for the observation set obs (values required)."""
+def adjoint_gradient(omega0, phys, n_steps, obs: Obs, sobolev=0.0):
+    """Return (J, dJ/d omega0) for the observation set obs (values required).
+
+    With sobolev = lambda > 0 the cost carries the term of Eq. (4),
+    (lambda/2) (2 pi / N)^2 sum_ij (P omega0)^2, whose gradient
+    lambda (2 pi / N)^2 P omega0 is added."""
     g = grid(phys.N)
     fh = forcing_hat(g, phys)
     E1 = lin_factor(g, phys, phys.dt)
@@ -125,6 +129,9 @@ def adjoint_gradient(omega0, phys, n_steps, obs: Obs):
             J += j
     # omega_0 = P omega0_in  =>  dJ/d omega0_in = P lam_0
     grad = g.to_phys(g.mask, lam)
+    if sobolev > 0.0:
+        J += sobolev_term(g, traj[0], sobolev)
+        grad = grad + sobolev * (2.0 * np.pi / g.N) ** 2 * g.to_phys(1.0, traj[0])
     return J, grad
 
 

@@ -178,10 +178,19 @@ def trajectory(omega0, phys, n_steps):
     return traj
 
 
-def forward(omega0, phys, n_steps, obs: Optional[Obs] = None):
+def sobolev_term(g, w0_hat, lam):
+    """(lam/2) int |grad u0|^2 dOmega of Eq. (4) for the band-limited initial
+    state: for a periodic divergence-free field int |grad u|^2 = int omega^2,
+    and the grid rule (2 pi / N)^2 sum_ij omega_ij^2 is exact for it."""
+    w = g.to_phys(1.0, w0_hat)
+    return 0.5 * lam * (2.0 * np.pi / g.N) ** 2 * float(np.sum(w * w))
+
+
+def forward(omega0, phys, n_steps, obs: Optional[Obs] = None, sobolev=0.0):
     """Run the forward model from a physical field.
 
     Returns (omega_T physical, J or None, model observations [n_t][2][M][M] or None).
+    With sobolev = lambda > 0, J includes the regularisation term of Eq. (4).
     """
     g = grid(phys.N)
     fh = forcing_hat(g, phys)
@@ -201,6 +210,8 @@ def forward(omega0, phys, n_steps, obs: Optional[Obs] = None):
                 r = o - obs.values[steps.index(n)]
                 J += 0.5 * float(np.sum(r * r))
 
+    if sobolev > 0.0 and obs is not None and obs.values is not None:
+        J += sobolev_term(g, w, sobolev)
     record(0, w)
     for n in range(n_steps):
         w, _st = lawson_step(g, phys, w, fh, E1, E2)

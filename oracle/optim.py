@@ -110,13 +110,14 @@ def minimize(fun_grad, fun, x0, method="lbfgs", max_iter=10, m=10, gtol=0.0):
     return x, hist, done, status
 
 
-def assimilate(omega_fg, phys, n_steps, obs, kern, method="lbfgs", max_iter=10, m=10):
+def assimilate(omega_fg, phys, n_steps, obs, kern, method="lbfgs", max_iter=10, m=10, sobolev=0.0):
     """Preconditioned 4D-Var from a first guess (Sec. II.C).
 
     Optimises the latent s = precondition(omega, -1/2); every evaluation maps
     back with omega0 = precondition(s, +1/2) and the latent gradient is
-    precondition(dJ/d omega0, +1/2).  Returns (omega0 estimate, J history,
-    iterations, status).
+    precondition(dJ/d omega0, +1/2).  sobolev = lambda > 0 adds the
+    regularisation term of Eq. (4) to the cost.  Returns (omega0 estimate,
+    J history, iterations, status).
     """
     N = phys.N
     shape = (N, N)
@@ -125,11 +126,11 @@ def assimilate(omega_fg, phys, n_steps, obs, kern, method="lbfgs", max_iter=10, 
         return precondition(x.reshape(shape), kern, 0.5)
 
     def fun_grad(x):
-        J, g = adjoint_gradient(to_phys(x), phys, n_steps, obs)
+        J, g = adjoint_gradient(to_phys(x), phys, n_steps, obs, sobolev)
         return J, precondition(g, kern, 0.5).ravel()
 
     def fun(x):
-        _w, J, _o = forward(to_phys(x), phys, n_steps, obs)
+        _w, J, _o = forward(to_phys(x), phys, n_steps, obs, sobolev)
         return J
 
     s0 = precondition(np.asarray(omega_fg, dtype=np.float64), kern, -0.5).ravel()

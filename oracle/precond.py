@@ -14,7 +14,9 @@ the hot path also uses exp(-sigma |k|).
 State and control here are vorticity fields.  The control metric multiplier
 m(k)^2 is |k|^2 for the velocity metric (default: sum_x s^2 equals the
 kinetic-energy norm sum_x |u|^2 when W = 1, so "identity" is the paper's
-velocity control) or 1 for the vorticity metric.  precondition(f, p) is
+velocity control), 1 for the vorticity metric, or |k|^4 for the
+streamfunction metric (sum_x s^2 = sum_x psi^2 when W = 1: the control
+variables u0, omega0, psi0 of Sec. III.A).  precondition(f, p) is
 
     F^-1[ (m^2 W)^p 1_S F f ]
 
@@ -32,7 +34,7 @@ from .dft import fft2, ifft2
 from .model import grid
 
 IDENTITY, EXP_ABS, FRACTIONAL, HEAT = 0, 1, 2, 3
-VELOCITY, VORTICITY = 0, 1
+VELOCITY, VORTICITY, STREAMFUNCTION = 0, 1, 2
 
 
 @dataclass(frozen=True)
@@ -63,7 +65,7 @@ def weight(g, kern: Kernel):
 def multiplier(g, kern: Kernel, power: float):
     """(m^2 W)^power on S, zero outside."""
     W = weight(g, kern)
-    m2 = g.k2 if kern.metric == VELOCITY else np.ones_like(g.k2)
+    m2 = {VELOCITY: g.k2, VORTICITY: np.ones_like(g.k2), STREAMFUNCTION: g.k2 * g.k2}[kern.metric]
     base = np.where(g.mask > 0, m2 * W, 1.0)
     return np.where(g.mask > 0, base ** power, 0.0)
 

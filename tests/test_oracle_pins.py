@@ -500,3 +500,61 @@ def test_ensemble_statistics_single_member_and_jensen():
     # mean energy is the average of the single-member rows
     rows = [ensemble.impulse_adjoint(x, ph, H, 5, 9, 8)[0] for x in w]
     assert np.allclose(st["mean_energy"], np.mean(rows, axis=0), rtol=1e-14, atol=0)
+
+
+# ---------------------------------------------------- regularisation, metrics -----
+
+def _grad_u_squared(g, w_hat):
+    """int |grad u|^2 dOmega on the grid from the velocity of w_hat, its four
+    derivatives formed spectrally (independent of the omega^2 form)."""
+    u_hat = g.m_u * w_hat
+    v_hat = g.m_v * w_hat
+    tot = 0.0
+    for f in (u_hat, v_hat):
+        for d in (1j * g.ikx, 1j * g.iky):
+            q = dft.ifft2(d * f).real
+            tot += float(np.sum(q * q))
+    return tot * (2 * np.pi / g.N) ** 2
+
+
+def test_sobolev_term_equals_velocity_gradient_integral():
+    N, lam = 32, 0.37
+    g = model.grid(N)
+    w_hat = g.mask * dft.fft2(O.init_field(N, [4], kind=0, k0=5.0)[0])
+    assert model.sobolev_term(g, w_hat, lam) == pytest.approx(0.5 * lam * _grad_u_squared(g, w_hat), rel=1e-12)
+
+
+def test_sobolev_gradient_finite_differences_and_zero_residual_closed_form():
+    N, steps, lam = 16, 10, 2e-3
+    ph = Physics(N=N, nu=1e-3, dt=5e-3)
+    osteps = [0, 5, 10]
+    obs = _twin_obs(N, ph, steps, osteps, 4, seed=21)
+    w0 = O.init_field(N, [22], kind=0, k0=3.0)[0]
+    J, grad = adjoint.adjoint_gradient(w0, ph, steps, obs, sobolev=lam)
+    d = np.random.default_rng(5).standard_normal((N, N))
+    eps = 1e-6
+    Jp = model.forward(w0 + eps * d, ph, steps, obs, sobolev=lam)[1]
+    Jm = model.forward(w0 - eps * d, ph, steps, obs, sobolev=lam)[1]
+    assert (Jp - Jm) / (2 * eps) == pytest.approx(float(np.sum(grad * d)), rel=1e-6)
+    # observations of the field itself: the residual vanishes, J and its gradient are the term alone
+    g = model.grid(N)
+    _, _, own = model.forward(w0, ph, steps, Obs(4, osteps))
+    J0, g0 = adjoint.adjoint_gradient(w0, ph, steps, Obs(4, osteps, own), sobolev=lam)
+    w_hat = g.mask * dft.fft2(w0)
+    assert J0 == pytest.approx(0.5 * lam * _grad_u_squared(g, w_hat), rel=1e-12)
+    # gradient of (lam/2) int omega^2 in the grid inner product: lam (2 pi/N)^2 P omega0
+    Pw = g.to_phys(1.0, w_hat)
+    assert np.allclose(g0, lam * (2 * np.pi / N) ** 2 * Pw, rtol=0, atol=1e-14 * np.abs(Pw).max())
+
+
+def test_streamfunction_metric():
+    N = 32
+    g = model.grid(N)
+    w = O.init_field(N, [9], kind=0, k0=5.0)[0]
+    # W = |k|^2 (fractional, alpha = -1) in the velocity metric is the identity in the streamfunction metric
+    a = precond.precondition(w, precond.Kernel(precond.FRACTIONAL, -1.0, precond.VELOCITY), -0.5)
+    b = precond.precondition(w, precond.Kernel(precond.IDENTITY, 0.0, precond.STREAMFUNCTION), -0.5)
+    assert np.allclose(a, b, rtol=0, atol=1e-12 * np.abs(b).max())
+    # with W = 1 the latent control's Euclidean norm is the streamfunction's: psi_hat = omega_hat / |k|^2
+    psi = dft.ifft2(g.mask * g.inv_k2 * dft.fft2(w)).real
+    assert float(np.sum(b * b)) == pytest.approx(float(np.sum(psi * psi)), rel=1e-12)
