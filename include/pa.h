@@ -18,7 +18,8 @@
  *   returned as dJ/d omega0 in the grid-Euclidean inner product.
  *   Preconditioner: Fourier multiplier (m(k)^2 W(|k|))^p with W one of the
  *   kernels of Sec. III.B (plus exp(-sigma|k|)), m^2 = |k|^2 (velocity
- *   metric) or 1 (vorticity metric); latent control s = G^(-1/2) omega0 and
+ *   metric), 1 (vorticity metric) or |k|^4 (streamfunction metric: the
+ *   control variables u0, omega0, psi0 of Sec. III.A); latent control s = G^(-1/2) omega0 and
  *   latent gradient G^(1/2) dJ/domega0 (Sec. II.B-C, Eqs. (13)-(19)).
  *   Optimiser: L-BFGS or steepest descent in the latent control (Sec. II.C).
  *
@@ -93,7 +94,9 @@ typedef struct pa_obs {
  *      1: exponential W = exp(-param |k|)
  *      2: fractional  W = |k|^(-2 param)
  *      3: heat kernel W = exp(-param |k|^2)    (param = nu*beta of the paper)
- * metric 0: velocity (m^2 = |k|^2), 1: vorticity (m^2 = 1).  W(0) = 1. */
+ * metric 0: velocity (m^2 = |k|^2), 1: vorticity (m^2 = 1), 2: streamfunction
+ * (m^2 = |k|^4): with W = 1 the latent control's Euclidean norm is that of
+ * u0, omega0 or psi0 (Sec. III.A).  W(0) = 1. */
 typedef struct pa_kernel {
     int32_t kind;
     int32_t metric;
@@ -299,6 +302,16 @@ typedef struct pa_tiles {
  * the sets above or an explicit col_block that does not fit; nothing changes
  * then. */
 pa_status pa_set_tiles(pa_ctx* ctx, const pa_tiles* tiles);
+
+/* Sobolev regularisation of the cost (Eq. (4)): J += (lambda/2) int |grad
+ * u0|^2 dOmega = (lambda/2) int omega0^2 dOmega (periodic, divergence-free),
+ * evaluated exactly on the grid for P omega0 as (lambda/2) (2 pi/N)^2
+ * sum_ij (P omega0)^2; the gradient gains lambda (2 pi/N)^2 P omega0.
+ * Applies to every cost and cost gradient of this context (pa_forward's J,
+ * pa_adjoint_gradient, pa_adjoint_from_checkpoints, pa_assimilate*), not to
+ * impulse responses.  lambda = 0 (the default) switches it off; PA_EINVAL for
+ * a negative or non-finite lambda. */
+pa_status pa_set_sobolev(pa_ctx* ctx, double lambda);
 
 /* Current tiles of the context. */
 pa_status pa_get_tiles(const pa_ctx* ctx, pa_tiles* tiles);

@@ -7,7 +7,8 @@ tensors and streams.  Importing the package does not load the library;
 constructing a Solver does, and fails loudly if it is missing.
 """
 
-from .solver import Solver, KernelSpec, Observations, IDENTITY, EXP_ABS, FRACTIONAL, HEAT, VELOCITY, VORTICITY
+from .solver import (Solver, KernelSpec, Observations, IDENTITY, EXP_ABS, FRACTIONAL, HEAT, VELOCITY, VORTICITY,
+                     STREAMFUNCTION)
 
 __all__ = ["Solver", "KernelSpec", "Observations", "IDENTITY", "EXP_ABS", "FRACTIONAL", "HEAT",
-           "VELOCITY", "VORTICITY"]
+           "VELOCITY", "VORTICITY", "STREAMFUNCTION"]

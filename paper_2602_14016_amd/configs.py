@@ -1,6 +1,6 @@
 """Named workloads of the hot path and a runner.
 
-    python -m paper_2602_14016_amd.configs c0|c1|c2|c3|sweep [--iters K] [--horizon H]
+    python -m paper_2602_14016_amd.configs c0|c1|c2|c3|sweep|controls [--iters K] [--horizon H]
 
 c0  decaying turbulence, 64^2, nu = 1e-3, Gaussian random field (k0 = 4,
     energy 0.5), 200 RK4 steps at dt = 5e-3, velocity at every 4th grid point
@@ -21,6 +21,9 @@ c3  ensemble of 64 realizations of the c1 spectrum (seeds 0..63), 500
 sweep  the c1 problem assimilated under 14 preconditioners at once (fractional
     |k|^(-2 alpha), alpha = -2..2, and heat exp(-nu beta |k|^2), beta = -0.1..0.8)
     as one batched solve, timed against one solve per kernel.
+controls  the c1 problem with the control variables of Sec. III.A: velocity,
+    vorticity and streamfunction (one batched solve) and velocity with the
+    Sobolev-regularised cost (lambda = 1e-3).
 
 Truth fields are seeded synthetic spectra (the paper's truth realizations are
 not available); observations are the model's own (twin experiment).
@@ -95,6 +98,32 @@ def sweep_kernels(nu=1e-4, alphas=(-2.0, -1.5, -1.0, -0.5, 0.0, 0.5, 1.0, 1.5, 2
     return [KernelSpec(2, a) for a in alphas] + [KernelSpec(3, nu * b) for b in betas]
 
 
+def run_controls(cfg: Config, iters, sobolev=1e-3, verbose=True):
+    """The control-variable comparison of Sec. III.A on cfg: velocity, vorticity and
+    streamfunction controls (identity kernel, three metrics) as one batched solve, and
+    the velocity control with the Sobolev term lambda/2 int |grad u0|^2 of the cost."""
+    from .solver import STREAMFUNCTION, VELOCITY, VORTICITY
+    s1 = Solver(cfg.N, 1, **cfg.physics())
+    truth, obs_vals = truth_and_obs(cfg, s1)
+    fg = s1.first_guess(cfg.stride, obs_vals[:, 0].contiguous())
+    names = ["u0", "omega0", "psi0"]
+    kernels = [KernelSpec(0, 0.0, VELOCITY), KernelSpec(0, 0.0, VORTICITY), KernelSpec(0, 0.0, STREAMFUNCTION)]
+    sb = Solver(cfg.N, 3, **cfg.physics())
+    obs_b = Observations(cfg.stride, cfg.obs_steps, obs_vals.expand(3, -1, -1, -1, -1).contiguous())
+    w, H, it = sb.assimilate(fg.expand(3, -1, -1).contiguous(), cfg.n_steps, obs_b, kernels, "lbfgs", iters,
+                             cfg.lbfgs_m, cfg.ckpt_every)
+    s1.set_sobolev(sobolev)
+    wr, Hr, itr = s1.assimilate(fg, cfg.n_steps, Observations(cfg.stride, cfg.obs_steps, obs_vals), kernels[0],
+                                "lbfgs", iters, cfg.lbfgs_m, cfg.ckpt_every)
+    ws = torch.cat([w, wr])
+    err = (torch.linalg.norm((ws - truth).reshape(4, -1), dim=1) / torch.linalg.norm(truth)).cpu().tolist()
+    out = {"config": cfg.name + "-controls", "controls": names + [f"u0+sobolev({sobolev:g})"],
+           "iterations": it + itr, "J_history": H + Hr, "rel_err_omega0": err}
+    if verbose:
+        print(json.dumps(out), flush=True)
+    return out
+
+
 def run_sweep(cfg: Config, kernels, iters, sequential=True, verbose=True):
     """Assimilate cfg once per kernel: all kernels as one batched solve, then (if
     sequential) one solve per kernel; returns timings and per-kernel results."""
@@ -167,7 +196,7 @@ def run_config(cfg: Config, iters=None, verbose=True):
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("config", choices=sorted(list(CONFIGS) + ["c3", "sweep"]))
+    ap.add_argument("config", choices=sorted(list(CONFIGS) + ["c3", "sweep", "controls"]))
     ap.add_argument("--iters", type=int, default=None)
     ap.add_argument("--horizon", type=int, default=None)
     ap.add_argument("--members", type=int, default=64, help="c3: ensemble size (statistics in batches beyond 64)")
@@ -197,6 +226,13 @@ def main(argv=None):
                 "subsets": {str(n): {"snr_at_tau_1": float(v["snr"][min(int(round(1.0 / 2e-3)), H)].cpu())}
                             for n, v in st.subsets.items()}}
         print(json.dumps(out))
+        return
+    if args.config == "controls":
+        cfg = c1()
+        if args.horizon:
+            cfg.n_steps = args.horizon
+            cfg.obs_steps = evenly_spaced(args.horizon, 5)
+        run_controls(cfg, args.iters or 10)
         return
     if args.config == "sweep":
         cfg = c1()

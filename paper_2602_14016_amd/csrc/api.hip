@@ -59,6 +59,7 @@ struct pa_ctx {
     int n_shell_max;
     double forcing;     // curl-force spectrum value at (0, +-n_f)
     int nf;             // n_f if inside the band, else 0
+    double sobolev = 0; // lambda of the Sobolev term (lambda/2) int |grad u0|^2 of the cost
     // launch timing of one kernel class with HIP events on the context stream
     int prof_class = -1;
     int prof_every = 1;
@@ -381,6 +382,10 @@ pa_status forward_sweep(pa_ctx* c, WS& w, const double* omega0, int n_steps, con
     cd* f0[4] = {w.Yf[0], w.Yf[1], w.Yf[2], w.Yf[3]};
     if (store && n_last == 0) seg_fields(c, w, 0, 0, f0);
     PA_TRY(start_state(c, w, omega0, ckpt ? ckpt_slot(c, ckpt, 0) : nullptr, f0));
+    // Sobolev term (lambda/2) int |grad u0|^2 = (lambda/2) int omega0^2 (periodic, divergence-free),
+    // exact on the grid for the band-limited P omega0: 4 pi^2 lambda * (1/2) sum |omega_hat|^2 / N^4
+    const bool reg = c->sobolev > 0.0 && op.values && op.n_times > 0;
+    if (reg) PA_HIP(launch_state_energy(c->d, w.omega, 4.0 * M_PI * M_PI * c->sobolev, w.J2, c->stream));
     if (n_last > 0) {
         PA_TRY(run_steps(c, w, 0, n_last, n_steps, K, false, &op, obs_out, ckpt, !store && final_obs));
         if (store) {
@@ -401,6 +406,7 @@ pa_status forward_sweep(pa_ctx* c, WS& w, const double* omega0, int n_steps, con
     if (final_obs) PA_TRY(observe_final(c, w, op, n_steps, fH, obs_out));
     if (op.values && op.n_times > 0)
         PA_HIP(launch_reduce_j(c->d.B, op.n_times * op.M, w.jpart, w.J, c->stream));
+    if (reg) PA_HIP(launch_axpy(c->d.B, 1, nullptr, 1.0, w.J2, w.J, nullptr, c->stream));
     return PA_OK;
 }
 
@@ -522,6 +528,19 @@ pa_status terminal(pa_ctx* c, WS& w, const ObsPlan* op, int n_steps, cd* const f
     return PA_OK;
 }
 
+// Gradient of the Sobolev term, lambda (2 pi / N)^2 P omega0 (times the
+// member's scale), added to grad_out; P omega0 is checkpoint 0.  Cost
+// gradients only (observations given, not the impulse response).
+pa_status add_sobolev_gradient(pa_ctx* c, WS& w, const cd* ckpt, const ObsPlan* op, int impulse,
+                               const double* scale, double* grad_out) {
+    if (!(c->sobolev > 0.0) || impulse || !op || !op->values || op->n_times == 0) return PA_OK;
+    const size_t n = (size_t)c->d.N * c->d.N;
+    PA_TRY(state_to_phys(c, w, ckpt_slot(c, const_cast<cd*>(ckpt), 0), w.P0));
+    const double coef = c->sobolev * 4.0 * M_PI * M_PI / (double)n;
+    PA_HIP(launch_axpy(c->d.B, n, scale, coef, w.P0, grad_out, nullptr, c->stream));
+    return PA_OK;
+}
+
 // Backward sweep from checkpoints: recompute each segment storing every
 // stage's fields, then run the adjoint steps of the segment in reverse.  With
 // last_ready the last segment's fields are already in the segment slots (a
@@ -542,11 +561,13 @@ pa_status backward_sweep(pa_ctx* c, WS& w, const cd* ckpt, int n_steps, int K, c
         const int slot = op ? op->slot_of[0] : -1;
         if (!impulse && slot < 0) {
             if (grad_out) PA_HIP(launch_fill(grad_out, 0.0, (size_t)c->d.B * c->d.N * c->d.N, c->stream));
+            if (grad_out) PA_TRY(add_sobolev_gradient(c, w, ckpt, op, impulse, scale, grad_out));
             return PA_OK;
         }
         PA_TRY(terminal(c, w, op, 0, f0, impulse, ix, iy, true, scale));
         PA_TRY(record_shells(c, w, sh, 0));
         if (grad_out) PA_HIP(launch_row_c2r(c->d, w.YL[0], grad_out, c->tw, c->stream));
+        if (grad_out) PA_TRY(add_sobolev_gradient(c, w, ckpt, op, impulse, scale, grad_out));
         return PA_OK;
     }
     if (!w.seg) return fail(PA_EINVAL, "workspace carved without a segment buffer");
@@ -585,6 +606,7 @@ pa_status backward_sweep(pa_ctx* c, WS& w, const cd* ckpt, int n_steps, int K, c
         }
     }
     if (grad_out) PA_HIP(launch_row_c2r(c->d, w.YL[0], grad_out, c->tw, c->stream));
+    if (grad_out) PA_TRY(add_sobolev_gradient(c, w, ckpt, op, impulse, scale, grad_out));
     return PA_OK;
 }
 
@@ -608,7 +630,7 @@ pa_status apply_filter(pa_ctx* c, WS& w, const double* mult, const double* in, d
 pa_status valid_kernel(const pa_kernel* k) {
     if (!k) return fail(PA_EINVAL, "kernel is NULL");
     if (k->kind < 0 || k->kind > 3) return fail(PA_EINVAL, "kernel kind must be 0..3");
-    if (k->metric < 0 || k->metric > 1) return fail(PA_EINVAL, "kernel metric must be 0 or 1");
+    if (k->metric < 0 || k->metric > 2) return fail(PA_EINVAL, "kernel metric must be 0, 1 or 2");
     if (!std::isfinite(k->param)) return fail(PA_EINVAL, "kernel parameter must be finite");
     return PA_OK;
 }
@@ -795,6 +817,13 @@ pa_status pa_set_tiles(pa_ctx* c, const pa_tiles* t) {
         while (d.cb > 1 && !col_fits(d.cb)) d.cb >>= 1;
     }
     c->d = d;
+    return PA_OK;
+}
+
+pa_status pa_set_sobolev(pa_ctx* c, double lambda) {
+    if (!c) return fail(PA_EINVAL, "ctx is NULL");
+    if (!std::isfinite(lambda) || lambda < 0.0) return fail(PA_EINVAL, "lambda must be finite and >= 0");
+    c->sobolev = lambda;
     return PA_OK;
 }
 

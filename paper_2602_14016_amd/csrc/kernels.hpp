@@ -142,6 +142,9 @@ hipError_t launch_scal_copy(int B, size_t n, const double* alpha, const double* 
 hipError_t launch_nonfinite(int B, size_t n, const double* x, int* flags, hipStream_t s);
 hipError_t launch_scatter_probes(int B, int N, int stride, const double* probes, double* grid_u, double* grid_v,
                                  hipStream_t s);
+// out[b] = scale * sum_k 1/2 |state_hat_b|^2 / N^4 over the band (= scale * grid mean of the field's
+// square / 2 by Parseval)
+hipError_t launch_state_energy(const Dims& d, const cd* state, double scale, double* out, hipStream_t s);
 // ensemble statistics: add one batch at one row (adjoint step), and the final statistics
 hipError_t launch_ens_accumulate(const Dims& d, const cd* lam, cd* lambda_sum_row, const double* shells_row,
                                  size_t shells_stride, int n_shells, double* shell_sum_row, double* etot_scratch,

@@ -58,7 +58,7 @@ __global__ void make_mult_kernel(Dims d, int kind, int metric, double param, dou
     if (kind == 1) W = exp(-param * kap);
     else if (kind == 2) W = pow(kap, -2.0 * param);
     else if (kind == 3) W = exp(-param * k2);
-    const double base = (metric == 0 ? k2 : 1.0) * W;
+    const double base = (metric == 0 ? k2 : metric == 2 ? k2 * k2 : 1.0) * W;
     mult[i] = pow(base, power);
 }
 hipError_t launch_make_mult(const Dims& d, int kind, int metric, double param, double power, double* mult,
@@ -246,12 +246,14 @@ __global__ void ens_scalar_sum_kernel(int B, const double* __restrict__ v, size_
     acc[k] = a;
 }
 
-// Total adjoint velocity energy sum_k 1/2 |k|^2 |lam_hat|^2 / N^4 of each of
-// d.B compact states (kx > 0 counted twice for the Hermitian half), times
-// scale; one workgroup per state, fixed-order tree.
+// sum_k 1/2 |k|^(2 p) |lam_hat|^2 / N^4 over the band of each of d.B compact
+// states (kx > 0 counted twice for the Hermitian half), times scale, for p =
+// k2pow in {0, 1}: with p = 1 the adjoint velocity energy, with p = 0 half
+// the grid mean of the field's square.  One workgroup per state,
+// fixed-order tree.
 constexpr int ETOT_THREADS = 256;
 __global__ void __launch_bounds__(ETOT_THREADS) energy_total_kernel(Dims d, const cd* __restrict__ lam, double scale,
-                                                                    double* __restrict__ out) {
+                                                                    double* __restrict__ out, int k2pow) {
     __shared__ double sh[ETOT_THREADS];
     const int b = blockIdx.x;
     const size_t SC = (size_t)d.KY * d.KXP;
@@ -263,7 +265,7 @@ __global__ void __launch_bounds__(ETOT_THREADS) energy_total_kernel(Dims d, cons
         const int ky = (r <= d.K) ? r : r - d.KY;
         const double k2 = (double)kx * kx + (double)ky * ky;
         const double wgt = kx > 0 ? 2.0 : 1.0;
-        s += wgt * 0.5 * k2 * (l[i].x * l[i].x + l[i].y * l[i].y);
+        s += wgt * 0.5 * (k2pow ? k2 : 1.0) * (l[i].x * l[i].x + l[i].y * l[i].y);
     }
     sh[threadIdx.x] = s;
     __syncthreads();
@@ -299,6 +301,12 @@ __global__ void ens_finish_kernel(int rows, int n_shells, double inv_count, cons
     }
 }
 
+hipError_t launch_state_energy(const Dims& d, const cd* state, double scale, double* out, hipStream_t s) {
+    if (!state || !out) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(energy_total_kernel, dim3(d.B), dim3(ETOT_THREADS), 0, s, d, state, scale, out, 0);
+    return hipGetLastError();
+}
+
 hipError_t launch_ens_accumulate(const Dims& d, const cd* lam, cd* lambda_sum_row, const double* shells_row,
                                  size_t shells_stride, int n_shells, double* shell_sum_row, double* etot_scratch,
                                  double* energy_sum_row, hipStream_t s) {
@@ -308,7 +316,7 @@ hipError_t launch_ens_accumulate(const Dims& d, const cd* lam, cd* lambda_sum_ro
     hipLaunchKernelGGL(ens_lambda_sum_kernel, dim3((n + 255) / 256), dim3(256), 0, s, d, lam, lambda_sum_row);
     hipLaunchKernelGGL(ens_scalar_sum_kernel, dim3((n_shells + 63) / 64), dim3(64), 0, s, d.B, shells_row,
                        shells_stride, n_shells, shell_sum_row);
-    hipLaunchKernelGGL(energy_total_kernel, dim3(d.B), dim3(ETOT_THREADS), 0, s, d, lam, 1.0, etot_scratch);
+    hipLaunchKernelGGL(energy_total_kernel, dim3(d.B), dim3(ETOT_THREADS), 0, s, d, lam, 1.0, etot_scratch, 1);
     hipLaunchKernelGGL(ens_scalar_sum_kernel, dim3(1), dim3(64), 0, s, d.B, etot_scratch, (size_t)1, 1,
                        energy_sum_row);
     return hipGetLastError();
@@ -325,7 +333,8 @@ hipError_t launch_ens_stats(const Dims& d, int rows, int n_shells, double inv_co
     dr.B = rows;   // the rows of the member sum take the place of members
     hipLaunchKernelGGL(shells_kernel, dim3(n_shells, rows), dim3(SHELL_THREADS), 0, s, dr, lambda_sum, shell_start,
                        shell_modes, n_shells, energy_of_mean, (size_t)n_shells);
-    hipLaunchKernelGGL(energy_total_kernel, dim3(rows), dim3(ETOT_THREADS), 0, s, dr, lambda_sum, 1.0, total_of_mean);
+    hipLaunchKernelGGL(energy_total_kernel, dim3(rows), dim3(ETOT_THREADS), 0, s, dr, lambda_sum, 1.0, total_of_mean,
+                       1);
     hipLaunchKernelGGL(ens_finish_kernel, dim3(rows), dim3(64), 0, s, rows, n_shells, inv_count, shell_sum,
                        energy_sum, mean_energy, energy_of_mean, total_mean, total_of_mean, snr);
     return hipGetLastError();

@@ -81,6 +81,7 @@ EXPORTS = {
                                     c_void_p, c_void_p, c_void_p]),
     "pa_set_tiles": (c_int32, [c_void_p, POINTER(Tiles)]),
     "pa_get_tiles": (c_int32, [c_void_p, POINTER(Tiles)]),
+    "pa_set_sobolev": (c_int32, [c_void_p, c_double]),
     "pa_first_guess": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_size_t]),
     "pa_shell_growth": (c_int32, [c_void_p, c_void_p, c_int32, c_int32, c_double, c_double, c_void_p, c_void_p]),
     "pa_profile_start": (c_int32, [c_void_p, c_int32, c_int32]),

@@ -15,7 +15,7 @@ import torch
 from . import native as nv
 
 IDENTITY, EXP_ABS, FRACTIONAL, HEAT = 0, 1, 2, 3
-VELOCITY, VORTICITY = 0, 1
+VELOCITY, VORTICITY, STREAMFUNCTION = 0, 1, 2
 
 
 @dataclass(frozen=True)
@@ -143,6 +143,10 @@ class Solver:
             raise ValueError(f"unknown tile keys {sorted(unknown)}")
         t = nv.Tiles(*[int(tiles.get(k, -1)) for k in nv.TILE_FIELDS])
         nv.check(self.lib.pa_set_tiles(self.ctx, byref(t)))
+
+    def set_sobolev(self, lam):
+        """Sobolev regularisation (lambda/2) int |grad u0|^2 of every cost of this solver (pa_set_sobolev)."""
+        nv.check(self.lib.pa_set_sobolev(self.ctx, float(lam)))
 
     def get_tiles(self):
         t = nv.Tiles()

@@ -97,3 +97,27 @@ def test_kernel_sweep_one_batch_equals_separate_solves():
     assert iters[3] == it_ref
     assert np.allclose(H[3][: it_ref + 1], h_ref, rtol=ITER_TOL, atol=0)
     assert rel(w[3], w_ref) < ITER_TOL
+
+
+def test_lbfgs_sobolev_streamfunction_control_parity():
+    """The control-variable variants of the paper's comparison: L-BFGS in the streamfunction metric,
+    and in the velocity metric with the Sobolev term of the cost (lambda = 1e-3)."""
+    from paper_2602_14016_amd import KernelSpec, Observations, Solver
+    print("CASE lbfgs-sobolev-psi", flush=True)
+    N, steps = 32, 24
+    osteps = synth.evenly_spaced_steps(steps, 3)
+    ph, mo = _setup(N, steps, osteps, 4, seeds=(11, 12))
+    fg = 0.5 * O.init_field(N, [13, 14], kind=0, k0=4.0)
+    for kern, lam in ((Kernel(0, 0.0, 2), 0.0), (Kernel(0, 0.0, 0), 1e-3)):
+        s = Solver(N, 2, nu=ph.nu, dt=ph.dt)
+        s.set_sobolev(lam)
+        w, H, iters = s.assimilate(dev(fg), steps, Observations(4, osteps, dev(mo)),
+                                   KernelSpec(kern.kind, kern.param, kern.metric), method="lbfgs", max_iter=4,
+                                   lbfgs_m=3, ckpt_every=10)
+        w = w.cpu().numpy()
+        for b in range(2):
+            w_ref, h_ref, it_ref, _ = O.assimilate(fg[b], ph, steps, Obs(4, osteps, mo[b]), kern, "lbfgs", 4, 3,
+                                                  sobolev=lam)
+            assert iters[b] == it_ref, (kern, lam, b)
+            assert np.allclose(H[b][: it_ref + 1], h_ref, rtol=ITER_TOL, atol=0), (kern, lam, b)
+            assert rel(w[b], w_ref) < ITER_TOL, (kern, lam, b)

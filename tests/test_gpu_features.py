@@ -28,15 +28,20 @@ def _twin(N, ph, steps, osteps, stride, seeds):
     return np.stack(out)
 
 
-def test_autograd_function_matches_adjoint_and_fd():
+@pytest.mark.parametrize("lam", [0.0, 2e-3])
+def test_autograd_function_matches_adjoint_and_fd(lam):
+    """torch.autograd.Function over the checkpointed forward and the adjoint (with and without the
+    Sobolev term of the cost): backward equals the direct adjoint gradient times grad_output and
+    central finite differences of the GPU cost."""
     from paper_2602_14016_amd import Observations, Solver
     from paper_2602_14016_amd.autograd import adjoint_cost
-    print("CASE autograd", flush=True)
+    print("CASE autograd", lam, flush=True)
     N, steps, K = 32, 30, 7
     ph = Physics(N=N, nu=1e-3, dt=5e-3)
     osteps = [0, 15, 30]
     mo = _twin(N, ph, steps, osteps, 4, [1, 2])
     s = Solver(N, 2, nu=ph.nu, dt=ph.dt)
+    s.set_sobolev(lam)
     obs = Observations(4, osteps, dev(mo))
     w0 = dev(O.init_field(N, [3, 4], kind=0, k0=4.0)).requires_grad_(True)
     J = adjoint_cost(w0, s, steps, obs, K)

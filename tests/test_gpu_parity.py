@@ -44,7 +44,7 @@ def announce(*a):
     print("CASE", *a, flush=True)
 
 
-KERNELS = [Kernel(0, 0.0, 0), Kernel(1, 0.1, 0), Kernel(2, 0.5, 0), Kernel(3, 0.01, 0), Kernel(2, 0.25, 1)]
+KERNELS = [Kernel(0, 0.0, 0), Kernel(1, 0.1, 0), Kernel(2, 0.5, 0), Kernel(3, 0.01, 0), Kernel(2, 0.25, 1), Kernel(0, 0.0, 2), Kernel(1, 0.1, 2)]
 
 
 @pytest.mark.parametrize("N", [8, 16, 32, 64, 128, 256, 512])
@@ -309,3 +309,31 @@ def test_impulse_shells_parity():
         rows, field = O.impulse_adjoint(w0[b], ph, steps, N // 2, N // 2, nsh)
         assert rel(sh[b], rows) < GRAD_TOL
         assert rel(f[b], field) < GRAD_TOL
+
+
+def test_sobolev_regularised_cost_and_gradient_parity():
+    from paper_2602_14016_amd import Observations
+    from paper_2602_14016_amd.native import PaError
+    announce("sobolev")
+    N, steps, lam = 32, 20, 2e-3
+    ph = _hit(N)
+    osteps = [0, 10, 20]
+    mo = np.stack([_twin(N, ph, steps, osteps, 4, seed=60 + b) for b in range(2)])
+    w0 = O.init_field(N, [61, 62], kind=0, k0=4.0)
+    s = solver(N, 2, ph)
+    s.set_sobolev(lam)
+    J, g = s.adjoint_gradient(dev(w0), steps, Observations(4, osteps, dev(mo)), ckpt_every=7)
+    Jf = s.forward(dev(w0), steps, Observations(4, osteps, dev(mo)))["J"]
+    Jh, gh, Jfh = host(J), host(g), host(Jf)
+    for b in range(2):
+        Jref, gref = O.adjoint_gradient(w0[b], ph, steps, Obs(4, osteps, mo[b]), sobolev=lam)
+        assert abs(float(Jh[b]) - Jref) <= FIELD_TOL * Jref
+        assert abs(float(Jfh[b]) - Jref) <= FIELD_TOL * Jref
+        assert rel(gh[b], gref) < GRAD_TOL
+    # the term is off again at lambda = 0, and rejected when negative
+    s.set_sobolev(0.0)
+    J0, _ = s.adjoint_gradient(dev(w0), steps, Observations(4, osteps, dev(mo)), ckpt_every=7)
+    assert abs(float(host(J0)[0]) - O.adjoint_gradient(w0[0], ph, steps, Obs(4, osteps, mo[0]))[0]) <= \
+        FIELD_TOL * float(host(J0)[0])
+    with pytest.raises(PaError):
+        s.set_sobolev(-1.0)
