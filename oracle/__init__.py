@@ -25,6 +25,7 @@ precond    weighting kernels W(k), metric, precondition (Sec. II.B-C,
 optim      steepest descent and L-BFGS in the latent variable (Sec. II.C)
 fields     counter-based RNG, initial fields, first guess (Sec. III)
 ensemble   adjoint impulse response, shell energies, growth rates, ensemble statistics (Sec. IV)
+checkpoint fewest recomputations that reverse a chain under a snapshot budget
 """
 
 from .dft import twiddles, dft_matrix, fft2, ifft2
@@ -34,6 +35,7 @@ from .precond import Kernel, weight, precondition
 from .optim import lbfgs_two_loop, assimilate
 from .fields import splitmix64, uniform01, init_field, first_guess
 from .ensemble import impulse_adjoint, impulse_lambdas, shell_energy, total_energy, growth_rates, ensemble_statistics
+from .checkpoint import min_advances, optimal_first_advances
 
 __all__ = [
     "twiddles", "dft_matrix", "fft2", "ifft2",
@@ -43,5 +45,5 @@ __all__ = [
     "lbfgs_two_loop", "assimilate",
     "splitmix64", "uniform01", "init_field", "first_guess",
     "impulse_adjoint", "impulse_lambdas", "shell_energy", "total_energy", "growth_rates",
-    "ensemble_statistics",
+    "ensemble_statistics", "min_advances", "optimal_first_advances",
 ]

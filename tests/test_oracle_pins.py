@@ -558,3 +558,80 @@ def test_streamfunction_metric():
     # with W = 1 the latent control's Euclidean norm is the streamfunction's: psi_hat = omega_hat / |k|^2
     psi = dft.ifft2(g.mask * g.inv_k2 * dft.fft2(w)).real
     assert float(np.sum(b * b)) == pytest.approx(float(np.sum(psi * psi)), rel=1e-12)
+
+
+# ----------------------------------------------------- checkpoint schedules
+
+def _binom_beta(a, t):
+    """beta(a, t) = C(a + t, a): steps reversible with a snapshots and t advances per step (0 for t < 0)."""
+    return math.comb(a + t, a) if t >= 0 else 0
+
+
+def test_checkpoint_cost_matches_binomial_closed_form():
+    # Griewank & Walther: with the first state held and s free slots, let t be the
+    # least integer with beta(s + 1, t) >= l; the fewest advances are t l - beta(s + 2, t - 1)
+    for s in range(1, 7):
+        for l in range(1, 90):
+            t = 0
+            while _binom_beta(s + 1, t) < l:
+                t += 1
+            assert O.min_advances(l, s) == t * l - _binom_beta(s + 2, t - 1), (l, s)
+
+
+def test_checkpoint_cost_special_cases():
+    for l in range(1, 40):
+        assert O.min_advances(l, 0) == l * (l - 1) // 2       # no slot: every step from the start
+        assert O.min_advances(l, max(l - 1, 0)) == l - 1      # a slot per step: each advanced once
+        assert O.min_advances(l, l + 5) == l - 1
+    # optimal first advances of the closed form's range
+    for s in range(1, 6):
+        for l in range(2, 60):
+            t = 0
+            while _binom_beta(s + 1, t) < l:
+                t += 1
+            lo = max(_binom_beta(s + 1, t - 2), l - _binom_beta(s, t), 1)
+            hi = min(_binom_beta(s + 1, t - 1), l - _binom_beta(s, t - 1))
+            assert O.optimal_first_advances(l, s) == list(range(lo, hi + 1)), (l, s)
+
+
+def _exhaustive_min_advances(l, s):
+    """Fewest unit advances over every strategy (not only recursive ones): states are
+    (live position or -1, held snapshot positions, steps left to reverse).  Moves:
+    advance the live state one step (cost 1), store it, drop a snapshot other than
+    the first, restore a snapshot, or reverse the next step when the live state is
+    at its start."""
+    import collections
+    start = (0, frozenset([0]), l)
+    dist = {start: 0}
+    dq = collections.deque([start])
+    while dq:
+        st = dq.popleft()
+        live, snaps, r = st
+        d = dist[st]
+        if r == 0:
+            return d
+        moves = []
+        if 0 <= live < r - 1:
+            moves.append(((live + 1, snaps, r), 1))
+        if live >= 0 and live not in snaps and len(snaps) < s + 1:
+            moves.append(((live, snaps | {live}, r), 0))
+        for q in snaps:
+            if q != 0:
+                moves.append(((live, snaps - {q}, r), 0))
+            moves.append(((q, snaps, r), 0))
+        if live == r - 1:
+            moves.append(((-1, snaps, r - 1), 0))
+        for nst, c in moves:
+            if nst not in dist or dist[nst] > d + c:
+                dist[nst] = d + c
+                if c == 0:
+                    dq.appendleft(nst)
+                else:
+                    dq.append(nst)
+    raise AssertionError("unreachable")
+
+
+def test_checkpoint_cost_is_the_optimum_over_all_strategies():
+    for s in range(0, 4):
+        for l in range(1, 9):
+            assert O.min_advances(l, s) == _exhaustive_min_advances(l, s), (l, s)
