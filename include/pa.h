@@ -127,7 +127,9 @@ pa_status pa_get_shape(const pa_ctx* ctx, int32_t* N, int32_t* B, int32_t* Kc);
  * ckpt_every steps (1 <= ckpt_every), n_obs_times observation times, and an
  * L-BFGS memory lbfgs_m (0 when not assimilating).  Any call documented as
  * taking "a workspace" accepts one of at least this size for its arguments;
- * pa_precondition and pa_init_field need pa_workspace_bytes(ctx,0,1,0,0). */
+ * pa_precondition and pa_init_field need pa_workspace_bytes(ctx,0,1,0,0).
+ * The size depends on the context's snapshot budget (pa_set_checkpoint_slots)
+ * at the time of the query, which must not grow before the workspace is used. */
 pa_status pa_workspace_bytes(const pa_ctx* ctx, int32_t n_steps, int32_t ckpt_every,
                              int32_t n_obs_times, int32_t lbfgs_m, size_t* bytes);
 
@@ -312,6 +314,48 @@ pa_status pa_set_tiles(pa_ctx* ctx, const pa_tiles* tiles);
  * impulse responses.  lambda = 0 (the default) switches it off; PA_EINVAL for
  * a negative or non-finite lambda. */
 pa_status pa_set_sobolev(pa_ctx* ctx, double lambda);
+
+/* Snapshot budget of the checkpoints kept inside the workspace by
+ * pa_adjoint_gradient, pa_adjoint_impulse and pa_assimilate* (the adjoint's
+ * recomputation, Sec. I and Sec. II.A).  The horizon splits into L =
+ * ceil(n_steps / ckpt_every) segments; each segment is recomputed once with
+ * all its stage fields kept before the adjoint runs through it.  slots = 0
+ * (the default), or slots > L: the state at every segment boundary is kept
+ * (L + 1 spectral states per member) and the forward runs once more in all.
+ * 1 <= slots <= L: only `slots` spectral states per member are kept (the
+ * first holds the initial state) and the segments are reversed by the
+ * binomial schedule of Griewank & Walther, which re-advances the fewest
+ * segments for that budget (pa_checkpoint_advances).  Results are the same
+ * either way, bit for bit: only the schedule changes.  pa_forward and
+ * pa_adjoint_from_checkpoints keep the caller's one-per-boundary layout.
+ * PA_EINVAL for slots < 0. */
+pa_status pa_set_checkpoint_slots(pa_ctx* ctx, int32_t slots);
+
+/* Current snapshot budget of the context. */
+pa_status pa_get_checkpoint_slots(const pa_ctx* ctx, int32_t* slots);
+
+/* Host only (no device, no context).  Segment advances (forward segment
+ * runs without stored fields, the first forward sweep included) of the
+ * schedule that reverses n_segments segments with `slots` snapshot slots:
+ * t L - C(s + t + 1, t - 1) for s = slots - 1 free slots, where t is the
+ * least integer with C(s + 1 + t, t) >= L; L (L - 1) / 2 for one slot and
+ * L - 1 for slots >= L.  Each segment is also run once with its fields
+ * kept.  PA_EINVAL unless n_segments >= 1 and slots >= 1. */
+pa_status pa_checkpoint_advances(int32_t n_segments, int32_t slots, int64_t* advances);
+
+/* Host only.  The schedule itself: *n_actions actions, and if actions is not
+ * NULL (host, at least 5 * capacity int32), each as (kind, a, b, src, dst):
+ *   kind 0, advance: run segments a .. b-1 from the state in slot src (-1:
+ *           the state the previous action left), keep the state of boundary
+ *           b in slot dst (-1: none);
+ *   kind 1, reverse: run segment a keeping its stage fields, from slot src
+ *           (-1: the state the previous advance left), then the adjoint
+ *           steps through it.
+ * Slot 0 holds boundary 0 throughout.  The actions before the first reverse
+ * form the forward sweep.  PA_EINVAL if capacity < *n_actions (n_actions is
+ * still set) or for sizes as in pa_checkpoint_advances. */
+pa_status pa_checkpoint_schedule(int32_t n_segments, int32_t slots, int32_t* actions, int64_t capacity,
+                                 int64_t* n_actions);
 
 /* Current tiles of the context. */
 pa_status pa_get_tiles(const pa_ctx* ctx, pa_tiles* tiles);

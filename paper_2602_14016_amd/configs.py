@@ -1,6 +1,6 @@
 """Named workloads of the hot path and a runner.
 
-    python -m paper_2602_14016_amd.configs c0|c1|c2|c3|sweep|controls [--iters K] [--horizon H]
+    python -m paper_2602_14016_amd.configs c0|c1|c2|c3|sweep|controls|longwindow [--iters K] [--horizon H]
 
 c0  decaying turbulence, 64^2, nu = 1e-3, Gaussian random field (k0 = 4,
     energy 0.5), 200 RK4 steps at dt = 5e-3, velocity at every 4th grid point
@@ -24,6 +24,9 @@ sweep  the c1 problem assimilated under 14 preconditioners at once (fractional
 controls  the c1 problem with the control variables of Sec. III.A: velocity,
     vorticity and streamfunction (one batched solve) and velocity with the
     Sobolev-regularised cost (lambda = 1e-3).
+longwindow  the c1 flow over 20000 steps (64 members) with a 16 GiB workspace,
+    below what one checkpoint per segment needs: binomial checkpointing,
+    timed and compared bit for bit with the unbudgeted gradient.
 
 Truth fields are seeded synthetic spectra (the paper's truth realizations are
 not available); observations are the model's own (twin experiment).
@@ -124,6 +127,63 @@ def run_controls(cfg: Config, iters, sobolev=1e-3, verbose=True):
     return out
 
 
+def run_longwindow(N=256, B=64, n_steps=20000, budget_gib=16.0, n_obs=5, stride=8, verbose=True):
+    """A long assimilation window under a memory budget (binomial checkpointing).
+
+    The c1 flow (N^2, nu = 1e-4, dt = 2e-3) over n_steps steps, B members,
+    observations at n_obs evenly spaced times.  The budget is set below what
+    one checkpoint per segment boundary needs at any segment length, so the
+    gradient runs with the binomial schedule that fit_checkpointing picks;
+    it is timed, then the same gradient without a budget (one checkpoint per
+    boundary, longest segments that fit the device), and the two are
+    compared bit for bit."""
+    from .autotune import autotune
+    s = Solver(N, B, nu=1e-4, dt=2e-3)
+    tiles = {k: v for k, v in autotune(s, n_steps=8).items() if k in s.get_tiles()}
+    s.set_tiles(**tiles)
+    steps = evenly_spaced(n_steps, n_obs)
+    truth = s.init_field([1000 + b for b in range(B)], kind=0, k0=10.0, target=0.5)
+    obs = Observations(stride, steps, s.forward(truth, n_steps, Observations(stride, steps), want_obs=True)["obs"])
+    del truth
+    w0 = s.init_field(list(range(B)), kind=0, k0=10.0, target=0.5)
+    budget = int(budget_gib * (1 << 30))
+    s.set_checkpoint_slots(0)
+    uniform_floor = min(s.workspace_bytes(n_steps, -(-n_steps // L), len(steps), 0) for L in range(1, n_steps + 1))
+    K, slots, fwd = s.fit_checkpointing(n_steps, len(steps), 0, budget_bytes=budget)
+    if not K:
+        raise SystemExit(f"nothing fits in {budget_gib} GiB")
+
+    def timed_gradient(K_):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        J, g = s.adjoint_gradient(w0, n_steps, obs, ckpt_every=K_)
+        torch.cuda.synchronize()
+        return J, g, time.perf_counter() - t0
+
+    s.set_checkpoint_slots(slots)
+    ws_bin = s.workspace_bytes(n_steps, K, len(steps), 0)
+    Jb, gb, tb = timed_gradient(K)
+    Jb, gb = Jb.cpu(), gb.cpu()
+    s._ws = None
+    torch.cuda.empty_cache()
+    s.set_checkpoint_slots(0)
+    Ku = s.fit_ckpt_every(n_steps, len(steps))
+    Lu = -(-n_steps // Ku)
+    ws_uni = s.workspace_bytes(n_steps, Ku, len(steps), 0)
+    Ju, gu, tu = timed_gradient(Ku)
+    same = bool(torch.equal(Jb, Ju.cpu()) and torch.equal(gb, gu.cpu()))
+    out = {"config": f"longwindow-{N}x{B}-H{n_steps}", "budget_gib": budget_gib,
+           "uniform_min_workspace_gib": uniform_floor / (1 << 30),
+           "binomial": {"segment_steps": K, "segments": -(-n_steps // K), "slots": slots,
+                        "workspace_gib": ws_bin / (1 << 30), "forward_steps": fwd, "seconds": tb},
+           "unbudgeted": {"segment_steps": Ku, "segments": Lu, "workspace_gib": ws_uni / (1 << 30),
+                          "forward_steps": n_steps + (Lu - 1) * Ku, "seconds": tu},
+           "bitwise_equal": same, "grad_finite": bool(torch.isfinite(gb).all())}
+    if verbose:
+        print(json.dumps(out), flush=True)
+    return out
+
+
 def run_sweep(cfg: Config, kernels, iters, sequential=True, verbose=True):
     """Assimilate cfg once per kernel: all kernels as one batched solve, then (if
     sequential) one solve per kernel; returns timings and per-kernel results."""
@@ -196,11 +256,12 @@ def run_config(cfg: Config, iters=None, verbose=True):
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("config", choices=sorted(list(CONFIGS) + ["c3", "sweep", "controls"]))
+    ap.add_argument("config", choices=sorted(list(CONFIGS) + ["c3", "sweep", "controls", "longwindow"]))
     ap.add_argument("--iters", type=int, default=None)
     ap.add_argument("--horizon", type=int, default=None)
     ap.add_argument("--members", type=int, default=64, help="c3: ensemble size (statistics in batches beyond 64)")
     ap.add_argument("--batch", type=int, default=64, help="c3: members per batched solve")
+    ap.add_argument("--budget-gib", type=float, default=16.0, help="longwindow: workspace budget")
     args = ap.parse_args(argv)
     if args.config == "c3":
         from . import ensemble
@@ -226,6 +287,9 @@ def main(argv=None):
                 "subsets": {str(n): {"snr_at_tau_1": float(v["snr"][min(int(round(1.0 / 2e-3)), H)].cpu())}
                             for n, v in st.subsets.items()}}
         print(json.dumps(out))
+        return
+    if args.config == "longwindow":
+        run_longwindow(B=args.batch, n_steps=args.horizon or 20000, budget_gib=args.budget_gib)
         return
     if args.config == "controls":
         cfg = c1()

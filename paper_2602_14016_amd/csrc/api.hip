@@ -43,6 +43,17 @@ bool is_pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
 
 bool finite_nonneg(double v) { return std::isfinite(v) && v >= 0.0; }
 
+// One action of a checkpoint schedule over segment boundaries 0..L (segment i
+// runs from boundary i to i + 1).  ADVANCE runs segments a .. b-1 without
+// keeping their stage fields, starting from snapshot slot src (or from the
+// live state, src = -1) and storing the state of boundary b in slot dst (if
+// dst >= 0).  REVERSE recomputes segment a keeping its stage fields, from
+// slot src (or the live state), and runs the adjoint steps through it.
+enum { ACT_ADVANCE = 0, ACT_REVERSE = 1 };
+struct PlanAct {
+    int kind, a, b, src, dst;
+};
+
 }  // namespace
 
 struct pa_ctx {
@@ -60,6 +71,11 @@ struct pa_ctx {
     double forcing;     // curl-force spectrum value at (0, +-n_f)
     int nf;             // n_f if inside the band, else 0
     double sobolev = 0; // lambda of the Sobolev term (lambda/2) int |grad u0|^2 of the cost
+    // snapshot budget of the internal checkpoints (0: one per segment boundary)
+    int ckpt_slots = 0;
+    int plan_L = -1, plan_slots = -1;
+    std::vector<PlanAct> plan;       // binomial schedule for plan_L segments and plan_slots slots
+    std::vector<int> plan_fwd_slot;  // boundary -> slot written by the schedule's first chain (-1: none)
     // launch timing of one kernel class with HIP events on the context stream
     int prof_class = -1;
     int prof_every = 1;
@@ -117,6 +133,11 @@ struct Carver {
 int seg_len(int n_steps, int ckpt_every) { return std::max(1, std::min(ckpt_every, std::max(n_steps, 1))); }
 int n_segments(int n_steps, int K) { return n_steps <= 0 ? 0 : (n_steps + K - 1) / K; }
 
+// The internal checkpoints follow a binomial schedule when the snapshot
+// budget is set and smaller than one slot per boundary.
+bool plan_mode(const pa_ctx* c, int nseg) { return c->ckpt_slots > 0 && c->ckpt_slots <= nseg; }
+int ckpt_count(const pa_ctx* c, int nseg) { return plan_mode(c, nseg) ? c->ckpt_slots : nseg + 1; }
+
 WS carve(const pa_ctx* c, int n_steps, int ckpt_every, int n_obs, int m, void* base) {
     const Dims& d = c->d;
     const size_t SY = (size_t)d.B * d.N * d.KXP;
@@ -138,7 +159,7 @@ WS carve(const pa_ctx* c, int n_steps, int ckpt_every, int n_obs, int m, void* b
     w.lam = cv.take<cd>(SC);
     w.omb = cv.take<cd>(SC);
     w.seg = n_steps > 0 ? cv.take<cd>((size_t)(4 * K + 1) * 4 * SY) : nullptr;
-    w.ckpt = cv.take<cd>((size_t)(nseg + 1) * SC);
+    w.ckpt = cv.take<cd>((size_t)ckpt_count(c, nseg) * SC);
     w.jpart = cv.take<double>((size_t)d.B * std::max(n_obs, 1) * d.N);
     w.J = cv.take<double>(d.B);
     w.J2 = cv.take<double>(d.B);
@@ -178,6 +199,108 @@ void seg_fields(const pa_ctx* c, const WS& w, int j, int s, cd* out[4]) {
     const size_t SY = (size_t)c->d.B * c->d.N * c->d.KXP;
     const size_t slot = (size_t)j * 4 + s;
     for (int f = 0; f < 4; ++f) out[f] = w.seg + (slot * 4 + f) * SY;
+}
+
+// ------------------------------------------------- checkpoint schedule --
+// Binomial checkpointing (Griewank 1992; Griewank & Walther 2000).  With the
+// state of the first boundary held and s free slots, l segments reverse in
+// the fewest segment advances, t l - beta(s + 2, t - 1), where beta(a, t) =
+// C(a + t, t) and t is the least integer with beta(s + 1, t) >= l; a first
+// advance attaining it is min(beta(s + 1, t - 1), l - beta(s, t - 1)).
+
+const int64_t BETA_SAT = int64_t(1) << 62;
+
+// beta(a, t) = C(a + t, t), saturated at BETA_SAT; 0 for t < 0
+int64_t beta_sat(int64_t a, int64_t t) {
+    if (t < 0) return 0;
+    unsigned __int128 r = 1;
+    for (int64_t i = 1; i <= t; ++i) {
+        r = r * (unsigned __int128)(a + i) / (unsigned __int128)i;   // C(a+i-1, i-1) (a+i) / i is exact
+        if (r >= (unsigned __int128)BETA_SAT) return BETA_SAT;
+    }
+    return (int64_t)r;
+}
+
+// least t with beta(s + 1, t) >= l
+int64_t repetitions(int64_t l, int64_t s) {
+    int64_t t = 0;
+    unsigned __int128 b = 1;
+    while (b < (unsigned __int128)l) {
+        ++t;
+        b = b * (unsigned __int128)(s + 1 + t) / (unsigned __int128)t;
+    }
+    return t;
+}
+
+int64_t min_segment_advances(int64_t l, int64_t s) {
+    if (l <= 1) return 0;
+    if (s == 0) return l * (l - 1) / 2;
+    const int64_t t = repetitions(l, s);
+    return t * l - beta_sat(s + 2, t - 1);
+}
+
+int64_t first_advance(int64_t l, int64_t s) {
+    const int64_t t = repetitions(l, s);
+    return std::min(beta_sat(s + 1, t - 1), l - beta_sat(s, t - 1));
+}
+
+// Schedule reversing L segments with `slots` snapshot slots, slot 0 holding
+// boundary 0.  The actions up to the first REVERSE (of segment L-1, from the
+// live state) form the forward sweep; the rest run in the backward sweep.
+void build_plan(int L, int slots, std::vector<PlanAct>& out) {
+    out.clear();
+    struct Task {
+        int a, b, src, live, free_slot;   // free_slot >= 0: return that slot to the pool
+    };
+    std::vector<int> pool;
+    for (int i = slots - 1; i >= 1; --i) pool.push_back(i);
+    std::vector<Task> stack{{0, L, 0, 1, -1}};
+    while (!stack.empty()) {
+        const Task t = stack.back();
+        stack.pop_back();
+        if (t.free_slot >= 0) {
+            pool.push_back(t.free_slot);
+            continue;
+        }
+        const int l = t.b - t.a;
+        const int from = t.live ? -1 : t.src;
+        if (l == 1) {
+            out.push_back({ACT_REVERSE, t.a, t.a + 1, from, -1});
+            continue;
+        }
+        if (pool.empty()) {
+            // no free slot: every segment from the held state
+            for (int i = t.b - 1; i > t.a; --i) {
+                out.push_back({ACT_ADVANCE, t.a, i, i == t.b - 1 ? from : t.src, -1});
+                out.push_back({ACT_REVERSE, i, i + 1, -1, -1});
+            }
+            out.push_back({ACT_REVERSE, t.a, t.a + 1, t.src, -1});
+            continue;
+        }
+        const int m = t.a + (int)first_advance(l, (int64_t)pool.size());
+        const int dst = pool.back();
+        pool.pop_back();
+        out.push_back({ACT_ADVANCE, t.a, m, from, dst});
+        stack.push_back({t.a, m, t.src, 0, -1});
+        stack.push_back({0, 0, 0, 0, dst});
+        stack.push_back({m, t.b, dst, 1, -1});
+    }
+}
+
+// the context's schedule for nseg segments, or nullptr for one checkpoint per boundary
+const std::vector<PlanAct>* plan_for(pa_ctx* c, int nseg) {
+    if (!plan_mode(c, nseg)) return nullptr;
+    if (c->plan_L != nseg || c->plan_slots != c->ckpt_slots) {
+        build_plan(nseg, c->ckpt_slots, c->plan);
+        c->plan_fwd_slot.assign((size_t)nseg + 1, -1);
+        for (const PlanAct& a : c->plan) {
+            if (a.kind == ACT_REVERSE) break;
+            if (a.dst >= 0) c->plan_fwd_slot[(size_t)a.b] = a.dst;
+        }
+        c->plan_L = nseg;
+        c->plan_slots = c->ckpt_slots;
+    }
+    return &c->plan;
 }
 
 // --------------------------------------------------------- validation --
@@ -299,13 +422,21 @@ pa_status start_state(pa_ctx* c, WS& w, const double* omega0, cd* ck0, cd* const
     return PA_OK;
 }
 
+// Where run_steps writes checkpoints: boundary i (step i K, or n_total for
+// the last) goes to slot map[i] of base (none if -1), or to slot i without a map.
+struct CkptTarget {
+    cd* base = nullptr;
+    const std::vector<int>* map = nullptr;
+};
+
 // Steps n0 .. n1-1 from the state in w.omega whose stage-a fields are in
 // `start` (which must equal the segment slot (0,0) when store).  With store
 // the fields of every stage are kept in the segment slots; otherwise they
-// live in w.Yf.  Checkpoints are written to ckpt (if non-null) at multiples
-// of K and at the final step n_total.  Observations via op (J partials).
+// live in w.Yf.  Checkpoints are written to ckpt (if it has a base) at the
+// boundaries, multiples of K and the final step n_total.  Observations via
+// op (J partials).
 pa_status run_steps(pa_ctx* c, WS& w, int n0, int n1, int n_total, int K, bool store, const ObsPlan* op,
-                    double* obs_out, cd* ckpt, bool final_fields) {
+                    double* obs_out, CkptTarget ckpt, bool final_fields) {
     const int nseg = n_segments(n_total, K);
     for (int n = n0; n < n1; ++n) {
         const int j = n - n0;
@@ -333,7 +464,11 @@ pa_status run_steps(pa_ctx* c, WS& w, int n0, int n1, int n_total, int K, bool s
             set_stage_fields(a, fout);
             if (s == 3) {
                 const int nn = n + 1;
-                if (ckpt && (nn % K == 0 || nn == n_total)) a.ckpt = ckpt_slot(c, ckpt, nn == n_total ? nseg : nn / K);
+                if (ckpt.base && (nn % K == 0 || nn == n_total)) {
+                    const int bi = nn == n_total ? nseg : nn / K;
+                    const int slot = ckpt.map ? (*ckpt.map)[(size_t)bi] : bi;
+                    if (slot >= 0) a.ckpt = ckpt_slot(c, ckpt.base, slot);
+                }
                 if (nn == n1 && !final_fields) a.nout = 0;
             }
             PA_HIP(timed(c, PROF_COL_FWD, [&] { return launch_col(c->d, COL_A + s, a, c->stream); }));
@@ -373,9 +508,14 @@ pa_status state_to_phys(pa_ctx* c, WS& w, const cd* state, double* out) {
 // backward sweep that follows (last_ready) starts that segment without
 // recomputing it.  With ckpt_every >= n_steps the whole trajectory is kept
 // and the gradient needs no recomputation at all.  The stage fields are the
-// same either way (same kernels, only their output addresses differ).
+// same either way (same kernels, only their output addresses differ).  With
+// a schedule (plan_for) the checkpoints are those of its first chain, in its
+// slots, and the last segment is always stored.
 pa_status forward_sweep(pa_ctx* c, WS& w, const double* omega0, int n_steps, const ObsPlan& op,
-                        double* obs_out, cd* ckpt, int K, bool store_last) {
+                        double* obs_out, cd* ckpt, int K, bool store_last,
+                        const std::vector<PlanAct>* plan = nullptr) {
+    if (plan && !(store_last && w.seg && n_steps > 0)) return fail(PA_EINVAL, "schedule needs the segment store");
+    const CkptTarget tgt{ckpt, plan ? &c->plan_fwd_slot : nullptr};
     const bool store = store_last && w.seg && n_steps > 0;
     const int n_last = store ? (n_segments(n_steps, K) - 1) * K : n_steps;   // first step of the stored segment
     const bool final_obs = op.slot_of[(size_t)n_steps] >= 0;
@@ -387,7 +527,7 @@ pa_status forward_sweep(pa_ctx* c, WS& w, const double* omega0, int n_steps, con
     const bool reg = c->sobolev > 0.0 && op.values && op.n_times > 0;
     if (reg) PA_HIP(launch_state_energy(c->d, w.omega, 4.0 * M_PI * M_PI * c->sobolev, w.J2, c->stream));
     if (n_last > 0) {
-        PA_TRY(run_steps(c, w, 0, n_last, n_steps, K, false, &op, obs_out, ckpt, !store && final_obs));
+        PA_TRY(run_steps(c, w, 0, n_last, n_steps, K, false, &op, obs_out, tgt, !store && final_obs));
         if (store) {
             // stage-a fields of the state at n_last (in w.omega) into segment slot (0, 0)
             cd* s0[4];
@@ -400,7 +540,7 @@ pa_status forward_sweep(pa_ctx* c, WS& w, const double* omega0, int n_steps, con
     }
     cd* fH[4] = {w.Yf[0], w.Yf[1], w.Yf[2], w.Yf[3]};
     if (store) {
-        PA_TRY(run_steps(c, w, n_last, n_steps, n_steps, K, true, &op, obs_out, ckpt, true));
+        PA_TRY(run_steps(c, w, n_last, n_steps, n_steps, K, true, &op, obs_out, tgt, true));
         seg_fields(c, w, n_steps - n_last, 0, fH);
     }
     if (final_obs) PA_TRY(observe_final(c, w, op, n_steps, fH, obs_out));
@@ -545,10 +685,12 @@ pa_status add_sobolev_gradient(pa_ctx* c, WS& w, const cd* ckpt, const ObsPlan* 
 // stage's fields, then run the adjoint steps of the segment in reverse.  With
 // last_ready the last segment's fields are already in the segment slots (a
 // forward sweep with store_last just ran in this workspace).  The final
-// field (P lambda_0 times scale) is written to grad_out (physical).
+// field (P lambda_0 times scale) is written to grad_out (physical).  With a
+// schedule (plan_for; needs last_ready) the segments are reversed in its
+// order, re-advancing from its snapshot slots in ckpt.
 pa_status backward_sweep(pa_ctx* c, WS& w, const cd* ckpt, int n_steps, int K, const ObsPlan* op, int impulse,
                          int ix, int iy, const double* scale, double* grad_out, const Shells& sh,
-                         bool last_ready) {
+                         bool last_ready, const std::vector<PlanAct>* plan = nullptr) {
     const int nseg = n_segments(n_steps, K);
     if (n_steps == 0) {
         // no segment buffer exists for a zero horizon: the stage fields of omega_0 go to w.Yf
@@ -571,18 +713,23 @@ pa_status backward_sweep(pa_ctx* c, WS& w, const cd* ckpt, int n_steps, int K, c
         return PA_OK;
     }
     if (!w.seg) return fail(PA_EINVAL, "workspace carved without a segment buffer");
-    for (int seg = nseg - 1; seg >= 0; --seg) {
+    if (plan && !last_ready) return fail(PA_EINVAL, "a schedule's backward sweep follows its forward sweep");
+    cd* const ck = const_cast<cd*>(ckpt);
+    // Recompute segment `seg` keeping its stage fields (from state src; src ==
+    // w.omega is the live state), unless its fields are already stored, then
+    // run the adjoint steps through it.
+    auto reverse_segment = [&](int seg, const cd* src, bool recompute) -> pa_status {
         const int n0 = seg * K, n1 = std::min(n_steps, n0 + K), L = n1 - n0;
         const bool last = seg == nseg - 1;
-        if (!(last && last_ready)) {
+        if (recompute) {
             cd* f0[4];
             seg_fields(c, w, 0, 0, f0);
             ColArgs a = col_base(c);
-            a.state_in = ckpt_slot(c, const_cast<cd*>(ckpt), seg);
-            a.omega = w.omega;
+            a.state_in = src;
+            a.omega = src == w.omega ? nullptr : w.omega;
             set_stage_fields(a, f0);
             PA_HIP(launch_col(c->d, COL_FROM_STATE, a, c->stream));
-            PA_TRY(run_steps(c, w, n0, n1, n_steps, K, true, nullptr, nullptr, nullptr, last));
+            PA_TRY(run_steps(c, w, n0, n1, n_steps, K, true, nullptr, nullptr, CkptTarget(), last));
         }
         if (last) {
             cd* fH[4];
@@ -603,6 +750,39 @@ pa_status backward_sweep(pa_ctx* c, WS& w, const cd* ckpt, int n_steps, int K, c
             const int slot = (op && !impulse) ? op->slot_of[(size_t)n] : -1;
             PA_TRY(adj_stage(c, w, fs, COL_ADJ_N, op, slot, n == 0 ? 1 : 0, scale));
             PA_TRY(record_shells(c, w, sh, n_steps - n));
+        }
+        return PA_OK;
+    };
+    if (!plan) {
+        for (int seg = nseg - 1; seg >= 0; --seg)
+            PA_TRY(reverse_segment(seg, ckpt_slot(c, ck, seg), !(seg == nseg - 1 && last_ready)));
+    } else {
+        // the forward sweep ran the schedule up to its first REVERSE (segment nseg-1, stored)
+        size_t i = 0;
+        while (i < plan->size() && (*plan)[i].kind != ACT_REVERSE) ++i;
+        if (i == plan->size() || (*plan)[i].a != nseg - 1) return fail(PA_EINVAL, "internal: malformed checkpoint schedule");
+        PA_TRY(reverse_segment(nseg - 1, nullptr, false));
+        std::vector<int> end_slot((size_t)nseg + 1, -1);
+        for (++i; i < plan->size(); ++i) {
+            const PlanAct& act = (*plan)[i];
+            const cd* src = act.src >= 0 ? ckpt_slot(c, ck, act.src) : w.omega;
+            if (act.kind == ACT_REVERSE) {
+                PA_TRY(reverse_segment(act.a, src, true));
+                continue;
+            }
+            // advance: the stage-a fields of the start state into w.Yf (a live start has them there)
+            cd* f0[4] = {w.Yf[0], w.Yf[1], w.Yf[2], w.Yf[3]};
+            if (act.src >= 0) {
+                ColArgs a = col_base(c);
+                a.state_in = src;
+                a.omega = w.omega;
+                set_stage_fields(a, f0);
+                PA_HIP(launch_col(c->d, COL_FROM_STATE, a, c->stream));
+            }
+            if (act.dst >= 0) end_slot[(size_t)act.b] = act.dst;
+            PA_TRY(run_steps(c, w, act.a * K, std::min(n_steps, act.b * K), n_steps, K, false, nullptr, nullptr,
+                             CkptTarget{ck, &end_slot}, true));
+            end_slot[(size_t)act.b] = -1;
         }
     }
     if (grad_out) PA_HIP(launch_row_c2r(c->d, w.YL[0], grad_out, c->tw, c->stream));
@@ -827,6 +1007,47 @@ pa_status pa_set_sobolev(pa_ctx* c, double lambda) {
     return PA_OK;
 }
 
+pa_status pa_set_checkpoint_slots(pa_ctx* c, int32_t slots) {
+    if (!c) return fail(PA_EINVAL, "ctx is NULL");
+    if (slots < 0) return fail(PA_EINVAL, "slots must be >= 0");
+    c->ckpt_slots = slots;
+    return PA_OK;
+}
+
+pa_status pa_get_checkpoint_slots(const pa_ctx* c, int32_t* slots) {
+    if (!c || !slots) return fail(PA_EINVAL, "NULL argument");
+    *slots = c->ckpt_slots;
+    return PA_OK;
+}
+
+pa_status pa_checkpoint_advances(int32_t n_segments, int32_t slots, int64_t* advances) {
+    if (!advances) return fail(PA_EINVAL, "NULL argument");
+    if (n_segments < 1 || slots < 1) return fail(PA_EINVAL, "need n_segments >= 1 and slots >= 1");
+    *advances = min_segment_advances(n_segments, slots - 1);
+    return PA_OK;
+}
+
+pa_status pa_checkpoint_schedule(int32_t n_segments, int32_t slots, int32_t* actions, int64_t capacity,
+                                 int64_t* n_actions) {
+    if (!n_actions) return fail(PA_EINVAL, "n_actions is NULL");
+    if (n_segments < 1 || slots < 1) return fail(PA_EINVAL, "need n_segments >= 1 and slots >= 1");
+    std::vector<PlanAct> plan;
+    build_plan(n_segments, std::min(slots, n_segments), plan);
+    *n_actions = (int64_t)plan.size();
+    if (!actions) return PA_OK;
+    if (capacity < (int64_t)plan.size()) return fail(PA_EINVAL, "actions buffer too small");
+    for (size_t i = 0; i < plan.size(); ++i) {
+        const PlanAct& a = plan[i];
+        int32_t* o = actions + 5 * i;
+        o[0] = a.kind;
+        o[1] = a.a;
+        o[2] = a.b;
+        o[3] = a.src;
+        o[4] = a.dst;
+    }
+    return PA_OK;
+}
+
 pa_status pa_get_tiles(const pa_ctx* c, pa_tiles* t) {
     if (!c || !t) return fail(PA_EINVAL, "NULL argument");
     t->row_variant = c->d.var;
@@ -949,12 +1170,13 @@ pa_status pa_adjoint_gradient(pa_ctx* c, const double* omega0, int32_t n_steps, 
     WS w;
     PA_TRY(check_ws(c, workspace, wbytes, n_steps, ckpt_every, op.n_times, 0, &w));
     const int K = seg_len(n_steps, ckpt_every);
-    PA_TRY(forward_sweep(c, w, omega0, n_steps, op, nullptr, w.ckpt, K, true));
+    const std::vector<PlanAct>* plan = plan_for(c, n_segments(n_steps, K));
+    PA_TRY(forward_sweep(c, w, omega0, n_steps, op, nullptr, w.ckpt, K, true, plan));
     if (J_out) {
         if (op.n_times > 0) PA_HIP(launch_copy(J_out, w.J, c->d.B, c->stream));
         else PA_HIP(launch_fill(J_out, 0.0, c->d.B, c->stream));
     }
-    return backward_sweep(c, w, w.ckpt, n_steps, K, &op, 0, -1, -1, nullptr, grad_out, Shells(), true);
+    return backward_sweep(c, w, w.ckpt, n_steps, K, &op, 0, -1, -1, nullptr, grad_out, Shells(), true, plan);
 }
 
 pa_status pa_ensemble_acc_bytes(const pa_ctx* c, int32_t n_steps, int32_t n_shells, size_t* lambda_bytes,
@@ -986,13 +1208,14 @@ pa_status pa_adjoint_impulse(pa_ctx* c, const double* omega0, int32_t n_steps, i
     const int K = seg_len(n_steps, ckpt_every);
     ObsPlan none;
     none.slot_of.assign((size_t)n_steps + 1, -1);
-    PA_TRY(forward_sweep(c, w, omega0, n_steps, none, nullptr, w.ckpt, K, true));
+    const std::vector<PlanAct>* plan = plan_for(c, n_segments(n_steps, K));
+    PA_TRY(forward_sweep(c, w, omega0, n_steps, none, nullptr, w.ckpt, K, true, plan));
     Shells sh;
     sh.out = shells_out;
     sh.n = n_shells;
     sh.stride = (size_t)(n_steps + 1) * n_shells;
     sh.acc = acc;
-    PA_TRY(backward_sweep(c, w, w.ckpt, n_steps, K, nullptr, 1, ix, iy, nullptr, field_out, sh, true));
+    PA_TRY(backward_sweep(c, w, w.ckpt, n_steps, K, nullptr, 1, ix, iy, nullptr, field_out, sh, true, plan));
     if (acc) acc->count += c->d.B;
     return PA_OK;
 }
@@ -1134,14 +1357,15 @@ static pa_status assimilate_impl(pa_ctx* c, double* omega_inout, int32_t n_steps
         PA_HIP(launch_make_mult(c->d, k->kind, k->metric, k->param, -0.5, mult_m + b * MT, c->stream));
     }
     Opt o{c, w, n, B, {}};
+    const std::vector<PlanAct>* plan = plan_for(c, n_segments(n_steps, K));
 
     auto eval_J = [&](const double* x) -> pa_status {
         PA_TRY(apply_filter(c, w, mult_p, x, w.w, per_member));
-        return forward_sweep(c, w, w.w, n_steps, op, nullptr, w.ckpt, K, true);
+        return forward_sweep(c, w, w.w, n_steps, op, nullptr, w.ckpt, K, true, plan);
     };
     // gradient at the point whose forward sweep last filled w.ckpt
     auto eval_grad = [&](double* gout) -> pa_status {
-        PA_TRY(backward_sweep(c, w, w.ckpt, n_steps, K, &op, 0, -1, -1, nullptr, w.gw, Shells(), true));
+        PA_TRY(backward_sweep(c, w, w.ckpt, n_steps, K, &op, 0, -1, -1, nullptr, w.gw, Shells(), true, plan));
         return apply_filter(c, w, mult_p, w.gw, gout, per_member);
     };
 

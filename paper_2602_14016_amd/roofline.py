@@ -51,14 +51,18 @@ def column_mode_bytes(mode, N):
             10: 4 * Yb + 2 * Cb}.get(mode)  # adjoint n: read 2 products, omega-bar; write lambda, 2 fields
 
 
+# the sources that define and instantiate the row and column kernels, and the
+# build flags they are compiled with (host-side files do not change them)
+KERNEL_SOURCES = ("csrc/fft.hpp", "csrc/kernels.hpp", "csrc/kernels_impl.hpp", "csrc/kernels.hip", "build.py")
+
+
 def kernel_source_sha():
-    """Hash of the HIP sources: a traffic record applies only to the kernels it was taken on."""
+    """Hash of the row/column kernel sources and build flags: a traffic record
+    applies only to the kernels it was taken on."""
     h = hashlib.sha256()
-    csrc = os.path.join(HERE, "csrc")
-    for f in sorted(os.listdir(csrc)):
-        if f.endswith((".hip", ".hpp")):
-            with open(os.path.join(csrc, f), "rb") as fh:
-                h.update(fh.read())
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(HERE, f), "rb") as fh:
+            h.update(fh.read())
     return h.hexdigest()[:16]
 
 

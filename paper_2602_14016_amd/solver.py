@@ -56,6 +56,23 @@ def _need(t, shape, name):
         raise ValueError(f"{name} must be contiguous")
 
 
+def checkpoint_advances(n_segments, slots):
+    """Segment advances of the binomial schedule for n_segments and `slots` snapshot slots (host only)."""
+    v = ctypes.c_int64()
+    nv.check(nv.load().pa_checkpoint_advances(int(n_segments), int(slots), byref(v)))
+    return v.value
+
+
+def checkpoint_schedule(n_segments, slots):
+    """The schedule's actions as (kind, a, b, src, dst) tuples (kind 0 advance, 1 reverse; host only)."""
+    lib = nv.load()
+    n = ctypes.c_int64()
+    nv.check(lib.pa_checkpoint_schedule(int(n_segments), int(slots), None, 0, byref(n)))
+    buf = (ctypes.c_int32 * (5 * max(n.value, 1)))()
+    nv.check(lib.pa_checkpoint_schedule(int(n_segments), int(slots), buf, n.value, byref(n)))
+    return [tuple(buf[5 * i: 5 * i + 5]) for i in range(n.value)]
+
+
 class Solver:
     def __init__(self, N, B=1, nu=1e-3, dt=5e-3, mu=0.0, forcing_amp=0.0, forcing_k=4,
                  device="cuda", stream: Optional[torch.cuda.Stream] = None):
@@ -123,6 +140,71 @@ class Solver:
             if self.workspace_bytes(n_steps, K, n_obs, lbfgs_m) + 256 <= budget_bytes:
                 return K
         return 0
+
+    def set_checkpoint_slots(self, slots):
+        """Snapshot budget of the internal checkpoints (pa_set_checkpoint_slots):
+        0 keeps one state per segment boundary; 1 <= slots < segments reverses
+        the segments with the binomial schedule in that many states."""
+        nv.check(self.lib.pa_set_checkpoint_slots(self.ctx, int(slots)))
+
+    def get_checkpoint_slots(self):
+        v = ctypes.c_int32()
+        nv.check(self.lib.pa_get_checkpoint_slots(self.ctx, byref(v)))
+        return v.value
+
+    def fit_checkpointing(self, n_steps, n_obs=0, lbfgs_m=0, budget_bytes=None, reserve=0.1):
+        """Segment length K and snapshot budget that fit the workspace in
+        budget_bytes with the fewest forward steps.
+
+        Returns (K, slots, forward_steps): slots = 0 when a state per segment
+        boundary fits (forward_steps = n_steps + (L - 1) K for L segments),
+        else the binomial budget (forward_steps = n_steps + K times the
+        schedule's segment advances).  (0, 0, 0) if nothing fits.  The
+        default budget is as in fit_ckpt_every.
+        """
+        if budget_bytes is None:
+            free, _ = torch.cuda.mem_get_info(self.device)
+            held = self._ws.numel() if self._ws is not None else 0
+            budget_bytes = int((free + held) * (1.0 - reserve))
+        H = max(int(n_steps), 0)
+        if H <= 1:
+            K = self.fit_ckpt_every(H, n_obs, lbfgs_m, budget_bytes)
+            return (K, 0, H) if K else (0, 0, 0)
+        saved = self.get_checkpoint_slots()
+        best = None
+        try:
+            for L in range(1, H + 1):
+                K = -(-H // L)
+                if L > 1 and -(-H // (L - 1)) == K:
+                    continue                    # same K as a smaller L: fewer segments, same store
+                L = -(-H // K)
+                self.set_checkpoint_slots(0)
+                full = self.workspace_bytes(H, K, n_obs, lbfgs_m) + 256
+                if full <= budget_bytes:
+                    cand = (H + (L - 1) * K, -K, 0)
+                else:
+                    if L < 2:
+                        continue
+                    self.set_checkpoint_slots(1)
+                    one = self.workspace_bytes(H, K, n_obs, lbfgs_m) + 256
+                    if one > budget_bytes:
+                        continue
+                    self.set_checkpoint_slots(2)
+                    per_slot = self.workspace_bytes(H, K, n_obs, lbfgs_m) + 256 - one
+                    slots = min(L, 1 + (budget_bytes - one) // max(per_slot, 1))
+                    while slots > 1:            # alignment padding: confirm the size
+                        self.set_checkpoint_slots(slots)
+                        if self.workspace_bytes(H, K, n_obs, lbfgs_m) + 256 <= budget_bytes:
+                            break
+                        slots -= 1
+                    cand = (H + checkpoint_advances(L, slots) * K, -K, slots)
+                if best is None or cand < best:
+                    best = cand
+        finally:
+            self.set_checkpoint_slots(saved)
+        if best is None:
+            return 0, 0, 0
+        return -best[1], best[2], best[0]
 
     def workspace(self, n_steps=0, ckpt_every=1, n_obs=0, lbfgs_m=0):
         need = self.workspace_bytes(n_steps, ckpt_every, n_obs, lbfgs_m)
