@@ -17,7 +17,9 @@ c2  forced Kolmogorov flow, 512^2, nu = 1/40, drag 0.1, f_x = sin 4y, spin-up
 c3  ensemble of 64 realizations of the c1 spectrum (seeds 0..63), 500
     forward + 500 adjoint steps from a unit u-impulse, shell energies and
     growth rates for |k| = 1..85; with --members M > 64 the ensemble
-    statistics of M realizations in batches.
+    statistics of M realizations in batches.  --flow kolmogorov: the paper's
+    Kolmogorov flow (512^2, Re = 400, no drag, 40-unit precursor per
+    realization) with 150 realizations over T = 8 in batches of 50 (App. C).
 sweep  the c1 problem assimilated under 14 preconditioners at once (fractional
     |k|^(-2 alpha), alpha = -2..2, and heat exp(-nu beta |k|^2), beta = -0.1..0.8)
     as one batched solve, timed against one solve per kernel.
@@ -122,6 +124,39 @@ def run_controls(cfg: Config, iters, sobolev=1e-3, verbose=True):
     err = (torch.linalg.norm((ws - truth).reshape(4, -1), dim=1) / torch.linalg.norm(truth)).cpu().tolist()
     out = {"config": cfg.name + "-controls", "controls": names + [f"u0+sobolev({sobolev:g})"],
            "iterations": it + itr, "J_history": H + Hr, "rel_err_omega0": err}
+    if verbose:
+        print(json.dumps(out), flush=True)
+    return out
+
+
+def run_kolmogorov_ensemble(members=150, batch=50, n_steps=8000, spinup=40000, verbose=True):
+    """Ensemble adjoint statistics of the forced Kolmogorov flow (App. C) with
+    the paper's setup of that flow (Sec. III.E, Table 1): 512^2, Re = 400
+    (nu = 1/400), no drag, f_x = sin 4y, dt = 1e-3; each realization is a
+    random-phase field (k0 = 4, energy 0.5; seeds 0..members-1) advanced
+    `spinup` steps (the 40-time-unit precursor), then a unit u-impulse at the
+    centre after n_steps (T = 8) is propagated back; shell energies for |k| =
+    1..170, statistics at subset sizes 50, 100, 150."""
+    from . import ensemble
+    from .autotune import autotune
+    N, nu, dt, amp, kf = 512, 1.0 / 400, 1e-3, 1.0, 4
+    probe = Solver(N, batch, nu=nu, dt=dt, forcing_amp=amp, forcing_k=kf)
+    tiles = {k: v for k, v in autotune(probe, n_steps=8).items() if k in probe.get_tiles()}
+    probe.close()
+    del probe
+    st = ensemble.statistics(N=N, members=members, batch=batch, n_steps=n_steps, nu=nu, dt=dt, k0=4.0,
+                             subsets=(50, 100, 150), tiles=tiles, verbose=verbose, forcing_amp=amp, forcing_k=kf,
+                             init_kind=0, init_target=0.5, spinup=spinup)
+    every = max(1, n_steps // 16)
+    out = {"config": "c3-kolmogorov", "members": st.members, "seconds": st.seconds,
+           "tau": [float(x) for x in st.tau[::every].cpu()],
+           "total_mean": [float(x) for x in st.total_mean[::every].cpu()],
+           "total_of_mean": [float(x) for x in st.total_of_mean[::every].cpu()],
+           "snr": [float(x) for x in st.snr[::every].cpu()],
+           "subsets": {str(n): {"total_mean_at_T": float(v["total_mean"][-1].cpu()),
+                                "snr_at_T": float(v["snr"][-1].cpu())} for n, v in st.subsets.items()},
+           "mean_energy_shells_at": {f"{float(st.tau[r]):.1f}": [float(x) for x in st.mean_energy[r, :40].cpu()]
+                                     for r in (0, n_steps // 4, n_steps // 2, n_steps)}}
     if verbose:
         print(json.dumps(out), flush=True)
     return out
@@ -262,7 +297,13 @@ def main(argv=None):
     ap.add_argument("--members", type=int, default=64, help="c3: ensemble size (statistics in batches beyond 64)")
     ap.add_argument("--batch", type=int, default=64, help="c3: members per batched solve")
     ap.add_argument("--budget-gib", type=float, default=16.0, help="longwindow: workspace budget")
+    ap.add_argument("--flow", choices=["hit", "kolmogorov"], default="hit",
+                    help="c3: decaying HIT (256^2) or forced Kolmogorov flow (512^2, T = 8; App. C)")
     args = ap.parse_args(argv)
+    if args.config == "c3" and args.flow == "kolmogorov":
+        run_kolmogorov_ensemble(members=args.members if args.members != 64 else 150,
+                                batch=args.batch if args.batch != 64 else 50, n_steps=args.horizon or 8000)
+        return
     if args.config == "c3":
         from . import ensemble
         t0 = time.perf_counter()

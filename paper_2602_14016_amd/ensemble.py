@@ -57,13 +57,18 @@ class EnsembleStats:
 
 def statistics(N=256, members=3000, batch=64, n_steps=500, nu=1e-4, dt=2e-3, k0=10.0, n_shells=None,
                ckpt_every=None, impulse=None, subsets=(50, 100, 200, 400, 1000, 3000), seed0=0, tiles=None,
-               verbose=False):
+               verbose=False, mu=0.0, forcing_amp=0.0, forcing_k=4, init_kind=0, init_target=0.5, spinup=0):
     """Ensemble adjoint statistics of Sec. IV over `members` realizations (seeds
     seed0, seed0 + 1, ...), run in batches of at most `batch` members whose
     ends fall on every requested subset size.  The member sums are
     accumulated on the device in member order, so the statistics do not
     depend on the batch split; the statistics at each subset size are kept
-    to show their convergence."""
+    to show their convergence.
+
+    Each realization starts from init_field(kind=init_kind, k0, init_target)
+    of its seed, advanced `spinup` steps; with mu, forcing_amp and forcing_k
+    the flow is the forced Kolmogorov flow (App. C: white noise, spin-up to
+    the statistically stationary state)."""
     import time
     n_shells = n_shells or (N - 1) // 3
     ix, iy = impulse or (N // 2, N // 2)
@@ -72,7 +77,7 @@ def statistics(N=256, members=3000, batch=64, n_steps=500, nu=1e-4, dt=2e-3, k0=
 
     def solver_for(b):
         if b not in solvers:
-            sv = Solver(N, b, nu=nu, dt=dt)
+            sv = Solver(N, b, nu=nu, dt=dt, mu=mu, forcing_amp=forcing_amp, forcing_k=forcing_k)
             if tiles:
                 sv.set_tiles(**tiles)
             solvers[b] = sv
@@ -94,7 +99,9 @@ def statistics(N=256, members=3000, batch=64, n_steps=500, nu=1e-4, dt=2e-3, k0=
                 current._ws = None
                 torch.cuda.empty_cache()
                 current = sv
-            w0 = sv.init_field(list(range(seed0 + done, seed0 + done + b)), kind=0, k0=k0, target=0.5)
+            w0 = sv.init_field(list(range(seed0 + done, seed0 + done + b)), kind=init_kind, k0=k0, target=init_target)
+            if spinup:
+                w0 = sv.forward(w0, spinup)["omega_T"]
             sv.adjoint_impulse(w0, n_steps, ix, iy, n_shells, ckpt_every=K, acc=acc)
             done += b
             if verbose:

@@ -168,6 +168,32 @@ def test_ensemble_statistics_parity_and_batch_split_invariance():
     assert abs(got["snr"][0] - 1.0) < 1e-12 and np.all(got["snr"][1:] < 1)
 
 
+def test_kolmogorov_ensemble_statistics_parity():
+    """The forced-flow statistics path (App. C): white-noise realizations spun up
+    under forcing and drag, then impulse responses, in batches, against the oracle."""
+    import oracle as O
+    from oracle.model import Physics
+    from paper_2602_14016_amd import ensemble
+    print("CASE ensemble-kolmogorov", flush=True)
+    N, H, nsh, M, spin = 32, 10, 10, 4, 6
+    ph = Physics(N=N, nu=1.0 / 40, dt=1e-3, mu=0.1, forcing_amp=1.0, forcing_k=4)
+    w = O.init_field(N, list(range(M)), kind=2, target=1e-2)
+    spun = [O.forward(w[b], ph, spin)[0] for b in range(M)]
+    ref = O.ensemble_statistics(spun, ph, H, N // 2, N // 2, nsh)
+    st = ensemble.statistics(N=N, members=M, batch=3, n_steps=H, nu=ph.nu, dt=ph.dt, n_shells=nsh, ckpt_every=4,
+                             subsets=(2, 4), mu=ph.mu, forcing_amp=ph.forcing_amp, forcing_k=ph.forcing_k,
+                             init_kind=2, init_target=1e-2, spinup=spin)
+    assert st.members == M
+    for gk, ok in (("mean_energy", "mean_energy"), ("energy_of_mean", "energy_of_mean"),
+                   ("total_mean", "total_mean_energy"), ("total_of_mean", "total_energy_of_mean"), ("snr", "snr")):
+        a, b = getattr(st, gk).cpu().numpy(), ref[ok]
+        assert np.linalg.norm(a - b) <= 1e-9 * np.linalg.norm(b), (gk, np.linalg.norm(a - b) / np.linalg.norm(b))
+    # the subset of the first two members
+    ref2 = O.ensemble_statistics(spun[:2], ph, H, N // 2, N // 2, nsh)
+    a = st.subsets[2]["snr"].cpu().numpy()
+    assert np.linalg.norm(a - ref2["snr"]) <= 1e-9 * np.linalg.norm(ref2["snr"])
+
+
 def test_ensemble_stats_rejects_empty_accumulator():
     from paper_2602_14016_amd import Solver
     from paper_2602_14016_amd.native import PaError
