@@ -179,41 +179,65 @@ hipError_t launch_state_scale(const Dims& d, cd* state, int kind, double target,
 
 // Shell energies 1/2 |k|^2 |lam|^2 / N^4 per unit-width shell k = 1..n_shells.
 // shell_modes lists compact indices r*KXP + kx grouped by shell (CSR with
-// shell_start).  One workgroup per (shell, member): threads stride over the
-// shell's modes, then a fixed-order tree sums the partials.
+// shell_start).  One wavefront per (shell, member), so the whole grid is
+// resident at once.  Each lane takes up to SHELL_BATCH modes of the shell per
+// pass and issues all their index loads, then all their value loads, before
+// adding: a pass costs two memory latencies (one pass covers any shell of
+// 256^2).  Lanes add in a fixed stride and a fixed butterfly.
+// A shell is an annulus that meets most rows in one or two modes, so its
+// gather uses a small part of each cache line; the other shells of the member
+// use the rest.  Workgroups are dealt to the XCDs in turn, so workgroup w is
+// mapped to member (w mod XCDS) + XCDS * (w / (XCDS n_shells)): all shells of
+// a member run on one XCD and share its L2, which holds the few members of
+// that XCD.
 constexpr int SHELL_THREADS = 64;
+constexpr int SHELL_BATCH = 8;
+constexpr int SHELL_XCDS = 8;   // accelerator complex dies of the device
 __global__ void __launch_bounds__(SHELL_THREADS) shells_kernel(Dims d, const cd* __restrict__ lam,
                                                                const int* __restrict__ start,
                                                                const int* __restrict__ modes, int n_shells,
                                                                double* __restrict__ out, size_t out_stride) {
-    __shared__ double sh[SHELL_THREADS];
-    const int k = blockIdx.x;
-    const int b = blockIdx.y;
-    const cd* l = lam + (size_t)b * d.KY * d.KXP;
+    const int w = blockIdx.x;
+    const int q = w / SHELL_XCDS;
+    const int b = w % SHELL_XCDS + SHELL_XCDS * (q / n_shells);
+    const int k = q % n_shells;
+    if (b >= d.B) return;   // the last group of members may be partial
+    const int lane = threadIdx.x;
+    const cd* __restrict__ l = lam + (size_t)b * d.KY * d.KXP;
+    const int lo = start[k], hi = start[k + 1];
     double s = 0.0;
-    for (int i = start[k] + threadIdx.x; i < start[k + 1]; i += SHELL_THREADS) {
-        const int idx = modes[i];
-        const int r = idx / d.KXP, kx = idx % d.KXP;
-        const int ky = (r <= d.K) ? r : r - d.KY;
-        const double k2 = (double)kx * kx + (double)ky * ky;
-        const double wgt = kx > 0 ? 2.0 : 1.0;
-        s += wgt * 0.5 * k2 * (l[idx].x * l[idx].x + l[idx].y * l[idx].y);
+    for (int base = lo; base < hi; base += SHELL_BATCH * SHELL_THREADS) {
+        int mb[SHELL_BATCH];
+        cd vb[SHELL_BATCH];
+#pragma unroll
+        for (int u = 0; u < SHELL_BATCH; ++u) {
+            const int i = base + u * SHELL_THREADS + lane;
+            mb[u] = i < hi ? modes[i] : -1;
+        }
+#pragma unroll
+        for (int u = 0; u < SHELL_BATCH; ++u) vb[u] = mb[u] >= 0 ? l[mb[u]] : cd{0.0, 0.0};
+#pragma unroll
+        for (int u = 0; u < SHELL_BATCH; ++u) {
+            if (mb[u] < 0) continue;
+            const int r = mb[u] / d.KXP, kx = mb[u] - r * d.KXP;
+            const int ky = (r <= d.K) ? r : r - d.KY;
+            const double k2 = (double)kx * kx + (double)ky * ky;
+            const double wgt = kx > 0 ? 2.0 : 1.0;
+            s += wgt * 0.5 * k2 * (vb[u].x * vb[u].x + vb[u].y * vb[u].y);
+        }
     }
-    sh[threadIdx.x] = s;
-    __syncthreads();
-    for (int w = SHELL_THREADS / 2; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    if (lane == 0) {
         const double n4 = (double)d.N * d.N * (double)d.N * d.N;
-        out[(size_t)b * out_stride + k] = sh[0] / n4;
+        out[(size_t)b * out_stride + k] = s / n4;
     }
 }
 hipError_t launch_shells(const Dims& d, const cd* lam, const int* shell_start, const int* shell_modes,
                          int n_shells, double* out, size_t out_stride, hipStream_t s) {
     if (!lam || !shell_start || !shell_modes || !out || n_shells < 1) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(shells_kernel, dim3(n_shells, d.B), dim3(SHELL_THREADS), 0, s, d, lam, shell_start,
+    const size_t groups = (size_t)SHELL_XCDS * n_shells * ((d.B + SHELL_XCDS - 1) / SHELL_XCDS);
+    if (groups > 0x7fffffff) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(shells_kernel, dim3((unsigned)groups), dim3(SHELL_THREADS), 0, s, d, lam, shell_start,
                        shell_modes, n_shells, out, out_stride);
     return hipGetLastError();
 }
@@ -331,8 +355,9 @@ hipError_t launch_ens_stats(const Dims& d, int rows, int n_shells, double inv_co
         return hipErrorInvalidValue;
     Dims dr = d;
     dr.B = rows;   // the rows of the member sum take the place of members
-    hipLaunchKernelGGL(shells_kernel, dim3(n_shells, rows), dim3(SHELL_THREADS), 0, s, dr, lambda_sum, shell_start,
-                       shell_modes, n_shells, energy_of_mean, (size_t)n_shells);
+    hipError_t e = launch_shells(dr, lambda_sum, shell_start, shell_modes, n_shells, energy_of_mean,
+                                 (size_t)n_shells, s);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(energy_total_kernel, dim3(rows), dim3(ETOT_THREADS), 0, s, dr, lambda_sum, 1.0, total_of_mean,
                        1);
     hipLaunchKernelGGL(ens_finish_kernel, dim3(rows), dim3(64), 0, s, rows, n_shells, inv_count, shell_sum,

@@ -122,3 +122,63 @@ def test_c1_full_horizon_divergence_curve():
         print("c1 divergence step %4d: %.3e" % curve[-1], flush=True)
     assert curve[0][1] <= 1e-11
     assert curve[-1][1] <= 1e-8
+
+
+def _impulse_row0(N, n_shells):
+    """Shell energies of the terminal adjoint of a unit u-impulse at a grid point:
+    lambda_hat = conj(i ky / |k|^2) times a unit-modulus phase on the band, so shell
+    k holds sum 1/2 |k|^2 ky^2 / |k|^4 / N^4 over its band modes (any flow, any point)."""
+    Kc = (N - 1) // 3
+    out = np.zeros(n_shells)
+    for ky in range(-Kc, Kc + 1):
+        for kx in range(-Kc, Kc + 1):
+            k2 = kx * kx + ky * ky
+            if k2 == 0:
+                continue
+            sh = int(np.floor(np.sqrt(k2)))
+            while sh * sh > k2:
+                sh -= 1
+            while (sh + 1) * (sh + 1) <= k2:
+                sh += 1
+            if 1 <= sh <= n_shells:
+                out[sh - 1] += 0.5 * ky * ky / k2
+    return out / float(N) ** 4
+
+
+def test_ensemble_workload_in_its_launch_configuration():
+    """The ensemble workload at its full size (64 members of 256^2, nu = 1e-4,
+    dt = 2e-3, 500 forward + 500 adjoint steps, impulse at the centre, 85
+    shells) with autotuned tiles and the whole trajectory kept, as timed:
+    the terminal row against its closed form for every member, two sampled
+    members over the whole horizon against one-member solves with default
+    tiles and checkpoints every 50 steps, and the same configured solver
+    against the oracle over a 10-step horizon on two sampled members."""
+    from paper_2602_14016_amd import Solver
+    from paper_2602_14016_amd.autotune import autotune
+    N, B, H, nsh = 256, 64, 500, 85
+    ph = Physics(N=N, nu=1e-4, dt=2e-3)
+    print("CASE ensemble-workload setup", flush=True)
+    w0np = O.init_field(N, list(range(B)), kind=0, k0=10.0, target=0.5)
+    w0 = dev(w0np)
+    s = Solver(N, B, nu=ph.nu, dt=ph.dt)
+    autotune(s, w0, n_steps=8)
+    K = s.fit_ckpt_every(H)
+    assert K == H, "the whole trajectory should fit on this device"
+    print("CASE ensemble-workload full", s.get_tiles(), K, flush=True)
+    shells, _ = s.adjoint_impulse(w0, H, N // 2, N // 2, nsh, ckpt_every=K)
+    shells = shells.cpu().numpy()
+    assert shells.shape == (B, H + 1, nsh) and np.all(np.isfinite(shells))
+    row0 = _impulse_row0(N, nsh)
+    for b in range(B):
+        assert rel(shells[b, 0], row0) < 1e-12
+    ref_solver = Solver(N, 1, nu=ph.nu, dt=ph.dt)
+    for b in (5, 50):
+        print("CASE ensemble-workload member", b, flush=True)
+        one, _ = ref_solver.adjoint_impulse(w0[b:b + 1].contiguous(), H, N // 2, N // 2, nsh, ckpt_every=50)
+        assert rel(shells[b], one.cpu().numpy()[0]) < 1e-9
+    print("CASE ensemble-workload oracle", flush=True)
+    short, _ = s.adjoint_impulse(w0, 10, N // 2, N // 2, nsh, ckpt_every=10)
+    short = short.cpu().numpy()
+    for b in (0, 63):
+        ref = O.impulse_adjoint(w0np[b], ph, 10, N // 2, N // 2, nsh)[0]
+        assert rel(short[b], ref) < 1e-9
