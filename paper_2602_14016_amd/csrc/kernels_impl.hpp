@@ -91,14 +91,14 @@ __device__ __forceinline__ void split_store(const cd* z, int t, cd* lds, cd* __r
                                             cd* __restrict__ outB) {
     constexpr int T = Plan<N, V>::T, E = Plan<N, V>::E, K = band<N>();
 #pragma unroll
-    for (int m = 0; m < E; ++m) lds[lpad(t + T * m)] = z[m];
+    for (int m = 0; m < E; ++m) lds[lpos<N, V>(t + T * m)] = z[m];
     team_sync<WL>();
 #pragma unroll
     for (int m = 0; m < E; ++m) {
         const int k = t + T * m;
         if (slot_low<N, V>(m) && k <= K) {
             const cd zk = z[m];
-            const cd zn = lds[lpad((N - k) & (N - 1))];
+            const cd zn = lds[lpos<N, V>((N - k) & (N - 1))];
             outA[k] = mk(0.5 * (zk.x + zn.x), 0.5 * (zk.y - zn.y));
             outB[k] = mk(0.5 * (zk.y + zn.y), -0.5 * (zk.x - zn.x));
         }
