@@ -157,3 +157,53 @@ def test_fit_checkpointing_under_a_tight_budget():
     assert np.array_equal(host(J), J0)
     assert np.array_equal(host(g), g0)
     s.set_checkpoint_slots(0)
+
+
+def test_budget_leaves_the_caller_checkpoint_path_unchanged():
+    """pa_forward and pa_adjoint_from_checkpoints keep the caller's one-state-per-boundary
+    layout under a snapshot budget: the autograd path (which uses them) gives the uniform
+    gradient bit for bit, and so does the budgeted pa_adjoint_gradient."""
+    from paper_2602_14016_amd import Observations
+    from paper_2602_14016_amd.autograd import adjoint_cost
+    N, B, steps, K = 32, 2, 26, 3
+    ph = Physics(N=N, nu=1e-3, dt=5e-3)
+    osteps = [0, 13, 26]
+    mo = np.stack([_twin(N, ph, steps, osteps, 4, seed=70 + b) for b in range(B)])
+    s = _solver(N, B, ph)
+    obs = Observations(4, osteps, dev(mo))
+    w0np = O.init_field(N, [71, 72], kind=0, k0=4.0)
+    s.set_checkpoint_slots(0)
+    J0, g0 = s.adjoint_gradient(dev(w0np), steps, obs, ckpt_every=K)
+    J0, g0 = host(J0), host(g0)
+    announce("budget-autograd")
+    s.set_checkpoint_slots(2)
+    w0 = dev(w0np).requires_grad_(True)
+    J = adjoint_cost(w0, s, steps, obs, K)
+    J.sum().backward()
+    assert np.array_equal(host(J.detach()), J0)
+    assert np.array_equal(host(w0.grad), g0)
+    Jb, gb = s.adjoint_gradient(dev(w0np), steps, obs, ckpt_every=K)
+    assert np.array_equal(host(Jb), J0) and np.array_equal(host(gb), g0)
+    s.set_checkpoint_slots(0)
+
+
+def test_graph_capture_of_a_budgeted_solve():
+    """A budgeted impulse solve captured in a HIP graph replays the uniform result,
+    with eager work between the replays."""
+    from paper_2602_14016_amd.graph import CapturedSolve
+    N, B, steps, K = 64, 3, 14, 3
+    s = _solver(N, B, Physics(N=N, nu=1e-3, dt=5e-3))
+    w0 = s.init_field([5, 6, 7], kind=0, k0=4.0, target=0.5)
+    s.set_checkpoint_slots(0)
+    sh0, f0 = s.adjoint_impulse(w0, steps, 10, 20, 8, ckpt_every=K, want_field=True)
+    sh0, f0 = sh0.clone(), f0.clone()
+    announce("budget-graph")
+    s.set_checkpoint_slots(2)
+    cap = CapturedSolve(lambda: s.adjoint_impulse(w0, steps, 10, 20, 8, ckpt_every=K, want_field=True))
+    for rep in range(3):
+        sh, f = cap.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(sh, sh0) and torch.equal(f, f0), rep
+        s.forward(w0, 3)
+        torch.cuda.synchronize()
+    s.set_checkpoint_slots(0)
