@@ -363,14 +363,17 @@ hipError_t timed(pa_ctx* c, int cls, F&& launch) {
             c->prof_ev.push_back(e);
         }
     }
-    hipEvent_t e0 = c->prof_ev[c->prof_used], e1 = c->prof_ev[c->prof_used + 1];
-    hipError_t r = hipEventRecord(e0, c->stream);
+    // the kernel's dispatch records the pair (see launch_kernel)
+    DispatchEvents& de = dispatch_events();
+    de.start = c->prof_ev[c->prof_used];
+    de.stop = c->prof_ev[c->prof_used + 1];
+    de.used = false;
+    const hipError_t r = launch();
+    const bool used = de.used;
+    de = DispatchEvents();
     if (r != hipSuccess) return r;
-    r = launch();
-    if (r != hipSuccess) return r;
-    r = hipEventRecord(e1, c->stream);
-    c->prof_used += 2;
-    return r;
+    if (used) c->prof_used += 2;
+    return hipSuccess;
 }
 
 // -------------------------------------------------------------- sweeps --

@@ -310,4 +310,101 @@ __device__ __forceinline__ void fft(cd* v, int t, cd* lds, const cd* __restrict_
     }
 }
 
+// ---- transforms with the thread's twiddles held in registers ----
+// A kernel that runs several transforms of one plan per row reads each
+// twiddle factor from LDS once: the factors a thread needs depend only on the
+// plan and its index t, not on the data, and the compiler reloads an LDS
+// table after every exchange because the exchange stores may alias it.
+// Stage q (q >= 1, span S = R[0] ... R[q-1]) keeps NB (R[q] - 1) factors at
+// offset tw_reg_offset(q); all indices are compile-time, so the array stays
+// in registers.  Results are bitwise those of fft().
+template <int N, int V>
+constexpr int tw_reg_offset(int q) {
+    int o = 0;
+    for (int s = 1; s < q; ++s) o += (Plan<N, V>::E / Plan<N, V>::R[s]) * (Plan<N, V>::R[s] - 1);
+    return o;
+}
+template <int N, int V>
+struct TwReg {
+    static constexpr int COUNT = tw_reg_offset<N, V>(Plan<N, V>::NS);
+    cd w[COUNT > 0 ? COUNT : 1];
+};
+
+template <int N, int V, int Q, int S>
+__device__ __forceinline__ void load_tw_stage(cd* w, int t, const cd* __restrict__ tw) {
+    constexpr int T = Plan<N, V>::T, R = Plan<N, V>::R[Q], NB = Plan<N, V>::E / R;
+    constexpr int OFF = tw_reg_offset<N, V>(Q);
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        const int k = (t + T * b) % S;
+#pragma unroll
+        for (int r = 1; r < R; ++r) w[OFF + b * (R - 1) + r - 1] = tw[r * S + k - 1];
+    }
+}
+
+template <int N, int V>
+__device__ __forceinline__ void load_twiddles(TwReg<N, V>& tr, int t, const cd* __restrict__ tw) {
+    using P = Plan<N, V>;
+    constexpr int R0 = P::R[0], R1 = P::R[1], R2 = P::R[2];
+    if constexpr (P::NS >= 2) load_tw_stage<N, V, 1, R0>(tr.w, t, tw);
+    if constexpr (P::NS >= 3) load_tw_stage<N, V, 2, R0 * R1>(tr.w, t, tw);
+    if constexpr (P::NS >= 4) load_tw_stage<N, V, 3, R0 * R1 * R2>(tr.w, t, tw);
+}
+
+template <int N, int V, int R, int S, int OFF, bool INV, bool LAST, bool WL>
+__device__ __forceinline__ void fft_stage_reg(cd* v, int t, cd* lds, const cd* w) {
+    constexpr int T = Plan<N, V>::T, E = Plan<N, V>::E, NB = E / R;
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        const int j = t + T * b;
+        cd u[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) u[r] = v[b + r * NB];
+        if constexpr (S > 1) {
+#pragma unroll
+            for (int r = 1; r < R; ++r) {
+                const cd f = w[OFF + b * (R - 1) + r - 1];
+                u[r] = INV ? cmulc(u[r], f) : cmul(u[r], f);
+            }
+        }
+        dft<R, INV>(u);
+        if constexpr (LAST) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[b + r * NB] = u[r];
+        } else {
+            const int base = (j / S) * S * R + (j % S);
+#pragma unroll
+            for (int r = 0; r < R; ++r) lds[lpos<N, V>(base + r * S)] = u[r];
+        }
+    }
+    if constexpr (!LAST) {
+        team_sync<WL>();
+#pragma unroll
+        for (int m = 0; m < E; ++m) v[m] = lds[lpos<N, V>(t + T * m)];
+        team_sync<WL>();
+    }
+}
+
+template <int N, int V, bool INV, bool WL = false>
+__device__ __forceinline__ void fft(cd* v, int t, cd* lds, const TwReg<N, V>& tr) {
+    using P = Plan<N, V>;
+    constexpr int R0 = P::R[0], R1 = P::R[1], R2 = P::R[2], R3 = P::R[3];
+    constexpr int O1 = tw_reg_offset<N, V>(1), O2 = tw_reg_offset<N, V>(2), O3 = tw_reg_offset<N, V>(3);
+    if constexpr (P::NS == 1) {
+        fft_stage_reg<N, V, R0, 1, 0, INV, true, WL>(v, t, lds, tr.w);
+    } else if constexpr (P::NS == 2) {
+        fft_stage_reg<N, V, R0, 1, 0, INV, false, WL>(v, t, lds, tr.w);
+        fft_stage_reg<N, V, R1, R0, O1, INV, true, WL>(v, t, lds, tr.w);
+    } else if constexpr (P::NS == 3) {
+        fft_stage_reg<N, V, R0, 1, 0, INV, false, WL>(v, t, lds, tr.w);
+        fft_stage_reg<N, V, R1, R0, O1, INV, false, WL>(v, t, lds, tr.w);
+        fft_stage_reg<N, V, R2, R0 * R1, O2, INV, true, WL>(v, t, lds, tr.w);
+    } else {
+        fft_stage_reg<N, V, R0, 1, 0, INV, false, WL>(v, t, lds, tr.w);
+        fft_stage_reg<N, V, R1, R0, O1, INV, false, WL>(v, t, lds, tr.w);
+        fft_stage_reg<N, V, R2, R0 * R1, O2, INV, false, WL>(v, t, lds, tr.w);
+        fft_stage_reg<N, V, R3, R0 * R1 * R2, O3, INV, true, WL>(v, t, lds, tr.w);
+    }
+}
+
 }  // namespace pa

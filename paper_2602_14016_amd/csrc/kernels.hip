@@ -5,6 +5,11 @@
 
 namespace pa {
 
+DispatchEvents& dispatch_events() {
+    static thread_local DispatchEvents e;
+    return e;
+}
+
 static bool obs_ok(const RowObs& o) {
     if (o.slot < 0) return true;
     return o.stride >= 1 && o.M >= 1 && o.n_times > o.slot;

@@ -158,4 +158,14 @@ hipError_t launch_shell_growth(int B, int rows, int n_shells, const double* shel
 
 constexpr int DOT_BLOCKS = 64;   // partial sums per member in launch_dot
 
+// Events that the next row, column or pipelined-row kernel launched on this
+// thread records as part of its own dispatch (start and end of that kernel,
+// not of the packets around it).  Set by the launch timer; one launch
+// consumes them and marks them used.
+struct DispatchEvents {
+    hipEvent_t start = nullptr, stop = nullptr;
+    bool used = false;
+};
+DispatchEvents& dispatch_events();
+
 }  // namespace pa

@@ -53,7 +53,9 @@ def column_mode_bytes(mode, N):
 
 # the sources that define and instantiate the row and column kernels, and the
 # build flags they are compiled with (host-side files do not change them)
-KERNEL_SOURCES = ("csrc/fft.hpp", "csrc/kernels.hpp", "csrc/kernels_impl.hpp", "csrc/kernels.hip", "build.py")
+KERNEL_SOURCES = ("csrc/fft.hpp", "csrc/kernels.hpp", "csrc/kernels_impl.hpp", "csrc/kernels.hip",
+                  "csrc/kern_8.hip", "csrc/kern_16.hip", "csrc/kern_32.hip", "csrc/kern_64.hip",
+                  "csrc/kern_128.hip", "csrc/kern_256.hip", "csrc/kern_512.hip", "csrc/kern_1024.hip", "build.py")
 
 
 def kernel_source_sha():
