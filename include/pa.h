@@ -42,6 +42,10 @@
  *     reported by the *_bytes queries, 256-byte aligned, caller-owned.  Calls
  *     that share a workspace on one stream are serialised by the stream;
  *     concurrent calls on different streams need different workspaces.
+ *   - A context is used by one host thread at a time: its settings (tiles,
+ *     Sobolev weight, snapshot budget), its cached checkpoint schedule and
+ *     its launch timer are not locked.  Different contexts may be used from
+ *     different threads at once.
  */
 #ifndef PA_H
 #define PA_H
