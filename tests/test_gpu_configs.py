@@ -103,6 +103,30 @@ def test_c2_grid_short_parity():
     assert rel(g.cpu().numpy()[0], g_ref) < 1e-9
 
 
+def test_largest_grid_gradient_parity():
+    """1024^2, the largest grid: cost and gradient over 2 steps (one-step segments,
+    so the segment recomputation runs) against the oracle, and the same gradient
+    with a one-slot snapshot budget, bit for bit."""
+    from paper_2602_14016_amd import Observations, Solver
+    print("CASE grid-1024", flush=True)
+    N, H = 1024, 2
+    ph = Physics(N=N, nu=1e-4, dt=1e-3)
+    w0 = O.init_field(N, [3], kind=0, k0=20.0, target=0.5)[0]
+    truth = O.init_field(N, [4], kind=0, k0=20.0, target=0.5)[0]
+    _, _, mo = O.forward(truth, ph, H, Obs(32, [0, H]))
+    J_ref, g_ref = O.adjoint_gradient(w0, ph, H, Obs(32, [0, H], mo))
+    s = Solver(N, 1, nu=ph.nu, dt=ph.dt)
+    obs = Observations(32, [0, H], dev(mo[None]))
+    J, g = s.adjoint_gradient(dev(w0[None]), H, obs, ckpt_every=1)
+    J, g = J.cpu().numpy(), g.cpu().numpy()
+    assert abs(float(J[0]) - J_ref) <= 1e-11 * J_ref
+    assert rel(g[0], g_ref) < 1e-9
+    s.set_checkpoint_slots(1)
+    Jb, gb = s.adjoint_gradient(dev(w0[None]), H, obs, ckpt_every=1)
+    s.set_checkpoint_slots(0)
+    assert np.array_equal(Jb.cpu().numpy(), J) and np.array_equal(gb.cpu().numpy(), g)
+
+
 def test_c1_full_horizon_divergence_curve():
     """GPU vs oracle vorticity over the full 1000-step c1 horizon (256^2, nu = 1e-4): round-off
     differences grow with the flow's chaotic amplification; the curve is printed, the field bar

@@ -44,10 +44,11 @@ def announce(*a):
     print("CASE", *a, flush=True)
 
 
-KERNELS = [Kernel(0, 0.0, 0), Kernel(1, 0.1, 0), Kernel(2, 0.5, 0), Kernel(3, 0.01, 0), Kernel(2, 0.25, 1), Kernel(0, 0.0, 2), Kernel(1, 0.1, 2)]
+KERNELS = [Kernel(0, 0.0, 0), Kernel(1, 0.1, 0), Kernel(2, 0.5, 0), Kernel(3, 0.01, 0), Kernel(3, 0.001, 0),
+           Kernel(2, 0.25, 1), Kernel(0, 0.0, 2), Kernel(1, 0.1, 2)]
 
 
-@pytest.mark.parametrize("N", [8, 16, 32, 64, 128, 256, 512])
+@pytest.mark.parametrize("N", [8, 16, 32, 64, 128, 256, 512, 1024])
 def test_precondition_parity(N):
     from paper_2602_14016_amd import KernelSpec
     announce("precondition", N)
@@ -58,6 +59,11 @@ def test_precondition_parity(N):
         for p in (-0.5, 0.5, 1.0):
             got = host(s.precondition(dev(x), KernelSpec(k.kind, k.param, k.metric), p))
             ref = O.precondition(x, k, p)
+            if not np.all(np.isfinite(ref)):
+                # the exact multiplier leaves the double range (a heat kernel inverted at the
+                # largest |k| of 1024^2: exp(+1161)); both sides must overflow, not return numbers
+                assert not np.all(np.isfinite(got)), (k, p)
+                continue
             assert rel(got, ref) < 1e-13, (k, p, rel(got, ref))
 
 
