@@ -63,7 +63,10 @@ typedef int32_t pa_status;
 #define PA_EINVAL       (-1)  /* bad argument (size, pointer, parameter)      */
 #define PA_ENOMEM       (-2)  /* workspace too small / device allocation failed */
 #define PA_EDEVICE      (-3)  /* HIP runtime error or no device                */
-#define PA_ENONFINITE   (-4)  /* non-finite value met (reported per member)    */
+/* Reserved; no call of this version returns them.  Per-member outcomes of an
+ * assimilation (a line-search failure, a non-finite cost) are reported in
+ * iters_done and J_hist, and the call itself returns PA_OK. */
+#define PA_ENONFINITE   (-4)  /* non-finite value met                          */
 #define PA_ELINESEARCH  (-5)  /* Armijo line search failed (step collapse)     */
 #define PA_EUNSUPPORTED (-6)  /* valid request this build does not support     */
 
