@@ -213,10 +213,12 @@ __device__ __forceinline__ int lpad(int i) { return i + (i >> 4); }
 // XOR the low four bits of i with i >> A ^ i >> B ^ i >> C (a bijection within
 // each aligned block of 16 entries).  Counting bank groups over every exchange
 // of a plan suggests such swizzles for most plans, but measured on gfx950 only
-// the radix-4 plan of 256 points gains (adjoint rows 46.3 -> 43.9 us for 64
-// members); the radix-8 plan of 256 points loses 10 %.  Every other plan keeps
-// one padding slot per 16 entries.
+// the plans made of radix-4 stages gain (256 points: adjoint rows 46.3 -> 43.9
+// us for 64 members; 128 points: 3-4 %); every plan with a radix-8 stage
+// loses 8-26 % (128, 256, 512 and 1024 points) and 64 points is flat.  Those
+// keep one padding slot per 16 entries.
 template <int N, int V> struct LdsSwizzle { static constexpr int A = 0, B = 0, C = 0; };
+template <> struct LdsSwizzle<128, 2>  { static constexpr int A = 2, B = 0, C = 0; };
 template <> struct LdsSwizzle<256, 2>  { static constexpr int A = 2, B = 7, C = 0; };
 
 template <int N, int V>
