@@ -68,7 +68,7 @@ typedef int32_t pa_status;
  * iters_done and J_hist, and the call itself returns PA_OK. */
 #define PA_ENONFINITE   (-4)  /* non-finite value met                          */
 #define PA_ELINESEARCH  (-5)  /* Armijo line search failed (step collapse)     */
-#define PA_EUNSUPPORTED (-6)  /* valid request this build does not support     */
+#define PA_EUNSUPPORTED (-6)  /* valid request this version does not support   */
 
 typedef struct pa_ctx pa_ctx;
 
