@@ -28,7 +28,9 @@
  *     Nothing throws or aborts across the ABI; pa_last_error() returns a
  *     message for the calling thread's most recent failure.
  *   - Arguments are validated before any device call; on a validation error
- *     nothing is enqueued and no output is touched.
+ *     nothing is enqueued and no output is touched.  Every pointer documented
+ *     as "device" must be device (or managed) memory; host memory is refused
+ *     with PA_EINVAL (pa_is_device_memory).
  *   - "device" pointers are HIP device memory owned by the caller (e.g. torch
  *     tensors); "host" pointers are ordinary host memory.  The library owns only
  *     the opaque context (plans and small constant tables it allocates in
@@ -363,6 +365,12 @@ pa_status pa_checkpoint_advances(int32_t n_segments, int32_t slots, int64_t* adv
  * still set) or for sizes as in pa_checkpoint_advances. */
 pa_status pa_checkpoint_schedule(int32_t n_segments, int32_t slots, int32_t* actions, int64_t capacity,
                                  int64_t* n_actions);
+
+/* Whether ptr is memory the kernels may dereference (device or managed
+ * memory), the check every call makes on its device arguments before it
+ * enqueues anything (PA_EINVAL "... is not device memory" otherwise).
+ * *is_device = 0 for NULL and host memory.  Needs a device. */
+pa_status pa_is_device_memory(const void* ptr, int32_t* is_device);
 
 /* Current tiles of the context. */
 pa_status pa_get_tiles(const pa_ctx* ctx, pa_tiles* tiles);

@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <initializer_list>
 #include <string>
 #include <vector>
 
@@ -42,6 +43,33 @@ pa_status fail(pa_status code, const std::string& msg) {
 bool is_pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
 
 bool finite_nonneg(double v) { return std::isfinite(v) && v >= 0.0; }
+
+// Every pointer the kernels dereference must be device (or managed) memory: a
+// host pointer would fault the device instead of returning an error.  NULL
+// entries (optional arguments) pass.  A failed attribute query leaves no
+// sticky error behind (it is cleared here).  Skipped while the context's
+// stream is being captured into a graph.
+struct NamedPtr {
+    const void* p;
+    const char* name;
+};
+pa_status require_device(hipStream_t stream, std::initializer_list<NamedPtr> ptrs) {
+    // under graph capture the same call has already run eagerly with these pointers
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (stream && hipStreamIsCapturing(stream, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone) return PA_OK;
+    for (const NamedPtr& q : ptrs) {
+        if (!q.p) continue;
+        hipPointerAttribute_t at{};
+        const hipError_t e = hipPointerGetAttributes(&at, q.p);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(PA_EINVAL, std::string(q.name) + " is not device memory");
+        }
+        if (at.type != hipMemoryTypeDevice && at.type != hipMemoryTypeManaged && !at.isManaged)
+            return fail(PA_EINVAL, std::string(q.name) + " is not device memory");
+    }
+    return PA_OK;
+}
 
 // One action of a checkpoint schedule over segment boundaries 0..L (segment i
 // runs from boundary i to i + 1).  ADVANCE runs segments a .. b-1 without
@@ -1051,6 +1079,14 @@ pa_status pa_checkpoint_schedule(int32_t n_segments, int32_t slots, int32_t* act
     return PA_OK;
 }
 
+pa_status pa_is_device_memory(const void* ptr, int32_t* is_device) {
+    if (!is_device) return fail(PA_EINVAL, "NULL argument");
+    const pa_status st = require_device(nullptr, {{ptr, "pointer"}});
+    *is_device = (ptr && st == PA_OK) ? 1 : 0;
+    g_err.clear();
+    return PA_OK;
+}
+
 pa_status pa_get_tiles(const pa_ctx* c, pa_tiles* t) {
     if (!c || !t) return fail(PA_EINVAL, "NULL argument");
     t->row_variant = c->d.var;
@@ -1113,6 +1149,7 @@ pa_status pa_init_field(pa_ctx* c, const uint64_t* seeds, int32_t kind, double k
     if (kind < 0 || kind > 2) return fail(PA_EINVAL, "kind must be 0, 1 or 2");
     if (!(std::isfinite(target) && target > 0)) return fail(PA_EINVAL, "target must be > 0");
     if (kind != 2 && !(std::isfinite(k0) && k0 > 0)) return fail(PA_EINVAL, "k0 must be > 0");
+    PA_TRY(require_device(c->stream, {{omega_out, "omega_out"}, {workspace, "workspace"}}));
     WS w;
     PA_TRY(check_ws(c, workspace, wbytes, 0, 1, 0, 0, &w));
     PA_HIP(hipMemcpyAsync(w.seeds, seeds, sizeof(uint64_t) * c->d.B, hipMemcpyHostToDevice, c->stream));
@@ -1133,6 +1170,8 @@ pa_status pa_forward(pa_ctx* c, const double* omega0, int32_t n_steps, const pa_
     if (reinterpret_cast<uintptr_t>(ckpt) % 16) return fail(PA_EINVAL, "checkpoint buffer must be 16-byte aligned");
     if (J_out && (!obs || !obs->values)) return fail(PA_EINVAL, "J_out needs observation values");
     if (obs_out && !obs) return fail(PA_EINVAL, "obs_out needs observations");
+    PA_TRY(require_device(c->stream, {{omega0, "omega0"}, {J_out, "J_out"}, {obs_out, "obs_out"}, {omega_T, "omega_T"},
+                           {ckpt, "ckpt"}, {workspace, "workspace"}, {obs ? obs->values : nullptr, "obs values"}}));
     ObsPlan op;
     PA_TRY(make_obs_plan(c, obs, n_steps, false, &op));
     WS w;
@@ -1154,6 +1193,8 @@ pa_status pa_adjoint_from_checkpoints(pa_ctx* c, const void* ckpt, int32_t n_ste
     if (!c || !ckpt || !grad_out) return fail(PA_EINVAL, "NULL argument");
     if (reinterpret_cast<uintptr_t>(ckpt) % 16) return fail(PA_EINVAL, "checkpoint buffer must be 16-byte aligned");
     if (n_steps < 0 || ckpt_every < 1) return fail(PA_EINVAL, "bad sizes");
+    PA_TRY(require_device(c->stream, {{ckpt, "ckpt"}, {scale, "scale"}, {grad_out, "grad_out"}, {workspace, "workspace"},
+                           {obs ? obs->values : nullptr, "obs values"}}));
     ObsPlan op;
     PA_TRY(make_obs_plan(c, obs, n_steps, true, &op));
     WS w;
@@ -1168,6 +1209,8 @@ pa_status pa_adjoint_gradient(pa_ctx* c, const double* omega0, int32_t n_steps, 
     g_err.clear();
     if (!c || !omega0 || !grad_out) return fail(PA_EINVAL, "NULL argument");
     if (n_steps < 0 || ckpt_every < 1) return fail(PA_EINVAL, "bad sizes");
+    PA_TRY(require_device(c->stream, {{omega0, "omega0"}, {J_out, "J_out"}, {grad_out, "grad_out"}, {workspace, "workspace"},
+                           {obs ? obs->values : nullptr, "obs values"}}));
     ObsPlan op;
     PA_TRY(make_obs_plan(c, obs, n_steps, true, &op));
     WS w;
@@ -1206,6 +1249,9 @@ pa_status pa_adjoint_impulse(pa_ctx* c, const double* omega0, int32_t n_steps, i
         return fail(PA_EINVAL, "ensemble accumulator has a NULL buffer or a negative count");
     if (acc && reinterpret_cast<uintptr_t>(acc->lambda_sum) % 16)
         return fail(PA_EINVAL, "lambda_sum must be 16-byte aligned");
+    PA_TRY(require_device(c->stream, {{omega0, "omega0"}, {shells_out, "shells_out"}, {field_out, "field_out"},
+                           {workspace, "workspace"}, {acc ? acc->lambda_sum : nullptr, "lambda_sum"},
+                           {acc ? acc->energy_sum : nullptr, "energy_sum"}, {acc ? acc->shell_sum : nullptr, "shell_sum"}}));
     WS w;
     PA_TRY(check_ws(c, workspace, wbytes, n_steps, ckpt_every, 0, 0, &w));
     const int K = seg_len(n_steps, ckpt_every);
@@ -1232,6 +1278,10 @@ pa_status pa_ensemble_stats(pa_ctx* c, const pa_ensemble_acc* acc, int32_t rows,
         return fail(PA_EINVAL, "NULL argument");
     if (acc->count < 1) return fail(PA_EINVAL, "no members accumulated");
     if (rows < 1 || n_shells < 1 || n_shells > c->n_shell_max) return fail(PA_EINVAL, "bad sizes");
+    PA_TRY(require_device(c->stream, {{acc->lambda_sum, "lambda_sum"}, {acc->energy_sum, "energy_sum"},
+                           {acc->shell_sum, "shell_sum"}, {mean_energy, "mean_energy"},
+                           {energy_of_mean, "energy_of_mean"}, {total_mean, "total_mean"},
+                           {total_of_mean, "total_of_mean"}, {snr, "snr"}}));
     PA_HIP(launch_ens_stats(c->d, rows, n_shells, 1.0 / (double)acc->count, static_cast<const cd*>(acc->lambda_sum),
                             acc->shell_sum, acc->energy_sum, c->shell_start, c->shell_modes, mean_energy,
                             energy_of_mean, total_mean, total_of_mean, snr, c->stream));
@@ -1243,6 +1293,7 @@ pa_status pa_first_guess(pa_ctx* c, int32_t stride, const double* probes, double
     g_err.clear();
     if (!c || !probes || !omega_out) return fail(PA_EINVAL, "NULL argument");
     if (stride < 1 || stride > c->d.N || c->d.N % stride) return fail(PA_EINVAL, "stride must divide N");
+    PA_TRY(require_device(c->stream, {{probes, "probes"}, {omega_out, "omega_out"}, {workspace, "workspace"}}));
     WS w;
     PA_TRY(check_ws(c, workspace, wbytes, 0, 1, 0, 0, &w));
     double* gu = w.P0;
@@ -1270,6 +1321,7 @@ pa_status pa_shell_growth(pa_ctx* c, const double* shells, int32_t rows, int32_t
     if (rows < 1 || n_shells < 1) return fail(PA_EINVAL, "bad sizes");
     if (!std::isfinite(tau_min) || !std::isfinite(tau_max) || tau_max < tau_min)
         return fail(PA_EINVAL, "bad growth window");
+    PA_TRY(require_device(c->stream, {{shells, "shells"}, {mean_out, "mean_out"}, {rate_out, "rate_out"}}));
     PA_HIP(launch_shell_growth(c->d.B, rows, n_shells, shells, c->ph.dt, tau_min, tau_max, mean_out, rate_out,
                                c->stream));
     return PA_OK;
@@ -1281,6 +1333,7 @@ pa_status pa_precondition(pa_ctx* c, const pa_kernel* k, double power, const dou
     if (!c || !in || !out) return fail(PA_EINVAL, "NULL argument");
     PA_TRY(valid_kernel(k));
     if (!std::isfinite(power)) return fail(PA_EINVAL, "power must be finite");
+    PA_TRY(require_device(c->stream, {{in, "in"}, {out, "out"}, {workspace, "workspace"}}));
     WS w;
     PA_TRY(check_ws(c, workspace, wbytes, 0, 1, 0, 0, &w));
     PA_HIP(launch_make_mult(c->d, k->kind, k->metric, k->param, power, w.mult, c->stream));
@@ -1340,6 +1393,8 @@ static pa_status assimilate_impl(pa_ctx* c, double* omega_inout, int32_t n_steps
     if (method != 0 && method != 1) return fail(PA_EINVAL, "method must be 0 (L-BFGS) or 1 (steepest descent)");
     if (max_iter < 0 || n_steps < 0 || ckpt_every < 1) return fail(PA_EINVAL, "bad sizes");
     if (method == 0 && lbfgs_m < 1) return fail(PA_EINVAL, "lbfgs_m must be >= 1");
+    PA_TRY(require_device(c->stream, {{omega_inout, "omega_inout"}, {workspace, "workspace"},
+                           {obs ? obs->values : nullptr, "obs values"}}));
     ObsPlan op;
     PA_TRY(make_obs_plan(c, obs, n_steps, true, &op));
     if (op.n_times == 0) return fail(PA_EINVAL, "assimilation needs at least one observation time");

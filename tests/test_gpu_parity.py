@@ -343,3 +343,32 @@ def test_sobolev_regularised_cost_and_gradient_parity():
         FIELD_TOL * float(host(J0)[0])
     with pytest.raises(PaError):
         s.set_sobolev(-1.0)
+
+
+def test_host_memory_is_refused_before_any_launch():
+    """The boundary's device-memory check: the query classifies torch device memory,
+    host memory and NULL; only once it has refused host memory is an entry point
+    called with a host input, which must return PA_EINVAL without enqueuing work."""
+    import ctypes
+    from paper_2602_14016_amd import KernelSpec, native
+    announce("host-memory-check")
+    lib = native.load()
+    flag = ctypes.c_int32(-1)
+    d = torch.zeros(1024, dtype=torch.float64, device="cuda")
+    h = np.zeros(1024)
+    assert lib.pa_is_device_memory(ctypes.c_void_p(d.data_ptr()), ctypes.byref(flag)) == 0 and flag.value == 1
+    assert lib.pa_is_device_memory(ctypes.c_void_p(h.ctypes.data), ctypes.byref(flag)) == 0 and flag.value == 0
+    assert lib.pa_is_device_memory(None, ctypes.byref(flag)) == 0 and flag.value == 0
+    N, B = 32, 2
+    s = solver(N, B, Physics(N=N, nu=1e-3, dt=1e-3))
+    x_host = np.zeros((B, N, N))
+    out = torch.empty((B, N, N), dtype=torch.float64, device="cuda")
+    ws, wb = s.workspace()
+    k = KernelSpec(1, 0.1, 0).c()
+    st = lib.pa_precondition(s.ctx, ctypes.byref(k), ctypes.c_double(0.5), ctypes.c_void_p(x_host.ctypes.data),
+                             ctypes.c_void_p(out.data_ptr()), ws, wb)
+    assert st == -1 and b"not device memory" in lib.pa_last_error()   # PA_EINVAL
+    # the context still works
+    x = torch.from_numpy(synth.normal_field((B, N, N), seed=3)).cuda()
+    got = host(s.precondition(x, KernelSpec(1, 0.1, 0), 0.5))
+    assert rel(got, O.precondition(x.cpu().numpy(), Kernel(1, 0.1, 0), 0.5)) < 1e-13
