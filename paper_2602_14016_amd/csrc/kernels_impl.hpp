@@ -228,9 +228,11 @@ __device__ __forceinline__ void row_nl_body(const Dims& d, const RowArgs& a) {
     herm_load<N, V>(z1, a.yin[0] + roff, a.yin[2] + roff, t);   // u + i w_x
     herm_load<N, V>(z2, a.yin[1] + roff, a.yin[3] + roff, t);   // v + i w_y
     const cd* twl = stage_twiddles<N, V>(tw_lds, tw_g);
+    TwReg<N, V> tr;   // the three transforms of the row share the thread's twiddles
+    load_twiddles<N, V>(tr, t, twl);
     double part = 0.0;
-    fft<N, V, true, WL>(z1, t, lds, twl);
-    fft<N, V, true, WL>(z2, t, lds, twl);
+    fft<N, V, true, WL>(z1, t, lds, tr);
+    fft<N, V, true, WL>(z2, t, lds, tr);
     cd z[E];
 #pragma unroll
     for (int m = 0; m < E; ++m) {
@@ -244,7 +246,7 @@ __device__ __forceinline__ void row_nl_body(const Dims& d, const RowArgs& a) {
         const double s = team_sum<N, V, WL>(part, t, lds);
         if (t == 0) store_jpart(a.obs, b, y, s);
     }
-    fft<N, V, false, WL>(z, t, lds, twl);
+    fft<N, V, false, WL>(z, t, lds, tr);
     cd* o = a.yout[0] + roff;
 #pragma unroll
     for (int m = 0; m < E; ++m) {
@@ -253,11 +255,13 @@ __device__ __forceinline__ void row_nl_body(const Dims& d, const RowArgs& a) {
     }
 }
 
-// Occupancy hint for the right-hand-side row pass: with 8 register slots per
-// thread (one row per team) it fits the 128 VGPRs of four waves per SIMD; the
-// two-row kernel of the 4-slot plan holds both rows' loads and gets three.
+// Occupancy hint for the right-hand-side row pass: three waves per SIMD (168
+// VGPRs).  With 8 register slots per thread (one row per team) the row's data
+// and its twiddle factors in registers fit; at four waves (128 VGPRs) the
+// twiddles spill, and reading them from LDS instead is 3.5 % slower at 256^2.
+// The two-row kernel of the 4-slot plan holds both rows' loads.
 template <int N, int V>
-constexpr int nl_waves() { return V == 2 ? 3 : Plan<N, V>::E <= 8 ? 4 : 1; }
+constexpr int nl_waves() { return Plan<N, V>::E <= 8 ? 3 : 1; }
 
 // Two rows per team: q of both rows is real, so one complex transform of
 // q_a + i q_b, split into the two half spectra, replaces two transforms of
@@ -287,10 +291,15 @@ __device__ __forceinline__ void row_nl_pair_body(const Dims& d, const RowArgs& a
     split_store<N, V, WL>(z, t, lds, a.yout[0] + ra, a.yout[0] + rb);
 }
 
+// Variant 2 runs two rows per team where its plan has four values per thread
+// (16 to 256 points); with eight values the two rows' signals spill.
+template <int N>
+__host__ __device__ constexpr bool nl_pairs() { return Plan<N, 2>::E == 4; }
+
 template <int N, int V>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(nl_waves<N, V>())))
 row_nl_kernel(Dims d, RowArgs a) {
-    if constexpr (V == 2) row_nl_pair_body<N, V>(d, a);
+    if constexpr (V == 2 && nl_pairs<N>()) row_nl_pair_body<N, V>(d, a);
     else row_nl_body<N, V, false>(d, a);
 }
 template <int N, int V>
@@ -894,10 +903,13 @@ hipError_t Launch<N>::row_c2r(const Dims& d, const cd* in, double* out, const cd
 }
 template <int N>
 hipError_t Launch<N>::row_nl(const Dims& d, const RowArgs& a, hipStream_t s) {
+    // variant 3 without a pipelined kernel for N falls back to the variant-2 kernel launched with
+    // one team per row below, which must then be the one-row kernel
+    static_assert(Pipe<N>::OK || !nl_pairs<N>(), "the variant-3 fallback would launch the two-row kernel");
     if (a.obs.slot >= 0) PA_ROW_LAUNCH(d.var, d.tpb, row_nl_obs_kernel, N, d, a);
     if constexpr (Pipe<N>::OK)
         if (d.var == 3) return pipe_launch<N, 4>(row_nl_pipe_kernel<N>, d.tpb, d, a, s);
-    if (d.var == 2) PA_ROW_LAUNCH(d.var, d.tpb, row_nl_kernel, N / 2, d, a);   // two rows per team
+    if (d.var == 2 && nl_pairs<N>()) PA_ROW_LAUNCH(d.var, d.tpb, row_nl_kernel, N / 2, d, a);   // two rows per team
     PA_ROW_LAUNCH(d.var, d.tpb, row_nl_kernel, N, d, a);
 }
 template <int N>

@@ -215,6 +215,23 @@ def test_pipelined_rows_against_plain_rows(N, B):
         assert abs(float(res[key][0][0]) - Jref) <= FIELD_TOL * Jref
 
 
+@pytest.mark.parametrize("N", [8, 1024])
+def test_pipelined_variant_fallback(N):
+    """Row variant 3 where no pipelined kernel exists for N runs the variant-2 plan
+    one row per team: every member's forward matches variant 1."""
+    announce("variant-3 fallback", N)
+    ph = Physics(N=N, nu=1e-4, dt=1e-3)
+    B = 3
+    w0 = dev(O.init_field(N, [1, 2, 3], kind=0, k0=min(4.0, N / 4), target=0.5))
+    s = solver(N, B, ph)
+    s.set_tiles(row_variant=1, adj_variant=1)
+    ref = host(s.forward(w0, 3)["omega_T"])
+    s.set_tiles(row_variant=3, adj_variant=3)
+    got = host(s.forward(w0, 3)["omega_T"])
+    for b in range(B):
+        assert rel(got[b], ref[b]) < 1e-13, b
+
+
 def test_set_tiles_validation_and_readback():
     announce("tiles-api")
     from paper_2602_14016_amd.native import PaError
