@@ -175,8 +175,9 @@ def test_ensemble_workload_in_its_launch_configuration():
     shells) with autotuned tiles and the whole trajectory kept, as timed:
     the terminal row against its closed form for every member, two sampled
     members over the whole horizon against one-member solves with default
-    tiles and checkpoints every 50 steps, and the same configured solver
-    against the oracle over a 10-step horizon on two sampled members."""
+    tiles and checkpoints every 50 steps, the same configured solver against
+    the oracle over a 10-step horizon on two sampled members, and one sampled
+    member against the oracle over the whole horizon."""
     from paper_2602_14016_amd import Solver
     from paper_2602_14016_amd.autotune import autotune
     N, B, H, nsh = 256, 64, 500, 85
@@ -206,3 +207,9 @@ def test_ensemble_workload_in_its_launch_configuration():
     for b in (0, 63):
         ref = O.impulse_adjoint(w0np[b], ph, 10, N // 2, N // 2, nsh)[0]
         assert rel(short[b], ref) < 1e-9
+    # one sampled member over the whole 500 + 500-step horizon against the oracle (about a minute of CPU)
+    print("CASE ensemble-workload oracle full horizon, member 17", flush=True)
+    ref = O.impulse_adjoint(w0np[17], ph, H, N // 2, N // 2, nsh)[0]
+    err = rel(shells[17], ref)
+    print("CASE ensemble-workload member 17 rel", err, flush=True)
+    assert err < 1e-9
