@@ -61,6 +61,30 @@ def test_c1_shortened_horizon_gradient_parity():
     assert rel(g.cpu().numpy()[0], g_ref) < 1e-9
 
 
+def test_c1_full_horizon_gradient_against_oracle():
+    """c1 at its full horizon (256^2, nu = 1e-4, 1000 steps at dt = 2e-3, 5
+    observation times at stride 8, checkpoints every 50): cost and gradient
+    against the oracle (about two minutes of CPU for the oracle)."""
+    from paper_2602_14016_amd import Observations, Solver
+    print("CASE c1-1000 oracle truth", flush=True)
+    N, H = 256, 1000
+    ph = Physics(N=N, nu=1e-4, dt=2e-3)
+    osteps = synth.evenly_spaced_steps(H, 5)
+    truth = O.init_field(N, [0], kind=0, k0=10.0)[0]
+    _, _, mo = O.forward(truth, ph, H, Obs(8, osteps))
+    w0 = O.init_field(N, [1], kind=0, k0=10.0)[0]
+    print("CASE c1-1000 oracle gradient", flush=True)
+    J_ref, g_ref = O.adjoint_gradient(w0, ph, H, Obs(8, osteps, mo))
+    s = Solver(N, 1, nu=ph.nu, dt=ph.dt)
+    J, g = s.adjoint_gradient(dev(w0[None]), H, Observations(8, osteps, dev(mo[None])), ckpt_every=50)
+    torch.cuda.synchronize()
+    ej = abs(float(J.cpu()[0]) - J_ref) / J_ref
+    eg = rel(g.cpu().numpy()[0], g_ref)
+    print("CASE c1-1000 rel J", ej, "rel grad", eg, flush=True)
+    assert ej <= 1e-11
+    assert eg < 1e-9
+
+
 def test_c1_full_finite_differences():
     from paper_2602_14016_amd import Observations, Solver
     print("CASE c1-fd", flush=True)
