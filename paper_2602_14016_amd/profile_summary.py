@@ -3,6 +3,8 @@
     python -m paper_2602_14016_amd.profile_summary stats KERNEL_STATS_CSV --command CMD --title T --out FILE
     python -m paper_2602_14016_amd.profile_summary traffic FETCH_CSV WRITE_CSV --command CMD --members B --N N \
         --cls C --kernel NAME --calib-mib M --out FILE
+    python -m paper_2602_14016_amd.profile_summary counters CSV [CSV ...] --command CMD --title T \
+        --kernels NAME [NAME ...] --out FILE
 
 stats: per-kernel calls, average and total duration from a --kernel-trace
 --stats run (run_kernel_stats.csv).
@@ -102,6 +104,31 @@ def traffic(args):
     return "\n".join(out) + "\n"
 
 
+def counters(args):
+    """Mean per dispatch of every counter in the --pmc runs, for the named kernels,
+    with the wave-cycle shares of the SQ wait and issue counters."""
+    vals = collections.defaultdict(lambda: collections.defaultdict(list))
+    for path in args.csv:
+        for r in csv.DictReader(open(path)):
+            vals[short(r["Kernel_Name"])][r["Counter_Name"]].append(float(r["Counter_Value"]))
+    out = [f"# {args.title}", "#", "# commands (from /tmp, TMPDIR=/tmp; REPO = repository root), one pass each:"]
+    out += [f"#   {line}" for line in args.command.split("\n")]
+    out += ["#", "# mean per dispatch; shares are of SQ_WAVE_CYCLES (summed wave residency)", f"source_sha: {kernel_source_sha()}"]
+    for k in args.kernels:
+        if k not in vals:
+            raise SystemExit(f"kernel {k!r} not in the counter runs: {sorted(vals)}")
+        d = {c: sum(v) / len(v) for c, v in vals[k].items()}
+        out += ["", f"kernel: {k}"]
+        for c in sorted(d):
+            out.append(f"  {c:28s} {d[c]:16.6g}")
+        wc = d.get("SQ_WAVE_CYCLES")
+        if wc:
+            for c in ("SQ_ACTIVE_INST_VALU", "SQ_WAIT_INST_LDS", "SQ_WAIT_INST_ANY", "SQ_ACTIVE_INST_LDS"):
+                if c in d:
+                    out.append(f"  share {c:22s} {d[c] / wc:8.3f}")
+    return "\n".join(out) + "\n"
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     sub = ap.add_subparsers(dest="what", required=True)
@@ -121,8 +148,14 @@ def main(argv=None):
     b.add_argument("--kernel", required=True)
     b.add_argument("--calib-mib", type=int, required=True)
     b.add_argument("--out", required=True)
+    c = sub.add_parser("counters")
+    c.add_argument("csv", nargs="+")
+    c.add_argument("--command", required=True)
+    c.add_argument("--title", required=True)
+    c.add_argument("--kernels", nargs="+", required=True)
+    c.add_argument("--out", required=True)
     args = ap.parse_args(argv)
-    text = stats(args) if args.what == "stats" else traffic(args)
+    text = {"stats": stats, "traffic": traffic, "counters": counters}[args.what](args)
     with open(args.out, "w") as fh:
         fh.write(text)
     sys.stdout.write(text)
