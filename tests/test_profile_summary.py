@@ -51,3 +51,20 @@ def test_traffic_record_calibrates_and_round_trips(tmp_path, monkeypatch):
     stale = tmp_path / "stale.txt"
     stale.write_text(text.replace("source_sha: ", "source_sha: 0"))
     assert read_traffic(2, 256, 64, path=str(stale)) is None
+
+
+def test_counter_summary_means_and_shares(tmp_path):
+    k = "void pa::row_adj_kernel<256, 2>(pa::Dims, pa::RowArgs)"
+    a, b = tmp_path / "a.csv", tmp_path / "b.csv"
+    _counter_csv(a, "SQ_WAVE_CYCLES", [(k, 1000.0), (k, 3000.0), ("other", 5.0)])
+    _counter_csv(b, "SQ_WAIT_INST_LDS", [(k, 400.0), (k, 400.0)])
+    out = tmp_path / "c.txt"
+    text = ps.main(["counters", str(a), str(b), "--command", "cmd", "--title", "t",
+                    "--kernels", "row_adj_kernel<256, 2>", "--out", str(out)]) or out.read_text()
+    assert "kernel: row_adj_kernel<256, 2>" in text
+    lines = {l.split()[0]: l.split() for l in text.splitlines() if l.startswith("  SQ_")}
+    assert float(lines["SQ_WAVE_CYCLES"][1]) == 2000.0           # mean over the two dispatches
+    share = [l for l in text.splitlines() if "share SQ_WAIT_INST_LDS" in l][0]
+    assert float(share.split()[-1]) == pytest.approx(0.2)         # 400 / 2000
+    with pytest.raises(SystemExit):
+        ps.main(["counters", str(a), "--command", "c", "--title", "t", "--kernels", "missing", "--out", str(out)])
