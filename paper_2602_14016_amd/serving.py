@@ -99,33 +99,17 @@ def footprint_bytes(solver, req: Request):
     return ws + fields
 
 
-class Server:
-    def __init__(self, hbm_budget_bytes, slots=4, max_batch=8, device="cuda:0", tiles=None, verbose=False):
-        """tiles: optional {N: pa_tiles dict} applied to every solver of grid size N;
-        verbose: print one line per finished group."""
+class GpuBackend:
+    """The device work of the server: one HIP stream (default priority) and a
+    cache of solver contexts per slot.  footprint() sizes a group of B requests
+    of one shape, run() assimilates them as one batched solve on the slot's
+    stream and returns host results, release() frees the slot's workspace."""
+
+    def __init__(self, slots, device="cuda:0", tiles=None):
         self.device = torch.device(device)
         self.tiles = dict(tiles or {})
-        self.verbose = verbose
-        self.budget = int(hbm_budget_bytes)
-        self.in_use = 0
-        self.slots = slots
-        self.max_batch = max_batch
-        self.lock = threading.Condition()
-        self.queue: List[Request] = []
-        self.results = {}
-        self.free_slots = list(range(slots))
         self.streams = [torch.cuda.Stream(device=self.device) for _ in range(slots)]
-        self.t0 = None
         self._solvers = {}   # (slot, N, flow, B) -> Solver
-
-    # ------------------------------------------------------------------ API
-    def now(self):
-        return time.perf_counter() - self.t0
-
-    def submit(self, req: Request):
-        with self.lock:
-            self.queue.append(req)
-            self.lock.notify_all()
 
     def _solver(self, slot, N, flow, B):
         key = (slot, N, flow, B)
@@ -137,9 +121,72 @@ class Server:
                 self._solvers[key] = sv
         return self._solvers[key]
 
-    def _probe_solver(self, req, B):
-        # footprint query only (any slot's context of the same shape answers it)
-        return self._solver(0, req.N, req.flow, B)
+    def footprint(self, req: Request, B):
+        # any slot's context of the same shape answers the size query
+        return footprint_bytes(self._solver(0, req.N, req.flow, B), req)
+
+    def run(self, slot, group):
+        """(omega0 [B, N, N] on the host, J histories, iteration counts) of the group."""
+        head = group[0]
+        B = len(group)
+        s = self._solver(slot, head.N, head.flow, B)
+        with torch.cuda.stream(self.streams[slot]):
+            vals = torch.stack([r.obs_values for r in group]).to(self.device, dtype=torch.float64,
+                                                                  non_blocking=False).contiguous()
+            obs = Observations(head.stride, head.obs_steps, vals)
+            if head.first_guess == "interp" and head.obs_steps and head.obs_steps[0] == 0:
+                fg = s.first_guess(head.stride, vals[:, 0].contiguous())
+            else:
+                fg = torch.zeros((B, head.N, head.N), dtype=torch.float64, device=self.device)
+            w, H, iters = s.assimilate(fg, head.n_steps, obs, head.kernel, "lbfgs", head.iters,
+                                       head.lbfgs_m, head.ckpt_every)
+            return w.cpu(), H, iters
+
+    def release(self, slot, group):
+        head = group[0]
+        sv = self._solvers.get((slot, head.N, head.flow, len(group)))
+        if sv is not None:
+            sv._ws = None   # return the workspace to the allocator before the budget is released
+
+
+class Server:
+    def __init__(self, hbm_budget_bytes, slots=4, max_batch=8, device="cuda:0", tiles=None, verbose=False,
+                 backend=None):
+        """tiles: optional {N: pa_tiles dict} applied to every solver of grid size N;
+        verbose: print one line per finished group; backend: the device work
+        (GpuBackend by default; anything with footprint/run/release)."""
+        self.backend = backend if backend is not None else GpuBackend(slots, device, tiles)
+        self.verbose = verbose
+        self.budget = int(hbm_budget_bytes)
+        self.in_use = 0
+        self.slots = slots
+        self.max_batch = max_batch
+        self.lock = threading.Condition()
+        self.queue: List[Request] = []
+        self.results = {}
+        self.free_slots = list(range(slots))
+        self.t0 = None
+
+    # ------------------------------------------------------------------ API
+    def now(self):
+        return time.perf_counter() - self.t0
+
+    def submit(self, req: Request):
+        with self.lock:
+            self.queue.append(req)
+            self.lock.notify_all()
+
+    def cancel(self, rid):
+        """Withdraw a request that is still queued; False if it was admitted or is unknown."""
+        with self.lock:
+            for r in self.queue:
+                if r.rid == rid:
+                    self.queue.remove(r)
+                    t = self.now() if self.t0 is not None else 0.0
+                    self.results[rid] = Result(rid, None, [], 0, "cancelled", r.arrival, t, t, 0)
+                    self.lock.notify_all()
+                    return True
+        return False
 
     def _admit_locked(self):
         """Admit queued requests into free slots while memory allows (arrival order)."""
@@ -147,11 +194,10 @@ class Server:
         while self.free_slots and self.queue:
             head = self.queue[0]
             group = [r for r in self.queue if r.shape_key() == head.shape_key()][: self.max_batch]
-            solver = self._probe_solver(head, len(group))
-            need = footprint_bytes(solver, head)
+            need = self.backend.footprint(head, len(group))
             while need > self.budget - self.in_use and len(group) > 1:
                 group = group[:-1]
-                need = footprint_bytes(self._probe_solver(head, len(group)), head)
+                need = self.backend.footprint(head, len(group))
             if need > self.budget:
                 self.queue.remove(head)
                 self.results[head.rid] = Result(head.rid, None, [], 0, "rejected: exceeds HBM budget",
@@ -171,19 +217,7 @@ class Server:
         try:
             head = group[0]
             B = len(group)
-            s = self._solver(slot, head.N, head.flow, B)
-            stream = self.streams[slot]
-            with torch.cuda.stream(stream):
-                vals = torch.stack([r.obs_values for r in group]).to(self.device, dtype=torch.float64,
-                                                                      non_blocking=False).contiguous()
-                obs = Observations(head.stride, head.obs_steps, vals)
-                if head.first_guess == "interp" and head.obs_steps and head.obs_steps[0] == 0:
-                    fg = s.first_guess(head.stride, vals[:, 0].contiguous())
-                else:
-                    fg = torch.zeros((B, head.N, head.N), dtype=torch.float64, device=self.device)
-                w, H, iters = s.assimilate(fg, head.n_steps, obs, head.kernel, "lbfgs", head.iters,
-                                           head.lbfgs_m, head.ckpt_every)
-                w_host = w.cpu()
+            w_host, H, iters = self.backend.run(slot, group)
             fin = self.now()
             if self.verbose:
                 print(f"[serving] slot {slot}: {B} x {head.N}^2 {head.flow} H={head.n_steps} done at {fin:.2f} s "
@@ -199,8 +233,8 @@ class Server:
                 self.results[r.rid] = Result(r.rid, None, [], 0, f"error: {e}", r.arrival, admitted, fin, len(group))
         finally:
             try:
-                s._ws = None     # return the workspace to the allocator before the budget is released
-            except NameError:
+                self.backend.release(slot, group)
+            except Exception:
                 pass
             with self.lock:
                 self.in_use -= need

@@ -51,11 +51,11 @@ def test_alone_equals_mix_and_latency():
 
 
 def test_oversize_request_rejected_alone():
-    from paper_2602_14016_amd.serving import Server, footprint_bytes
+    from paper_2602_14016_amd.serving import GpuBackend, Server
     print("CASE serving-reject", flush=True)
     reqs = _make_requests()[:3]
-    probe = Server(hbm_budget_bytes=1 << 40, slots=1)
-    fp = [footprint_bytes(probe._probe_solver(r, 1), r) for r in reqs]
+    probe = GpuBackend(slots=1)
+    fp = [probe.footprint(r, 1) for r in reqs]
     assert fp[1] > max(fp[0], fp[2])            # the 64^2 request is the largest
     budget = (fp[1] + max(fp[0], fp[2])) // 2   # fits the 32^2 requests one at a time, never the 64^2 one
     res = Server(hbm_budget_bytes=budget, slots=2).run_trace(reqs)

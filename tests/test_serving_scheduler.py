@@ -1,0 +1,148 @@
+"""The serving scheduler on the CPU, with a sleep-model backend in place of the device.
+
+The backend stands for GpuBackend: footprint() sizes a group, run() "solves"
+it (sleeps, then returns identifiable host results, a NaN observation making
+that member's line search fail as the device solve would), release() frees
+it.  The tests check admission by bytes, slot recycling, batching of
+same-shape requests, rejection of oversize requests, a poisoned request
+failing alone, an exception failing only its group, cancellation of a
+queued request and arrival-order admission on a Poisson trace.
+"""
+
+import threading
+import time
+
+import numpy as np
+import torch
+
+from paper_2602_14016_amd.serving import Request, Server, latency_stats, poisson_arrivals
+from paper_2602_14016_amd.solver import KernelSpec
+
+
+class SleepBackend:
+    def __init__(self, bytes_per_member=100, solve_s=0.05, fail_rids=()):
+        self.bytes_per_member = bytes_per_member
+        self.solve_s = solve_s
+        self.fail_rids = set(fail_rids)
+        self.lock = threading.Lock()
+        self.active = 0
+        self.max_active = 0
+        self.calls = []          # (slot, [rids]) in start order
+        self.released = []
+
+    def footprint(self, req, B):
+        return self.bytes_per_member * B * (req.N // 8)
+
+    def run(self, slot, group):
+        with self.lock:
+            self.active += 1
+            self.max_active = max(self.max_active, self.active)
+            self.calls.append((slot, [r.rid for r in group]))
+        try:
+            time.sleep(self.solve_s)
+            if any(r.rid in self.fail_rids for r in group):
+                raise RuntimeError("backend failure")
+            B, N = len(group), group[0].N
+            w = torch.empty((B, N, N), dtype=torch.float64)
+            for b, r in enumerate(group):
+                w[b].fill_(float(r.rid))
+            finite = [bool(torch.isfinite(r.obs_values).all()) for r in group]
+            H = [[2.0, 1.0] if ok else [float("nan")] for ok in finite]
+            iters = [1 if ok else -1 for ok in finite]     # -(k+1): line search failed after k = 0
+            return w, H, iters
+        finally:
+            with self.lock:
+                self.active -= 1
+
+    def release(self, slot, group):
+        self.released.append([r.rid for r in group])
+
+
+def req(rid, arrival=0.0, N=8, n_steps=10, poisoned=False):
+    vals = torch.zeros((1, 2, 2, 2), dtype=torch.float64)
+    if poisoned:
+        vals[0, 0, 0, 0] = float("nan")
+    return Request(rid=rid, N=N, flow="decaying", n_steps=n_steps, stride=4, obs_steps=[0], obs_values=vals,
+                   kernel=KernelSpec(0, 0.0), arrival=arrival)
+
+
+def test_admission_respects_the_byte_budget_and_recycles_slots():
+    be = SleepBackend(bytes_per_member=100, solve_s=0.05)
+    # distinct horizons: no batching; the budget holds two requests at once although four slots exist
+    reqs = [req(i, n_steps=10 + i) for i in range(6)]
+    res = Server(250, slots=4, backend=be).run_trace(reqs)
+    assert all(res[r.rid].status == "ok" for r in reqs)
+    assert be.max_active == 2
+    assert {s for s, _ in be.calls} <= {0, 1, 2, 3}
+    assert sorted(sum((c for _, c in be.calls), [])) == list(range(6))
+    assert len(be.released) == 6
+    be1 = SleepBackend(solve_s=0.02)
+    res1 = Server(10 ** 9, slots=2, backend=be1).run_trace([req(i, n_steps=10 + i) for i in range(5)])
+    assert all(r.status == "ok" for r in res1.values())
+    assert {s for s, _ in be1.calls} == {0, 1} and be1.max_active <= 2
+
+
+def test_same_shape_requests_run_as_one_batch_up_to_max_batch():
+    be = SleepBackend(solve_s=0.05)
+    reqs = [req(i) for i in range(3)]            # one shape
+    res = Server(10 ** 9, slots=1, max_batch=2, backend=be).run_trace(reqs)
+    assert [len(c) for _, c in be.calls] == [2, 1]
+    assert [res[i].batch for i in range(3)] == [2, 2, 1]
+    for i in range(3):
+        assert torch.all(res[i].omega0 == float(i))     # each member gets its own result
+
+
+def test_oversize_request_is_rejected_alone():
+    be = SleepBackend(bytes_per_member=100)
+    reqs = [req(0), req(1, N=800), req(2, n_steps=11)]   # request 1 needs 100 * 100 bytes
+    res = Server(1000, slots=2, backend=be).run_trace(reqs)
+    assert res[1].status.startswith("rejected")
+    assert res[0].status == "ok" and res[2].status == "ok"
+
+
+def test_poisoned_request_fails_alone_inside_a_batch():
+    be = SleepBackend()
+    reqs = [req(0), req(1, poisoned=True), req(2)]        # one shape, batched together
+    res = Server(10 ** 9, slots=1, max_batch=8, backend=be).run_trace(reqs)
+    assert [len(c) for _, c in be.calls] == [3]
+    assert res[1].status == "line-search failure" and res[1].iters == 0
+    assert res[0].status == "ok" and res[2].status == "ok"
+
+
+def test_backend_exception_fails_only_its_group():
+    be = SleepBackend(fail_rids={1})
+    reqs = [req(0), req(1, n_steps=11), req(2, n_steps=12)]
+    res = Server(10 ** 9, slots=2, backend=be).run_trace(reqs)
+    assert res[1].status.startswith("error")
+    assert res[0].status == "ok" and res[2].status == "ok"
+    assert len(be.released) == 3          # the failed group's memory is released too
+
+
+def test_cancel_a_queued_request():
+    be = SleepBackend(solve_s=0.4)
+    srv = Server(10 ** 9, slots=1, backend=be)
+    reqs = [req(0), req(1, n_steps=11), req(2, n_steps=12)]
+    out = {}
+    th = threading.Thread(target=lambda: out.update(srv.run_trace(reqs)))
+    th.start()
+    time.sleep(0.15)                      # request 0 is running, 1 and 2 are queued
+    assert srv.cancel(1)
+    assert not srv.cancel(0)              # already admitted
+    assert not srv.cancel(99)
+    th.join(timeout=10)
+    assert not th.is_alive()
+    assert out[1].status == "cancelled"
+    assert out[0].status == "ok" and out[2].status == "ok"
+    assert [c for _, c in be.calls] == [[0], [2]]
+
+
+def test_poisson_trace_is_admitted_in_arrival_order():
+    arrivals = poisson_arrivals(12, rate=200.0, seed=3)
+    assert np.all(np.diff(arrivals) > 0)
+    be = SleepBackend(solve_s=0.01)
+    reqs = [req(i, arrival=float(a), n_steps=10 + i) for i, a in enumerate(arrivals)]
+    res = Server(10 ** 9, slots=1, backend=be).run_trace(list(reversed(reqs)))
+    assert [c[0] for _, c in be.calls] == list(range(12))
+    assert all(res[i].admitted >= reqs[i].arrival - 1e-3 for i in range(12))
+    st = latency_stats(res)
+    assert st["n"] == 12 and st["p99_s"] >= st["p50_s"] > 0
