@@ -204,7 +204,9 @@ pa_status pa_precondition(pa_ctx* ctx, const pa_kernel* kernel, double power,
  * J_hist: host [B][max_iter + 1], the cost after each accepted iteration
  * (unused entries NaN).  iters_done: host [B], iterations completed, negated
  * minus one (-(k+1)) if member b stopped on a line-search failure after k
- * iterations.  Members run in one batch; a failure stops only that member.
+ * iterations (a non-finite cost, e.g. from a NaN observation, fails every
+ * trial step and ends there too).  Members run in one batch; a failure stops
+ * only that member.
  * Synchronises the stream. */
 pa_status pa_assimilate(pa_ctx* ctx, double* omega_inout, int32_t n_steps, const pa_obs* obs,
                         const pa_kernel* kernel, int32_t method, int32_t max_iter,

@@ -121,3 +121,28 @@ def test_lbfgs_sobolev_streamfunction_control_parity():
             assert iters[b] == it_ref, (kern, lam, b)
             assert np.allclose(H[b][: it_ref + 1], h_ref, rtol=ITER_TOL, atol=0), (kern, lam, b)
             assert rel(w[b], w_ref) < ITER_TOL, (kern, lam, b)
+
+
+def test_non_finite_observations_fail_their_member_alone():
+    """A member whose observations hold a NaN stops on its first line search
+    (iteration count -(0 + 1)); the other member of the batch runs exactly as
+    it would alone."""
+    from paper_2602_14016_amd import KernelSpec, Observations, Solver
+    print("CASE poisoned member", flush=True)
+    N, steps = 32, 20
+    osteps = [0, 10, 20]
+    ph, mo = _setup(N, steps, osteps, 4, seeds=(3, 4))
+    mo_bad = mo.copy()
+    mo_bad[1, 1, 0, 2, 3] = np.nan
+    fg = dev(O.init_field(N, [5, 6], kind=0, k0=4.0))
+    k = KernelSpec(1, 0.1, 0)
+    s2 = Solver(N, 2, nu=ph.nu, dt=ph.dt)
+    w, H, iters = s2.assimilate(fg, steps, Observations(4, osteps, dev(mo_bad)), k, "lbfgs", 4, 3, ckpt_every=7)
+    s1 = Solver(N, 1, nu=ph.nu, dt=ph.dt)
+    w1, H1, it1 = s1.assimilate(fg[:1].contiguous(), steps, Observations(4, osteps, dev(mo[:1])), k, "lbfgs", 4, 3,
+                                ckpt_every=7)
+    assert iters[1] < 0
+    assert iters[0] == it1[0] >= 1
+    assert np.array_equal(np.array(H[0]), np.array(H1[0]), equal_nan=True)
+    assert np.array_equal(w.cpu().numpy()[0], w1.cpu().numpy()[0])
+    assert np.all(np.isfinite(w.cpu().numpy()[0]))
