@@ -26,6 +26,7 @@ optim      steepest descent and L-BFGS in the latent variable (Sec. II.C)
 fields     counter-based RNG, initial fields, first guess (Sec. III)
 ensemble   adjoint impulse response, shell energies, growth rates, ensemble statistics (Sec. IV)
 checkpoint fewest recomputations that reverse a chain under a snapshot budget
+stats      turbulence statistics of a field (Table 2 quantities)
 """
 
 from .dft import twiddles, dft_matrix, fft2, ifft2
@@ -36,6 +37,7 @@ from .optim import lbfgs_two_loop, assimilate
 from .fields import splitmix64, uniform01, init_field, first_guess
 from .ensemble import impulse_adjoint, impulse_lambdas, shell_energy, total_energy, growth_rates, ensemble_statistics
 from .checkpoint import min_advances, optimal_first_advances
+from .stats import turbulence_statistics
 
 __all__ = [
     "twiddles", "dft_matrix", "fft2", "ifft2",
@@ -45,5 +47,5 @@ __all__ = [
     "lbfgs_two_loop", "assimilate",
     "splitmix64", "uniform01", "init_field", "first_guess",
     "impulse_adjoint", "impulse_lambdas", "shell_energy", "total_energy", "growth_rates",
-    "ensemble_statistics", "min_advances", "optimal_first_advances",
+    "ensemble_statistics", "min_advances", "optimal_first_advances", "turbulence_statistics",
 ]

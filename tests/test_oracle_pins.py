@@ -635,3 +635,55 @@ def test_checkpoint_cost_is_the_optimum_over_all_strategies():
     for s in range(0, 4):
         for l in range(1, 9):
             assert O.min_advances(l, s) == _exhaustive_min_advances(l, s), (l, s)
+
+
+# ------------------------------------------------- truth-field statistics
+
+def _table2():
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "truth_statistics_table2.txt")
+    rows, re_l = {}, None
+    for line in open(path):
+        if line.startswith("#") or not line.strip():
+            continue
+        f = line.split()
+        if f[0] == "HIT_Re_L":
+            re_l = float(f[1])
+            continue
+        rows[f[0]] = dict(zip(("Re", "u_rms", "lambda", "Re_lambda", "Omega", "eps", "chi", "k_eta"),
+                              map(float, f[1:])))
+    return rows, re_l
+
+
+def test_table2_printed_statistics_obey_their_definitions():
+    # the paper's printed numbers satisfy the caption's definitions to their printed precision,
+    # which fixes the reading of each quantity used by oracle.stats
+    rows, re_l = _table2()
+    for name, r in rows.items():
+        nu = 1.0 / r["Re"]
+        assert r["u_rms"] * r["lambda"] / nu == pytest.approx(r["Re_lambda"], rel=1e-2), name
+        assert 2.0 * nu * r["Omega"] == pytest.approx(r["eps"], rel=1e-2), name       # eps = nu <|grad u|^2> = 2 nu Omega
+        assert abs((r["chi"] / nu ** 3) ** (1.0 / 6.0) - r["k_eta"]) <= 0.5, name   # printed to integers
+        # Taylor microscale of an isotropic field, lambda = u_rms / rms(du/dx) = u_rms sqrt(2 / Omega)
+        assert r["u_rms"] * math.sqrt(2.0 / r["Omega"]) == pytest.approx(r["lambda"], rel=3e-2), name
+    hit = rows["HIT"]
+    assert hit["u_rms"] * 2.0 * math.pi * hit["Re"] == pytest.approx(re_l, rel=1e-2)
+
+
+def test_turbulence_statistics_single_mode_and_identities():
+    from oracle.stats import turbulence_statistics
+    N, k, nu = 32, 3, 2e-3
+    x = 2 * np.pi * np.arange(N) / N
+    w = np.tile(np.cos(k * x), (N, 1))          # omega = cos(k x): v = sin(k x) / k, u = 0
+    st = turbulence_statistics(w, nu)
+    assert st["Omega"] == pytest.approx(0.25, rel=1e-13)
+    assert st["u_rms"] == pytest.approx(1.0 / (2 * k), rel=1e-13)
+    assert st["eps"] == pytest.approx(nu / 2, rel=1e-13)
+    assert st["chi"] == pytest.approx(nu * k * k / 2, rel=1e-13)
+    assert st["k_eta"] == pytest.approx((k * k / (2 * nu * nu)) ** (1.0 / 6.0), rel=1e-13)
+    # on a turbulent field: eps = 2 nu Omega (periodic, divergence-free) and u_rms^2 = the energy
+    w = O.init_field(N, [5], kind=0, k0=4.0, target=0.5)[0]
+    st = turbulence_statistics(w, nu)
+    assert st["eps"] == pytest.approx(2 * nu * st["Omega"], rel=1e-12)
+    assert st["u_rms"] ** 2 == pytest.approx(0.5, rel=1e-12)
+    assert st["Re_lambda"] == pytest.approx(st["u_rms"] * st["lambda"] / nu, rel=1e-14)
