@@ -1,0 +1,59 @@
+"""Writes the oracle's expected values for the full-horizon GPU parity tests.
+
+Run from the repository root:  python tests/golden/make_oracle_fixtures.py
+
+It calls only the CPU oracle (oracle/) and NumPy; every input is generated
+here from the oracle's seeded initial fields.  The GPU tests load the files
+(numpy.load, no pickles) instead of spending minutes of CPU on the oracle:
+
+  c1_full_horizon.npz   c1 at its full horizon: 256^2, nu = 1e-4, dt = 2e-3,
+                        1000 steps, velocity probes at stride 8 at 5 evenly
+                        spaced times from the truth of seed 0 (random phase,
+                        k0 = 10, energy 0.5), initial field of seed 1:
+                        observations, cost and gradient.
+  ensemble_member17.npz the ensemble workload's member 17 (256^2, nu = 1e-4,
+                        dt = 2e-3, seed 17, k0 = 10, energy 0.5): shell
+                        energies |k| = 1..85 of the adjoint of a unit
+                        u-impulse at (128, 128) after 500 steps, per backward
+                        step.
+"""
+
+import os
+import sys
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+import oracle as O  # noqa: E402
+from oracle.model import Obs, Physics  # noqa: E402
+
+
+def evenly_spaced(n_steps, n):
+    return sorted({int(round(i * n_steps / (n - 1))) for i in range(n)})
+
+
+def c1_full_horizon():
+    N, H = 256, 1000
+    ph = Physics(N=N, nu=1e-4, dt=2e-3)
+    osteps = evenly_spaced(H, 5)
+    truth = O.init_field(N, [0], kind=0, k0=10.0, target=0.5)[0]
+    _, _, mo = O.forward(truth, ph, H, Obs(8, osteps))
+    w0 = O.init_field(N, [1], kind=0, k0=10.0, target=0.5)[0]
+    J, g = O.adjoint_gradient(w0, ph, H, Obs(8, osteps, mo))
+    np.savez(os.path.join(HERE, "c1_full_horizon.npz"), obs_steps=np.array(osteps), obs=np.asarray(mo),
+             J=np.array(J), grad=g)
+
+
+def ensemble_member17():
+    N, H = 256, 500
+    ph = Physics(N=N, nu=1e-4, dt=2e-3)
+    w0 = O.init_field(N, [17], kind=0, k0=10.0, target=0.5)[0]
+    rows = O.impulse_adjoint(w0, ph, H, N // 2, N // 2, 85)[0]
+    np.savez(os.path.join(HERE, "ensemble_member17.npz"), shells=np.asarray(rows))
+
+
+if __name__ == "__main__":
+    c1_full_horizon()
+    ensemble_member17()

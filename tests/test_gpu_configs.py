@@ -61,20 +61,24 @@ def test_c1_shortened_horizon_gradient_parity():
     assert rel(g.cpu().numpy()[0], g_ref) < 1e-9
 
 
+def _golden(name):
+    import os
+    return np.load(os.path.join(os.path.dirname(__file__), "golden", name))
+
+
 def test_c1_full_horizon_gradient_against_oracle():
     """c1 at its full horizon (256^2, nu = 1e-4, 1000 steps at dt = 2e-3, 5
     observation times at stride 8, checkpoints every 50): cost and gradient
-    against the oracle (about two minutes of CPU for the oracle)."""
+    against the oracle's, written by tests/golden/make_oracle_fixtures.py."""
     from paper_2602_14016_amd import Observations, Solver
-    print("CASE c1-1000 oracle truth", flush=True)
+    print("CASE c1-1000", flush=True)
     N, H = 256, 1000
     ph = Physics(N=N, nu=1e-4, dt=2e-3)
     osteps = synth.evenly_spaced_steps(H, 5)
-    truth = O.init_field(N, [0], kind=0, k0=10.0)[0]
-    _, _, mo = O.forward(truth, ph, H, Obs(8, osteps))
-    w0 = O.init_field(N, [1], kind=0, k0=10.0)[0]
-    print("CASE c1-1000 oracle gradient", flush=True)
-    J_ref, g_ref = O.adjoint_gradient(w0, ph, H, Obs(8, osteps, mo))
+    ref = _golden("c1_full_horizon.npz")
+    assert list(ref["obs_steps"]) == list(osteps)
+    mo, J_ref, g_ref = ref["obs"], float(ref["J"]), ref["grad"]
+    w0 = O.init_field(N, [1], kind=0, k0=10.0, target=0.5)[0]
     s = Solver(N, 1, nu=ph.nu, dt=ph.dt)
     J, g = s.adjoint_gradient(dev(w0[None]), H, Observations(8, osteps, dev(mo[None])), ckpt_every=50)
     torch.cuda.synchronize()
@@ -231,9 +235,10 @@ def test_ensemble_workload_in_its_launch_configuration():
     for b in (0, 63):
         ref = O.impulse_adjoint(w0np[b], ph, 10, N // 2, N // 2, nsh)[0]
         assert rel(short[b], ref) < 1e-9
-    # one sampled member over the whole 500 + 500-step horizon against the oracle (about a minute of CPU)
+    # one sampled member over the whole 500 + 500-step horizon against the oracle's shells,
+    # written by tests/golden/make_oracle_fixtures.py from the same seed
     print("CASE ensemble-workload oracle full horizon, member 17", flush=True)
-    ref = O.impulse_adjoint(w0np[17], ph, H, N // 2, N // 2, nsh)[0]
+    ref = _golden("ensemble_member17.npz")["shells"]
     err = rel(shells[17], ref)
     print("CASE ensemble-workload member 17 rel", err, flush=True)
     assert err < 1e-9

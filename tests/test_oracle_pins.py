@@ -687,3 +687,25 @@ def test_turbulence_statistics_single_mode_and_identities():
     assert st["eps"] == pytest.approx(2 * nu * st["Omega"], rel=1e-12)
     assert st["u_rms"] ** 2 == pytest.approx(0.5, rel=1e-12)
     assert st["Re_lambda"] == pytest.approx(st["u_rms"] * st["lambda"] / nu, rel=1e-14)
+
+
+def test_stored_oracle_fixtures_are_intact():
+    # the full-horizon expectations written by tests/golden/make_oracle_fixtures.py: shapes, and the parts
+    # that are cheap to recompute (the step-0 observations of the c1 truth; the terminal impulse row)
+    import os
+    gold = os.path.join(os.path.dirname(__file__), "golden")
+    c1 = np.load(os.path.join(gold, "c1_full_horizon.npz"))
+    assert c1["obs"].shape == (5, 2, 32, 32) and c1["grad"].shape == (256, 256)
+    assert list(c1["obs_steps"]) == [0, 250, 500, 750, 1000]
+    assert np.all(np.isfinite(c1["grad"])) and float(c1["J"]) > 0
+    truth = O.init_field(256, [0], kind=0, k0=10.0, target=0.5)[0]
+    ph = Physics(N=256, nu=1e-4, dt=2e-3)
+    obs0 = O.forward(truth, ph, 0, Obs(8, [0]))[2][0]
+    assert np.allclose(c1["obs"][0], obs0, rtol=0, atol=1e-13 * np.abs(obs0).max())
+    sh = np.load(os.path.join(gold, "ensemble_member17.npz"))["shells"]
+    assert sh.shape == (501, 85) and np.all(np.isfinite(sh))
+    g = model.grid(256)
+    e = np.zeros((256, 256))
+    e[128, 128] = 1.0
+    row0 = ensemble.shell_energy(g, np.conj(g.m_u) * dft.fft2(e), 85)
+    assert np.allclose(sh[0], row0, rtol=1e-13, atol=0)
