@@ -86,19 +86,23 @@ def statistics(N=256, members=3000, batch=64, n_steps=500, nu=1e-4, dt=2e-3, k0=
     main = solver_for(min(batch, members))
     acc = main.ensemble_accumulator(n_steps, n_shells)
     K = ckpt_every or main.fit_ckpt_every(n_steps)
+    # One workspace, sized for the largest batch, serves every batch size in turn (batches run one
+    # at a time): a whole-horizon tape fills most of the device, and reallocating it whenever the
+    # batch size changes at a subset boundary would cost more than the solves.
+    shared = main._ws if main._ws is not None and main._ws.numel() >= main.workspace_bytes(n_steps, K) + 256 \
+        else None
+    if shared is None:
+        main._ws = None
+        torch.cuda.empty_cache()
+        shared = torch.empty(main.workspace_bytes(n_steps, K) + 256, dtype=torch.uint8, device=main.device)
     snaps = {}
     done = 0
     t0 = time.perf_counter()
-    current = main
     for end in bounds:
         while done < end:
             b = min(batch, end - done)
             sv = solver_for(b)
-            if sv is not current:
-                # one workspace at a time: a whole-horizon tape can fill most of the device
-                current._ws = None
-                torch.cuda.empty_cache()
-                current = sv
+            sv._ws = shared
             w0 = sv.init_field(list(range(seed0 + done, seed0 + done + b)), kind=init_kind, k0=k0, target=init_target)
             if spinup:
                 w0 = sv.forward(w0, spinup)["omega_T"]
