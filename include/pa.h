@@ -112,8 +112,12 @@ typedef struct pa_kernel {
     double  param;
 } pa_kernel;
 
+/* Largest batch of one context: members index the second launch-grid
+ * dimension, which holds at most 65535 workgroups. */
+#define PA_MAX_MEMBERS 65535
+
 /* Create a context for B fields of size N x N (N a power of two in
- * [8, 1024], B >= 1) with the given physics, enqueueing on hip_stream
+ * [8, 1024], 1 <= B <= PA_MAX_MEMBERS) with the given physics, enqueueing on hip_stream
  * (hipStream_t, NULL = default stream).  Allocates small constant tables on
  * the current device.  Errors: PA_EINVAL (bad sizes/parameters, NULL out),
  * PA_EDEVICE (no device / HIP failure), PA_ENOMEM. */
@@ -326,6 +330,10 @@ pa_status pa_set_tiles(pa_ctx* ctx, const pa_tiles* tiles);
  * a negative or non-finite lambda. */
 pa_status pa_set_sobolev(pa_ctx* ctx, double lambda);
 
+/* Most segments a binomial schedule covers: the schedule is a host list of
+ * at most about two actions per segment. */
+#define PA_MAX_SCHEDULE_SEGMENTS (1 << 22)
+
 /* Snapshot budget of the checkpoints kept inside the workspace by
  * pa_adjoint_gradient, pa_adjoint_impulse and pa_assimilate* (the adjoint's
  * recomputation, Sec. I and Sec. II.A).  The horizon splits into L =
@@ -339,7 +347,8 @@ pa_status pa_set_sobolev(pa_ctx* ctx, double lambda);
  * segments for that budget (pa_checkpoint_advances).  Results are the same
  * either way, bit for bit: only the schedule changes.  pa_forward and
  * pa_adjoint_from_checkpoints keep the caller's one-per-boundary layout.
- * PA_EINVAL for slots < 0. */
+ * PA_EINVAL for slots < 0, and from a solve whose binomial schedule would
+ * cover more than PA_MAX_SCHEDULE_SEGMENTS segments. */
 pa_status pa_set_checkpoint_slots(pa_ctx* ctx, int32_t slots);
 
 /* Current snapshot budget of the context. */
@@ -364,7 +373,8 @@ pa_status pa_checkpoint_advances(int32_t n_segments, int32_t slots, int64_t* adv
  *           steps through it.
  * Slot 0 holds boundary 0 throughout.  The actions before the first reverse
  * form the forward sweep.  PA_EINVAL if capacity < *n_actions (n_actions is
- * still set) or for sizes as in pa_checkpoint_advances. */
+ * still set), for sizes as in pa_checkpoint_advances, or for n_segments >
+ * PA_MAX_SCHEDULE_SEGMENTS. */
 pa_status pa_checkpoint_schedule(int32_t n_segments, int32_t slots, int32_t* actions, int64_t capacity,
                                  int64_t* n_actions);
 

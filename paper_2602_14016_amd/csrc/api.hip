@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstring>
 #include <initializer_list>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -26,6 +27,19 @@ pa_status fail(pa_status code, const std::string& msg) {
     g_err = msg;
     return code;
 }
+
+// A failed host allocation (a schedule, a table, the context itself) becomes
+// PA_ENOMEM: every entry point is a function-try-block closed by this, so no
+// C++ exception unwinds through the C ABI.
+pa_status fail_host_alloc() noexcept {
+    try {
+        g_err = "host memory allocation failed";
+    } catch (...) {
+    }
+    return PA_ENOMEM;
+}
+#define PA_CATCH_HOST \
+    catch (...) { return fail_host_alloc(); }
 
 #define PA_HIP(expr)                                                                         \
     do {                                                                                     \
@@ -159,7 +173,7 @@ struct Carver {
 };
 
 int seg_len(int n_steps, int ckpt_every) { return std::max(1, std::min(ckpt_every, std::max(n_steps, 1))); }
-int n_segments(int n_steps, int K) { return n_steps <= 0 ? 0 : (n_steps + K - 1) / K; }
+int n_segments(int n_steps, int K) { return n_steps <= 0 ? 0 : (int)(((int64_t)n_steps + K - 1) / K); }
 
 // The internal checkpoints follow a binomial schedule when the snapshot
 // budget is set and smaller than one slot per boundary.
@@ -364,9 +378,15 @@ pa_status make_obs_plan(const pa_ctx* c, const pa_obs* obs, int n_steps, bool ne
     return PA_OK;
 }
 
-pa_status check_ws(const pa_ctx* c, void* ws, size_t bytes, int n_steps, int K, int n_obs, int m, WS* out) {
+// `scheduled`: the solve reverses its segments by the context's schedule
+// (plan_for), whose size is checked here, before anything is enqueued
+pa_status check_ws(const pa_ctx* c, void* ws, size_t bytes, int n_steps, int K, int n_obs, int m, WS* out,
+                   bool scheduled = false) {
     if (!ws) return fail(PA_EINVAL, "workspace is NULL");
     if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(PA_EINVAL, "workspace must be 256-byte aligned");
+    if (scheduled && plan_mode(c, n_segments(n_steps, K)) && n_segments(n_steps, K) > PA_MAX_SCHEDULE_SEGMENTS)
+        return fail(PA_EINVAL, "binomial schedule over more than PA_MAX_SCHEDULE_SEGMENTS segments: "
+                               "raise ckpt_every");
     WS w = carve(c, n_steps, K, n_obs, m, ws);
     if (w.total > bytes)
         return fail(PA_ENOMEM, "workspace too small: need " + std::to_string(w.total) + " bytes");
@@ -877,13 +897,14 @@ extern "C" {
 
 const char* pa_last_error(void) { return g_err.c_str(); }
 
-pa_status pa_create(const pa_physics* phys, int32_t N, int32_t B, void* hip_stream, pa_ctx** out) {
+pa_status pa_create(const pa_physics* phys, int32_t N, int32_t B, void* hip_stream, pa_ctx** out) try {
     g_err.clear();
     if (!out) return fail(PA_EINVAL, "out is NULL");
     *out = nullptr;
     if (!phys) return fail(PA_EINVAL, "physics is NULL");
     if (!is_pow2(N) || N < 8 || N > 1024) return fail(PA_EINVAL, "N must be a power of two in [8, 1024]");
-    if (B < 1) return fail(PA_EINVAL, "B must be >= 1");
+    // members run along the second grid dimension of the column and batched kernels
+    if (B < 1 || B > PA_MAX_MEMBERS) return fail(PA_EINVAL, "B must be in [1, 65535]");
     if (!finite_nonneg(phys->nu) || !finite_nonneg(phys->mu)) return fail(PA_EINVAL, "nu, mu must be finite, >= 0");
     if (!std::isfinite(phys->dt) || phys->dt <= 0) return fail(PA_EINVAL, "dt must be finite and > 0");
     if (!std::isfinite(phys->forcing_amp)) return fail(PA_EINVAL, "forcing amplitude must be finite");
@@ -895,7 +916,10 @@ pa_status pa_create(const pa_physics* phys, int32_t N, int32_t B, void* hip_stre
 
     int dev = 0;
     PA_HIP(hipGetDevice(&dev));
-    pa_ctx* c = new pa_ctx();
+    // owned until it is handed out: every early return (or a failed host
+    // allocation below) frees it and whatever device tables it already holds
+    std::unique_ptr<pa_ctx, pa_status (*)(pa_ctx*)> owner(new pa_ctx(), pa_destroy);
+    pa_ctx* c = owner.get();
     c->ph = *phys;
     c->stream = reinterpret_cast<hipStream_t>(hip_stream);
     c->device = dev;
@@ -954,14 +978,13 @@ pa_status pa_create(const pa_physics* phys, int32_t N, int32_t B, void* hip_stre
     c->nf = (phys->forcing_amp != 0.0 && phys->forcing_k <= d.K) ? phys->forcing_k : 0;
     c->forcing = -phys->forcing_amp * phys->forcing_k * 0.5 * (double)N * (double)N;
 
-    auto cleanup = [&](pa_status s) { pa_destroy(c); return s; };
-    if (hipMalloc(&c->tw, sizeof(cd) * N) != hipSuccess) return cleanup(fail(PA_ENOMEM, "hipMalloc tables"));
-    if (hipMalloc(&c->invk2, sizeof(double) * invk2.size()) != hipSuccess) return cleanup(fail(PA_ENOMEM, "hipMalloc tables"));
-    if (hipMalloc(&c->ex2, sizeof(double) * ex2.size()) != hipSuccess) return cleanup(fail(PA_ENOMEM, "hipMalloc tables"));
-    if (hipMalloc(&c->ey2, sizeof(double) * ey2.size()) != hipSuccess) return cleanup(fail(PA_ENOMEM, "hipMalloc tables"));
-    if (hipMalloc(&c->shell_start, sizeof(int) * start.size()) != hipSuccess) return cleanup(fail(PA_ENOMEM, "hipMalloc tables"));
+    if (hipMalloc(&c->tw, sizeof(cd) * N) != hipSuccess) return fail(PA_ENOMEM, "hipMalloc tables");
+    if (hipMalloc(&c->invk2, sizeof(double) * invk2.size()) != hipSuccess) return fail(PA_ENOMEM, "hipMalloc tables");
+    if (hipMalloc(&c->ex2, sizeof(double) * ex2.size()) != hipSuccess) return fail(PA_ENOMEM, "hipMalloc tables");
+    if (hipMalloc(&c->ey2, sizeof(double) * ey2.size()) != hipSuccess) return fail(PA_ENOMEM, "hipMalloc tables");
+    if (hipMalloc(&c->shell_start, sizeof(int) * start.size()) != hipSuccess) return fail(PA_ENOMEM, "hipMalloc tables");
     if (hipMalloc(&c->shell_modes, sizeof(int) * std::max<size_t>(modes.size(), 1)) != hipSuccess)
-        return cleanup(fail(PA_ENOMEM, "hipMalloc tables"));
+        return fail(PA_ENOMEM, "hipMalloc tables");
     bool ok = hipMemcpy(c->tw, tw.data(), sizeof(cd) * N, hipMemcpyHostToDevice) == hipSuccess &&
               hipMemcpy(c->invk2, invk2.data(), sizeof(double) * invk2.size(), hipMemcpyHostToDevice) == hipSuccess &&
               hipMemcpy(c->ex2, ex2.data(), sizeof(double) * ex2.size(), hipMemcpyHostToDevice) == hipSuccess &&
@@ -969,12 +992,12 @@ pa_status pa_create(const pa_physics* phys, int32_t N, int32_t B, void* hip_stre
               hipMemcpy(c->shell_start, start.data(), sizeof(int) * start.size(), hipMemcpyHostToDevice) == hipSuccess &&
               (modes.empty() || hipMemcpy(c->shell_modes, modes.data(), sizeof(int) * modes.size(),
                                           hipMemcpyHostToDevice) == hipSuccess);
-    if (!ok) return cleanup(fail(PA_EDEVICE, "copying constant tables failed"));
-    *out = c;
+    if (!ok) return fail(PA_EDEVICE, "copying constant tables failed");
+    *out = owner.release();
     return PA_OK;
-}
+} PA_CATCH_HOST
 
-pa_status pa_destroy(pa_ctx* c) {
+pa_status pa_destroy(pa_ctx* c) try {
     if (!c) return PA_OK;
     (void)hipStreamSynchronize(c->stream);
     for (hipEvent_t e : c->prof_ev) (void)hipEventDestroy(e);
@@ -986,23 +1009,23 @@ pa_status pa_destroy(pa_ctx* c) {
     (void)hipFree(c->shell_modes);
     delete c;
     return PA_OK;
-}
+} PA_CATCH_HOST
 
-pa_status pa_set_stream(pa_ctx* c, void* s) {
+pa_status pa_set_stream(pa_ctx* c, void* s) try {
     if (!c) return fail(PA_EINVAL, "ctx is NULL");
     c->stream = reinterpret_cast<hipStream_t>(s);
     return PA_OK;
-}
+} PA_CATCH_HOST
 
-pa_status pa_get_shape(const pa_ctx* c, int32_t* N, int32_t* B, int32_t* Kc) {
+pa_status pa_get_shape(const pa_ctx* c, int32_t* N, int32_t* B, int32_t* Kc) try {
     if (!c) return fail(PA_EINVAL, "ctx is NULL");
     if (N) *N = c->d.N;
     if (B) *B = c->d.B;
     if (Kc) *Kc = c->d.K;
     return PA_OK;
-}
+} PA_CATCH_HOST
 
-pa_status pa_set_tiles(pa_ctx* c, const pa_tiles* t) {
+pa_status pa_set_tiles(pa_ctx* c, const pa_tiles* t) try {
     if (!c || !t) return fail(PA_EINVAL, "NULL argument");
     auto variant_ok = [](int v) { return v < 0 || v <= 2; };
     auto row_variant_ok = [](int v) { return v < 0 || v <= 3; };
@@ -1029,39 +1052,41 @@ pa_status pa_set_tiles(pa_ctx* c, const pa_tiles* t) {
     }
     c->d = d;
     return PA_OK;
-}
+} PA_CATCH_HOST
 
-pa_status pa_set_sobolev(pa_ctx* c, double lambda) {
+pa_status pa_set_sobolev(pa_ctx* c, double lambda) try {
     if (!c) return fail(PA_EINVAL, "ctx is NULL");
     if (!std::isfinite(lambda) || lambda < 0.0) return fail(PA_EINVAL, "lambda must be finite and >= 0");
     c->sobolev = lambda;
     return PA_OK;
-}
+} PA_CATCH_HOST
 
-pa_status pa_set_checkpoint_slots(pa_ctx* c, int32_t slots) {
+pa_status pa_set_checkpoint_slots(pa_ctx* c, int32_t slots) try {
     if (!c) return fail(PA_EINVAL, "ctx is NULL");
     if (slots < 0) return fail(PA_EINVAL, "slots must be >= 0");
     c->ckpt_slots = slots;
     return PA_OK;
-}
+} PA_CATCH_HOST
 
-pa_status pa_get_checkpoint_slots(const pa_ctx* c, int32_t* slots) {
+pa_status pa_get_checkpoint_slots(const pa_ctx* c, int32_t* slots) try {
     if (!c || !slots) return fail(PA_EINVAL, "NULL argument");
     *slots = c->ckpt_slots;
     return PA_OK;
-}
+} PA_CATCH_HOST
 
-pa_status pa_checkpoint_advances(int32_t n_segments, int32_t slots, int64_t* advances) {
+pa_status pa_checkpoint_advances(int32_t n_segments, int32_t slots, int64_t* advances) try {
     if (!advances) return fail(PA_EINVAL, "NULL argument");
     if (n_segments < 1 || slots < 1) return fail(PA_EINVAL, "need n_segments >= 1 and slots >= 1");
     *advances = min_segment_advances(n_segments, slots - 1);
     return PA_OK;
-}
+} PA_CATCH_HOST
 
 pa_status pa_checkpoint_schedule(int32_t n_segments, int32_t slots, int32_t* actions, int64_t capacity,
-                                 int64_t* n_actions) {
+                                 int64_t* n_actions) try {
     if (!n_actions) return fail(PA_EINVAL, "n_actions is NULL");
     if (n_segments < 1 || slots < 1) return fail(PA_EINVAL, "need n_segments >= 1 and slots >= 1");
+    if (n_segments > PA_MAX_SCHEDULE_SEGMENTS)
+        return fail(PA_EINVAL, "n_segments exceeds PA_MAX_SCHEDULE_SEGMENTS");
     std::vector<PlanAct> plan;
     build_plan(n_segments, std::min(slots, n_segments), plan);
     *n_actions = (int64_t)plan.size();
@@ -1077,17 +1102,17 @@ pa_status pa_checkpoint_schedule(int32_t n_segments, int32_t slots, int32_t* act
         o[4] = a.dst;
     }
     return PA_OK;
-}
+} PA_CATCH_HOST
 
-pa_status pa_is_device_memory(const void* ptr, int32_t* is_device) {
+pa_status pa_is_device_memory(const void* ptr, int32_t* is_device) try {
     if (!is_device) return fail(PA_EINVAL, "NULL argument");
     const pa_status st = require_device(nullptr, {{ptr, "pointer"}});
     *is_device = (ptr && st == PA_OK) ? 1 : 0;
     g_err.clear();
     return PA_OK;
-}
+} PA_CATCH_HOST
 
-pa_status pa_get_tiles(const pa_ctx* c, pa_tiles* t) {
+pa_status pa_get_tiles(const pa_ctx* c, pa_tiles* t) try {
     if (!c || !t) return fail(PA_EINVAL, "NULL argument");
     t->row_variant = c->d.var;
     t->row_teams = c->d.tpb;
@@ -1096,9 +1121,9 @@ pa_status pa_get_tiles(const pa_ctx* c, pa_tiles* t) {
     t->col_variant = c->d.cvar;
     t->col_block = c->d.cb;
     return PA_OK;
-}
+} PA_CATCH_HOST
 
-pa_status pa_profile_start(pa_ctx* c, int32_t kernel_class, int32_t sample_every) {
+pa_status pa_profile_start(pa_ctx* c, int32_t kernel_class, int32_t sample_every) try {
     if (!c) return fail(PA_EINVAL, "ctx is NULL");
     if (kernel_class < 0 || kernel_class > 3) return fail(PA_EINVAL, "kernel_class must be 0..3");
     if (sample_every < 1) return fail(PA_EINVAL, "sample_every must be >= 1");
@@ -1107,9 +1132,9 @@ pa_status pa_profile_start(pa_ctx* c, int32_t kernel_class, int32_t sample_every
     c->prof_seen = 0;
     c->prof_used = 0;
     return PA_OK;
-}
+} PA_CATCH_HOST
 
-pa_status pa_profile_stop(pa_ctx* c, int64_t* timed_launches, int64_t* seen_launches, double* total_ms) {
+pa_status pa_profile_stop(pa_ctx* c, int64_t* timed_launches, int64_t* seen_launches, double* total_ms) try {
     if (!c) return fail(PA_EINVAL, "ctx is NULL");
     PA_HIP(hipStreamSynchronize(c->stream));
     double tot = 0.0;
@@ -1125,25 +1150,25 @@ pa_status pa_profile_stop(pa_ctx* c, int64_t* timed_launches, int64_t* seen_laun
     c->prof_used = 0;
     c->prof_seen = 0;
     return PA_OK;
-}
+} PA_CATCH_HOST
 
 pa_status pa_workspace_bytes(const pa_ctx* c, int32_t n_steps, int32_t ckpt_every, int32_t n_obs_times,
-                             int32_t lbfgs_m, size_t* bytes) {
+                             int32_t lbfgs_m, size_t* bytes) try {
     if (!c || !bytes) return fail(PA_EINVAL, "NULL argument");
     if (n_steps < 0 || ckpt_every < 1 || n_obs_times < 0 || lbfgs_m < 0) return fail(PA_EINVAL, "bad sizes");
     *bytes = carve(c, n_steps, ckpt_every, n_obs_times, lbfgs_m, nullptr).total;
     return PA_OK;
-}
+} PA_CATCH_HOST
 
-pa_status pa_checkpoint_bytes(const pa_ctx* c, int32_t n_steps, int32_t ckpt_every, size_t* bytes) {
+pa_status pa_checkpoint_bytes(const pa_ctx* c, int32_t n_steps, int32_t ckpt_every, size_t* bytes) try {
     if (!c || !bytes) return fail(PA_EINVAL, "NULL argument");
     if (n_steps < 0 || ckpt_every < 1) return fail(PA_EINVAL, "bad sizes");
     *bytes = ckpt_bytes(c, n_steps, ckpt_every);
     return PA_OK;
-}
+} PA_CATCH_HOST
 
 pa_status pa_init_field(pa_ctx* c, const uint64_t* seeds, int32_t kind, double k0, double target,
-                        double* omega_out, void* workspace, size_t wbytes) {
+                        double* omega_out, void* workspace, size_t wbytes) try {
     g_err.clear();
     if (!c || !seeds || !omega_out) return fail(PA_EINVAL, "NULL argument");
     if (kind < 0 || kind > 2) return fail(PA_EINVAL, "kind must be 0, 1 or 2");
@@ -1158,11 +1183,11 @@ pa_status pa_init_field(pa_ctx* c, const uint64_t* seeds, int32_t kind, double k
     PA_HIP(launch_state_norm(c->d, w.omega, kind, w.norm, c->stream));
     PA_HIP(launch_state_scale(c->d, w.omega, kind, target, w.norm, c->stream));
     return state_to_phys(c, w, w.omega, omega_out);
-}
+} PA_CATCH_HOST
 
 pa_status pa_forward(pa_ctx* c, const double* omega0, int32_t n_steps, const pa_obs* obs, double* J_out,
                      double* obs_out, double* omega_T, int32_t ckpt_every, void* ckpt, void* workspace,
-                     size_t wbytes) {
+                     size_t wbytes) try {
     g_err.clear();
     if (!c || !omega0) return fail(PA_EINVAL, "NULL argument");
     if (n_steps < 0) return fail(PA_EINVAL, "n_steps must be >= 0");
@@ -1184,11 +1209,11 @@ pa_status pa_forward(pa_ctx* c, const double* omega0, int32_t n_steps, const pa_
     }
     if (omega_T) PA_TRY(state_to_phys(c, w, w.omega, omega_T));
     return PA_OK;
-}
+} PA_CATCH_HOST
 
 pa_status pa_adjoint_from_checkpoints(pa_ctx* c, const void* ckpt, int32_t n_steps, const pa_obs* obs,
                                       const double* scale, double* grad_out, int32_t ckpt_every, void* workspace,
-                                      size_t wbytes) {
+                                      size_t wbytes) try {
     g_err.clear();
     if (!c || !ckpt || !grad_out) return fail(PA_EINVAL, "NULL argument");
     if (reinterpret_cast<uintptr_t>(ckpt) % 16) return fail(PA_EINVAL, "checkpoint buffer must be 16-byte aligned");
@@ -1202,10 +1227,10 @@ pa_status pa_adjoint_from_checkpoints(pa_ctx* c, const void* ckpt, int32_t n_ste
     const int K = seg_len(n_steps, ckpt_every);
     return backward_sweep(c, w, reinterpret_cast<const cd*>(ckpt), n_steps, K, &op, 0, -1, -1, scale, grad_out,
                           Shells(), false);
-}
+} PA_CATCH_HOST
 
 pa_status pa_adjoint_gradient(pa_ctx* c, const double* omega0, int32_t n_steps, const pa_obs* obs, double* J_out,
-                              double* grad_out, int32_t ckpt_every, void* workspace, size_t wbytes) {
+                              double* grad_out, int32_t ckpt_every, void* workspace, size_t wbytes) try {
     g_err.clear();
     if (!c || !omega0 || !grad_out) return fail(PA_EINVAL, "NULL argument");
     if (n_steps < 0 || ckpt_every < 1) return fail(PA_EINVAL, "bad sizes");
@@ -1214,7 +1239,7 @@ pa_status pa_adjoint_gradient(pa_ctx* c, const double* omega0, int32_t n_steps, 
     ObsPlan op;
     PA_TRY(make_obs_plan(c, obs, n_steps, true, &op));
     WS w;
-    PA_TRY(check_ws(c, workspace, wbytes, n_steps, ckpt_every, op.n_times, 0, &w));
+    PA_TRY(check_ws(c, workspace, wbytes, n_steps, ckpt_every, op.n_times, 0, &w, true));
     const int K = seg_len(n_steps, ckpt_every);
     const std::vector<PlanAct>* plan = plan_for(c, n_segments(n_steps, K));
     PA_TRY(forward_sweep(c, w, omega0, n_steps, op, nullptr, w.ckpt, K, true, plan));
@@ -1223,10 +1248,10 @@ pa_status pa_adjoint_gradient(pa_ctx* c, const double* omega0, int32_t n_steps, 
         else PA_HIP(launch_fill(J_out, 0.0, c->d.B, c->stream));
     }
     return backward_sweep(c, w, w.ckpt, n_steps, K, &op, 0, -1, -1, nullptr, grad_out, Shells(), true, plan);
-}
+} PA_CATCH_HOST
 
 pa_status pa_ensemble_acc_bytes(const pa_ctx* c, int32_t n_steps, int32_t n_shells, size_t* lambda_bytes,
-                                size_t* energy_bytes, size_t* shell_bytes) {
+                                size_t* energy_bytes, size_t* shell_bytes) try {
     if (!c || !lambda_bytes || !energy_bytes || !shell_bytes) return fail(PA_EINVAL, "NULL argument");
     if (n_steps < 0 || n_shells < 1) return fail(PA_EINVAL, "bad sizes");
     const size_t rows = (size_t)n_steps + 1;
@@ -1234,11 +1259,11 @@ pa_status pa_ensemble_acc_bytes(const pa_ctx* c, int32_t n_steps, int32_t n_shel
     *energy_bytes = rows * sizeof(double);
     *shell_bytes = rows * n_shells * sizeof(double);
     return PA_OK;
-}
+} PA_CATCH_HOST
 
 pa_status pa_adjoint_impulse(pa_ctx* c, const double* omega0, int32_t n_steps, int32_t ix, int32_t iy,
                              int32_t n_shells, double* shells_out, double* field_out, pa_ensemble_acc* acc,
-                             int32_t ckpt_every, void* workspace, size_t wbytes) {
+                             int32_t ckpt_every, void* workspace, size_t wbytes) try {
     g_err.clear();
     if (!c || !omega0 || !shells_out) return fail(PA_EINVAL, "NULL argument");
     if (n_steps < 0 || ckpt_every < 1) return fail(PA_EINVAL, "bad sizes");
@@ -1253,7 +1278,7 @@ pa_status pa_adjoint_impulse(pa_ctx* c, const double* omega0, int32_t n_steps, i
                            {workspace, "workspace"}, {acc ? acc->lambda_sum : nullptr, "lambda_sum"},
                            {acc ? acc->energy_sum : nullptr, "energy_sum"}, {acc ? acc->shell_sum : nullptr, "shell_sum"}}));
     WS w;
-    PA_TRY(check_ws(c, workspace, wbytes, n_steps, ckpt_every, 0, 0, &w));
+    PA_TRY(check_ws(c, workspace, wbytes, n_steps, ckpt_every, 0, 0, &w, true));
     const int K = seg_len(n_steps, ckpt_every);
     ObsPlan none;
     none.slot_of.assign((size_t)n_steps + 1, -1);
@@ -1267,11 +1292,11 @@ pa_status pa_adjoint_impulse(pa_ctx* c, const double* omega0, int32_t n_steps, i
     PA_TRY(backward_sweep(c, w, w.ckpt, n_steps, K, nullptr, 1, ix, iy, nullptr, field_out, sh, true, plan));
     if (acc) acc->count += c->d.B;
     return PA_OK;
-}
+} PA_CATCH_HOST
 
 pa_status pa_ensemble_stats(pa_ctx* c, const pa_ensemble_acc* acc, int32_t rows, int32_t n_shells,
                             double* mean_energy, double* energy_of_mean, double* total_mean, double* total_of_mean,
-                            double* snr) {
+                            double* snr) try {
     g_err.clear();
     if (!c || !acc || !acc->lambda_sum || !acc->energy_sum || !acc->shell_sum || !mean_energy || !energy_of_mean ||
         !total_mean || !total_of_mean || !snr)
@@ -1286,10 +1311,10 @@ pa_status pa_ensemble_stats(pa_ctx* c, const pa_ensemble_acc* acc, int32_t rows,
                             acc->shell_sum, acc->energy_sum, c->shell_start, c->shell_modes, mean_energy,
                             energy_of_mean, total_mean, total_of_mean, snr, c->stream));
     return PA_OK;
-}
+} PA_CATCH_HOST
 
 pa_status pa_first_guess(pa_ctx* c, int32_t stride, const double* probes, double* omega_out, void* workspace,
-                         size_t wbytes) {
+                         size_t wbytes) try {
     g_err.clear();
     if (!c || !probes || !omega_out) return fail(PA_EINVAL, "NULL argument");
     if (stride < 1 || stride > c->d.N || c->d.N % stride) return fail(PA_EINVAL, "stride must divide N");
@@ -1312,10 +1337,10 @@ pa_status pa_first_guess(pa_ctx* c, int32_t stride, const double* probes, double
     PA_HIP(launch_col(c->d, COL_FIRST_GUESS, a, c->stream));
     PA_HIP(launch_row_c2r(c->d, w.Y0, omega_out, c->tw, c->stream));
     return PA_OK;
-}
+} PA_CATCH_HOST
 
 pa_status pa_shell_growth(pa_ctx* c, const double* shells, int32_t rows, int32_t n_shells, double tau_min,
-                          double tau_max, double* mean_out, double* rate_out) {
+                          double tau_max, double* mean_out, double* rate_out) try {
     g_err.clear();
     if (!c || !shells || !rate_out) return fail(PA_EINVAL, "NULL argument");
     if (rows < 1 || n_shells < 1) return fail(PA_EINVAL, "bad sizes");
@@ -1325,10 +1350,10 @@ pa_status pa_shell_growth(pa_ctx* c, const double* shells, int32_t rows, int32_t
     PA_HIP(launch_shell_growth(c->d.B, rows, n_shells, shells, c->ph.dt, tau_min, tau_max, mean_out, rate_out,
                                c->stream));
     return PA_OK;
-}
+} PA_CATCH_HOST
 
 pa_status pa_precondition(pa_ctx* c, const pa_kernel* k, double power, const double* in, double* out,
-                          void* workspace, size_t wbytes) {
+                          void* workspace, size_t wbytes) try {
     g_err.clear();
     if (!c || !in || !out) return fail(PA_EINVAL, "NULL argument");
     PA_TRY(valid_kernel(k));
@@ -1338,7 +1363,7 @@ pa_status pa_precondition(pa_ctx* c, const pa_kernel* k, double power, const dou
     PA_TRY(check_ws(c, workspace, wbytes, 0, 1, 0, 0, &w));
     PA_HIP(launch_make_mult(c->d, k->kind, k->metric, k->param, power, w.mult, c->stream));
     return apply_filter(c, w, w.mult, in, out);
-}
+} PA_CATCH_HOST
 
 }  // extern "C"
 
@@ -1400,7 +1425,7 @@ static pa_status assimilate_impl(pa_ctx* c, double* omega_inout, int32_t n_steps
     if (op.n_times == 0) return fail(PA_EINVAL, "assimilation needs at least one observation time");
     const int m = std::max(1, (int)lbfgs_m);
     WS w;
-    PA_TRY(check_ws(c, workspace, wbytes, n_steps, ckpt_every, op.n_times, m, &w));
+    PA_TRY(check_ws(c, workspace, wbytes, n_steps, ckpt_every, op.n_times, m, &w, true));
     const int B = c->d.B;
     const int K = seg_len(n_steps, ckpt_every);
     const size_t n = (size_t)c->d.N * c->d.N;
@@ -1588,15 +1613,15 @@ static pa_status assimilate_impl(pa_ctx* c, double* omega_inout, int32_t n_steps
 extern "C" pa_status pa_assimilate(pa_ctx* c, double* omega_inout, int32_t n_steps, const pa_obs* obs,
                                    const pa_kernel* kernel, int32_t method, int32_t max_iter, int32_t lbfgs_m,
                                    int32_t ckpt_every, double* J_hist, int32_t* iters_done, void* workspace,
-                                   size_t wbytes) {
+                                   size_t wbytes) try {
     return assimilate_impl(c, omega_inout, n_steps, obs, kernel, false, method, max_iter, lbfgs_m, ckpt_every,
                            J_hist, iters_done, workspace, wbytes);
-}
+} PA_CATCH_HOST
 
 extern "C" pa_status pa_assimilate_kernels(pa_ctx* c, double* omega_inout, int32_t n_steps, const pa_obs* obs,
                                            const pa_kernel* kernels, int32_t method, int32_t max_iter,
                                            int32_t lbfgs_m, int32_t ckpt_every, double* J_hist,
-                                           int32_t* iters_done, void* workspace, size_t wbytes) {
+                                           int32_t* iters_done, void* workspace, size_t wbytes) try {
     return assimilate_impl(c, omega_inout, n_steps, obs, kernels, true, method, max_iter, lbfgs_m, ckpt_every,
                            J_hist, iters_done, workspace, wbytes);
-}
+} PA_CATCH_HOST

@@ -48,6 +48,7 @@ def test_create_validates_before_device_calls():
         (good, 2048, 1),    # too large
         (good, 4, 1),       # too small
         (good, 64, 0),      # no members
+        (good, 8, 65536),   # more members than the launch grid's second dimension holds
         (nv.Physics(-1.0, 0.0, 5e-3, 0.0, 4, 0), 64, 1),
         (nv.Physics(1e-3, -0.1, 5e-3, 0.0, 4, 0), 64, 1),
         (nv.Physics(1e-3, 0.0, 0.0, 0.0, 4, 0), 64, 1),

@@ -119,4 +119,8 @@ def test_schedule_argument_errors():
     buf = (ctypes.c_int32 * 5)()
     assert lib.pa_checkpoint_schedule(6, 2, buf, 1, ctypes.byref(n)) != 0
     assert n.value > 1
+    # a schedule is a host list of about two actions per segment: bounded
+    assert lib.pa_checkpoint_schedule((1 << 22) + 1, 3, None, 0, ctypes.byref(n)) == -1
+    assert b"PA_MAX_SCHEDULE_SEGMENTS" in lib.pa_last_error()
+    assert lib.pa_checkpoint_advances((1 << 22) + 1, 3, ctypes.byref(a)) == 0 and a.value > 0
     assert lib.pa_set_checkpoint_slots(None, 3) != 0
