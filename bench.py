@@ -11,8 +11,8 @@ on a 288 GB device the whole stage trajectory of the 64 members (about 185 GB)
 stays resident, so the adjoint needs no recomputation (--ckpt-every 50 gives
 the checkpointed form).  Inputs are resident in HBM before the timed region.  value = members * N^2 * horizon * steps / seconds
 (grid-point-steps/s, each unit one point advanced one forward and one adjoint
-step).  Beside it: the plain path (one member per solve, same kernels),
-p50/p99 solve latency, the roofline of the dominant kernel measured with HIP
+step).  Beside it: the plain path (one member per solve, same kernels, the
+batch's members solved one after another: equal work), p50/p99 solve latency, the roofline of the dominant kernel measured with HIP
 events on its stream, the solve replayed from a captured HIP graph, and the
 CPU oracle timed on a bounded sample.
 
@@ -65,14 +65,15 @@ def cpu_baseline(N, nu, dt, steps_sample, k0):
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--members", type=int, default=64)
     ap.add_argument("--N", type=int, default=256)
     ap.add_argument("--horizon", type=int, default=500)
     ap.add_argument("--ckpt-every", type=int, default=0,
                     help="checkpoint interval; 0 = the largest that fits in free HBM (the whole horizon if possible)")
-    ap.add_argument("--plain-solves", type=int, default=4)
+    ap.add_argument("--plain-solves", type=int, default=64,
+                    help="one-member solves run one after another (default: the batch's members, equal work)")
     ap.add_argument("--roofline-class", type=int, default=2)
     ap.add_argument("--sample-every", type=int, default=8)
     ap.add_argument("--cpu-steps", type=int, default=100)
@@ -201,7 +202,7 @@ def main():
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record(stream)
-        p.adjoint_impulse(w0[m:m + 1].contiguous(), H, ix, iy, nshell, ckpt_every=Kp)
+        p.adjoint_impulse(w0[m % B:m % B + 1].contiguous(), H, ix, iy, nshell, ckpt_every=Kp)
         e1.record(stream)
         plain_lat.append((e0, e1))
     torch.cuda.synchronize()
