@@ -76,7 +76,7 @@ def main():
                     help="one-member solves run one after another (default: the batch's members, equal work)")
     ap.add_argument("--roofline-class", type=int, default=2)
     ap.add_argument("--sample-every", type=int, default=8)
-    ap.add_argument("--cpu-steps", type=int, default=100)
+    ap.add_argument("--cpu-steps", type=int, default=150)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--graph-replays", type=int, default=3,
                     help="also capture the batched solve in a HIP graph and time this many replays (0: skip)")
