@@ -47,6 +47,24 @@ def _twin(N, ph, steps, obs_steps, stride, seed):
     return O.forward(truth, ph, steps, Obs(stride, obs_steps))[2]
 
 
+def test_schedule_beyond_the_segment_cap_is_refused():
+    """A binomial schedule is a host list of about two actions per segment, bounded at 2^22
+    segments: a longer scheduled solve is refused before anything is enqueued, the uniform
+    layout (no snapshot budget) is not affected by the bound, and the context still solves."""
+    from paper_2602_14016_amd.native import PaError
+    announce("schedule-cap")
+    ph = Physics(N=8, nu=1e-2, dt=5e-3)
+    s = _solver(8, 1, ph)
+    w0 = s.init_field([0], kind=0, k0=2.0)
+    s.set_checkpoint_slots(2)
+    with pytest.raises(PaError, match="PA_MAX_SCHEDULE_SEGMENTS"):
+        s.adjoint_impulse(w0, (1 << 22) + 1, 3, 5, 2, ckpt_every=1)
+    sh2 = host(s.adjoint_impulse(w0, 6, 3, 5, 2, ckpt_every=1)[0])
+    s.set_checkpoint_slots(0)
+    sh0 = host(s.adjoint_impulse(w0, 6, 3, 5, 2, ckpt_every=1)[0])
+    assert np.array_equal(sh2, sh0)
+
+
 def test_binomial_gradient_equals_uniform_bitwise_and_oracle():
     from paper_2602_14016_amd import Observations
     N, B, steps = 32, 2, 37                      # ragged: the last segment is shorter

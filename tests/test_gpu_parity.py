@@ -319,6 +319,35 @@ def test_batch_member_alone_equals_in_batch_bitwise():
     assert host(JB)[1] == host(J1)[0]
 
 
+def test_largest_batch_at_the_grid_limit():
+    """B = 65535 members, the most one context takes (members index the launch grid's second
+    dimension), at 8^2: a gradient with observations and the impulse shells over the whole batch.
+    Members spread over it equal the same members solved alone, bitwise, and the last one matches
+    the oracle."""
+    from paper_2602_14016_amd import Observations
+    N, B, steps = 8, 65535, 6
+    announce("largest-batch", N, B)
+    ph = _hit(N, nu=1e-2, dt=5e-3)
+    osteps = [0, 3, 6]
+    rng = np.random.default_rng(5)
+    mo = 0.1 * rng.standard_normal((B, len(osteps), 2, 2, 2))    # observation values at stride 4 (2 x 2 probes)
+    s = solver(N, B, ph)
+    w0 = s.init_field(list(range(B)), kind=0, k0=2.0)
+    J, g = s.adjoint_gradient(w0, steps, Observations(4, osteps, dev(mo)), ckpt_every=4)
+    sh = s.adjoint_impulse(w0, steps, 3, 5, 2, ckpt_every=4)[0]
+    Jh, gh, shh, wh = host(J), host(g), host(sh), host(w0)
+    s1 = solver(N, 1, ph)
+    for b in (0, 1, 32767, B - 1):
+        w1 = s1.init_field([b], kind=0, k0=2.0)
+        assert np.array_equal(host(w1)[0], wh[b]), b
+        J1, g1 = s1.adjoint_gradient(w1, steps, Observations(4, osteps, dev(mo[b:b + 1])), ckpt_every=4)
+        assert host(J1)[0] == Jh[b] and np.array_equal(host(g1)[0], gh[b]), b
+        assert np.array_equal(host(s1.adjoint_impulse(w1, steps, 3, 5, 2, ckpt_every=4)[0])[0], shh[b]), b
+    Jref, gref = O.adjoint_gradient(wh[B - 1], ph, steps, Obs(4, osteps, mo[B - 1]))
+    assert abs(float(Jh[B - 1]) - Jref) <= FIELD_TOL * Jref
+    assert rel(gh[B - 1], gref) < GRAD_TOL
+
+
 def test_impulse_shells_parity():
     announce("impulse")
     N, steps, nsh = 32, 20, 10
