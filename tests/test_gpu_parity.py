@@ -319,6 +319,36 @@ def test_batch_member_alone_equals_in_batch_bitwise():
     assert host(JB)[1] == host(J1)[0]
 
 
+def test_repeated_runs_are_bitwise_identical():
+    """Determinism: no float atomics and fixed-order reductions, so the same solve run twice on
+    the same inputs gives the same bits: cost and gradient, impulse shells and their ensemble
+    sums, and the L-BFGS iterates with their cost histories (8 members at 256^2)."""
+    from paper_2602_14016_amd import Observations
+    from paper_2602_14016_amd.solver import KernelSpec
+    N, B, steps = 256, 8, 12
+    announce("determinism", N, B)
+    ph = _hit(N, nu=1e-4, dt=2e-3)
+    osteps = [0, 6, 12]
+    rng = np.random.default_rng(9)
+    mo = 0.1 * rng.standard_normal((B, len(osteps), 2, N // 8, N // 8))
+    s = solver(N, B, ph)
+    w0 = s.init_field(list(range(B)), kind=0, k0=10.0, target=0.5)
+    obs = Observations(8, osteps, dev(mo))
+
+    def run():
+        J, g = s.adjoint_gradient(w0, steps, obs, ckpt_every=5)
+        acc = s.ensemble_accumulator(steps, 85)
+        sh = s.adjoint_impulse(w0, steps, 128, 128, 85, ckpt_every=5, acc=acc)[0]
+        st = s.ensemble_stats(acc)
+        wa, hist, iters = s.assimilate(w0, steps, obs, KernelSpec(1, 0.05), max_iter=3, lbfgs_m=3, ckpt_every=5)
+        return [host(J), host(g), host(sh), host(st["snr"]), host(st["energy_of_mean"]), host(wa),
+                np.asarray(hist), np.asarray(iters)]
+
+    first, second = run(), run()
+    for a_, b_ in zip(first, second):
+        assert np.array_equal(a_, b_, equal_nan=True)
+
+
 def test_largest_batch_at_the_grid_limit():
     """B = 65535 members, the most one context takes (members index the launch grid's second
     dimension), at 8^2: a gradient with observations and the impulse shells over the whole batch.
