@@ -227,6 +227,33 @@ pa_status pa_assimilate_kernels(pa_ctx* ctx, double* omega_inout, int32_t n_step
                                 int32_t lbfgs_m, int32_t ckpt_every, double* J_hist,
                                 int32_t* iters_done, void* workspace, size_t workspace_bytes);
 
+/* Bytes of an optimiser state of this context for memory lbfgs_m (per_member:
+ * one kernel per member, as in pa_assimilate_kernels): a header, the O(B m)
+ * scalars of the batched line searches and pair ring, the latent iterate and
+ * gradient, and the m stored pairs (about (2 + 2m) B N^2 doubles). */
+pa_status pa_assimilate_state_bytes(const pa_ctx* ctx, int32_t lbfgs_m, int32_t per_member, size_t* bytes);
+
+/* pa_assimilate (per_member = 0, kernels: one kernel) or pa_assimilate_kernels
+ * (per_member = 1, kernels: B) that can stop and resume (the optimiser
+ * restart of an interrupted 4D-Var).  state_out (device, may be NULL): after
+ * the last iteration the gradient at the final iterate is taken and its pair
+ * stored, as a longer run would, and the whole optimiser state is written
+ * there.  state_in (device, may be NULL, may equal state_out): the run
+ * continues from that state instead of from omega_inout (which is then
+ * output only), so k iterations written out and j more resumed give the
+ * iterates, costs and final field of one run of k + j iterations bit for bit.
+ * J_hist[b][0] is then the cost at the resumed point and iters_done counts
+ * from the first run.  Each state is state_bytes >= pa_assimilate_state_bytes
+ * bytes, 256-byte aligned; a state is a plain byte image (it can be copied to
+ * host memory or a file and back).  PA_EINVAL if state_in was written for
+ * other sizes, method, memory, window length, observation times or stride,
+ * or other kernels.  The caller keeps the observations and physics the same. */
+pa_status pa_assimilate_ex(pa_ctx* ctx, double* omega_inout, int32_t n_steps, const pa_obs* obs,
+                           const pa_kernel* kernels, int32_t per_member, int32_t method,
+                           int32_t max_iter, int32_t lbfgs_m, int32_t ckpt_every, double* J_hist,
+                           int32_t* iters_done, const void* state_in, void* state_out,
+                           size_t state_bytes, void* workspace, size_t workspace_bytes);
+
 /* Running sums of an ensemble of impulse responses, accumulated by
  * pa_adjoint_impulse over any number of calls (batches of members), for the
  * ensemble statistics of Sec. IV.  The caller allocates the device buffers

@@ -1406,11 +1406,50 @@ struct Opt {
 
 }  // namespace
 
-// kernels: host array of B kernels (one per member) when per_member, else one kernel for all
+namespace {
+
+// Optimiser state of a batched solve (pa_assimilate_ex), caller-owned device
+// memory: a header and the O(B m) scalars, then the latent iterate x, its
+// gradient g and the m-slot pair ring (S, Y), each B N^2 doubles.
+const uint64_t OPT_MAGIC = 0x3154534f5054504fULL;   // "OPTPOST1"
+struct OptHeader {
+    uint64_t magic;
+    int32_t N, B, m, method, per_member, n_steps, n_times, stride, head, iters;
+};
+struct OptLayout {
+    size_t J, running, done, ok, rho, gam, kern, x, g, S, Y, total;
+};
+OptLayout opt_layout(int N, int B, int m, int nk) {
+    auto up = [](size_t v, size_t a) { return (v + a - 1) / a * a; };
+    const size_t SP = (size_t)B * N * N * sizeof(double);
+    OptLayout l;
+    size_t o = up(sizeof(OptHeader), 16);
+    l.J = o;        o = up(o + sizeof(double) * B, 16);
+    l.running = o;  o = up(o + sizeof(int32_t) * B, 16);
+    l.done = o;     o = up(o + sizeof(int32_t) * B, 16);
+    l.ok = o;       o = up(o + sizeof(int32_t) * (size_t)m * B, 16);
+    l.rho = o;      o = up(o + sizeof(double) * (size_t)m * B, 16);
+    l.gam = o;      o = up(o + sizeof(double) * (size_t)m * B, 16);
+    l.kern = o;     o = up(o + sizeof(pa_kernel) * nk, 256);
+    l.x = o;        o += SP;
+    l.g = o;        o += SP;
+    l.S = o;        o += SP * m;
+    l.Y = o;        o += SP * m;
+    l.total = o;
+    return l;
+}
+
+}  // namespace
+
+// kernels: host array of B kernels (one per member) when per_member, else one kernel for all.
+// state_in: resume from a state a previous call wrote (omega_inout is then output only);
+// state_out: write the state after the last iteration (which then also takes the gradient
+// and stores the pair, as a longer run would).
 static pa_status assimilate_impl(pa_ctx* c, double* omega_inout, int32_t n_steps, const pa_obs* obs,
                                  const pa_kernel* kernels, bool per_member, int32_t method, int32_t max_iter,
                                  int32_t lbfgs_m, int32_t ckpt_every, double* J_hist, int32_t* iters_done,
-                                 void* workspace, size_t wbytes) {
+                                 void* workspace, size_t wbytes, const void* state_in = nullptr,
+                                 void* state_out = nullptr, size_t state_bytes = 0) {
     g_err.clear();
     if (!c || !omega_inout || !J_hist || !iters_done) return fail(PA_EINVAL, "NULL argument");
     if (!kernels) return fail(PA_EINVAL, "kernel is NULL");
@@ -1419,11 +1458,38 @@ static pa_status assimilate_impl(pa_ctx* c, double* omega_inout, int32_t n_steps
     if (max_iter < 0 || n_steps < 0 || ckpt_every < 1) return fail(PA_EINVAL, "bad sizes");
     if (method == 0 && lbfgs_m < 1) return fail(PA_EINVAL, "lbfgs_m must be >= 1");
     PA_TRY(require_device(c->stream, {{omega_inout, "omega_inout"}, {workspace, "workspace"},
-                           {obs ? obs->values : nullptr, "obs values"}}));
+                           {obs ? obs->values : nullptr, "obs values"}, {state_in, "state_in"},
+                           {state_out, "state_out"}}));
     ObsPlan op;
     PA_TRY(make_obs_plan(c, obs, n_steps, true, &op));
     if (op.n_times == 0) return fail(PA_EINVAL, "assimilation needs at least one observation time");
     const int m = std::max(1, (int)lbfgs_m);
+    const int nk = per_member ? c->d.B : 1;
+    const OptLayout sl_ = opt_layout(c->d.N, c->d.B, m, nk);
+    if ((state_in && reinterpret_cast<uintptr_t>(state_in) % 256) ||
+        (state_out && reinterpret_cast<uintptr_t>(state_out) % 256))
+        return fail(PA_EINVAL, "optimiser state must be 256-byte aligned");
+    if ((state_in || state_out) && state_bytes < sl_.total)
+        return fail(PA_EINVAL, "optimiser state too small: need " + std::to_string(sl_.total) + " bytes");
+    OptHeader want{OPT_MAGIC, c->d.N, c->d.B, m, method, per_member ? 1 : 0, n_steps, op.n_times,
+                   obs ? obs->stride : 0, 0, 0};
+    // a resumed state: header and scalars read (and checked) before anything is enqueued
+    std::vector<unsigned char> hs;
+    OptHeader got{};
+    if (state_in) {
+        hs.resize(sl_.x);
+        PA_HIP(hipMemcpyAsync(hs.data(), state_in, sl_.x, hipMemcpyDeviceToHost, c->stream));
+        PA_HIP(hipStreamSynchronize(c->stream));
+        std::memcpy(&got, hs.data(), sizeof(got));
+        const bool same = got.magic == want.magic && got.N == want.N && got.B == want.B && got.m == want.m &&
+                          got.method == want.method && got.per_member == want.per_member &&
+                          got.n_steps == want.n_steps && got.n_times == want.n_times && got.stride == want.stride &&
+                          got.head >= 0 && got.iters >= 0 &&
+                          std::memcmp(hs.data() + sl_.kern, kernels, sizeof(pa_kernel) * nk) == 0;
+        if (!same)
+            return fail(PA_EINVAL, "optimiser state does not match this call (sizes, method, memory, window, "
+                                   "observation layout or kernels)");
+    }
     WS w;
     PA_TRY(check_ws(c, workspace, wbytes, n_steps, ckpt_every, op.n_times, m, &w, true));
     const int B = c->d.B;
@@ -1460,11 +1526,42 @@ static pa_status assimilate_impl(pa_ctx* c, double* omega_inout, int32_t n_steps
     std::vector<std::vector<double>> rho(m, std::vector<double>(B, 0.0)), gam(m, std::vector<double>(B, 1.0));
     std::vector<std::vector<double>> al(m, std::vector<double>(B, 0.0));
     int head = 0;
+    int it0 = 0;   // iterations completed before this call
 
-    PA_TRY(apply_filter(c, w, mult_m, omega_inout, w.x, per_member));
-    PA_TRY(eval_J(w.x));
-    PA_TRY(eval_grad(w.g));
-    PA_TRY(o.read_J(J));
+    if (state_in) {
+        const unsigned char* h = hs.data();
+        auto rd = [&](size_t off, size_t i, auto* v) { std::memcpy(v, h + off + i * sizeof(*v), sizeof(*v)); };
+        head = got.head;
+        it0 = got.iters;
+        for (int b = 0; b < B; ++b) {
+            int32_t r, d;
+            rd(sl_.J, b, &J[b]);
+            rd(sl_.running, b, &r);
+            rd(sl_.done, b, &d);
+            running[b] = r;
+            done[b] = d;
+            if (!running[b]) iters_done[b] = -(done[b] + 1);
+            for (int q = 0; q < m; ++q) {
+                int32_t k;
+                rd(sl_.ok, (size_t)q * B + b, &k);
+                ok[q][b] = k;
+                rd(sl_.rho, (size_t)q * B + b, &rho[q][b]);
+                rd(sl_.gam, (size_t)q * B + b, &gam[q][b]);
+            }
+        }
+        const unsigned char* d = static_cast<const unsigned char*>(state_in);
+        PA_HIP(launch_copy(w.x, reinterpret_cast<const double*>(d + sl_.x), SP, c->stream));
+        PA_HIP(launch_copy(w.g, reinterpret_cast<const double*>(d + sl_.g), SP, c->stream));
+        for (int q = 0; q < m; ++q) {
+            PA_HIP(launch_copy(w.S + q * SP, reinterpret_cast<const double*>(d + sl_.S) + q * SP, SP, c->stream));
+            PA_HIP(launch_copy(w.Yv + q * SP, reinterpret_cast<const double*>(d + sl_.Y) + q * SP, SP, c->stream));
+        }
+    } else {
+        PA_TRY(apply_filter(c, w, mult_m, omega_inout, w.x, per_member));
+        PA_TRY(eval_J(w.x));
+        PA_TRY(eval_grad(w.g));
+        PA_TRY(o.read_J(J));
+    }
     for (int b = 0; b < B; ++b) J_hist[(size_t)b * (max_iter + 1)] = J[b];
 
     for (int it = 0; it < max_iter; ++it) {
@@ -1571,7 +1668,8 @@ static pa_status assimilate_impl(pa_ctx* c, double* omega_inout, int32_t n_steps
             any_acc = any_acc || acc[b];
         }
         if (!any_acc) break;
-        const bool last = it == max_iter - 1;
+        // the last iteration skips the gradient at the new point, unless a state is kept for a resume
+        const bool last = it == max_iter - 1 && !state_out;
         if (!last) {
             // the last trial's forward sweep holds valid checkpoints for every accepted member
             PA_TRY(eval_grad(w.gt));
@@ -1598,7 +1696,7 @@ static pa_status assimilate_impl(pa_ctx* c, double* omega_inout, int32_t n_steps
         for (int b = 0; b < B; ++b) {
             if (!acc[b]) continue;
             J[b] = Jt[b];
-            done[b] = it + 1;
+            done[b] = it0 + it + 1;
             J_hist[(size_t)b * (max_iter + 1) + it + 1] = J[b];
         }
         if (last) break;
@@ -1606,6 +1704,36 @@ static pa_status assimilate_impl(pa_ctx* c, double* omega_inout, int32_t n_steps
     for (int b = 0; b < B; ++b)
         if (running[b]) iters_done[b] = done[b];
     PA_TRY(apply_filter(c, w, mult_p, w.x, omega_inout, per_member));
+    std::vector<unsigned char> out;   // staged header; lives until the stream is synchronised below
+    if (state_out) {
+        int iters = it0;
+        for (int b = 0; b < B; ++b) iters = std::max(iters, done[b]);
+        OptHeader hd = want;
+        hd.head = head;
+        hd.iters = iters;
+        out.assign(sl_.x, 0);
+        std::memcpy(out.data(), &hd, sizeof(hd));
+        auto wr = [&](size_t off, size_t i, auto v) { std::memcpy(out.data() + off + i * sizeof(v), &v, sizeof(v)); };
+        for (int b = 0; b < B; ++b) {
+            wr(sl_.J, b, J[b]);
+            wr(sl_.running, b, (int32_t)running[b]);
+            wr(sl_.done, b, (int32_t)done[b]);
+            for (int q = 0; q < m; ++q) {
+                wr(sl_.ok, (size_t)q * B + b, (int32_t)ok[q][b]);
+                wr(sl_.rho, (size_t)q * B + b, rho[q][b]);
+                wr(sl_.gam, (size_t)q * B + b, gam[q][b]);
+            }
+        }
+        std::memcpy(out.data() + sl_.kern, kernels, sizeof(pa_kernel) * nk);
+        unsigned char* d = static_cast<unsigned char*>(state_out);
+        PA_HIP(hipMemcpyAsync(d, out.data(), out.size(), hipMemcpyHostToDevice, c->stream));
+        PA_HIP(launch_copy(reinterpret_cast<double*>(d + sl_.x), w.x, SP, c->stream));
+        PA_HIP(launch_copy(reinterpret_cast<double*>(d + sl_.g), w.g, SP, c->stream));
+        for (int q = 0; q < m; ++q) {
+            PA_HIP(launch_copy(reinterpret_cast<double*>(d + sl_.S) + q * SP, w.S + q * SP, SP, c->stream));
+            PA_HIP(launch_copy(reinterpret_cast<double*>(d + sl_.Y) + q * SP, w.Yv + q * SP, SP, c->stream));
+        }
+    }
     PA_TRY(o.sync());
     return PA_OK;
 }
@@ -1616,6 +1744,23 @@ extern "C" pa_status pa_assimilate(pa_ctx* c, double* omega_inout, int32_t n_ste
                                    size_t wbytes) try {
     return assimilate_impl(c, omega_inout, n_steps, obs, kernel, false, method, max_iter, lbfgs_m, ckpt_every,
                            J_hist, iters_done, workspace, wbytes);
+} PA_CATCH_HOST
+
+extern "C" pa_status pa_assimilate_state_bytes(const pa_ctx* c, int32_t lbfgs_m, int32_t per_member,
+                                               size_t* bytes) try {
+    if (!c || !bytes) return fail(PA_EINVAL, "NULL argument");
+    if (lbfgs_m < 0) return fail(PA_EINVAL, "lbfgs_m must be >= 0");
+    *bytes = opt_layout(c->d.N, c->d.B, std::max(1, (int)lbfgs_m), per_member ? c->d.B : 1).total;
+    return PA_OK;
+} PA_CATCH_HOST
+
+extern "C" pa_status pa_assimilate_ex(pa_ctx* c, double* omega_inout, int32_t n_steps, const pa_obs* obs,
+                                      const pa_kernel* kernels, int32_t per_member, int32_t method,
+                                      int32_t max_iter, int32_t lbfgs_m, int32_t ckpt_every, double* J_hist,
+                                      int32_t* iters_done, const void* state_in, void* state_out,
+                                      size_t state_bytes, void* workspace, size_t wbytes) try {
+    return assimilate_impl(c, omega_inout, n_steps, obs, kernels, per_member != 0, method, max_iter, lbfgs_m,
+                           ckpt_every, J_hist, iters_done, workspace, wbytes, state_in, state_out, state_bytes);
 } PA_CATCH_HOST
 
 extern "C" pa_status pa_assimilate_kernels(pa_ctx* c, double* omega_inout, int32_t n_steps, const pa_obs* obs,

@@ -304,11 +304,23 @@ class Solver:
         nv.check(self.lib.pa_precondition(self.ctx, byref(k), float(power), _ptr(x), _ptr(out), ws, wb))
         return out
 
+    def optimizer_state(self, kernel, method="lbfgs", lbfgs_m=10):
+        """A device buffer for the optimiser state of assimilate(..., state_out=...) with this
+        kernel argument, method and memory (pa_assimilate_state_bytes); a plain byte image."""
+        per_member = not isinstance(kernel, KernelSpec)
+        m = int(lbfgs_m) if method == "lbfgs" else 1
+        b = c_size_t()
+        nv.check(self.lib.pa_assimilate_state_bytes(self.ctx, max(m, 1), int(per_member), byref(b)))
+        return torch.empty(b.value, dtype=torch.uint8, device=self.device)
+
     def assimilate(self, omega_fg, n_steps, obs: Observations, kernel, method="lbfgs",
-                   max_iter=10, lbfgs_m=10, ckpt_every=50):
+                   max_iter=10, lbfgs_m=10, ckpt_every=50, state_in=None, state_out=None):
         """4D-Var from the first guess omega_fg [B, N, N].  kernel: one KernelSpec for every
         member, or a sequence of B KernelSpecs (one preconditioner per member: a kernel sweep
-        as one batched solve).  Returns (omega0 [B, N, N], J history per member, iterations)."""
+        as one batched solve).  Returns (omega0 [B, N, N], J history per member, iterations).
+        state_out / state_in (buffers from optimizer_state): write the optimiser state after the
+        last iteration / resume from one (omega_fg is then ignored); k iterations written and j
+        resumed equal one run of k + j iterations bit for bit (pa_assimilate_ex)."""
         _need(omega_fg, (self.B, self.N, self.N), "omega_fg")
         per_member = not isinstance(kernel, KernelSpec)
         if per_member and len(kernel) != self.B:
@@ -321,7 +333,19 @@ class Solver:
         m = int(lbfgs_m) if method == "lbfgs" else 1
         ws, wb = self.workspace(n_steps, ckpt_every, len(obs.steps), max(m, 1))
         meth = 0 if method == "lbfgs" else 1
-        if per_member:
+        if state_in is not None or state_out is not None:
+            states = [t for t in (state_in, state_out) if t is not None]
+            idx = self.device.index if self.device.index is not None else torch.cuda.current_device()
+            for t in states:
+                if t.dtype != torch.uint8 or t.device != torch.device("cuda", idx) or not t.is_contiguous():
+                    raise ValueError("optimiser states are contiguous uint8 tensors on the solver's device")
+            sb = min(t.numel() for t in states)
+            ks = (nv.Kernel * self.B)(*[k.c() for k in kernel]) if per_member else (nv.Kernel * 1)(kernel.c())
+            nv.check(self.lib.pa_assimilate_ex(self.ctx, _ptr(w), int(n_steps), byref(o_c), ks, int(per_member),
+                                               meth, int(max_iter), m, int(ckpt_every), hist, iters,
+                                               _ptr(state_in) if state_in is not None else None,
+                                               _ptr(state_out) if state_out is not None else None, sb, ws, wb))
+        elif per_member:
             ks = (nv.Kernel * self.B)(*[k.c() for k in kernel])
             nv.check(self.lib.pa_assimilate_kernels(self.ctx, _ptr(w), int(n_steps), byref(o_c), ks, meth,
                                                     int(max_iter), m, int(ckpt_every), hist, iters, ws, wb))

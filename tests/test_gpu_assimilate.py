@@ -146,3 +146,44 @@ def test_non_finite_observations_fail_their_member_alone():
     assert np.array_equal(np.array(H[0]), np.array(H1[0]), equal_nan=True)
     assert np.array_equal(w.cpu().numpy()[0], w1.cpu().numpy()[0])
     assert np.all(np.isfinite(w.cpu().numpy()[0]))
+
+
+@pytest.mark.parametrize("method,per_member", [("lbfgs", False), ("lbfgs", True), ("sd", False)])
+def test_resume_from_a_saved_optimiser_state_is_bitwise(method, per_member):
+    """An interrupted 4D-Var resumed from its saved optimiser state (the state copied to host
+    memory and back, as a file would hold it) runs the iterates of one uninterrupted run:
+    3 + 4 iterations give the 7-iteration field, cost history and iteration counts bit for bit,
+    with the L-BFGS memory (m = 3) wrapping around across the restart."""
+    from paper_2602_14016_amd import KernelSpec, Observations, Solver
+    print("CASE resume", method, per_member, flush=True)
+    N, steps = 32, 20
+    osteps = synth.evenly_spaced_steps(steps, 3)
+    ph, mo = _setup(N, steps, osteps, 4, seeds=(3, 4, 5))
+    fg = dev(0.5 * O.init_field(N, [6, 7, 8], kind=0, k0=4.0))
+    kern = [KernelSpec(1, 0.1), KernelSpec(0, 0.0), KernelSpec(2, 0.25)] if per_member else KernelSpec(1, 0.05)
+    s = Solver(N, 3, nu=ph.nu, dt=ph.dt)
+    obs = Observations(4, osteps, dev(mo))
+    kw = dict(method=method, lbfgs_m=3, ckpt_every=7)
+    w_all, H_all, it_all = s.assimilate(fg, steps, obs, kern, max_iter=7, **kw)
+    st = s.optimizer_state(kern, method=method, lbfgs_m=3)
+    w_a, H_a, it_a = s.assimilate(fg, steps, obs, kern, max_iter=3, state_out=st, **kw)
+    image = st.cpu().numpy().tobytes()                      # serialised
+    st2 = torch.frombuffer(bytearray(image), dtype=torch.uint8).cuda()
+    st2 = st2.clone() if st2.data_ptr() % 256 else st2
+    w_b, H_b, it_b = s.assimilate(torch.zeros_like(fg), steps, obs, kern, max_iter=4, state_in=st2, **kw)
+    torch.cuda.synchronize()
+    assert np.array_equal(w_b.cpu().numpy(), w_all.cpu().numpy())
+    for b in range(3):
+        assert H_a[b][:4] == H_all[b][:4]
+        assert H_b[b][0] == H_a[b][3]
+        assert np.array_equal(np.array(H_b[b]), np.array(H_all[b][3:]), equal_nan=True)
+        assert it_a[b] == 3 and it_b[b] == it_all[b] == 7
+    # the state records what it was written for
+    from paper_2602_14016_amd.native import PaError
+    other = [KernelSpec(1, 0.2)] * 3 if per_member else KernelSpec(1, 0.2)
+    with pytest.raises(PaError, match="does not match"):
+        s.assimilate(fg, steps, obs, other, max_iter=1, state_in=st, **kw)
+    with pytest.raises(PaError, match="does not match"):
+        s.assimilate(fg, steps + 1, obs, kern, max_iter=1, state_in=st, **kw)
+    with pytest.raises(PaError, match="too small"):
+        s.assimilate(fg, steps, obs, kern, max_iter=1, state_in=st[:-256], **kw)
