@@ -109,6 +109,12 @@ int main() {
     EXPECT(pa_set_tiles(nullptr, &t) == PA_EINVAL);
     EXPECT(pa_set_checkpoint_slots(nullptr, 2) == PA_EINVAL);
     EXPECT(pa_set_sobolev(nullptr, 1.0) == PA_EINVAL);
+    EXPECT(pa_assimilate_state_bytes(nullptr, 3, 0, &bytes) == PA_EINVAL);
+    double jh[4];
+    int32_t it[1];
+    pa_kernel k = {0, 0, 0.0};
+    EXPECT(pa_assimilate_ex(nullptr, nullptr, 10, nullptr, &k, 0, 0, 3, 3, 5, jh, it, nullptr, nullptr, 0,
+                            nullptr, 0) == PA_EINVAL);
     int32_t is_dev = -1;
     EXPECT(pa_is_device_memory(nullptr, &is_dev) == PA_OK && is_dev == 0);
     EXPECT(pa_is_device_memory(&good, nullptr) == PA_EINVAL);
