@@ -227,6 +227,19 @@ pa_status pa_assimilate_kernels(pa_ctx* ctx, double* omega_inout, int32_t n_step
                                 int32_t lbfgs_m, int32_t ckpt_every, double* J_hist,
                                 int32_t* iters_done, void* workspace, size_t workspace_bytes);
 
+/* Cancellation of running 4D-Var members: flags is host memory [B] (or
+ * NULL to switch it off) that pa_assimilate* read, never write, at every
+ * iteration boundary; another thread may set an entry non-zero at any time.
+ * A member whose flag is set stops before its next iteration: its field, cost
+ * history and iteration count (positive) are those of its last completed
+ * iteration, and the other members run on unchanged.  With a state_out
+ * (pa_assimilate_ex) the cancelled member is recorded as paused, so a resume
+ * continues it; when the whole batch is cancelled at one boundary, the
+ * resumed run is bit for bit the uninterrupted one (a member paused while
+ * others go on keeps fewer stored pairs).  The pointer stays in use until it
+ * is replaced or cleared. */
+pa_status pa_set_cancel_flags(pa_ctx* ctx, const int32_t* flags);
+
 /* Bytes of an optimiser state of this context for memory lbfgs_m (per_member:
  * one kernel per member, as in pa_assimilate_kernels): a header, the O(B m)
  * scalars of the batched line searches and pair ring, the latent iterate and

@@ -115,6 +115,7 @@ struct pa_ctx {
     double sobolev = 0; // lambda of the Sobolev term (lambda/2) int |grad u0|^2 of the cost
     // snapshot budget of the internal checkpoints (0: one per segment boundary)
     int ckpt_slots = 0;
+    const int32_t* cancel = nullptr;   // host [B]: members to stop at the next iteration boundary
     int plan_L = -1, plan_slots = -1;
     std::vector<PlanAct> plan;       // binomial schedule for plan_L segments and plan_slots slots
     std::vector<int> plan_fwd_slot;  // boundary -> slot written by the schedule's first chain (-1: none)
@@ -1061,6 +1062,12 @@ pa_status pa_set_sobolev(pa_ctx* c, double lambda) try {
     return PA_OK;
 } PA_CATCH_HOST
 
+pa_status pa_set_cancel_flags(pa_ctx* c, const int32_t* flags) try {
+    if (!c) return fail(PA_EINVAL, "ctx is NULL");
+    c->cancel = flags;
+    return PA_OK;
+} PA_CATCH_HOST
+
 pa_status pa_set_checkpoint_slots(pa_ctx* c, int32_t slots) try {
     if (!c) return fail(PA_EINVAL, "ctx is NULL");
     if (slots < 0) return fail(PA_EINVAL, "slots must be >= 0");
@@ -1520,13 +1527,13 @@ static pa_status assimilate_impl(pa_ctx* c, double* omega_inout, int32_t n_steps
 
     for (int i = 0; i < B * (max_iter + 1); ++i) J_hist[i] = NAN;
     std::vector<double> J(B), Jt(B), gg, gd, alpha(B), coef(B), tmp;
-    std::vector<int> running(B, 1), done(B, 0), pend(B, 0), acc(B, 0);
+    std::vector<int> running(B, 1), done(B, 0), pend(B, 0), acc(B, 0), paused(B, 0);
     // pair ring: push p lives in slot p % m; ok[slot][b] marks a stored pair of member b
     std::vector<std::vector<int>> ok(m, std::vector<int>(B, 0));
     std::vector<std::vector<double>> rho(m, std::vector<double>(B, 0.0)), gam(m, std::vector<double>(B, 1.0));
     std::vector<std::vector<double>> al(m, std::vector<double>(B, 0.0));
     int head = 0;
-    int it0 = 0;   // iterations completed before this call
+    int it0 = 0;   // iterations completed before this call (the most any member has done)
 
     if (state_in) {
         const unsigned char* h = hs.data();
@@ -1565,6 +1572,15 @@ static pa_status assimilate_impl(pa_ctx* c, double* omega_inout, int32_t n_steps
     for (int b = 0; b < B; ++b) J_hist[(size_t)b * (max_iter + 1)] = J[b];
 
     for (int it = 0; it < max_iter; ++it) {
+        // members cancelled by the caller (another thread may set their flags at any time) stop here,
+        // after their last completed iteration
+        if (c->cancel)
+            for (int b = 0; b < B; ++b)
+                if (running[b] && __atomic_load_n(c->cancel + b, __ATOMIC_ACQUIRE)) {
+                    running[b] = 0;
+                    paused[b] = 1;
+                    iters_done[b] = done[b];
+                }
         bool any = false;
         for (int b = 0; b < B; ++b) any = any || running[b];
         if (!any) break;
@@ -1696,7 +1712,7 @@ static pa_status assimilate_impl(pa_ctx* c, double* omega_inout, int32_t n_steps
         for (int b = 0; b < B; ++b) {
             if (!acc[b]) continue;
             J[b] = Jt[b];
-            done[b] = it0 + it + 1;
+            ++done[b];
             J_hist[(size_t)b * (max_iter + 1) + it + 1] = J[b];
         }
         if (last) break;
@@ -1716,7 +1732,7 @@ static pa_status assimilate_impl(pa_ctx* c, double* omega_inout, int32_t n_steps
         auto wr = [&](size_t off, size_t i, auto v) { std::memcpy(out.data() + off + i * sizeof(v), &v, sizeof(v)); };
         for (int b = 0; b < B; ++b) {
             wr(sl_.J, b, J[b]);
-            wr(sl_.running, b, (int32_t)running[b]);
+            wr(sl_.running, b, (int32_t)(running[b] || paused[b]));   // a cancelled member resumes
             wr(sl_.done, b, (int32_t)done[b]);
             for (int q = 0; q < m; ++q) {
                 wr(sl_.ok, (size_t)q * B + b, (int32_t)ok[q][b]);

@@ -87,6 +87,7 @@ EXPORTS = {
     "pa_get_tiles": (c_int32, [c_void_p, POINTER(Tiles)]),
     "pa_set_sobolev": (c_int32, [c_void_p, c_double]),
     "pa_set_checkpoint_slots": (c_int32, [c_void_p, c_int32]),
+    "pa_set_cancel_flags": (c_int32, [c_void_p, c_void_p]),
     "pa_is_device_memory": (c_int32, [c_void_p, POINTER(c_int32)]),
     "pa_get_checkpoint_slots": (c_int32, [c_void_p, POINTER(c_int32)]),
     "pa_checkpoint_advances": (c_int32, [c_int32, c_int32, POINTER(ctypes.c_int64)]),

@@ -110,6 +110,8 @@ class GpuBackend:
         self.tiles = dict(tiles or {})
         self.streams = [torch.cuda.Stream(device=self.device) for _ in range(slots)]
         self._solvers = {}   # (slot, N, flow, B) -> Solver
+        self._lock = threading.Lock()
+        self._running = {}   # rid -> (cancel flags of its solver, member index)
 
     def _solver(self, slot, N, flow, B):
         key = (slot, N, flow, B)
@@ -138,9 +140,28 @@ class GpuBackend:
                 fg = s.first_guess(head.stride, vals[:, 0].contiguous())
             else:
                 fg = torch.zeros((B, head.N, head.N), dtype=torch.float64, device=self.device)
-            w, H, iters = s.assimilate(fg, head.n_steps, obs, head.kernel, "lbfgs", head.iters,
-                                       head.lbfgs_m, head.ckpt_every)
+            flags = s.cancel_flags()
+            with self._lock:
+                for b, r in enumerate(group):
+                    self._running[r.rid] = (flags, b)
+            try:
+                w, H, iters = s.assimilate(fg, head.n_steps, obs, head.kernel, "lbfgs", head.iters,
+                                           head.lbfgs_m, head.ckpt_every)
+            finally:
+                with self._lock:
+                    for r in group:
+                        self._running.pop(r.rid, None)
             return w.cpu(), H, iters
+
+    def cancel(self, rid):
+        """Stop a running request at its next iteration boundary; False if it is not running."""
+        with self._lock:
+            hit = self._running.get(rid)
+            if hit is None:
+                return False
+            flags, b = hit
+            flags[b] = 1
+            return True
 
     def release(self, slot, group):
         head = group[0]
@@ -164,6 +185,7 @@ class Server:
         self.lock = threading.Condition()
         self.queue: List[Request] = []
         self.results = {}
+        self.cancelled = set()   # running requests asked to stop
         self.free_slots = list(range(slots))
         self.t0 = None
 
@@ -177,7 +199,10 @@ class Server:
             self.lock.notify_all()
 
     def cancel(self, rid):
-        """Withdraw a request that is still queued; False if it was admitted or is unknown."""
+        """Withdraw a queued request, or stop a running one at its next iteration boundary (its
+        result is then the last completed iterate, status "cancelled"; the other requests of its
+        batch run on unchanged).  False if it is finished, unknown, or the backend cannot stop
+        a running solve."""
         with self.lock:
             for r in self.queue:
                 if r.rid == rid:
@@ -186,6 +211,10 @@ class Server:
                     self.results[rid] = Result(rid, None, [], 0, "cancelled", r.arrival, t, t, 0)
                     self.lock.notify_all()
                     return True
+            stop = getattr(self.backend, "cancel", None)
+            if stop is not None and rid not in self.results and stop(rid):
+                self.cancelled.add(rid)
+                return True
         return False
 
     def _admit_locked(self):
@@ -224,6 +253,8 @@ class Server:
                       f"(admitted {admitted:.2f} s)", flush=True)
             for b, r in enumerate(group):
                 status = "ok" if iters[b] >= 0 else "line-search failure"
+                if r.rid in self.cancelled and iters[b] >= 0 and iters[b] < r.iters:
+                    status = "cancelled"
                 self.results[r.rid] = Result(r.rid, w_host[b].clone(), [h for h in H[b] if h == h],
                                              iters[b] if iters[b] >= 0 else -iters[b] - 1, status, r.arrival,
                                              admitted, fin, B)

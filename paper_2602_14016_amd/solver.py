@@ -89,6 +89,7 @@ class Solver:
         nv.check(self.lib.pa_get_shape(self.ctx, None, None, byref(kc)))
         self.Kc = kc.value
         self._ws = None
+        self._cancel = None
 
     # ------------------------------------------------------------- plumbing
     def _stream_handle(self):
@@ -97,6 +98,17 @@ class Solver:
 
     def _sync_stream(self):
         nv.check(self.lib.pa_set_stream(self.ctx, self._stream_handle()))
+
+    def cancel_flags(self):
+        """Host int32 flags [B] bound to this solver (pa_set_cancel_flags), all clear on return:
+        setting flags[b] non-zero, from any thread, stops member b of a running assimilate at
+        its next iteration boundary with the result of its last completed iteration."""
+        if self._cancel is None:
+            self._cancel = (c_int32 * self.B)()
+            nv.check(self.lib.pa_set_cancel_flags(self.ctx, ctypes.cast(self._cancel, c_void_p)))
+        for b in range(self.B):
+            self._cancel[b] = 0
+        return self._cancel
 
     def close(self):
         if getattr(self, "ctx", None):

@@ -187,3 +187,48 @@ def test_resume_from_a_saved_optimiser_state_is_bitwise(method, per_member):
         s.assimilate(fg, steps + 1, obs, kern, max_iter=1, state_in=st, **kw)
     with pytest.raises(PaError, match="too small"):
         s.assimilate(fg, steps, obs, kern, max_iter=1, state_in=st[:-256], **kw)
+
+
+def test_cancelled_members_stop_alone():
+    """Cancellation flags (pa_set_cancel_flags): a member flagged before the solve does no
+    iteration while the others run bitwise as without it; a member flagged from another thread
+    while the solve runs stops at an iteration boundary, its cost history an exact prefix of the
+    uncancelled one."""
+    import threading
+    import time
+    from paper_2602_14016_amd import KernelSpec, Observations, Solver
+    print("CASE cancel", flush=True)
+    N, steps = 64, 40
+    osteps = synth.evenly_spaced_steps(steps, 3)
+    ph, mo = _setup(N, steps, osteps, 4, seeds=(3, 4, 5))
+    fg = dev(0.5 * O.init_field(N, [6, 7, 8], kind=0, k0=4.0))
+    s = Solver(N, 3, nu=ph.nu, dt=ph.dt)
+    obs = Observations(4, osteps, dev(mo))
+    kw = dict(method="lbfgs", lbfgs_m=4, ckpt_every=10)
+    iters = 25
+    flags = s.cancel_flags()
+    t0 = time.perf_counter()
+    w_ref, H_ref, it_ref = s.assimilate(fg, steps, obs, KernelSpec(1, 0.05), max_iter=iters, **kw)
+    torch.cuda.synchronize()
+    solve_s = time.perf_counter() - t0
+    assert it_ref == [iters] * 3
+    flags = s.cancel_flags()
+    flags[1] = 1
+    w, H, it = s.assimilate(fg, steps, obs, KernelSpec(1, 0.05), max_iter=iters, **kw)
+    torch.cuda.synchronize()
+    assert it[1] == 0 and np.isnan(H[1][1:]).all() and H[1][0] == H_ref[1][0]
+    for b in (0, 2):
+        assert it[b] == iters and H[b] == H_ref[b]
+        assert np.array_equal(w[b].cpu().numpy(), w_ref[b].cpu().numpy())
+    flags = s.cancel_flags()
+    timer = threading.Timer(0.4 * solve_s, lambda: flags.__setitem__(2, 1))
+    timer.start()
+    w, H, it = s.assimilate(fg, steps, obs, KernelSpec(1, 0.05), max_iter=iters, **kw)
+    torch.cuda.synchronize()
+    timer.join()
+    k = it[2]
+    assert 0 <= k <= iters
+    assert H[2][:k + 1] == H_ref[2][:k + 1] and np.isnan(H[2][k + 1:]).all()
+    for b in (0, 1):
+        assert it[b] == iters and H[b] == H_ref[b]
+    s.cancel_flags()

@@ -61,3 +61,28 @@ def test_oversize_request_rejected_alone():
     res = Server(hbm_budget_bytes=budget, slots=2).run_trace(reqs)
     assert res[1].status.startswith("rejected")
     assert res[0].status == "ok" and res[2].status == "ok"
+
+
+def test_cancel_a_running_request():
+    """A request cancelled while its batch runs stops at its next iteration boundary: status
+    "cancelled", the field of its last completed iteration, fewer iterations than asked."""
+    import threading
+    import time
+    from paper_2602_14016_amd.serving import Server
+    print("CASE serving-cancel", flush=True)
+    r = _make_requests()[0]
+    r.iters, r.arrival = 400, 0.0
+    srv = Server(hbm_budget_bytes=8 << 30, slots=1)
+    out = {}
+    th = threading.Thread(target=lambda: out.update(srv.run_trace([r])))
+    th.start()
+    t0 = time.time()
+    while r.rid not in srv.backend._running and th.is_alive() and time.time() - t0 < 60:
+        time.sleep(0.002)
+    assert srv.cancel(r.rid)
+    th.join(timeout=120)
+    assert not th.is_alive()
+    res = out[r.rid]
+    assert res.status == "cancelled", res.status
+    assert 0 <= res.iters < 400 and res.omega0 is not None and torch.isfinite(res.omega0).all()
+    assert len(res.J_hist) == res.iters + 1

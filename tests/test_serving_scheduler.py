@@ -146,3 +146,58 @@ def test_poisson_trace_is_admitted_in_arrival_order():
     assert all(res[i].admitted >= reqs[i].arrival - 1e-3 for i in range(12))
     st = latency_stats(res)
     assert st["n"] == 12 and st["p99_s"] >= st["p50_s"] > 0
+
+
+class CancellableSleepBackend(SleepBackend):
+    """Solves in 10 ms ticks, one iteration per tick; cancel(rid) stops that member at its next tick."""
+
+    def __init__(self, ticks=40):
+        super().__init__(solve_s=0.0)
+        self.ticks = ticks
+        self.stop = set()
+        self.running = set()
+
+    def run(self, slot, group):
+        with self.lock:
+            self.running |= {r.rid for r in group}
+        try:
+            done = {r.rid: 0 for r in group}
+            for _ in range(self.ticks):
+                time.sleep(0.01)
+                with self.lock:
+                    for r in group:
+                        if r.rid not in self.stop:
+                            done[r.rid] += 1
+            w, H, _ = super().run(slot, group)
+            return w, H, [done[r.rid] for r in group]
+        finally:
+            with self.lock:
+                self.running -= {r.rid for r in group}
+
+    def cancel(self, rid):
+        with self.lock:
+            if rid not in self.running:
+                return False
+            self.stop.add(rid)
+            return True
+
+
+def test_cancel_a_running_request_stops_it_alone():
+    be = CancellableSleepBackend(ticks=40)
+    srv = Server(10 ** 9, slots=1, max_batch=8, backend=be)
+    reqs = [req(0), req(1)]        # one shape: one batch
+    for r in reqs:
+        r.iters = 40
+    out = {}
+    th = threading.Thread(target=lambda: out.update(srv.run_trace(reqs)))
+    th.start()
+    t0 = time.time()
+    while not be.running and time.time() - t0 < 5:
+        time.sleep(0.005)
+    time.sleep(0.05)
+    assert srv.cancel(1)
+    th.join(timeout=10)
+    assert not th.is_alive()
+    assert out[1].status == "cancelled" and 0 < out[1].iters < 40
+    assert out[0].status == "ok" and out[0].iters == 40
+    assert not srv.cancel(1) and not srv.cancel(0)        # finished
