@@ -110,6 +110,7 @@ int main() {
     EXPECT(pa_set_checkpoint_slots(nullptr, 2) == PA_EINVAL);
     EXPECT(pa_set_sobolev(nullptr, 1.0) == PA_EINVAL);
     EXPECT(pa_assimilate_state_bytes(nullptr, 3, 0, &bytes) == PA_EINVAL);
+    EXPECT(pa_set_cancel_flags(nullptr, nullptr) == PA_EINVAL);
     double jh[4];
     int32_t it[1];
     pa_kernel k = {0, 0, 0.0};
