@@ -16,6 +16,13 @@ here from the oracle's seeded initial fields.  The GPU tests load the files
                         energies |k| = 1..85 of the adjoint of a unit
                         u-impulse at (128, 128) after 500 steps, per backward
                         step.
+  c2_100_steps.npz      the Kolmogorov configuration's physics on its grid
+                        (512^2, nu = 1/40, drag 0.1, f_x = sin 4y, dt = 1e-3)
+                        over a 100-step window: the field after 100 steps
+                        from the random-phase field of seed 0 (k0 = 6,
+                        energy 0.5), velocity probes at stride 16 at steps
+                        0, 50, 100 from the field of seed 1, and the cost and
+                        gradient at the seed-0 field.
 """
 
 import os
@@ -54,6 +61,24 @@ def ensemble_member17():
     np.savez(os.path.join(HERE, "ensemble_member17.npz"), shells=np.asarray(rows))
 
 
+def c2_100_steps():
+    N, H = 512, 100
+    ph = Physics(N=N, nu=1.0 / 40, dt=1e-3, mu=0.1, forcing_amp=1.0, forcing_k=4)
+    osteps = [0, 50, 100]
+    w0 = O.init_field(N, [0], kind=0, k0=6.0, target=0.5)[0]
+    truth = O.init_field(N, [1], kind=0, k0=6.0, target=0.5)[0]
+    omega_T = O.forward(w0, ph, H)[0]
+    _, _, mo = O.forward(truth, ph, H, Obs(16, osteps))
+    J, g = O.adjoint_gradient(w0, ph, H, Obs(16, osteps, mo))
+    np.savez(os.path.join(HERE, "c2_100_steps.npz"), obs_steps=np.array(osteps), obs=np.asarray(mo),
+             omega_T=np.asarray(omega_T), J=np.array(J), grad=g)
+
+
 if __name__ == "__main__":
-    c1_full_horizon()
-    ensemble_member17()
+    which = sys.argv[1:] or ["c1", "ensemble", "c2"]
+    if "c1" in which:
+        c1_full_horizon()
+    if "ensemble" in which:
+        ensemble_member17()
+    if "c2" in which:
+        c2_100_steps()

@@ -131,6 +131,26 @@ def test_c2_grid_short_parity():
     assert rel(g.cpu().numpy()[0], g_ref) < 1e-9
 
 
+def test_c2_100_step_field_and_gradient_against_oracle():
+    """The Kolmogorov configuration's physics on its 512^2 grid over 100 steps (forcing, drag,
+    nu = 1/40, dt = 1e-3): the field after 100 steps within 1e-11 and the cost and gradient of a
+    3-time observation window (stride 16) within 1e-11 and 1e-9 of the oracle's, stored by
+    tests/golden/make_oracle_fixtures.py."""
+    from paper_2602_14016_amd import Observations, Solver
+    print("CASE c2-100", flush=True)
+    N, H = 512, 100
+    ref = _golden("c2_100_steps.npz")
+    w0 = O.init_field(N, [0], kind=0, k0=6.0, target=0.5)[0]
+    s = Solver(N, 1, nu=1.0 / 40, dt=1e-3, mu=0.1, forcing_amp=1.0, forcing_k=4)
+    wT = s.forward(dev(w0[None]), H)["omega_T"]
+    osteps = [int(x) for x in ref["obs_steps"]]
+    J, g = s.adjoint_gradient(dev(w0[None]), H, Observations(16, osteps, dev(ref["obs"][None])), ckpt_every=25)
+    torch.cuda.synchronize()
+    assert rel(wT.cpu().numpy()[0], ref["omega_T"]) < 1e-11
+    assert abs(float(J.cpu()[0]) - float(ref["J"])) <= 1e-11 * float(ref["J"])
+    assert rel(g.cpu().numpy()[0], ref["grad"]) < 1e-9
+
+
 def test_largest_grid_gradient_parity():
     """1024^2, the largest grid: cost and gradient over 2 steps (one-step segments,
     so the segment recomputation runs) against the oracle, and the same gradient

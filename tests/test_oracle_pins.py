@@ -709,3 +709,11 @@ def test_stored_oracle_fixtures_are_intact():
     e[128, 128] = 1.0
     row0 = ensemble.shell_energy(g, np.conj(g.m_u) * dft.fft2(e), 85)
     assert np.allclose(sh[0], row0, rtol=1e-13, atol=0)
+    c2 = np.load(os.path.join(gold, "c2_100_steps.npz"))
+    assert c2["obs"].shape == (3, 2, 32, 32) and c2["grad"].shape == (512, 512) and c2["omega_T"].shape == (512, 512)
+    assert list(c2["obs_steps"]) == [0, 50, 100]
+    assert np.all(np.isfinite(c2["grad"])) and np.all(np.isfinite(c2["omega_T"])) and float(c2["J"]) > 0
+    ph2 = Physics(N=512, nu=1.0 / 40, dt=1e-3, mu=0.1, forcing_amp=1.0, forcing_k=4)
+    truth2 = O.init_field(512, [1], kind=0, k0=6.0, target=0.5)[0]
+    obs20 = O.forward(truth2, ph2, 0, Obs(16, [0]))[2][0]
+    assert np.allclose(c2["obs"][0], obs20, rtol=0, atol=1e-13 * np.abs(obs20).max())
