@@ -10,7 +10,9 @@ same shape (grid, physics, horizon, observation layout, kernel, iterations)
 that are waiting are admitted together as one batched solve.  A slot uploads
 its observations, forms the first guess, runs pa_assimilate on its stream and
 copies the result back; its memory is released for the next admission as soon
-as it finishes.  Solves on different slots overlap on the device.  Latency is
+as it finishes.  Each admitted group gets the largest checkpoint interval
+that fits its slot's share of the budget, so gradients recompute fewer
+segments (none when the whole trajectory fits); results do not depend on it.  Solves on different slots overlap on the device.  Latency is
 stamped from arrival to result-ready.
 
 Results of a request are identical whether it runs alone, batched with
@@ -31,7 +33,7 @@ import heapq
 import queue
 import threading
 import time
-from dataclasses import dataclass, field
+from dataclasses import dataclass, replace, field
 from typing import List, Optional
 
 import numpy as np
@@ -168,14 +170,21 @@ class GpuBackend:
         sv = self._solvers.get((slot, head.N, head.flow, len(group)))
         if sv is not None:
             sv._ws = None   # return the workspace to the allocator before the budget is released
+            # ... and its segments to the device: a cached workspace (tens of GB) would otherwise
+            # be split to serve smaller blocks and could no longer be handed back whole, so the
+            # next large workspace fails with most of the memory reserved but unused
+            torch.cuda.empty_cache()
 
 
 class Server:
     def __init__(self, hbm_budget_bytes, slots=4, max_batch=8, device="cuda:0", tiles=None, verbose=False,
-                 backend=None):
+                 backend=None, adaptive_ckpt=True):
         """tiles: optional {N: pa_tiles dict} applied to every solver of grid size N;
         verbose: print one line per finished group; backend: the device work
-        (GpuBackend by default; anything with footprint/run/release)."""
+        (GpuBackend by default; anything with footprint/run/release);
+        adaptive_ckpt: give each admitted group the largest checkpoint interval
+        that fits its share of the budget (fewer recomputed segments, the same
+        result bit for bit) instead of the requests' own."""
         self.backend = backend if backend is not None else GpuBackend(slots, device, tiles)
         self.verbose = verbose
         self.budget = int(hbm_budget_bytes)
@@ -186,6 +195,7 @@ class Server:
         self.queue: List[Request] = []
         self.results = {}
         self.cancelled = set()   # running requests asked to stop
+        self.adaptive_ckpt = adaptive_ckpt
         self.free_slots = list(range(slots))
         self.t0 = None
 
@@ -234,12 +244,39 @@ class Server:
                 continue
             if need > self.budget - self.in_use:
                 break   # wait for memory to free up
+            K = self._interval(head, len(group))
+            if K != head.ckpt_every:
+                for r in group:
+                    r.ckpt_every = K
+                need = self.backend.footprint(head, len(group))
             for r in group:
                 self.queue.remove(r)
             slot = self.free_slots.pop(0)
             self.in_use += need
             started.append((slot, group, need))
         return started
+
+    def _interval(self, head, B):
+        """The largest checkpoint interval, from the requests' own up to the whole horizon, whose
+        group footprint fits this slot's share of the budget and the memory free now.  A longer
+        interval recomputes fewer segments in every gradient (none once the whole trajectory is
+        kept), and the solve's result does not depend on it.  The footprint grows with the
+        interval (the segment store dominates), so a bisection finds it."""
+        own = max(1, min(head.ckpt_every, head.n_steps))
+        if not self.adaptive_ckpt or head.n_steps <= own:
+            return head.ckpt_every
+        share = min(self.budget // self.slots, self.budget - self.in_use)
+        fits = lambda k: self.backend.footprint(replace(head, ckpt_every=k), B) <= share
+        if fits(head.n_steps):
+            return head.n_steps
+        lo, hi = own, head.n_steps        # lo: the requests' own interval or one that fits
+        while hi - lo > 1:
+            mid = (lo + hi) // 2
+            if fits(mid):
+                lo = mid
+            else:
+                hi = mid
+        return lo
 
     def _run_group(self, slot, group, need):
         admitted = self.now()
@@ -361,10 +398,16 @@ def trace_report(results, requests, t_wall):
     ok = [r for r in results.values() if r.status == "ok"]
     work = sum(q.N * q.N * q.n_steps for q in requests if results[q.rid].status == "ok")
     out = latency_stats(results)
+    statuses = {}
+    for r in results.values():
+        statuses[r.status] = statuses.get(r.status, 0) + 1
     out.update({"requests": len(requests), "completed": len(ok), "wall_s": t_wall,
                 "throughput_req_per_s": len(ok) / t_wall if t_wall > 0 else None,
                 "grid_point_steps_per_iteration_per_s": work * (requests[0].iters if requests else 0) / t_wall,
-                "batched_solves": sum(1 for r in ok if r.batch > 1)})
+                "batched_solves": sum(1 for r in ok if r.batch > 1), "statuses": statuses,
+                "not_ok": [[q.rid, q.N, q.flow, q.n_steps, q.ckpt_every, results[q.rid].status]
+                           for q in requests if results[q.rid].status != "ok"],
+                "intervals": [[q.rid, q.N, q.n_steps, q.ckpt_every] for q in requests]})
     return out
 
 
@@ -380,6 +423,8 @@ def main(argv=None):
     ap.add_argument("--max-batch", type=int, default=8)
     ap.add_argument("--budget-gb", type=float, default=200.0)
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--fixed-ckpt", action="store_true",
+                    help="keep each request's own checkpoint interval (50) instead of the largest that fits")
     ap.add_argument("--out", default=None)
     args = ap.parse_args(argv)
     tiles = tile_table()
@@ -390,7 +435,7 @@ def main(argv=None):
         reqs = make_trace(args.requests, rate, seed=args.seed, iters=args.iters)
         print(f"trace {label}: {len(reqs)} requests at {rate:.2f}/s", flush=True)
         srv = Server(int(args.budget_gb * (1 << 30)), slots=args.slots, max_batch=args.max_batch, tiles=tiles,
-                     verbose=True)
+                     verbose=True, adaptive_ckpt=not args.fixed_ckpt)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         res = srv.run_trace(reqs)

@@ -201,3 +201,34 @@ def test_cancel_a_running_request_stops_it_alone():
     assert out[1].status == "cancelled" and 0 < out[1].iters < 40
     assert out[0].status == "ok" and out[0].iters == 40
     assert not srv.cancel(1) and not srv.cancel(0)        # finished
+
+
+class IntervalBackend(SleepBackend):
+    """Footprint grows with the checkpoint interval, as the segment store does."""
+
+    def footprint(self, req, B):
+        return B * (1000 + 10 * req.ckpt_every)
+
+    def run(self, slot, group):
+        with self.lock:
+            self.intervals = getattr(self, "intervals", []) + [(group[0].rid, group[0].ckpt_every)]
+        return super().run(slot, group)
+
+
+def test_admitted_groups_get_the_largest_interval_that_fits():
+    be = IntervalBackend(solve_s=0.01)
+    # budget 40000 over 2 slots: share 20000 -> 1000 + 10 K <= 20000 -> K = 1900 for one member
+    reqs = [req(0, n_steps=5000), req(1, n_steps=300), req(2, n_steps=40)]
+    for r in reqs:
+        r.ckpt_every = 50
+    res = Server(40000, slots=2, backend=be).run_trace(reqs)
+    assert all(r.status == "ok" for r in res.values())
+    got = dict(be.intervals)
+    assert got[0] == 1900            # the largest that fits the slot's share
+    assert got[1] == 300             # the whole horizon fits
+    assert got[2] == 50              # the own interval already covers the horizon
+    be2 = IntervalBackend(solve_s=0.01)
+    r = req(3, n_steps=5000)
+    r.ckpt_every = 50
+    Server(40000, slots=2, backend=be2, adaptive_ckpt=False).run_trace([r])
+    assert dict(be2.intervals)[3] == 50
