@@ -333,6 +333,9 @@ def main(argv=None):
     ap.add_argument("--batch", type=int, default=64, help="c3: members per batched solve")
     ap.add_argument("--budget-gib", type=float, default=16.0, help="longwindow: workspace budget")
     ap.add_argument("--batched", action="store_true", help="c0/c1/c2: all kernels as one batched solve")
+    ap.add_argument("--ckpt-every", type=int, default=None,
+                    help="c0/c1/c2: checkpoint interval instead of the configuration's (the horizon keeps the "
+                         "whole trajectory; results do not depend on it)")
     ap.add_argument("--flow", choices=["hit", "kolmogorov"], default="hit",
                     help="c3: decaying HIT (256^2) or forced Kolmogorov flow (512^2, T = 8; App. C)")
     args = ap.parse_args(argv)
@@ -386,6 +389,8 @@ def main(argv=None):
     if args.horizon:
         cfg.n_steps = args.horizon
         cfg.obs_steps = [s for s in cfg.obs_steps if s <= args.horizon] or [args.horizon]
+    if args.ckpt_every:
+        cfg.ckpt_every = args.ckpt_every
     run_config(cfg, args.iters, batched=args.batched)
 
 
