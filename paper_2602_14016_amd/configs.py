@@ -252,6 +252,22 @@ def run_sweep(cfg: Config, kernels, iters, sequential=True, verbose=True):
     return out
 
 
+def velocity_error_in_time(solver: Solver, truth, est, n_steps, n_points=11):
+    """The reconstruction error over the window, eps(t) / u_rms (Sec. III.C-D): the RMS velocity
+    error of the trajectory started from est against the truth's, over the truth's RMS velocity,
+    at n_points evenly spaced steps; velocities on the full grid are stride-1 observations.
+    truth is [1, N, N], est [B, N, N]; returns (steps, [B][n_points])."""
+    steps = evenly_spaced(n_steps, n_points)
+    full = Observations(1, steps)
+    B = est.shape[0]
+    if solver.B != B:
+        raise ValueError("est must have the solver's batch")
+    ut = solver.forward(truth.expand(B, -1, -1).contiguous(), n_steps, full, want_obs=True)["obs"]
+    ue = solver.forward(est, n_steps, full, want_obs=True)["obs"]
+    err = ((ue - ut) ** 2).sum(dim=(2, 3, 4)).sqrt() / (ut ** 2).sum(dim=(2, 3, 4)).sqrt()
+    return steps, err.cpu().tolist()
+
+
 def truth_and_obs(cfg: Config, solver: Solver):
     """Seeded truth (after spin-up) and its model observations [B, n_times, 2, M, M]."""
     w = solver.init_field([cfg.truth_seed + b for b in range(solver.B)], kind=cfg.truth_kind, k0=cfg.truth_k0,
@@ -283,9 +299,11 @@ def run_config(cfg: Config, iters=None, verbose=True, batched=False):
                                 cfg.ckpt_every)
         torch.cuda.synchronize()
         err = float(torch.linalg.norm(w - truth) / torch.linalg.norm(truth))
+        secs = time.perf_counter() - t1
+        t_steps, eps = velocity_error_in_time(s, truth, w, cfg.n_steps)
         rec = {"config": cfg.name, "kernel": [kern.kind, kern.param, kern.metric], "iterations": it[0],
-               "J": [h for h in H[0] if h == h], "rel_err_omega0": err, "seconds": time.perf_counter() - t1,
-               "setup_seconds": setup_s}
+               "J": [h for h in H[0] if h == h], "rel_err_omega0": err, "seconds": secs,
+               "setup_seconds": setup_s, "eps_over_urms": {"steps": t_steps, "value": eps[0]}}
         out.append(rec)
         if verbose:
             print(json.dumps(rec), flush=True)
@@ -312,12 +330,13 @@ def _run_config_batched(cfg: Config, iters, verbose):
                             iters or cfg.iters, cfg.lbfgs_m, cfg.ckpt_every)
     torch.cuda.synchronize()
     secs = time.perf_counter() - t1
+    t_steps, eps = velocity_error_in_time(s, truth, w, cfg.n_steps)
     out = []
     for b, kern in enumerate(cfg.kernels):
         err = float(torch.linalg.norm(w[b] - truth[0]) / torch.linalg.norm(truth[0]))
         rec = {"config": cfg.name + "-batched", "kernel": [kern.kind, kern.param, kern.metric], "iterations": it[b],
                "J": [h for h in H[b] if h == h], "rel_err_omega0": err, "seconds_all_kernels": secs,
-               "setup_seconds": setup_s}
+               "setup_seconds": setup_s, "eps_over_urms": {"steps": t_steps, "value": eps[b]}}
         out.append(rec)
         if verbose:
             print(json.dumps(rec), flush=True)

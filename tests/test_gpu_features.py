@@ -202,3 +202,30 @@ def test_ensemble_stats_rejects_empty_accumulator():
     acc = s.ensemble_accumulator(4, 5)
     with pytest.raises(PaError):
         s.ensemble_stats(acc)
+
+
+def test_velocity_error_in_time_against_oracle():
+    """eps(t)/u_rms of a trajectory against the truth's (full-grid velocities as stride-1
+    observations): 0 for the truth itself, 1 at every step for the zero field of a decaying flow,
+    and the oracle's value for another field."""
+    import numpy as np
+    import oracle as O
+    from oracle.model import Obs, Physics
+    from paper_2602_14016_amd import Solver
+    from paper_2602_14016_amd.configs import velocity_error_in_time
+    print("CASE eps-t", flush=True)
+    N, H = 32, 40
+    ph = Physics(N=N, nu=1e-3, dt=5e-3)
+    truth = O.init_field(N, [2], kind=0, k0=4.0)[0]
+    est = O.init_field(N, [3], kind=0, k0=4.0)[0]
+    s = Solver(N, 3, nu=ph.nu, dt=ph.dt)
+    t = torch.from_numpy(truth[None]).cuda()
+    e = torch.from_numpy(np.stack([truth, np.zeros((N, N)), est])).cuda()
+    steps, eps = velocity_error_in_time(s, t, e, H, n_points=5)
+    assert steps == [0, 10, 20, 30, 40]
+    assert all(v == 0.0 for v in eps[0])
+    assert all(abs(v - 1.0) < 1e-15 for v in eps[1])
+    ut = O.forward(truth, ph, H, Obs(1, steps))[2]
+    ue = O.forward(est, ph, H, Obs(1, steps))[2]
+    ref = [float(np.linalg.norm(ue[i] - ut[i]) / np.linalg.norm(ut[i])) for i in range(len(steps))]
+    assert np.allclose(eps[2], ref, rtol=1e-11, atol=0)
