@@ -292,17 +292,17 @@ def run_config(cfg: Config, iters=None, verbose=True, batched=False):
     else:
         fg = torch.zeros_like(truth)
     setup_s = time.perf_counter() - t0
+    K = cfg.ckpt_every if cfg.ckpt_every > 0 else s.fit_ckpt_every(cfg.n_steps, len(cfg.obs_steps), cfg.lbfgs_m)
     out = []
     for kern in cfg.kernels:
         t1 = time.perf_counter()
-        w, H, it = s.assimilate(fg, cfg.n_steps, obs, kern, cfg.method, iters or cfg.iters, cfg.lbfgs_m,
-                                cfg.ckpt_every)
+        w, H, it = s.assimilate(fg, cfg.n_steps, obs, kern, cfg.method, iters or cfg.iters, cfg.lbfgs_m, K)
         torch.cuda.synchronize()
         err = float(torch.linalg.norm(w - truth) / torch.linalg.norm(truth))
         secs = time.perf_counter() - t1
         t_steps, eps = velocity_error_in_time(s, truth, w, cfg.n_steps)
         rec = {"config": cfg.name, "kernel": [kern.kind, kern.param, kern.metric], "iterations": it[0],
-               "J": [h for h in H[0] if h == h], "rel_err_omega0": err, "seconds": secs,
+               "ckpt_every": K, "J": [h for h in H[0] if h == h], "rel_err_omega0": err, "seconds": secs,
                "setup_seconds": setup_s, "eps_over_urms": {"steps": t_steps, "value": eps[0]}}
         out.append(rec)
         if verbose:
@@ -324,10 +324,11 @@ def _run_config_batched(cfg: Config, iters, verbose):
     del s1
     s = Solver(cfg.N, nk, **cfg.physics())
     obs = Observations(cfg.stride, cfg.obs_steps, obs_vals.expand(nk, -1, -1, -1, -1).contiguous())
+    K = cfg.ckpt_every if cfg.ckpt_every > 0 else s.fit_ckpt_every(cfg.n_steps, len(cfg.obs_steps), cfg.lbfgs_m)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     w, H, it = s.assimilate(fg.expand(nk, -1, -1).contiguous(), cfg.n_steps, obs, list(cfg.kernels), cfg.method,
-                            iters or cfg.iters, cfg.lbfgs_m, cfg.ckpt_every)
+                            iters or cfg.iters, cfg.lbfgs_m, K)
     torch.cuda.synchronize()
     secs = time.perf_counter() - t1
     t_steps, eps = velocity_error_in_time(s, truth, w, cfg.n_steps)
@@ -335,7 +336,7 @@ def _run_config_batched(cfg: Config, iters, verbose):
     for b, kern in enumerate(cfg.kernels):
         err = float(torch.linalg.norm(w[b] - truth[0]) / torch.linalg.norm(truth[0]))
         rec = {"config": cfg.name + "-batched", "kernel": [kern.kind, kern.param, kern.metric], "iterations": it[b],
-               "J": [h for h in H[b] if h == h], "rel_err_omega0": err, "seconds_all_kernels": secs,
+               "ckpt_every": K, "J": [h for h in H[b] if h == h], "rel_err_omega0": err, "seconds_all_kernels": secs,
                "setup_seconds": setup_s, "eps_over_urms": {"steps": t_steps, "value": eps[b]}}
         out.append(rec)
         if verbose:
@@ -354,7 +355,7 @@ def main(argv=None):
     ap.add_argument("--batched", action="store_true", help="c0/c1/c2: all kernels as one batched solve")
     ap.add_argument("--ckpt-every", type=int, default=None,
                     help="c0/c1/c2: checkpoint interval instead of the configuration's (the horizon keeps the "
-                         "whole trajectory; results do not depend on it)")
+                         "whole trajectory, 0 the largest that fits in free HBM; results do not depend on it)")
     ap.add_argument("--flow", choices=["hit", "kolmogorov"], default="hit",
                     help="c3: decaying HIT (256^2) or forced Kolmogorov flow (512^2, T = 8; App. C)")
     args = ap.parse_args(argv)
@@ -408,7 +409,7 @@ def main(argv=None):
     if args.horizon:
         cfg.n_steps = args.horizon
         cfg.obs_steps = [s for s in cfg.obs_steps if s <= args.horizon] or [args.horizon]
-    if args.ckpt_every:
+    if args.ckpt_every is not None:
         cfg.ckpt_every = args.ckpt_every
     run_config(cfg, args.iters, batched=args.batched)
 
