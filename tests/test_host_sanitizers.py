@@ -3,7 +3,7 @@
 api.hip is compiled with both sanitizers on its host code only (every
 -fsanitize flag goes to the host pass; the device code is built as usual) and
 linked, with the library's other objects as built, into abi_host_driver.cpp.
-The driver calls the entry points that run without a device: argument
+The C++ program calls the entry points that run without a device: argument
 validation before any device call, and the binomial checkpoint schedule over
 every chain of up to 80 segments under budgets 1..10 plus long chains, each
 schedule replayed and its advance count compared with the optimum.  Any
