@@ -1,0 +1,61 @@
+"""Randomly drawn small problems (hypothesis, derandomised) through the library's
+C ABI against the oracle: grid 8..64, 1..3 members, horizon 1..10 steps, any
+checkpoint interval (ragged last segments included), any observation stride
+and set of observed steps, random viscosity, drag and forcing.  The cost of
+every member within 1e-11 and its gradient within 1e-9 (relative), as the
+fixed parity cases."""
+
+import numpy as np
+import pytest
+import torch
+from hypothesis import given, settings, strategies as st
+
+import oracle as O
+from oracle.model import Obs, Physics
+
+pytestmark = pytest.mark.gpu
+
+_SOLVERS = {}
+
+
+def _solver(N, B, ph):
+    from paper_2602_14016_amd import Solver
+    key = (N, B, ph.nu, ph.mu, ph.forcing_amp, ph.dt)
+    if key not in _SOLVERS:
+        _SOLVERS.clear()
+        _SOLVERS[key] = Solver(N, B=B, nu=ph.nu, dt=ph.dt, mu=ph.mu, forcing_amp=ph.forcing_amp, forcing_k=2)
+    return _SOLVERS[key]
+
+
+@st.composite
+def problems(draw):
+    N = draw(st.sampled_from([8, 16, 32, 64]))
+    B = draw(st.integers(1, 3))
+    steps = draw(st.integers(1, 10))
+    K = draw(st.integers(1, 12))
+    stride = draw(st.sampled_from([s for s in (1, 2, 4, 8) if N % s == 0 and N // s >= 2]))
+    osteps = sorted(draw(st.sets(st.integers(0, steps), min_size=1, max_size=4)))
+    ph = Physics(N=N, nu=draw(st.floats(1e-4, 2e-2)), dt=draw(st.floats(1e-3, 8e-3)),
+                 mu=draw(st.floats(0.0, 0.2)), forcing_amp=draw(st.sampled_from([0.0, 1.0])), forcing_k=2)
+    seed = draw(st.integers(0, 10 ** 6))
+    return N, B, steps, K, stride, osteps, ph, seed
+
+
+@settings(max_examples=15, deadline=None, derandomize=True)
+@given(p=problems())
+def test_random_gradient_cases_against_oracle(p):
+    from paper_2602_14016_amd import Observations
+    N, B, steps, K, stride, osteps, ph, seed = p
+    print("CASE random", N, B, steps, K, stride, osteps, ph, seed, flush=True)
+    w0 = O.init_field(N, [seed + b for b in range(B)], kind=0, k0=min(4.0, N / 4))
+    mo = np.stack([O.forward(O.init_field(N, [seed + 100 + b], kind=0, k0=min(4.0, N / 4))[0], ph, steps,
+                             Obs(stride, osteps))[2] for b in range(B)])
+    s = _solver(N, B, ph)
+    J, g = s.adjoint_gradient(torch.from_numpy(w0).cuda(), steps,
+                              Observations(stride, osteps, torch.from_numpy(mo).cuda()), ckpt_every=K)
+    torch.cuda.synchronize()
+    Jh, gh = J.cpu().numpy(), g.cpu().numpy()
+    for b in range(B):
+        Jr, gr = O.adjoint_gradient(w0[b], ph, steps, Obs(stride, osteps, mo[b]))
+        assert abs(float(Jh[b]) - Jr) <= 1e-11 * Jr, (b, float(Jh[b]), Jr)
+        assert np.linalg.norm(gh[b] - gr) <= 1e-9 * np.linalg.norm(gr), b
