@@ -105,3 +105,37 @@ def test_random_assimilation_cases_against_oracle(p):
         n = len(h_ref)
         assert np.allclose(np.array(H[b][:n]), np.array(h_ref), rtol=1e-9, atol=0), b
         assert np.linalg.norm(wh[b] - w_ref) <= 1e-9 * np.linalg.norm(w_ref), b
+
+
+@st.composite
+def impulse_problems(draw):
+    N = draw(st.sampled_from([8, 16, 32]))
+    B = draw(st.integers(1, 3))
+    steps = draw(st.integers(1, 10))
+    K = draw(st.integers(1, 12))
+    ix, iy = draw(st.integers(0, N - 1)), draw(st.integers(0, N - 1))
+    n_shells = draw(st.integers(1, (N - 1) // 3))
+    ph = Physics(N=N, nu=draw(st.floats(1e-4, 1e-2)), dt=draw(st.floats(1e-3, 6e-3)),
+                 mu=draw(st.floats(0.0, 0.2)), forcing_amp=draw(st.sampled_from([0.0, 1.0])), forcing_k=2)
+    seed = draw(st.integers(0, 10 ** 6))
+    return N, B, steps, K, ix, iy, n_shells, ph, seed
+
+
+@settings(max_examples=10, deadline=None, derandomize=True)
+@given(p=impulse_problems())
+def test_random_impulse_cases_against_oracle(p):
+    """Randomly drawn adjoint impulse responses (Sec. IV): the shell energies after every backward
+    step and the final adjoint field of every member against the oracle, for any impulse point,
+    shell count and checkpoint interval."""
+    N, B, steps, K, ix, iy, n_shells, ph, seed = p
+    print("CASE random-impulse", N, B, steps, K, ix, iy, n_shells, ph, seed, flush=True)
+    w0 = O.init_field(N, [seed + b for b in range(B)], kind=0, k0=min(4.0, N / 4))
+    s = _solver(N, B, ph)
+    sh, f = s.adjoint_impulse(torch.from_numpy(w0).cuda(), steps, ix, iy, n_shells, ckpt_every=K, want_field=True)
+    torch.cuda.synchronize()
+    shh, fh = sh.cpu().numpy(), f.cpu().numpy()
+    for b in range(B):
+        rows, field = O.impulse_adjoint(w0[b], ph, steps, ix, iy, n_shells)
+        rows = np.asarray(rows)
+        assert np.linalg.norm(shh[b] - rows) <= 1e-9 * np.linalg.norm(rows), b
+        assert np.linalg.norm(fh[b] - field) <= 1e-9 * np.linalg.norm(field), b
