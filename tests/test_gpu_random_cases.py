@@ -1,7 +1,8 @@
 """Randomly drawn small problems (hypothesis, derandomised) through the library's
 C ABI against the oracle: grid 8..64, 1..3 members, horizon 1..10 steps, any
-checkpoint interval (ragged last segments included), any observation stride
-and set of observed steps, random viscosity, drag and forcing.  The cost of
+checkpoint interval (ragged last segments included) and snapshot budget
+(binomial schedule), any observation stride and set of observed steps, random
+viscosity, drag and forcing.  The cost of
 every member within 1e-11 and its gradient within 1e-9 (relative), as the
 fixed parity cases."""
 
@@ -38,21 +39,25 @@ def problems(draw):
     ph = Physics(N=N, nu=draw(st.floats(1e-4, 2e-2)), dt=draw(st.floats(1e-3, 8e-3)),
                  mu=draw(st.floats(0.0, 0.2)), forcing_amp=draw(st.sampled_from([0.0, 1.0])), forcing_k=2)
     seed = draw(st.integers(0, 10 ** 6))
-    return N, B, steps, K, stride, osteps, ph, seed
+    n_seg = -(-steps // min(K, steps))
+    slots = draw(st.sampled_from(list(range(1, n_seg + 1)) + [0]))   # 0: one checkpoint per boundary
+    return N, B, steps, K, stride, osteps, ph, seed, slots
 
 
 @settings(max_examples=15, deadline=None, derandomize=True)
 @given(p=problems())
 def test_random_gradient_cases_against_oracle(p):
     from paper_2602_14016_amd import Observations
-    N, B, steps, K, stride, osteps, ph, seed = p
-    print("CASE random", N, B, steps, K, stride, osteps, ph, seed, flush=True)
+    N, B, steps, K, stride, osteps, ph, seed, slots = p
+    print("CASE random", N, B, steps, K, stride, osteps, ph, seed, slots, flush=True)
     w0 = O.init_field(N, [seed + b for b in range(B)], kind=0, k0=min(4.0, N / 4))
     mo = np.stack([O.forward(O.init_field(N, [seed + 100 + b], kind=0, k0=min(4.0, N / 4))[0], ph, steps,
                              Obs(stride, osteps))[2] for b in range(B)])
     s = _solver(N, B, ph)
+    s.set_checkpoint_slots(slots)
     J, g = s.adjoint_gradient(torch.from_numpy(w0).cuda(), steps,
                               Observations(stride, osteps, torch.from_numpy(mo).cuda()), ckpt_every=K)
+    s.set_checkpoint_slots(0)
     torch.cuda.synchronize()
     Jh, gh = J.cpu().numpy(), g.cpu().numpy()
     for b in range(B):
