@@ -86,3 +86,22 @@ def test_cancel_a_running_request():
     assert res.status == "cancelled", res.status
     assert 0 <= res.iters < 400 and res.omega0 is not None and torch.isfinite(res.omega0).all()
     assert len(res.J_hist) == res.iters + 1
+
+
+def test_adaptive_interval_gives_the_same_results():
+    """The server's per-group checkpoint interval (the largest its budget share holds) changes
+    only how much is recomputed: every request's field and cost history are bitwise those of
+    its own interval."""
+    from paper_2602_14016_amd.serving import Server
+    print("CASE serving-interval", flush=True)
+    reqs_a = _make_requests(seed=1)
+    reqs_f = _make_requests(seed=1)
+    for r in reqs_a + reqs_f:
+        r.ckpt_every = 4
+    res_a = Server(hbm_budget_bytes=8 << 30, slots=2).run_trace(reqs_a)
+    res_f = Server(hbm_budget_bytes=8 << 30, slots=2, adaptive_ckpt=False).run_trace(reqs_f)
+    assert any(r.ckpt_every > 4 for r in reqs_a) and all(r.ckpt_every == 4 for r in reqs_f)
+    for r in reqs_a:
+        a, f = res_a[r.rid], res_f[r.rid]
+        assert a.status == f.status == "ok", (a.status, f.status)
+        assert torch.equal(a.omega0, f.omega0) and a.J_hist == f.J_hist, r.rid
