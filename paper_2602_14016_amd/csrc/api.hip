@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -125,6 +126,8 @@ struct pa_ctx {
     long prof_seen = 0;
     size_t prof_used = 0;
     std::vector<hipEvent_t> prof_ev;   // pairs (start, stop)
+    // (kind, metric, param, power) of multiplier tables already found finite on this grid
+    std::vector<std::array<double, 4>> mult_checked;
 };
 
 namespace {
@@ -867,6 +870,43 @@ pa_status valid_kernel(const pa_kernel* k) {
     return PA_OK;
 }
 
+// The multiplier (m^2 W)^power must be finite on the whole band of the
+// context's grid.  It is evaluated here with the operations of
+// make_mult_kernel (W, then m^2 W, then the power), before anything is
+// enqueued: a kernel whose W underflows to zero where it is inverted, or whose
+// power leaves the double range, has no finite latent map on this grid and is
+// refused rather than turned into infinite fields.  The multiplier depends on
+// kx^2 + ky^2 only, so 0 <= kx <= ky <= Kc covers the band.  Tables found
+// finite are remembered per context.
+pa_status check_multiplier(pa_ctx* c, const pa_kernel* k, double power) {
+    const std::array<double, 4> key{(double)k->kind, (double)k->metric, k->param, power};
+    for (const auto& q : c->mult_checked)
+        if (q == key) return PA_OK;
+    const int K = c->d.K;
+    for (int ky = 1; ky <= K; ++ky) {
+        for (int kx = 0; kx <= ky; ++kx) {
+            const double k2 = (double)kx * kx + (double)ky * ky;
+            const double kap = std::sqrt(k2);
+            double W = 1.0;
+            if (k->kind == 1) W = std::exp(-k->param * kap);
+            else if (k->kind == 2) W = std::pow(kap, -2.0 * k->param);
+            else if (k->kind == 3) W = std::exp(-k->param * k2);
+            const double base = (k->metric == 0 ? k2 : k->metric == 2 ? k2 * k2 : 1.0) * W;
+            const double v = std::pow(base, power);
+            if (!std::isfinite(v)) {
+                char msg[256];
+                std::snprintf(msg, sizeof msg,
+                              "kernel (kind %d, metric %d, param %.17g) to the power %.17g is not finite at "
+                              "|k| = %.6g of the %d^2 grid's band: no finite preconditioner there",
+                              k->kind, k->metric, k->param, power, kap, c->d.N);
+                return fail(PA_EINVAL, msg);
+            }
+        }
+    }
+    c->mult_checked.push_back(key);
+    return PA_OK;
+}
+
 // host twiddle exp(-2 pi i m/N) from the first octant with exact symmetries
 void host_twiddles(int N, std::vector<cd>& tw) {
     tw.resize(N);
@@ -1365,6 +1405,7 @@ pa_status pa_precondition(pa_ctx* c, const pa_kernel* k, double power, const dou
     if (!c || !in || !out) return fail(PA_EINVAL, "NULL argument");
     PA_TRY(valid_kernel(k));
     if (!std::isfinite(power)) return fail(PA_EINVAL, "power must be finite");
+    PA_TRY(check_multiplier(c, k, power));
     PA_TRY(require_device(c->stream, {{in, "in"}, {out, "out"}, {workspace, "workspace"}}));
     WS w;
     PA_TRY(check_ws(c, workspace, wbytes, 0, 1, 0, 0, &w));
@@ -1460,7 +1501,11 @@ static pa_status assimilate_impl(pa_ctx* c, double* omega_inout, int32_t n_steps
     g_err.clear();
     if (!c || !omega_inout || !J_hist || !iters_done) return fail(PA_EINVAL, "NULL argument");
     if (!kernels) return fail(PA_EINVAL, "kernel is NULL");
-    for (int b = 0; b < (per_member ? c->d.B : 1); ++b) PA_TRY(valid_kernel(&kernels[b]));
+    for (int b = 0; b < (per_member ? c->d.B : 1); ++b) {
+        PA_TRY(valid_kernel(&kernels[b]));
+        PA_TRY(check_multiplier(c, &kernels[b], 0.5));
+        PA_TRY(check_multiplier(c, &kernels[b], -0.5));
+    }
     if (method != 0 && method != 1) return fail(PA_EINVAL, "method must be 0 (L-BFGS) or 1 (steepest descent)");
     if (max_iter < 0 || n_steps < 0 || ckpt_every < 1) return fail(PA_EINVAL, "bad sizes");
     if (method == 0 && lbfgs_m < 1) return fail(PA_EINVAL, "lbfgs_m must be >= 1");

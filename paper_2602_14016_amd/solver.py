@@ -56,6 +56,15 @@ def _need(t, shape, name):
         raise ValueError(f"{name} must be contiguous")
 
 
+def _need_bytes(t, nbytes, name):
+    if not (isinstance(t, torch.Tensor) and t.dtype == torch.uint8 and t.is_cuda):
+        raise TypeError(f"{name} must be a uint8 CUDA tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.numel() < nbytes:
+        raise ValueError(f"{name} holds {t.numel()} bytes, needs {nbytes}")
+
+
 def checkpoint_advances(n_segments, slots):
     """Segment advances of the binomial schedule for n_segments and `slots` snapshot slots (host only)."""
     v = ctypes.c_int64()
@@ -92,6 +101,20 @@ class Solver:
         self._cancel = None
 
     # ------------------------------------------------------------- plumbing
+    def _obs(self, obs: Observations, need_values=False):
+        """The C struct of obs (and the step array it points to) after checking that its values,
+        which the library reads through a bare pointer, are a contiguous float64 tensor of shape
+        [B, n_times, 2, M, M] on the device (M = N / stride)."""
+        stride = int(obs.stride)
+        if stride < 1 or self.N % stride:
+            raise ValueError(f"observation stride {stride} must divide N = {self.N}")
+        if obs.values is not None:
+            M = self.N // stride
+            _need(obs.values, (self.B, len(obs.steps), 2, M, M), "observation values")
+        elif need_values:
+            raise ValueError("observation values are required")
+        return obs.c()
+
     def _stream_handle(self):
         s = self.stream if self.stream is not None else torch.cuda.current_stream(self.device)
         return c_void_p(s.cuda_stream)
@@ -268,7 +291,9 @@ class Solver:
         o_c = None
         keep = None
         if obs is not None:
-            o_c, keep = obs.c()
+            o_c, keep = self._obs(obs)
+        if ckpt is not None:
+            _need_bytes(ckpt, self.checkpoint_bytes(n_steps, ckpt_every), "ckpt")
         if want_J is None:
             want_J = obs is not None and obs.values is not None
         J = torch.empty(self.B, dtype=torch.float64, device=self.device) if want_J else None
@@ -288,7 +313,7 @@ class Solver:
     def adjoint_gradient(self, omega0, n_steps, obs: Observations, ckpt_every=50):
         _need(omega0, (self.B, self.N, self.N), "omega0")
         self._sync_stream()
-        o_c, keep = obs.c()
+        o_c, keep = self._obs(obs, need_values=True)
         J = torch.empty(self.B, dtype=torch.float64, device=self.device)
         g = self.empty()
         ws, wb = self.workspace(n_steps, ckpt_every, len(obs.steps))
@@ -298,8 +323,11 @@ class Solver:
         return J, g
 
     def adjoint_from_checkpoints(self, ckpt, n_steps, obs: Observations, ckpt_every, scale=None):
+        _need_bytes(ckpt, self.checkpoint_bytes(n_steps, ckpt_every), "ckpt")
+        if scale is not None:
+            _need(scale, (self.B,), "scale")
         self._sync_stream()
-        o_c, keep = obs.c()
+        o_c, keep = self._obs(obs, need_values=True)
         g = self.empty()
         ws, wb = self.workspace(n_steps, ckpt_every, len(obs.steps))
         nv.check(self.lib.pa_adjoint_from_checkpoints(self.ctx, _ptr(ckpt), int(n_steps), byref(o_c), _ptr(scale),
@@ -339,7 +367,7 @@ class Solver:
             raise ValueError(f"{len(kernel)} kernels for {self.B} members")
         self._sync_stream()
         w = omega_fg.clone()
-        o_c, keep = obs.c()
+        o_c, keep = self._obs(obs, need_values=True)
         hist = (c_double * (self.B * (max_iter + 1)))()
         iters = (c_int32 * self.B)()
         m = int(lbfgs_m) if method == "lbfgs" else 1

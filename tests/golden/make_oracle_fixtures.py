@@ -23,6 +23,22 @@ here from the oracle's seeded initial fields.  The GPU tests load the files
                         energy 0.5), velocity probes at stride 16 at steps
                         0, 50, 100 from the field of seed 1, and the cost and
                         gradient at the seed-0 field.
+  c1_grid_lbfgs.npz     L-BFGS at the differentiation configuration's grid and
+                        physics (256^2, nu = 1e-4, dt = 2e-3) over a 50-step
+                        window: probes at stride 8 at steps 0, 12, 25, 38, 50
+                        from the truth of seed 0 (random phase, k0 = 10,
+                        energy 0.5), the interpolated first guess from the
+                        t = 0 probes, kernel exp(-0.05 |k|) in the velocity
+                        metric, memory 10: the cost after each of 10
+                        iterations and the estimates after 1, 5 and 10.
+  grid1024_50_steps.npz the largest grid (1024^2, nu = 1e-4, dt = 5e-4) over 50
+                        steps from the random-phase field of seed 3 (k0 =
+                        1024/25, energy 0.5): the field after 50 steps and the
+                        cost and gradient of velocity probes at stride 16 at
+                        steps 0, 25, 50 from the field of seed 4.  The field
+                        and gradient are kept at every 4th grid point in each
+                        direction (the tests compare those samples), the cost
+                        in full.
 """
 
 import os
@@ -74,11 +90,48 @@ def c2_100_steps():
              omega_T=np.asarray(omega_T), J=np.array(J), grad=g)
 
 
+def c1_grid_lbfgs():
+    from oracle.precond import Kernel
+    N, H, stride = 256, 50, 8
+    ph = Physics(N=N, nu=1e-4, dt=2e-3)
+    osteps = evenly_spaced(H, 5)
+    truth = O.init_field(N, [0], kind=0, k0=10.0, target=0.5)[0]
+    _, _, mo = O.forward(truth, ph, H, Obs(stride, osteps))
+    fg = O.first_guess(N, stride, mo[0])
+    kern = Kernel(1, 0.05, 0)
+    out = {"obs_steps": np.array(osteps), "obs": np.asarray(mo), "first_guess": fg}
+    for k in (1, 5, 10):
+        w, hist, it, status = O.assimilate(fg, ph, H, Obs(stride, osteps, mo), kern, "lbfgs", k, 10)
+        assert status == 0 and it == k, (status, it)
+        out[f"omega_{k}"] = w
+        out[f"J_hist_{k}"] = np.array(hist)
+        print(f"c1 grid L-BFGS: {k} iterations, J {hist[0]:.6e} -> {hist[-1]:.6e}", flush=True)
+    np.savez(os.path.join(HERE, "c1_grid_lbfgs.npz"), **out)
+
+
+def grid1024_50_steps():
+    N, H, stride, every = 1024, 50, 16, 4
+    ph = Physics(N=N, nu=1e-4, dt=5e-4)
+    osteps = [0, 25, 50]
+    w0 = O.init_field(N, [3], kind=0, k0=N / 25.0, target=0.5)[0]
+    truth = O.init_field(N, [4], kind=0, k0=N / 25.0, target=0.5)[0]
+    omega_T = O.forward(w0, ph, H)[0]
+    _, _, mo = O.forward(truth, ph, H, Obs(stride, osteps))
+    J, g = O.adjoint_gradient(w0, ph, H, Obs(stride, osteps, mo))
+    np.savez(os.path.join(HERE, "grid1024_50_steps.npz"), obs_steps=np.array(osteps), obs=np.asarray(mo),
+             sample_every=np.array(every), omega_T=np.asarray(omega_T)[::every, ::every].copy(), J=np.array(J),
+             grad=np.asarray(g)[::every, ::every].copy())
+
+
 if __name__ == "__main__":
-    which = sys.argv[1:] or ["c1", "ensemble", "c2"]
+    which = sys.argv[1:] or ["c1", "ensemble", "c2", "lbfgs", "1024"]
     if "c1" in which:
         c1_full_horizon()
     if "ensemble" in which:
         ensemble_member17()
     if "c2" in which:
         c2_100_steps()
+    if "lbfgs" in which:
+        c1_grid_lbfgs()
+    if "1024" in which:
+        grid1024_50_steps()

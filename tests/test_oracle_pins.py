@@ -377,6 +377,17 @@ def test_splitmix64_mix_is_a_bijection_and_uniform():
     assert u.min() >= 0.0 and u.max() < 1.0
 
 
+def test_splitmix64_known_answers():
+    """Known-answer pin of the generator: the published SplitMix64 stream seeded with 0 (the
+    reference generator advances its state by the golden-ratio increment, then mixes it, so its
+    n-th output is output n of this counter form).  A wrong increment or multiplier anywhere
+    changes these."""
+    z = fields.splitmix64(0, np.arange(1, 4, dtype=np.uint64))
+    assert [int(v) for v in z] == [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F]
+    # uniforms are the top 53 bits
+    assert fields.uniform01(z[:1])[0] == (0xE220A8397B1DCDAF >> 11) * 2.0 ** -53
+
+
 @pytest.mark.parametrize("kind", [0, 1])
 def test_init_field_energy_and_spectrum(kind):
     N = 64
