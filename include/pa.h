@@ -227,6 +227,28 @@ pa_status pa_assimilate_kernels(pa_ctx* ctx, double* omega_inout, int32_t n_step
                                 int32_t lbfgs_m, int32_t ckpt_every, double* J_hist,
                                 int32_t* iters_done, void* workspace, size_t workspace_bytes);
 
+/* pa_assimilate_kernels with one observation set per member: the requests
+ * of a serving queue that share a grid and physics but differ in horizon,
+ * probe stride, observation times and kernel, as one batched solve
+ * (Sec. II.A Eqs. (2)-(3) per member; Sec. II.C).  obs: host array of B
+ * sets, each with its own stride, n_times >= 1 increasing steps and values
+ * (device [1][n_times][2][M_b][M_b] of that member alone, M_b = N / stride_b);
+ * kernels: host array of B.  A member's horizon is its last observation
+ * step; n_steps must be the latest of them.  Member b advances only through
+ * its own horizon (the steps past it are not computed for it), and its cost,
+ * gradients, iterates, J_hist row and iteration count are those of
+ * pa_assimilate_kernels run for it alone with its own horizon, bit for bit.
+ * Members ordered by decreasing horizon share every launch of a step; the
+ * order does not change results.  Workspace: pa_workspace_bytes(ctx,
+ * n_steps, ckpt_every, largest n_times, lbfgs_m).  The snapshot budget must
+ * be 0 (one checkpoint per segment boundary).  PA_EINVAL for a member
+ * without observations or n_steps other than the latest horizon.
+ * Synchronises the stream. */
+pa_status pa_assimilate_members(pa_ctx* ctx, double* omega_inout, int32_t n_steps, const pa_obs* obs,
+                                const pa_kernel* kernels, int32_t method, int32_t max_iter,
+                                int32_t lbfgs_m, int32_t ckpt_every, double* J_hist,
+                                int32_t* iters_done, void* workspace, size_t workspace_bytes);
+
 /* Cancellation of running 4D-Var members: flags is host memory [B] (or
  * NULL to switch it off) that pa_assimilate* read, never write, at every
  * iteration boundary; another thread may set an entry non-zero at any time.

@@ -351,18 +351,44 @@ const std::vector<PlanAct>* plan_for(pa_ctx* c, int nseg) {
 
 // --------------------------------------------------------- validation --
 
-struct ObsPlan {
-    std::vector<int> slot_of;   // step -> slot or -1
+// Observations of a solve as ranges of members [b0, b0 + nb) that share one
+// observation set (stride, steps, values): one range when every member has
+// the same set (a pa_obs), one per member for per-member sets.  Observation
+// work at a step is launched range by range on the members' slices of the
+// buffers, so a shared set costs exactly one launch per observed step.
+struct ObsRange {
+    int b0 = 0, nb = 0;
     int stride = 1, M = 1, n_times = 0;
-    const double* values = nullptr;
+    const int32_t* steps = nullptr;     // host, strictly increasing
+    const double* values = nullptr;     // device [nb][n_times][2][M][M], or null
+    size_t jrow0 = 0;                   // first cost-partial row of the range ([nb][n_times][M] rows)
+    // index of step n among the observation steps, or -1 (binary search; allocates nothing)
+    int slot(int n) const {
+        int lo = 0, hi = n_times;
+        while (lo < hi) {
+            const int mid = (lo + hi) / 2;
+            if (steps[mid] < n) lo = mid + 1;
+            else hi = mid;
+        }
+        return (lo < n_times && steps[lo] == n) ? lo : -1;
+    }
 };
 
-pa_status make_obs_plan(const pa_ctx* c, const pa_obs* obs, int n_steps, bool need_values, ObsPlan* p) {
-    p->slot_of.assign((size_t)n_steps + 1, -1);
-    if (!obs) {
-        if (need_values) return fail(PA_EINVAL, "observations required");
-        return PA_OK;
-    }
+struct ObsPlan {
+    ObsRange one;                       // storage of a set shared by every member
+    const ObsRange* r = nullptr;        // the ranges (n = 0: no observations)
+    int n = 0;
+    int B = 0;
+    bool values = false;                // every range has values: the cost is formed
+    int max_times = 0;                  // most observation times of a range
+    // active[n]: the members [0, active[n]) advance through step n (n < n_steps); null: all of
+    // them at every step.  A member whose last observation is at step L needs steps 0 .. L-1
+    // only; members past their horizon keep their buffers untouched.
+    const int* active = nullptr;
+    int act(int step) const { return active ? active[step] : B; }
+};
+
+pa_status check_obs_set(const pa_ctx* c, const pa_obs* obs, int n_steps, bool need_values) {
     if (obs->stride < 1 || obs->stride > c->d.N || c->d.N % obs->stride)
         return fail(PA_EINVAL, "obs stride must divide N");
     if (obs->n_times < 0 || obs->n_times > n_steps + 1) return fail(PA_EINVAL, "bad n_times");
@@ -372,13 +398,78 @@ pa_status make_obs_plan(const pa_ctx* c, const pa_obs* obs, int n_steps, bool ne
     for (int i = 0; i < obs->n_times; ++i) {
         const int s = obs->steps[i];
         if (s <= prev || s > n_steps) return fail(PA_EINVAL, "obs steps must increase within [0, n_steps]");
-        p->slot_of[(size_t)s] = i;
         prev = s;
     }
-    p->stride = obs->stride;
-    p->M = c->d.N / obs->stride;
-    p->n_times = obs->n_times;
-    p->values = obs->values;
+    return PA_OK;
+}
+
+void fill_range(const pa_ctx* c, const pa_obs* obs, int b0, int nb, size_t jrow0, ObsRange* r) {
+    r->b0 = b0;
+    r->nb = nb;
+    r->stride = obs->stride;
+    r->M = c->d.N / obs->stride;
+    r->n_times = obs->n_times;
+    r->steps = obs->steps;
+    r->values = obs->values;
+    r->jrow0 = jrow0;
+}
+
+// One observation set for every member (obs may be NULL: no observations).
+pa_status make_obs_plan(const pa_ctx* c, const pa_obs* obs, int n_steps, bool need_values, ObsPlan* p) {
+    p->B = c->d.B;
+    p->n = 0;
+    p->r = nullptr;
+    p->active = nullptr;
+    p->values = false;
+    p->max_times = 0;
+    if (!obs) {
+        if (need_values) return fail(PA_EINVAL, "observations required");
+        return PA_OK;
+    }
+    PA_TRY(check_obs_set(c, obs, n_steps, need_values));
+    fill_range(c, obs, 0, c->d.B, 0, &p->one);
+    p->r = &p->one;
+    p->n = obs->n_times > 0 ? 1 : 0;
+    p->values = obs->values != nullptr;
+    p->max_times = obs->n_times;
+    return PA_OK;
+}
+
+// One observation set per member (obs: host array of B, each with values for its own member
+// only, [1][n_times][2][M][M]).  n_steps must be the latest observation step of all members.
+// Member b advances only through its own last observation step; ranges and active counts live
+// in the caller's vectors.
+pa_status make_member_plan(const pa_ctx* c, const pa_obs* obs, int n_steps, std::vector<ObsRange>& ranges,
+                           std::vector<int>& active, ObsPlan* p) {
+    const int B = c->d.B;
+    p->B = B;
+    ranges.assign((size_t)B, ObsRange());
+    std::vector<int> top((size_t)n_steps + 1, 0);   // top[t]: 1 + last member whose horizon is t
+    size_t jrow = 0;
+    int latest = -1, most = 0;
+    for (int b = 0; b < B; ++b) {
+        PA_TRY(check_obs_set(c, &obs[b], n_steps, true));
+        if (obs[b].n_times < 1) return fail(PA_EINVAL, "every member needs at least one observation time");
+        fill_range(c, &obs[b], b, 1, jrow, &ranges[(size_t)b]);
+        jrow += (size_t)obs[b].n_times * (size_t)(c->d.N / obs[b].stride);
+        const int last = obs[b].steps[obs[b].n_times - 1];
+        top[(size_t)last] = b + 1;
+        latest = std::max(latest, last);
+        most = std::max(most, (int)obs[b].n_times);
+    }
+    if (latest != n_steps) return fail(PA_EINVAL, "n_steps must equal the latest observation step of the members");
+    // active[n] = 1 + last member whose horizon exceeds n (a suffix maximum of top)
+    active.assign((size_t)n_steps + 1, 0);
+    int run = 0;
+    for (int t = n_steps; t >= 0; --t) {
+        active[(size_t)t] = run;          // members with horizon > t
+        run = std::max(run, top[(size_t)t]);
+    }
+    p->r = ranges.data();
+    p->n = B;
+    p->values = true;
+    p->max_times = most;
+    p->active = active.data();
     return PA_OK;
 }
 
@@ -430,17 +521,108 @@ hipError_t timed(pa_ctx* c, int cls, F&& launch) {
 
 // -------------------------------------------------------------- sweeps --
 
-RowObs row_obs_args(const ObsPlan& op, int slot, double* obs_out, double* jpart) {
+RowObs row_obs_args(const ObsRange* r, int slot, double* obs_out, double* jpart) {
     RowObs o{};
     o.slot = slot;
-    o.stride = op.stride;
-    o.M = op.M;
-    o.n_times = op.n_times;
-    o.values = op.values;
+    if (r) {
+        o.stride = r->stride;
+        o.M = r->M;
+        o.n_times = r->n_times;
+        o.values = r->values;
+    } else {
+        o.stride = o.M = 1;
+    }
     o.obs_out = obs_out;
     o.jpart = jpart;
     o.imp_x = o.imp_y = -1;
     return o;
+}
+
+// Per-member sizes of the buffer kinds, for launches on a slice of members.
+size_t per_y(const pa_ctx* c) { return (size_t)c->d.N * c->d.KXP; }
+size_t per_c(const pa_ctx* c) { return (size_t)c->d.KY * c->d.KXP; }
+
+// Members [lo, hi) of a context's batch as a launch of their own.
+Dims slice_dims(const pa_ctx* c, int lo, int hi) {
+    Dims d = c->d;
+    d.B = hi - lo;
+    (void)lo;
+    return d;
+}
+
+// Observation of range r at its slot (velocity probes and cost partials) from the
+// stage-a fields (U, V first) of the state at that step.
+pa_status observe_range(pa_ctx* c, WS& w, const ObsRange& r, int slot, cd* const fields[4], double* obs_out) {
+    RowArgs ra{};
+    ra.yin[0] = fields[0] + (size_t)r.b0 * per_y(c);
+    ra.yin[1] = fields[1] + (size_t)r.b0 * per_y(c);
+    ra.tw = c->tw;
+    ra.obs = row_obs_args(&r, slot, obs_out, w.jpart + r.jrow0);
+    PA_HIP(launch_row_obs(slice_dims(c, r.b0, r.b0 + r.nb), ra, c->stream));
+    return PA_OK;
+}
+
+// Every range observed at step n.
+pa_status observe_step(pa_ctx* c, WS& w, const ObsPlan& op, int n, cd* const fields[4], double* obs_out) {
+    for (int i = 0; i < op.n; ++i) {
+        const int slot = op.r[i].slot(n);
+        if (slot >= 0) PA_TRY(observe_range(c, w, op.r[i], slot, fields, obs_out));
+    }
+    return PA_OK;
+}
+
+// Residual source rows (-S^T r_u, -S^T r_v, row-transformed) of the members [lo, hi) of
+// range r at its slot, into out[0..1] (full-batch buffers; the slice is written).
+pa_status source_rows(pa_ctx* c, const ObsRange& r, int slot, int lo, int hi, cd* const fields[4],
+                      cd* const out[2]) {
+    const size_t off = (size_t)lo * per_y(c);
+    RowArgs rs{};
+    rs.yin[0] = fields[0] + off;
+    rs.yin[1] = fields[1] + off;
+    rs.yout[0] = out[0] + off;
+    rs.yout[1] = out[1] + off;
+    rs.tw = c->tw;
+    rs.obs = row_obs_args(&r, slot, nullptr, nullptr);
+    if (r.values) rs.obs.values = r.values + (size_t)(lo - r.b0) * r.n_times * 2 * r.M * r.M;
+    PA_HIP(launch_row_src(slice_dims(c, lo, hi), rs, 0, c->stream));
+    return PA_OK;
+}
+
+// Source rows at step n for the members [lo, hi): the observing ranges write their
+// members' rows; the rest of the slice is zeroed unless the ranges cover it.  Returns
+// (in *any) whether some member of the slice observes at n.
+pa_status sources_at(pa_ctx* c, WS& w, const ObsPlan& op, int n, int lo, int hi, cd* const fields[4],
+                     cd* const out[2], bool* any) {
+    *any = false;
+    int covered = 0;
+    for (int i = 0; i < op.n; ++i) {
+        const ObsRange& r = op.r[i];
+        const int a = std::max(lo, r.b0), b = std::min(hi, r.b0 + r.nb);
+        if (a < b && r.slot(n) >= 0) covered += b - a;
+    }
+    if (covered == 0) return PA_OK;
+    *any = true;
+    if (covered < hi - lo) {
+        const size_t off = (size_t)lo * per_y(c), cnt = 2 * (size_t)(hi - lo) * per_y(c);
+        PA_HIP(launch_fill(reinterpret_cast<double*>(out[0] + off), 0.0, cnt, c->stream));
+        PA_HIP(launch_fill(reinterpret_cast<double*>(out[1] + off), 0.0, cnt, c->stream));
+    }
+    for (int i = 0; i < op.n; ++i) {
+        const ObsRange& r = op.r[i];
+        const int a = std::max(lo, r.b0), b = std::min(hi, r.b0 + r.nb);
+        const int slot = r.slot(n);
+        if (a < b && slot >= 0) PA_TRY(source_rows(c, r, slot, a, b, fields, out));
+    }
+    return PA_OK;
+}
+
+// Cost per member from the partial rows of every range (fixed order within a member).
+pa_status reduce_cost(pa_ctx* c, WS& w, const ObsPlan& op) {
+    for (int i = 0; i < op.n; ++i) {
+        const ObsRange& r = op.r[i];
+        PA_HIP(launch_reduce_j(r.nb, r.n_times * r.M, w.jpart + r.jrow0, w.J + r.b0, c->stream));
+    }
+    return PA_OK;
 }
 
 ColArgs col_base(const pa_ctx* c) {
@@ -488,13 +670,17 @@ struct CkptTarget {
 // `start` (which must equal the segment slot (0,0) when store).  With store
 // the fields of every stage are kept in the segment slots; otherwise they
 // live in w.Yf.  Checkpoints are written to ckpt (if it has a base) at the
-// boundaries, multiples of K and the final step n_total.  Observations via
-// op (J partials).
+// boundaries, multiples of K and the final step n_total.  With op, the
+// ranges observed at a step are observed from its stage-a fields before the
+// step (cost partials, model observations) when `observe`, and only the
+// members [0, op->act(n)) advance through step n.
 pa_status run_steps(pa_ctx* c, WS& w, int n0, int n1, int n_total, int K, bool store, const ObsPlan* op,
-                    double* obs_out, CkptTarget ckpt, bool final_fields) {
+                    bool observe, double* obs_out, CkptTarget ckpt, bool final_fields) {
     const int nseg = n_segments(n_total, K);
     for (int n = n0; n < n1; ++n) {
         const int j = n - n0;
+        Dims dn = c->d;
+        if (op) dn.B = op->act(n);
         for (int s = 0; s < 4; ++s) {
             cd* fin[4];
             cd* fout[4];
@@ -505,13 +691,14 @@ pa_status run_steps(pa_ctx* c, WS& w, int n0, int n1, int n_total, int K, bool s
             } else {
                 for (int i = 0; i < 4; ++i) fin[i] = fout[i] = w.Yf[i];
             }
+            if (s == 0 && op && observe) PA_TRY(observe_step(c, w, *op, n, fin, obs_out));
+            if (dn.B < 1) continue;
             RowArgs ra{};
             for (int i = 0; i < 4; ++i) ra.yin[i] = fin[i];
             ra.yout[0] = w.Yp[0];
             ra.tw = c->tw;
-            const int slot = (s == 0 && op) ? op->slot_of[(size_t)n] : -1;
-            ra.obs = op ? row_obs_args(*op, slot, obs_out, w.jpart) : row_obs_args(ObsPlan(), -1, nullptr, nullptr);
-            PA_HIP(timed(c, PROF_ROW_NL, [&] { return launch_row_nl(c->d, ra, c->stream); }));
+            ra.obs = row_obs_args(nullptr, -1, nullptr, nullptr);
+            PA_HIP(timed(c, PROF_ROW_NL, [&] { return launch_row_nl(dn, ra, c->stream); }));
             ColArgs a = col_base(c);
             a.yin[0] = w.Yp[0];
             a.omega = w.omega;
@@ -526,22 +713,9 @@ pa_status run_steps(pa_ctx* c, WS& w, int n0, int n1, int n_total, int K, bool s
                 }
                 if (nn == n1 && !final_fields) a.nout = 0;
             }
-            PA_HIP(timed(c, PROF_COL_FWD, [&] { return launch_col(c->d, COL_A + s, a, c->stream); }));
+            PA_HIP(timed(c, PROF_COL_FWD, [&] { return launch_col(dn, COL_A + s, a, c->stream); }));
         }
     }
-    return PA_OK;
-}
-
-// Observation at the final step from the stage-a fields of omega_H.
-pa_status observe_final(pa_ctx* c, WS& w, const ObsPlan& op, int n_steps, cd* const fields[4], double* obs_out) {
-    const int slot = op.slot_of[(size_t)n_steps];
-    if (slot < 0) return PA_OK;
-    RowArgs ra{};
-    ra.yin[0] = fields[0];
-    ra.yin[1] = fields[1];
-    ra.tw = c->tw;
-    ra.obs = row_obs_args(op, slot, obs_out, w.jpart);
-    PA_HIP(launch_row_obs(c->d, ra, c->stream));
     return PA_OK;
 }
 
@@ -573,18 +747,20 @@ pa_status forward_sweep(pa_ctx* c, WS& w, const double* omega0, int n_steps, con
     const CkptTarget tgt{ckpt, plan ? &c->plan_fwd_slot : nullptr};
     const bool store = store_last && w.seg && n_steps > 0;
     const int n_last = store ? (n_segments(n_steps, K) - 1) * K : n_steps;   // first step of the stored segment
-    const bool final_obs = op.slot_of[(size_t)n_steps] >= 0;
+    bool final_obs = false;
+    for (int i = 0; i < op.n; ++i) final_obs = final_obs || op.r[i].slot(n_steps) >= 0;
     cd* f0[4] = {w.Yf[0], w.Yf[1], w.Yf[2], w.Yf[3]};
     if (store && n_last == 0) seg_fields(c, w, 0, 0, f0);
     PA_TRY(start_state(c, w, omega0, ckpt ? ckpt_slot(c, ckpt, 0) : nullptr, f0));
     // Sobolev term (lambda/2) int |grad u0|^2 = (lambda/2) int omega0^2 (periodic, divergence-free),
     // exact on the grid for the band-limited P omega0: 4 pi^2 lambda * (1/2) sum |omega_hat|^2 / N^4
-    const bool reg = c->sobolev > 0.0 && op.values && op.n_times > 0;
+    const bool reg = c->sobolev > 0.0 && op.values && op.n > 0;
     if (reg) PA_HIP(launch_state_energy(c->d, w.omega, 4.0 * M_PI * M_PI * c->sobolev, w.J2, c->stream));
     if (n_last > 0) {
-        PA_TRY(run_steps(c, w, 0, n_last, n_steps, K, false, &op, obs_out, tgt, !store && final_obs));
+        PA_TRY(run_steps(c, w, 0, n_last, n_steps, K, false, &op, true, obs_out, tgt, !store && final_obs));
         if (store) {
-            // stage-a fields of the state at n_last (in w.omega) into segment slot (0, 0)
+            // stage-a fields of the state at n_last (in w.omega) into segment slot (0, 0), for
+            // every member: a member whose horizon is n_last is observed from them
             cd* s0[4];
             seg_fields(c, w, 0, 0, s0);
             ColArgs a = col_base(c);
@@ -595,21 +771,24 @@ pa_status forward_sweep(pa_ctx* c, WS& w, const double* omega0, int n_steps, con
     }
     cd* fH[4] = {w.Yf[0], w.Yf[1], w.Yf[2], w.Yf[3]};
     if (store) {
-        PA_TRY(run_steps(c, w, n_last, n_steps, n_steps, K, true, &op, obs_out, tgt, true));
+        PA_TRY(run_steps(c, w, n_last, n_steps, n_steps, K, true, &op, true, obs_out, tgt, true));
         seg_fields(c, w, n_steps - n_last, 0, fH);
     }
-    if (final_obs) PA_TRY(observe_final(c, w, op, n_steps, fH, obs_out));
-    if (op.values && op.n_times > 0)
-        PA_HIP(launch_reduce_j(c->d.B, op.n_times * op.M, w.jpart, w.J, c->stream));
+    if (final_obs) PA_TRY(observe_step(c, w, op, n_steps, fH, obs_out));
+    if (op.values && op.n > 0) PA_TRY(reduce_cost(c, w, op));
     if (reg) PA_HIP(launch_axpy(c->d.B, 1, nullptr, 1.0, w.J2, w.J, nullptr, c->stream));
     return PA_OK;
 }
 
-// Adjoint stage: row products + column transposes for stage `mode`.  At an
-// observed step (stage n) the residual source rows are formed from the same
-// stage fields and enter the column pass as two extra inputs.
-pa_status adj_stage(pa_ctx* c, WS& w, cd* const fields[4], int mode, const ObsPlan* op, int obs_slot,
-                    int final_out, const double* scale) {
+// Adjoint stage of step n: row products + column transposes for stage
+// `mode`, for the members [0, op->act(n)) (all members without op).  At
+// stage n of a step that members observe, their residual source rows are
+// formed from the same stage fields and enter the column pass as two extra
+// inputs (zero for the other members of the launch).
+pa_status adj_stage(pa_ctx* c, WS& w, cd* const fields[4], int mode, const ObsPlan* op, int n, int final_out,
+                    const double* scale) {
+    Dims dn = c->d;
+    if (op) dn.B = op->act(n);
     RowArgs ra{};
     for (int i = 0; i < 4; ++i) ra.yin[i] = fields[i];
     ra.yin[4] = w.YL[0];
@@ -617,28 +796,25 @@ pa_status adj_stage(pa_ctx* c, WS& w, cd* const fields[4], int mode, const ObsPl
     ra.yout[0] = w.Yp[0];
     ra.yout[1] = w.Yp[1];
     ra.tw = c->tw;
-    ra.obs = row_obs_args(ObsPlan(), -1, nullptr, nullptr);
-    PA_HIP(timed(c, PROF_ROW_ADJ, [&] { return launch_row_adj(c->d, ra, c->stream); }));
+    ra.obs = row_obs_args(nullptr, -1, nullptr, nullptr);
+    PA_HIP(timed(c, PROF_ROW_ADJ, [&] { return launch_row_adj(dn, ra, c->stream); }));
     ColArgs a = col_base(c);
     a.yin[0] = w.Yp[0];
     a.yin[1] = w.Yp[1];
     a.nin = 2;
     a.inmul[0] = IN_INVK2;
     a.inmul[1] = IN_ONE;
-    if (op && obs_slot >= 0) {
-        RowArgs rs{};
-        rs.yin[0] = fields[0];
-        rs.yin[1] = fields[1];
-        rs.yout[0] = w.Yp[2];
-        rs.yout[1] = w.Yp[3];
-        rs.tw = c->tw;
-        rs.obs = row_obs_args(*op, obs_slot, nullptr, nullptr);
-        PA_HIP(launch_row_src(c->d, rs, 0, c->stream));
-        a.yin[2] = w.Yp[2];
-        a.yin[3] = w.Yp[3];
-        a.nin = 4;
-        a.inmul[2] = IN_IKY_INVK2;
-        a.inmul[3] = IN_MIKX_INVK2;
+    if (mode == COL_ADJ_N && op && op->values) {
+        bool any = false;
+        cd* const out[2] = {w.Yp[2], w.Yp[3]};
+        PA_TRY(sources_at(c, w, *op, n, 0, dn.B, fields, out, &any));
+        if (any) {
+            a.yin[2] = w.Yp[2];
+            a.yin[3] = w.Yp[3];
+            a.nin = 4;
+            a.inmul[2] = IN_IKY_INVK2;
+            a.inmul[3] = IN_MIKX_INVK2;
+        }
     }
     a.lam = w.lam;
     a.omb = w.omb;
@@ -654,7 +830,7 @@ pa_status adj_stage(pa_ctx* c, WS& w, cd* const fields[4], int mode, const ObsPl
         a.fields[1] = F_WY;
     }
     const int cmode = (mode == COL_ADJ_N && a.nin > 2) ? COL_ADJ_NSRC : mode;
-    PA_HIP(timed(c, PROF_COL_ADJ, [&] { return launch_col(c->d, cmode, a, c->stream); }));
+    PA_HIP(timed(c, PROF_COL_ADJ, [&] { return launch_col(dn, cmode, a, c->stream); }));
     return PA_OK;
 }
 
@@ -679,47 +855,56 @@ pa_status record_shells(pa_ctx* c, WS& w, const Shells& sh, int row) {
     return PA_OK;
 }
 
-// Terminal adjoint state lambda_H from observations (op) or an impulse.
-pa_status terminal(pa_ctx* c, WS& w, const ObsPlan* op, int n_steps, cd* const fieldsH[4], int impulse, int ix,
-                   int iy, bool final_out, const double* scale) {
-    const size_t SC = (size_t)c->d.B * c->d.KY * c->d.KXP;
-    const size_t SY = (size_t)c->d.B * c->d.N * c->d.KXP;
-    const int slot = op ? op->slot_of[(size_t)n_steps] : -1;
-    if (!impulse && slot < 0) {
-        PA_HIP(launch_fill(reinterpret_cast<double*>(w.lam), 0.0, 2 * SC, c->stream));
-        PA_HIP(launch_fill(reinterpret_cast<double*>(w.YL[0]), 0.0, 2 * SY, c->stream));
-        PA_HIP(launch_fill(reinterpret_cast<double*>(w.YL[1]), 0.0, 2 * SY, c->stream));
+// Terminal adjoint state of the members [lo, hi) at step `step` (their last
+// step, or the first one at which they take part in the backward sweep):
+// lambda = the residual sources of the members observed there, or a unit
+// u-impulse at (ix, iy) (impulse), else zero.  Writes lambda and the Lambda
+// fields of the slice (with final_out the gradient field, times scale).
+pa_status terminal(pa_ctx* c, WS& w, const ObsPlan* op, int step, cd* const fields[4], int impulse, int ix,
+                   int iy, bool final_out, const double* scale, int lo, int hi) {
+    const size_t offY = (size_t)lo * per_y(c), offC = (size_t)lo * per_c(c);
+    const size_t nY = (size_t)(hi - lo) * per_y(c), nC = (size_t)(hi - lo) * per_c(c);
+    const Dims ds = slice_dims(c, lo, hi);
+    cd* const src[2] = {w.Yp[0], w.Yp[1]};
+    bool any = false;
+    if (impulse) {
+        RowArgs ra{};
+        ra.yout[0] = src[0] + offY;
+        ra.yout[1] = src[1] + offY;
+        ra.tw = c->tw;
+        ra.obs = row_obs_args(nullptr, -1, nullptr, nullptr);
+        ra.obs.imp_x = ix;
+        ra.obs.imp_y = iy;
+        PA_HIP(launch_row_src(ds, ra, 1, c->stream));
+        any = true;
+    } else if (op && op->values) {
+        PA_TRY(sources_at(c, w, *op, step, lo, hi, fields, src, &any));
+    }
+    if (!any) {
+        PA_HIP(launch_fill(reinterpret_cast<double*>(w.lam + offC), 0.0, 2 * nC, c->stream));
+        PA_HIP(launch_fill(reinterpret_cast<double*>(w.YL[0] + offY), 0.0, 2 * nY, c->stream));
+        PA_HIP(launch_fill(reinterpret_cast<double*>(w.YL[1] + offY), 0.0, 2 * nY, c->stream));
         return PA_OK;
     }
-    RowArgs ra{};
-    ra.yin[0] = fieldsH[0];
-    ra.yin[1] = fieldsH[1];
-    ra.yout[0] = w.Yp[0];
-    ra.yout[1] = w.Yp[1];
-    ra.tw = c->tw;
-    ra.obs = op ? row_obs_args(*op, slot, nullptr, nullptr) : row_obs_args(ObsPlan(), -1, nullptr, nullptr);
-    ra.obs.imp_x = ix;
-    ra.obs.imp_y = iy;
-    PA_HIP(launch_row_src(c->d, ra, impulse, c->stream));
     ColArgs a = col_base(c);
-    a.yin[0] = w.Yp[0];
-    a.yin[1] = w.Yp[1];
+    a.yin[0] = src[0] + offY;
+    a.yin[1] = src[1] + offY;
     a.nin = 2;
     a.inmul[0] = IN_IKY_INVK2;
     a.inmul[1] = IN_MIKX_INVK2;
-    a.lam = w.lam;
+    a.lam = w.lam + offC;
     a.final_out = final_out ? 1 : 0;
-    a.scale = scale;
-    a.yout[0] = w.YL[0];
+    a.scale = scale ? scale + lo : nullptr;
+    a.yout[0] = w.YL[0] + offY;
     a.fields[0] = F_OMEGA;
     if (final_out) {
         a.nout = 1;
     } else {
         a.nout = 2;
-        a.yout[1] = w.YL[1];
+        a.yout[1] = w.YL[1] + offY;
         a.fields[1] = F_WY;
     }
-    PA_HIP(launch_col(c->d, COL_ADJ_SRC, a, c->stream));
+    PA_HIP(launch_col(ds, COL_ADJ_SRC, a, c->stream));
     return PA_OK;
 }
 
@@ -728,7 +913,7 @@ pa_status terminal(pa_ctx* c, WS& w, const ObsPlan* op, int n_steps, cd* const f
 // gradients only (observations given, not the impulse response).
 pa_status add_sobolev_gradient(pa_ctx* c, WS& w, const cd* ckpt, const ObsPlan* op, int impulse,
                                const double* scale, double* grad_out) {
-    if (!(c->sobolev > 0.0) || impulse || !op || !op->values || op->n_times == 0) return PA_OK;
+    if (!(c->sobolev > 0.0) || impulse || !op || !op->values || op->n == 0) return PA_OK;
     const size_t n = (size_t)c->d.N * c->d.N;
     PA_TRY(state_to_phys(c, w, ckpt_slot(c, const_cast<cd*>(ckpt), 0), w.P0));
     const double coef = c->sobolev * 4.0 * M_PI * M_PI / (double)n;
@@ -747,21 +932,35 @@ pa_status backward_sweep(pa_ctx* c, WS& w, const cd* ckpt, int n_steps, int K, c
                          int ix, int iy, const double* scale, double* grad_out, const Shells& sh,
                          bool last_ready, const std::vector<PlanAct>* plan = nullptr) {
     const int nseg = n_segments(n_steps, K);
-    if (n_steps == 0) {
-        // no segment buffer exists for a zero horizon: the stage fields of omega_0 go to w.Yf
+    const int B = c->d.B;
+    auto act = [&](int n) { return op ? op->act(n) : B; };
+    cd* const ck = const_cast<cd*>(ckpt);
+    // members that take part in no step (their only observation is at step 0) start and
+    // end at step 0: the gradient field straight from their sources, from the state in slot 0
+    auto finish_idle = [&](int lo) -> pa_status {
+        if (lo >= B) return PA_OK;
         cd* f0[4] = {w.Yf[0], w.Yf[1], w.Yf[2], w.Yf[3]};
+        const size_t offY = (size_t)lo * per_y(c);
         ColArgs a = col_base(c);
-        a.state_in = ckpt_slot(c, const_cast<cd*>(ckpt), 0);
-        a.omega = w.omega;
-        set_stage_fields(a, f0);
-        PA_HIP(launch_col(c->d, COL_FROM_STATE, a, c->stream));
-        const int slot = op ? op->slot_of[0] : -1;
-        if (!impulse && slot < 0) {
-            if (grad_out) PA_HIP(launch_fill(grad_out, 0.0, (size_t)c->d.B * c->d.N * c->d.N, c->stream));
+        a.state_in = ckpt_slot(c, ck, 0) + (size_t)lo * per_c(c);
+        a.nout = 4;
+        a.fields[0] = F_U;
+        a.fields[1] = F_V;
+        a.fields[2] = F_WX;
+        a.fields[3] = F_WY;
+        for (int i = 0; i < 4; ++i) a.yout[i] = f0[i] + offY;
+        PA_HIP(launch_col(slice_dims(c, lo, B), COL_FROM_STATE, a, c->stream));
+        return terminal(c, w, op, 0, f0, impulse, ix, iy, true, scale, lo, B);
+    };
+    if (n_steps == 0) {
+        bool obs0 = impulse != 0;
+        for (int i = 0; op && op->values && i < op->n; ++i) obs0 = obs0 || op->r[i].slot(0) >= 0;
+        if (!obs0) {
+            if (grad_out) PA_HIP(launch_fill(grad_out, 0.0, (size_t)B * c->d.N * c->d.N, c->stream));
             if (grad_out) PA_TRY(add_sobolev_gradient(c, w, ckpt, op, impulse, scale, grad_out));
             return PA_OK;
         }
-        PA_TRY(terminal(c, w, op, 0, f0, impulse, ix, iy, true, scale));
+        PA_TRY(finish_idle(0));
         PA_TRY(record_shells(c, w, sh, 0));
         if (grad_out) PA_HIP(launch_row_c2r(c->d, w.YL[0], grad_out, c->tw, c->stream));
         if (grad_out) PA_TRY(add_sobolev_gradient(c, w, ckpt, op, impulse, scale, grad_out));
@@ -769,10 +968,11 @@ pa_status backward_sweep(pa_ctx* c, WS& w, const cd* ckpt, int n_steps, int K, c
     }
     if (!w.seg) return fail(PA_EINVAL, "workspace carved without a segment buffer");
     if (plan && !last_ready) return fail(PA_EINVAL, "a schedule's backward sweep follows its forward sweep");
-    cd* const ck = const_cast<cd*>(ckpt);
     // Recompute segment `seg` keeping its stage fields (from state src; src ==
     // w.omega is the live state), unless its fields are already stored, then
-    // run the adjoint steps through it.
+    // run the adjoint steps through it.  Members join the sweep at the step
+    // after their last: their terminal state is formed there, from the stage-a
+    // fields of their final state.
     auto reverse_segment = [&](int seg, const cd* src, bool recompute) -> pa_status {
         const int n0 = seg * K, n1 = std::min(n_steps, n0 + K), L = n1 - n0;
         const bool last = seg == nseg - 1;
@@ -783,27 +983,29 @@ pa_status backward_sweep(pa_ctx* c, WS& w, const cd* ckpt, int n_steps, int K, c
             a.state_in = src;
             a.omega = src == w.omega ? nullptr : w.omega;
             set_stage_fields(a, f0);
-            PA_HIP(launch_col(c->d, COL_FROM_STATE, a, c->stream));
-            PA_TRY(run_steps(c, w, n0, n1, n_steps, K, true, nullptr, nullptr, CkptTarget(), last));
-        }
-        if (last) {
-            cd* fH[4];
-            seg_fields(c, w, L, 0, fH);
-            PA_TRY(terminal(c, w, op, n_steps, fH, impulse, ix, iy, false, scale));
-            PA_TRY(record_shells(c, w, sh, 0));
+            PA_HIP(launch_col(slice_dims(c, 0, act(n0)), COL_FROM_STATE, a, c->stream));
+            // the fields of the segment's end state are needed when members join at its last step
+            const bool joins = !last && act(n1 - 1) > act(n1);
+            PA_TRY(run_steps(c, w, n0, n1, n_steps, K, true, op, false, nullptr, CkptTarget(), last || joins));
         }
         for (int j = L - 1; j >= 0; --j) {
             const int n = n0 + j;
+            const int hi = act(n), lo = (n + 1 >= n_steps) ? 0 : act(n + 1);
+            if (hi > lo) {
+                cd* fm[4];
+                seg_fields(c, w, j + 1, 0, fm);
+                PA_TRY(terminal(c, w, op, n + 1, fm, impulse, ix, iy, false, scale, lo, hi));
+                if (n + 1 == n_steps) PA_TRY(record_shells(c, w, sh, 0));
+            }
             cd* fs[4];
             seg_fields(c, w, j, 3, fs);
-            PA_TRY(adj_stage(c, w, fs, COL_ADJ_C, nullptr, -1, 0, nullptr));
+            PA_TRY(adj_stage(c, w, fs, COL_ADJ_C, op, n, 0, nullptr));
             seg_fields(c, w, j, 2, fs);
-            PA_TRY(adj_stage(c, w, fs, COL_ADJ_B, nullptr, -1, 0, nullptr));
+            PA_TRY(adj_stage(c, w, fs, COL_ADJ_B, op, n, 0, nullptr));
             seg_fields(c, w, j, 1, fs);
-            PA_TRY(adj_stage(c, w, fs, COL_ADJ_A, nullptr, -1, 0, nullptr));
+            PA_TRY(adj_stage(c, w, fs, COL_ADJ_A, op, n, 0, nullptr));
             seg_fields(c, w, j, 0, fs);
-            const int slot = (op && !impulse) ? op->slot_of[(size_t)n] : -1;
-            PA_TRY(adj_stage(c, w, fs, COL_ADJ_N, op, slot, n == 0 ? 1 : 0, scale));
+            PA_TRY(adj_stage(c, w, fs, COL_ADJ_N, impulse ? nullptr : op, n, n == 0 ? 1 : 0, scale));
             PA_TRY(record_shells(c, w, sh, n_steps - n));
         }
         return PA_OK;
@@ -819,27 +1021,28 @@ pa_status backward_sweep(pa_ctx* c, WS& w, const cd* ckpt, int n_steps, int K, c
         PA_TRY(reverse_segment(nseg - 1, nullptr, false));
         std::vector<int> end_slot((size_t)nseg + 1, -1);
         for (++i; i < plan->size(); ++i) {
-            const PlanAct& act = (*plan)[i];
-            const cd* src = act.src >= 0 ? ckpt_slot(c, ck, act.src) : w.omega;
-            if (act.kind == ACT_REVERSE) {
-                PA_TRY(reverse_segment(act.a, src, true));
+            const PlanAct& act_ = (*plan)[i];
+            const cd* src = act_.src >= 0 ? ckpt_slot(c, ck, act_.src) : w.omega;
+            if (act_.kind == ACT_REVERSE) {
+                PA_TRY(reverse_segment(act_.a, src, true));
                 continue;
             }
             // advance: the stage-a fields of the start state into w.Yf (a live start has them there)
             cd* f0[4] = {w.Yf[0], w.Yf[1], w.Yf[2], w.Yf[3]};
-            if (act.src >= 0) {
+            if (act_.src >= 0) {
                 ColArgs a = col_base(c);
                 a.state_in = src;
                 a.omega = w.omega;
                 set_stage_fields(a, f0);
                 PA_HIP(launch_col(c->d, COL_FROM_STATE, a, c->stream));
             }
-            if (act.dst >= 0) end_slot[(size_t)act.b] = act.dst;
-            PA_TRY(run_steps(c, w, act.a * K, std::min(n_steps, act.b * K), n_steps, K, false, nullptr, nullptr,
-                             CkptTarget{ck, &end_slot}, true));
-            end_slot[(size_t)act.b] = -1;
+            if (act_.dst >= 0) end_slot[(size_t)act_.b] = act_.dst;
+            PA_TRY(run_steps(c, w, act_.a * K, std::min(n_steps, act_.b * K), n_steps, K, false, nullptr, false,
+                             nullptr, CkptTarget{ck, &end_slot}, true));
+            end_slot[(size_t)act_.b] = -1;
         }
     }
+    PA_TRY(finish_idle(act(0)));
     if (grad_out) PA_HIP(launch_row_c2r(c->d, w.YL[0], grad_out, c->tw, c->stream));
     if (grad_out) PA_TRY(add_sobolev_gradient(c, w, ckpt, op, impulse, scale, grad_out));
     return PA_OK;
@@ -1247,11 +1450,11 @@ pa_status pa_forward(pa_ctx* c, const double* omega0, int32_t n_steps, const pa_
     ObsPlan op;
     PA_TRY(make_obs_plan(c, obs, n_steps, false, &op));
     WS w;
-    PA_TRY(check_ws(c, workspace, wbytes, 0, ckpt_every, op.n_times, 0, &w));
+    PA_TRY(check_ws(c, workspace, wbytes, 0, ckpt_every, op.max_times, 0, &w));
     const int K = seg_len(n_steps, ckpt_every);
     PA_TRY(forward_sweep(c, w, omega0, n_steps, op, obs_out, reinterpret_cast<cd*>(ckpt), K, false));
     if (J_out) {
-        if (op.n_times > 0) PA_HIP(launch_copy(J_out, w.J, c->d.B, c->stream));
+        if (op.n > 0) PA_HIP(launch_copy(J_out, w.J, c->d.B, c->stream));
         else PA_HIP(launch_fill(J_out, 0.0, c->d.B, c->stream));
     }
     if (omega_T) PA_TRY(state_to_phys(c, w, w.omega, omega_T));
@@ -1270,7 +1473,7 @@ pa_status pa_adjoint_from_checkpoints(pa_ctx* c, const void* ckpt, int32_t n_ste
     ObsPlan op;
     PA_TRY(make_obs_plan(c, obs, n_steps, true, &op));
     WS w;
-    PA_TRY(check_ws(c, workspace, wbytes, n_steps, ckpt_every, op.n_times, 0, &w));
+    PA_TRY(check_ws(c, workspace, wbytes, n_steps, ckpt_every, op.max_times, 0, &w));
     const int K = seg_len(n_steps, ckpt_every);
     return backward_sweep(c, w, reinterpret_cast<const cd*>(ckpt), n_steps, K, &op, 0, -1, -1, scale, grad_out,
                           Shells(), false);
@@ -1286,12 +1489,12 @@ pa_status pa_adjoint_gradient(pa_ctx* c, const double* omega0, int32_t n_steps, 
     ObsPlan op;
     PA_TRY(make_obs_plan(c, obs, n_steps, true, &op));
     WS w;
-    PA_TRY(check_ws(c, workspace, wbytes, n_steps, ckpt_every, op.n_times, 0, &w, true));
+    PA_TRY(check_ws(c, workspace, wbytes, n_steps, ckpt_every, op.max_times, 0, &w, true));
     const int K = seg_len(n_steps, ckpt_every);
     const std::vector<PlanAct>* plan = plan_for(c, n_segments(n_steps, K));
     PA_TRY(forward_sweep(c, w, omega0, n_steps, op, nullptr, w.ckpt, K, true, plan));
     if (J_out) {
-        if (op.n_times > 0) PA_HIP(launch_copy(J_out, w.J, c->d.B, c->stream));
+        if (op.n > 0) PA_HIP(launch_copy(J_out, w.J, c->d.B, c->stream));
         else PA_HIP(launch_fill(J_out, 0.0, c->d.B, c->stream));
     }
     return backward_sweep(c, w, w.ckpt, n_steps, K, &op, 0, -1, -1, nullptr, grad_out, Shells(), true, plan);
@@ -1328,7 +1531,7 @@ pa_status pa_adjoint_impulse(pa_ctx* c, const double* omega0, int32_t n_steps, i
     PA_TRY(check_ws(c, workspace, wbytes, n_steps, ckpt_every, 0, 0, &w, true));
     const int K = seg_len(n_steps, ckpt_every);
     ObsPlan none;
-    none.slot_of.assign((size_t)n_steps + 1, -1);
+    PA_TRY(make_obs_plan(c, nullptr, n_steps, false, &none));
     const std::vector<PlanAct>* plan = plan_for(c, n_segments(n_steps, K));
     PA_TRY(forward_sweep(c, w, omega0, n_steps, none, nullptr, w.ckpt, K, true, plan));
     Shells sh;
@@ -1497,9 +1700,11 @@ static pa_status assimilate_impl(pa_ctx* c, double* omega_inout, int32_t n_steps
                                  const pa_kernel* kernels, bool per_member, int32_t method, int32_t max_iter,
                                  int32_t lbfgs_m, int32_t ckpt_every, double* J_hist, int32_t* iters_done,
                                  void* workspace, size_t wbytes, const void* state_in = nullptr,
-                                 void* state_out = nullptr, size_t state_bytes = 0) {
+                                 void* state_out = nullptr, size_t state_bytes = 0, bool member_obs = false) {
     g_err.clear();
     if (!c || !omega_inout || !J_hist || !iters_done) return fail(PA_EINVAL, "NULL argument");
+    if (member_obs && (state_in || state_out)) return fail(PA_EINVAL, "per-member observations keep no optimiser state");
+    if (member_obs && !obs) return fail(PA_EINVAL, "obs is NULL");
     if (!kernels) return fail(PA_EINVAL, "kernel is NULL");
     for (int b = 0; b < (per_member ? c->d.B : 1); ++b) {
         PA_TRY(valid_kernel(&kernels[b]));
@@ -1513,8 +1718,19 @@ static pa_status assimilate_impl(pa_ctx* c, double* omega_inout, int32_t n_steps
                            {obs ? obs->values : nullptr, "obs values"}, {state_in, "state_in"},
                            {state_out, "state_out"}}));
     ObsPlan op;
-    PA_TRY(make_obs_plan(c, obs, n_steps, true, &op));
-    if (op.n_times == 0) return fail(PA_EINVAL, "assimilation needs at least one observation time");
+    std::vector<ObsRange> ranges;
+    std::vector<int> active;
+    if (member_obs) {
+        for (int b = 0; b < c->d.B; ++b)
+            if (obs[b].values) PA_TRY(require_device(c->stream, {{obs[b].values, "obs values"}}));
+        PA_TRY(make_member_plan(c, obs, n_steps, ranges, active, &op));
+        if (plan_mode(c, n_segments(n_steps, seg_len(n_steps, ckpt_every))))
+            return fail(PA_EINVAL, "per-member observations keep one state per segment boundary: "
+                                   "set the snapshot budget to 0");
+    } else {
+        PA_TRY(make_obs_plan(c, obs, n_steps, true, &op));
+    }
+    if (op.n == 0) return fail(PA_EINVAL, "assimilation needs at least one observation time");
     const int m = std::max(1, (int)lbfgs_m);
     const int nk = per_member ? c->d.B : 1;
     const OptLayout sl_ = opt_layout(c->d.N, c->d.B, m, nk);
@@ -1523,7 +1739,7 @@ static pa_status assimilate_impl(pa_ctx* c, double* omega_inout, int32_t n_steps
         return fail(PA_EINVAL, "optimiser state must be 256-byte aligned");
     if ((state_in || state_out) && state_bytes < sl_.total)
         return fail(PA_EINVAL, "optimiser state too small: need " + std::to_string(sl_.total) + " bytes");
-    OptHeader want{OPT_MAGIC, c->d.N, c->d.B, m, method, per_member ? 1 : 0, n_steps, op.n_times,
+    OptHeader want{OPT_MAGIC, c->d.N, c->d.B, m, method, per_member ? 1 : 0, n_steps, op.max_times,
                    obs ? obs->stride : 0, 0, 0};
     // a resumed state: header and scalars read (and checked) before anything is enqueued
     std::vector<unsigned char> hs;
@@ -1543,7 +1759,7 @@ static pa_status assimilate_impl(pa_ctx* c, double* omega_inout, int32_t n_steps
                                    "observation layout or kernels)");
     }
     WS w;
-    PA_TRY(check_ws(c, workspace, wbytes, n_steps, ckpt_every, op.n_times, m, &w, true));
+    PA_TRY(check_ws(c, workspace, wbytes, n_steps, ckpt_every, op.max_times, m, &w, true));
     const int B = c->d.B;
     const int K = seg_len(n_steps, ckpt_every);
     const size_t n = (size_t)c->d.N * c->d.N;
@@ -1822,6 +2038,14 @@ extern "C" pa_status pa_assimilate_ex(pa_ctx* c, double* omega_inout, int32_t n_
                                       size_t state_bytes, void* workspace, size_t wbytes) try {
     return assimilate_impl(c, omega_inout, n_steps, obs, kernels, per_member != 0, method, max_iter, lbfgs_m,
                            ckpt_every, J_hist, iters_done, workspace, wbytes, state_in, state_out, state_bytes);
+} PA_CATCH_HOST
+
+extern "C" pa_status pa_assimilate_members(pa_ctx* c, double* omega_inout, int32_t n_steps, const pa_obs* obs,
+                                           const pa_kernel* kernels, int32_t method, int32_t max_iter,
+                                           int32_t lbfgs_m, int32_t ckpt_every, double* J_hist,
+                                           int32_t* iters_done, void* workspace, size_t wbytes) try {
+    return assimilate_impl(c, omega_inout, n_steps, obs, kernels, true, method, max_iter, lbfgs_m, ckpt_every,
+                           J_hist, iters_done, workspace, wbytes, nullptr, nullptr, 0, true);
 } PA_CATCH_HOST
 
 extern "C" pa_status pa_assimilate_kernels(pa_ctx* c, double* omega_inout, int32_t n_steps, const pa_obs* obs,

@@ -212,13 +212,12 @@ __global__ void __launch_bounds__(256) row_c2r_kernel(Dims d, const cd* __restri
     }
 }
 
-// Right-hand side products of one row:  q = u w_x + v w_y  (+ observation
-// when OBS).  Inputs yin[0..3] = U, V, Wx, Wy (Y layout), output yout[0] =
-// row transform of q.  Every input load is issued before the first transform,
-// so the memory latency is paid once per kernel rather than once per
-// transform.  The observing variant is a separate instantiation so that the
-// plain one carries none of its index arithmetic or registers.
-template <int N, int V, bool OBS>
+// Right-hand side products of one row:  q = u w_x + v w_y.  Inputs
+// yin[0..3] = U, V, Wx, Wy (Y layout), output yout[0] = row transform of q.
+// Every input load is issued before the first transform, so the memory
+// latency is paid once per kernel rather than once per transform.
+// Observations are formed by row_obs_kernel from the same fields.
+template <int N, int V>
 __device__ __forceinline__ void row_nl_body(const Dims& d, const RowArgs& a) {
     const cd* __restrict__ tw_g = a.tw;
     PA_TEAM_SETUP(N, V, N)
@@ -230,22 +229,11 @@ __device__ __forceinline__ void row_nl_body(const Dims& d, const RowArgs& a) {
     const cd* twl = stage_twiddles<N, V>(tw_lds, tw_g);
     TwReg<N, V> tr;   // the three transforms of the row share the thread's twiddles
     load_twiddles<N, V>(tr, t, twl);
-    double part = 0.0;
     fft<N, V, true, WL>(z1, t, lds, tr);
     fft<N, V, true, WL>(z2, t, lds, tr);
     cd z[E];
 #pragma unroll
-    for (int m = 0; m < E; ++m) {
-        if (OBS) {
-            part += observe_comp(a.obs, b, y, t + T * m, 0, z1[m].x);
-            part += observe_comp(a.obs, b, y, t + T * m, 1, z2[m].x);
-        }
-        z[m] = mk(z1[m].x * z1[m].y + z2[m].x * z2[m].y, 0.0);
-    }
-    if (OBS) {
-        const double s = team_sum<N, V, WL>(part, t, lds);
-        if (t == 0) store_jpart(a.obs, b, y, s);
-    }
+    for (int m = 0; m < E; ++m) z[m] = mk(z1[m].x * z1[m].y + z2[m].x * z2[m].y, 0.0);
     fft<N, V, false, WL>(z, t, lds, tr);
     cd* o = a.yout[0] + roff;
 #pragma unroll
@@ -300,10 +288,8 @@ template <int N, int V>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(nl_waves<N, V>())))
 row_nl_kernel(Dims d, RowArgs a) {
     if constexpr (V == 2 && nl_pairs<N>()) row_nl_pair_body<N, V>(d, a);
-    else row_nl_body<N, V, false>(d, a);
+    else row_nl_body<N, V>(d, a);
 }
-template <int N, int V>
-__global__ void __launch_bounds__(256) row_nl_obs_kernel(Dims d, RowArgs a) { row_nl_body<N, V, true>(d, a); }
 
 // Observation only (final time): team per observed row; yin[0..1] = U, V.
 template <int N, int V>
@@ -906,7 +892,6 @@ hipError_t Launch<N>::row_nl(const Dims& d, const RowArgs& a, hipStream_t s) {
     // variant 3 without a pipelined kernel for N falls back to the variant-2 kernel launched with
     // one team per row below, which must then be the one-row kernel
     static_assert(Pipe<N>::OK || !nl_pairs<N>(), "the variant-3 fallback would launch the two-row kernel");
-    if (a.obs.slot >= 0) PA_ROW_LAUNCH(d.var, d.tpb, row_nl_obs_kernel, N, d, a);
     if constexpr (Pipe<N>::OK)
         if (d.var == 3) return pipe_launch<N, 4>(row_nl_pipe_kernel<N>, d.tpb, d, a, s);
     if (d.var == 2 && nl_pairs<N>()) PA_ROW_LAUNCH(d.var, d.tpb, row_nl_kernel, N / 2, d, a);   // two rows per team

@@ -73,6 +73,9 @@ EXPORTS = {
     "pa_assimilate_kernels": (c_int32, [c_void_p, c_void_p, c_int32, POINTER(Obs), POINTER(Kernel), c_int32,
                                         c_int32, c_int32, c_int32, POINTER(c_double), POINTER(c_int32), c_void_p,
                                         c_size_t]),
+    "pa_assimilate_members": (c_int32, [c_void_p, c_void_p, c_int32, POINTER(Obs), POINTER(Kernel), c_int32,
+                                        c_int32, c_int32, c_int32, POINTER(c_double), POINTER(c_int32), c_void_p,
+                                        c_size_t]),
     "pa_assimilate_state_bytes": (c_int32, [c_void_p, c_int32, c_int32, POINTER(c_size_t)]),
     "pa_assimilate_ex": (c_int32, [c_void_p, c_void_p, c_int32, POINTER(Obs), POINTER(Kernel), c_int32, c_int32,
                                    c_int32, c_int32, c_int32, POINTER(c_double), POINTER(c_int32), c_void_p,

@@ -5,20 +5,25 @@ iteration count, observations) arrive over time.  The server keeps a queue
 and a fixed number of slots; each slot owns a HIP stream (default priority)
 and a worker thread.  Whenever a slot is free, queued requests are admitted in
 arrival order if their device footprint (workspace + fields + observations,
-from pa_workspace_bytes) fits in the remaining HBM budget; requests with the
-same shape (grid, physics, horizon, observation layout, kernel, iterations)
-that are waiting are admitted together as one batched solve.  A slot uploads
-its observations, forms the first guess, runs pa_assimilate on its stream and
-copies the result back; its memory is released for the next admission as soon
-as it finishes.  Each admitted group gets the largest checkpoint interval
-that fits its slot's share of the budget, so gradients recompute fewer
-segments (none when the whole trajectory fits); results do not depend on it.  Solves on different slots overlap on the device.  Latency is
-stamped from arrival to result-ready.
+from pa_workspace_bytes) fits in the remaining HBM budget.  Waiting requests
+of the same grid and flow physics (and iteration count) are admitted
+together as one batched solve, whatever their horizons, probe strides,
+observation times and kernels: pa_assimilate_members gives every member its
+own observation set, and a member advances only through its own horizon, so
+batching costs no padded work.  A slot uploads the group's observations,
+forms each request's first guess, runs the solve on its stream and copies the
+results back; its memory is released for the next admission as soon as it
+finishes.  Each admitted group gets the largest checkpoint interval that fits
+its slot's share of the budget, so gradients recompute fewer segments (none
+when the whole trajectory fits); results do not depend on it.  Solves on
+different slots overlap on the device.  Latency is stamped from arrival to
+result-ready.
 
 Results of a request are identical whether it runs alone, batched with
 others or concurrently with other slots: every member uses the same kernels
 with the same tiles (a fixed table per grid size, never chosen per batch),
-and no reduction crosses members.
+no reduction crosses members, and a member's steps are those of its own
+horizon.
 
     python -m paper_2602_14016_amd.serving --requests R --rate HZ [--load F] --out FILE
 
@@ -71,9 +76,10 @@ class Request:
     first_guess: str = "interp"       # "interp" (spectral interpolation of t=0 probes) or "zero"
     arrival: float = 0.0              # seconds from trace start
 
-    def shape_key(self):
-        return (self.N, self.flow, self.n_steps, self.stride, tuple(self.obs_steps), self.kernel, self.iters,
-                self.lbfgs_m, self.ckpt_every, self.first_guess)
+    def batch_key(self):
+        """Requests with equal keys run as one batched solve: one grid and physics, one iteration
+        count and memory; horizons, strides, observation times and kernels may differ."""
+        return (self.N, self.flow, self.iters, self.lbfgs_m, self.first_guess)
 
 
 @dataclass
@@ -93,67 +99,89 @@ class Result:
         return self.finished - self.arrival
 
 
-def footprint_bytes(solver, req: Request):
-    n_obs = len(req.obs_steps)
-    M = req.N // req.stride
-    ws = solver.workspace_bytes(req.n_steps, req.ckpt_every, n_obs, max(req.lbfgs_m, 1))
-    fields = solver.B * (3 * req.N * req.N + n_obs * 2 * M * M) * 8
+def group_shape(group):
+    """(horizon, most observation times) of a batched group: its solve runs to the longest horizon."""
+    return max(r.n_steps for r in group), max(len(r.obs_steps) for r in group)
+
+
+def footprint_bytes(solver, group, ckpt_every):
+    """Device bytes of a group's solve: the workspace at the group's longest horizon and largest
+    observation count, plus each member's field, first guess, result and observations."""
+    H, n_obs = group_shape(group)
+    m = max(max(r.lbfgs_m for r in group), 1)
+    ws = solver.workspace_bytes(H, ckpt_every, n_obs, m)
+    N = group[0].N
+    fields = sum((3 * N * N + len(r.obs_steps) * 2 * (N // r.stride) ** 2) * 8 for r in group)
     return ws + fields
 
 
 class GpuBackend:
-    """The device work of the server: one HIP stream (default priority) and a
-    cache of solver contexts per slot.  footprint() sizes a group of B requests
-    of one shape, run() assimilates them as one batched solve on the slot's
-    stream and returns host results, release() frees the slot's workspace."""
+    """The device work of the server: one HIP stream (default priority) per slot.
+    footprint() sizes a group from a sizing context per (grid, batch size) that only
+    the scheduler thread uses; run() creates the group's contexts on its slot's stream,
+    assimilates the group as one batched solve and returns host results; release()
+    frees the group's contexts and workspace."""
 
     def __init__(self, slots, device="cuda:0", tiles=None):
         self.device = torch.device(device)
         self.tiles = dict(tiles or {})
         self.streams = [torch.cuda.Stream(device=self.device) for _ in range(slots)]
-        self._solvers = {}   # (slot, N, flow, B) -> Solver
+        self._sizing = {}    # (N, B) -> Solver, scheduler thread only (workspace-size queries)
+        self._live = {}      # slot -> Solvers of the group running there
         self._lock = threading.Lock()
         self._running = {}   # rid -> (cancel flags of its solver, member index)
 
-    def _solver(self, slot, N, flow, B):
-        key = (slot, N, flow, B)
-        if key not in self._solvers:
-            with torch.cuda.stream(self.streams[slot]):
-                sv = Solver(N, B, device=self.device, stream=self.streams[slot], **physics_for(flow, N))
-                if N in self.tiles:
-                    sv.set_tiles(**self.tiles[N])
-                self._solvers[key] = sv
-        return self._solvers[key]
+    def _new_solver(self, slot, N, flow, B):
+        with torch.cuda.stream(self.streams[slot]):
+            sv = Solver(N, B, device=self.device, stream=self.streams[slot], **physics_for(flow, N))
+        if N in self.tiles:
+            sv.set_tiles(**self.tiles[N])
+        return sv
 
-    def footprint(self, req: Request, B):
-        # any slot's context of the same shape answers the size query
-        return footprint_bytes(self._solver(0, req.N, req.flow, B), req)
+    def footprint(self, group, ckpt_every=None):
+        """Device bytes of running `group` (requests of one batch key) with checkpoints every
+        ckpt_every steps (default: the head's own interval)."""
+        head = group[0]
+        key = (head.N, len(group))
+        if key not in self._sizing:
+            self._sizing[key] = Solver(head.N, len(group), device=self.device, **physics_for(DECAYING, head.N))
+        K = head.ckpt_every if ckpt_every is None else ckpt_every
+        return footprint_bytes(self._sizing[key], group, K)
 
-    def run(self, slot, group):
-        """(omega0 [B, N, N] on the host, J histories, iteration counts) of the group."""
+    def run(self, slot, group, ckpt_every=None):
+        """(omega0 [B, N, N] on the host, J histories, iteration counts) of the group, in its order."""
         head = group[0]
         B = len(group)
-        s = self._solver(slot, head.N, head.flow, B)
+        K = head.ckpt_every if ckpt_every is None else ckpt_every
+        # longest horizon first: at every step the members still advancing share one launch
+        order = sorted(range(B), key=lambda i: -group[i].n_steps)
+        g = [group[i] for i in order]
+        s = self._new_solver(slot, head.N, head.flow, B)
+        one = self._new_solver(slot, head.N, head.flow, 1)   # first guesses, member by member
+        self._live[slot] = (s, one)
         with torch.cuda.stream(self.streams[slot]):
-            vals = torch.stack([r.obs_values for r in group]).to(self.device, dtype=torch.float64,
-                                                                  non_blocking=False).contiguous()
-            obs = Observations(head.stride, head.obs_steps, vals)
-            if head.first_guess == "interp" and head.obs_steps and head.obs_steps[0] == 0:
-                fg = s.first_guess(head.stride, vals[:, 0].contiguous())
-            else:
-                fg = torch.zeros((B, head.N, head.N), dtype=torch.float64, device=self.device)
+            obs, fg = [], torch.zeros((B, head.N, head.N), dtype=torch.float64, device=self.device)
+            for b, r in enumerate(g):
+                vals = r.obs_values.to(self.device, dtype=torch.float64, non_blocking=False).contiguous()[None]
+                obs.append(Observations(r.stride, r.obs_steps, vals))
+                if r.first_guess == "interp" and r.obs_steps and r.obs_steps[0] == 0:
+                    fg[b] = one.first_guess(r.stride, vals[:, 0].contiguous())[0]
             flags = s.cancel_flags()
             with self._lock:
-                for b, r in enumerate(group):
+                for b, r in enumerate(g):
                     self._running[r.rid] = (flags, b)
             try:
-                w, H, iters = s.assimilate(fg, head.n_steps, obs, head.kernel, "lbfgs", head.iters,
-                                           head.lbfgs_m, head.ckpt_every)
+                w, H, iters = s.assimilate_members(fg, obs, [r.kernel for r in g], "lbfgs", head.iters,
+                                                   head.lbfgs_m, K)
             finally:
                 with self._lock:
-                    for r in group:
+                    for r in g:
                         self._running.pop(r.rid, None)
-            return w.cpu(), H, iters
+            w = w.cpu()
+        back = [0] * B
+        for b, i in enumerate(order):
+            back[i] = b
+        return w[back], [H[back[i]] for i in range(B)], [iters[back[i]] for i in range(B)]
 
     def cancel(self, rid):
         """Stop a running request at its next iteration boundary; False if it is not running."""
@@ -166,14 +194,13 @@ class GpuBackend:
             return True
 
     def release(self, slot, group):
-        head = group[0]
-        sv = self._solvers.get((slot, head.N, head.flow, len(group)))
-        if sv is not None:
+        for sv in self._live.pop(slot, ()):
             sv._ws = None   # return the workspace to the allocator before the budget is released
-            # ... and its segments to the device: a cached workspace (tens of GB) would otherwise
-            # be split to serve smaller blocks and could no longer be handed back whole, so the
-            # next large workspace fails with most of the memory reserved but unused
-            torch.cuda.empty_cache()
+            sv.close()
+        # ... and its segments to the device: a cached workspace (tens of GB) would otherwise
+        # be split to serve smaller blocks and could no longer be handed back whole, so the
+        # next large workspace fails with most of the memory reserved but unused
+        torch.cuda.empty_cache()
 
 
 class Server:
@@ -228,15 +255,16 @@ class Server:
         return False
 
     def _admit_locked(self):
-        """Admit queued requests into free slots while memory allows (arrival order)."""
+        """Admit queued requests into free slots while memory allows (arrival order): the oldest
+        request and the waiting requests of its batch key, up to max_batch, as one group."""
         started = []
         while self.free_slots and self.queue:
             head = self.queue[0]
-            group = [r for r in self.queue if r.shape_key() == head.shape_key()][: self.max_batch]
-            need = self.backend.footprint(head, len(group))
+            group = [r for r in self.queue if r.batch_key() == head.batch_key()][: self.max_batch]
+            need = self.backend.footprint(group)
             while need > self.budget - self.in_use and len(group) > 1:
                 group = group[:-1]
-                need = self.backend.footprint(head, len(group))
+                need = self.backend.footprint(group)
             if need > self.budget:
                 self.queue.remove(head)
                 self.results[head.rid] = Result(head.rid, None, [], 0, "rejected: exceeds HBM budget",
@@ -244,32 +272,31 @@ class Server:
                 continue
             if need > self.budget - self.in_use:
                 break   # wait for memory to free up
-            K = self._interval(head, len(group))
-            if K != head.ckpt_every:
-                for r in group:
-                    r.ckpt_every = K
-                need = self.backend.footprint(head, len(group))
+            K = self._interval(group)
+            need = self.backend.footprint(group, K)
             for r in group:
                 self.queue.remove(r)
             slot = self.free_slots.pop(0)
             self.in_use += need
-            started.append((slot, group, need))
+            started.append((slot, group, need, K))
         return started
 
-    def _interval(self, head, B):
-        """The largest checkpoint interval, from the requests' own up to the whole horizon, whose
-        group footprint fits this slot's share of the budget and the memory free now.  A longer
+    def _interval(self, group):
+        """The largest checkpoint interval, from the requests' own up to the group's whole horizon,
+        whose footprint fits this slot's share of the budget and the memory free now.  A longer
         interval recomputes fewer segments in every gradient (none once the whole trajectory is
         kept), and the solve's result does not depend on it.  The footprint grows with the
         interval (the segment store dominates), so a bisection finds it."""
-        own = max(1, min(head.ckpt_every, head.n_steps))
-        if not self.adaptive_ckpt or head.n_steps <= own:
+        head = group[0]
+        H = max(r.n_steps for r in group)
+        own = max(1, min(head.ckpt_every, H))
+        if not self.adaptive_ckpt or H <= own:
             return head.ckpt_every
         share = min(self.budget // self.slots, self.budget - self.in_use)
-        fits = lambda k: self.backend.footprint(replace(head, ckpt_every=k), B) <= share
-        if fits(head.n_steps):
-            return head.n_steps
-        lo, hi = own, head.n_steps        # lo: the requests' own interval or one that fits
+        fits = lambda k: self.backend.footprint(group, k) <= share
+        if fits(H):
+            return H
+        lo, hi = own, H                   # lo: the requests' own interval or one that fits
         while hi - lo > 1:
             mid = (lo + hi) // 2
             if fits(mid):
@@ -278,16 +305,18 @@ class Server:
                 hi = mid
         return lo
 
-    def _run_group(self, slot, group, need):
+    def _run_group(self, slot, group, need, K):
         admitted = self.now()
         try:
             head = group[0]
             B = len(group)
-            w_host, H, iters = self.backend.run(slot, group)
+            for r in group:
+                r.ckpt_every = K
+            w_host, H, iters = self.backend.run(slot, group, K)
             fin = self.now()
             if self.verbose:
-                print(f"[serving] slot {slot}: {B} x {head.N}^2 {head.flow} H={head.n_steps} done at {fin:.2f} s "
-                      f"(admitted {admitted:.2f} s)", flush=True)
+                print(f"[serving] slot {slot}: {B} x {head.N}^2 {head.flow} H={[r.n_steps for r in group]} K={K} "
+                      f"done at {fin:.2f} s (admitted {admitted:.2f} s)", flush=True)
             for b, r in enumerate(group):
                 status = "ok" if iters[b] >= 0 else "line-search failure"
                 if r.rid in self.cancelled and iters[b] >= 0 and iters[b] < r.iters:
@@ -323,8 +352,8 @@ class Server:
                 i += 1
             with self.lock:
                 started = self._admit_locked()
-            for slot, group, need in started:
-                th = threading.Thread(target=self._run_group, args=(slot, group, need), daemon=True)
+            for slot, group, need, K in started:
+                th = threading.Thread(target=self._run_group, args=(slot, group, need, K), daemon=True)
                 th.start()
                 threads.append(th)
             with self.lock:

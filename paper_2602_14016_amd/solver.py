@@ -397,6 +397,41 @@ class Solver:
         H = [[hist[b * (max_iter + 1) + i] for i in range(max_iter + 1)] for b in range(self.B)]
         return w, H, [iters[b] for b in range(self.B)]
 
+    def assimilate_members(self, omega_fg, obs, kernels, method="lbfgs", max_iter=10, lbfgs_m=10, ckpt_every=50):
+        """4D-Var of B independent problems that share the grid and physics but not their
+        observations (pa_assimilate_members): obs is a list of B Observations, each with its own
+        stride, steps and values [1, n_times, 2, M, M]; kernels a list of B KernelSpecs.  A
+        member's horizon is its last observation step; each member's result is that of a solve
+        of it alone over its own horizon.  Returns (omega0 [B, N, N], J histories, iterations)."""
+        _need(omega_fg, (self.B, self.N, self.N), "omega_fg")
+        if len(obs) != self.B or len(kernels) != self.B:
+            raise ValueError(f"need {self.B} observation sets and kernels")
+        keep, sets = [], []
+        for o in obs:
+            stride = int(o.stride)
+            if stride < 1 or self.N % stride:
+                raise ValueError(f"observation stride {stride} must divide N = {self.N}")
+            M = self.N // stride
+            _need(o.values, (1, len(o.steps), 2, M, M), "observation values")
+            c_o, arr = o.c()
+            keep.append(arr)
+            sets.append(c_o)
+        n_steps = max(int(o.steps[-1]) for o in obs)
+        self._sync_stream()
+        w = omega_fg.clone()
+        obs_arr = (nv.Obs * self.B)(*sets)
+        ks = (nv.Kernel * self.B)(*[k.c() for k in kernels])
+        hist = (c_double * (self.B * (max_iter + 1)))()
+        iters = (c_int32 * self.B)()
+        m = int(lbfgs_m) if method == "lbfgs" else 1
+        ws, wb = self.workspace(n_steps, ckpt_every, max(len(o.steps) for o in obs), max(m, 1))
+        nv.check(self.lib.pa_assimilate_members(self.ctx, _ptr(w), int(n_steps), obs_arr, ks,
+                                                0 if method == "lbfgs" else 1, int(max_iter), m, int(ckpt_every),
+                                                hist, iters, ws, wb))
+        del keep
+        H = [[hist[b * (max_iter + 1) + i] for i in range(max_iter + 1)] for b in range(self.B)]
+        return w, H, [iters[b] for b in range(self.B)]
+
     def adjoint_impulse(self, omega0, n_steps, ix, iy, n_shells, ckpt_every=50, want_field=False, acc=None):
         """Impulse response shells [B][n_steps + 1][n_shells] (and P lambda_0 if want_field);
         with acc (an EnsembleAccumulator), the batch is added to its ensemble sums."""

@@ -232,3 +232,73 @@ def test_cancelled_members_stop_alone():
     for b in (0, 1):
         assert it[b] == iters and H[b] == H_ref[b]
     s.cancel_flags()
+
+
+def _member_problems(N, ph, specs, seed0=40):
+    """(stride, horizon, kernel) per member -> observations from its own truth, first guesses."""
+    probs = []
+    for i, (stride, H, kern) in enumerate(specs):
+        osteps = synth.evenly_spaced_steps(H, 3 if H >= 2 else 1 + H)
+        truth = O.init_field(N, [seed0 + i], kind=1, k0=4.0)[0]
+        mo = O.forward(truth, ph, H, Obs(stride, osteps))[2]
+        fg = 0.5 * O.init_field(N, [seed0 + 50 + i], kind=0, k0=4.0)[0]
+        probs.append((stride, H, kern, osteps, mo, fg))
+    return probs
+
+
+# members with different probe strides, horizons (observation windows) and kernels; the order
+# (longest horizon first, or not) changes which members share a launch, never the results
+MEMBER_SPECS = [
+    [(4, 30, Kernel(1, 0.05, 0)), (8, 18, Kernel(0, 0.0, 0)), (2, 9, Kernel(2, 0.5, 0)), (4, 0, Kernel(0, 0.0, 1))],
+    [(8, 9, Kernel(2, 0.5, 0)), (4, 30, Kernel(1, 0.05, 0)), (4, 0, Kernel(0, 0.0, 1)), (2, 18, Kernel(3, 0.01, 0))],
+]
+
+
+@pytest.mark.parametrize("order", [0, 1])
+def test_member_observation_sets_alone_equal_batch_and_oracle(order):
+    """One batched solve of members with their own observation sets (pa_assimilate_members): each
+    member's iterates, cost history and iteration count are bitwise those of its own solve over its
+    own horizon, alone, and match the oracle's solve of that member (1e-9)."""
+    from paper_2602_14016_amd import KernelSpec, Observations, Solver
+    print("CASE members", order, flush=True)
+    N = 32
+    ph = Physics(N=N, nu=1e-3, dt=5e-3)
+    probs = _member_problems(N, ph, MEMBER_SPECS[order])
+    B = len(probs)
+    sv = Solver(N, B, nu=ph.nu, dt=ph.dt)
+    obs = [Observations(st, os_, dev(mo[None])) for (st, H, k, os_, mo, fg) in probs]
+    kerns = [KernelSpec(k.kind, k.param, k.metric) for (st, H, k, os_, mo, fg) in probs]
+    fg = dev(np.stack([p[5] for p in probs]))
+    w, Hh, it = sv.assimilate_members(fg, obs, kerns, "lbfgs", max_iter=4, lbfgs_m=3, ckpt_every=7)
+    w = w.cpu().numpy()
+    one = Solver(N, 1, nu=ph.nu, dt=ph.dt)
+    for b, (st, H, k, os_, mo, fgb) in enumerate(probs):
+        print("CASE members member", order, b, st, H, flush=True)
+        w1, H1, it1 = one.assimilate(dev(fgb[None]), H, Observations(st, os_, dev(mo[None])), [kerns[b]], "lbfgs",
+                                     max_iter=4, lbfgs_m=3, ckpt_every=7)
+        assert np.array_equal(w[b], w1.cpu().numpy()[0]), (b, float(np.abs(w[b] - w1.cpu().numpy()[0]).max()))
+        assert Hh[b] == H1[0] and it[b] == it1[0], (b, Hh[b], H1[0])
+        w_ref, h_ref, it_ref, _ = O.assimilate(fgb, ph, H, Obs(st, os_, mo), k, "lbfgs", 4, 3)
+        assert it[b] == it_ref
+        assert np.allclose(Hh[b][: it_ref + 1], h_ref, rtol=ITER_TOL, atol=0), (b, Hh[b], h_ref)
+        assert rel(w[b], w_ref) < ITER_TOL, (b, rel(w[b], w_ref))
+
+
+def test_member_observation_sets_refusals():
+    """n_steps other than the latest horizon, a member without observation times and a snapshot
+    budget are refused before anything is enqueued."""
+    from paper_2602_14016_amd import KernelSpec, Observations, Solver
+    from paper_2602_14016_amd.native import PaError
+    print("CASE members-refusals", flush=True)
+    N = 16
+    sv = Solver(N, 2, nu=1e-3, dt=5e-3)
+    vals = lambda nt, st: torch.zeros((1, nt, 2, N // st, N // st), dtype=torch.float64, device="cuda")
+    fg = torch.zeros((2, N, N), dtype=torch.float64, device="cuda")
+    ks = [KernelSpec(), KernelSpec()]
+    with pytest.raises((PaError, ValueError, IndexError)):
+        sv.assimilate_members(fg, [Observations(4, [0, 5], vals(2, 4)), Observations(4, [], vals(0, 4))], ks)
+    sv.set_checkpoint_slots(1)
+    with pytest.raises(PaError):
+        sv.assimilate_members(fg, [Observations(4, [0, 6], vals(2, 4)), Observations(2, [3], vals(1, 2))], ks,
+                              ckpt_every=2)
+    sv.set_checkpoint_slots(0)

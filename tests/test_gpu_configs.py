@@ -87,10 +87,25 @@ def test_c1_full_horizon_gradient_against_oracle():
     print("CASE c1-1000 rel J", ej, "rel grad", eg, flush=True)
     assert ej <= 1e-11
     assert eg < 1e-9
+    # the same gradient through the autograd path as the configuration runs it: checkpoints
+    # every 50 steps in the forward, segment recomputation in the backward, grad_output 1
+    from paper_2602_14016_amd.autograd import adjoint_cost
+    print("CASE c1-1000 autograd", flush=True)
+    w = dev(w0[None]).requires_grad_(True)
+    Ja = adjoint_cost(w, s, H, Observations(8, osteps, dev(mo[None])), 50)
+    Ja.sum().backward()
+    ea = rel(w.grad.detach().cpu().numpy()[0], g_ref)
+    print("CASE c1-1000 autograd rel J", abs(float(Ja.detach().cpu()[0]) - J_ref) / J_ref, "rel grad", ea, flush=True)
+    assert abs(float(Ja.detach().cpu()[0]) - J_ref) <= 1e-11 * J_ref
+    assert ea < 1e-9
 
 
 def test_c1_full_finite_differences():
+    """The differentiation configuration as specified: the gradient from the autograd path
+    (checkpoints every 50 steps, segment recomputation in the backward) against central finite
+    differences (eps = 1e-6) of the cost on 20 random directions."""
     from paper_2602_14016_amd import Observations, Solver
+    from paper_2602_14016_amd.autograd import adjoint_cost
     print("CASE c1-fd", flush=True)
     N, H, ndir = 256, 1000, 20
     s1 = Solver(N, 1, nu=1e-4, dt=2e-3)
@@ -99,7 +114,9 @@ def test_c1_full_finite_differences():
     mo = s1.forward(truth, H, Observations(8, osteps), want_obs=True)["obs"]
     fg = s1.first_guess(8, mo[:, 0].contiguous())
     obs1 = Observations(8, osteps, mo)
-    J0, g = s1.adjoint_gradient(fg, H, obs1, ckpt_every=50)
+    w = fg.clone().requires_grad_(True)
+    adjoint_cost(w, s1, H, obs1, 50).sum().backward()
+    g = w.grad.detach()
     rms = float(fg.pow(2).mean().sqrt())
     d = torch.stack([torch.from_numpy(synth.normal_field((N, N), 1000 + i)) for i in range(ndir)]).cuda()
     d = d * (rms / d.pow(2).mean(dim=(1, 2), keepdim=True).sqrt())
@@ -149,6 +166,60 @@ def test_c2_100_step_field_and_gradient_against_oracle():
     assert rel(wT.cpu().numpy()[0], ref["omega_T"]) < 1e-11
     assert abs(float(J.cpu()[0]) - float(ref["J"])) <= 1e-11 * float(ref["J"])
     assert rel(g.cpu().numpy()[0], ref["grad"]) < 1e-9
+
+
+def test_c1_grid_lbfgs_iterates_against_oracle():
+    """L-BFGS at the differentiation configuration's grid and physics (256^2, nu = 1e-4, dt =
+    2e-3) over a 50-step window (5 observation times, stride 8), kernel exp(-0.05|k|), memory 10,
+    from the oracle's interpolated first guess: the cost after each of 10 iterations and the
+    estimates after 1, 5 and 10 iterations against the oracle's (1e-9), stored by
+    tests/golden/make_oracle_fixtures.py; and the library's own first guess from the t = 0 probes
+    against the oracle's."""
+    from paper_2602_14016_amd import KernelSpec, Observations, Solver
+    print("CASE c1-grid-lbfgs", flush=True)
+    N, H = 256, 50
+    ref = _golden("c1_grid_lbfgs.npz")
+    osteps = [int(x) for x in ref["obs_steps"]]
+    assert osteps == synth.evenly_spaced_steps(H, 5)
+    mo = dev(ref["obs"][None])
+    s = Solver(N, 1, nu=1e-4, dt=2e-3)
+    fg = s.first_guess(8, mo[:, 0].contiguous())
+    assert rel(fg.cpu().numpy()[0], ref["first_guess"]) < 1e-13
+    obs = Observations(8, osteps, mo)
+    for k in (1, 5, 10):
+        w, Hh, it = s.assimilate(dev(ref["first_guess"][None]), H, obs, KernelSpec(1, 0.05), "lbfgs", max_iter=k,
+                                 lbfgs_m=10, ckpt_every=25)
+        href = ref[f"J_hist_{k}"]
+        ew = rel(w.cpu().numpy()[0], ref[f"omega_{k}"])
+        eh = float(np.max(np.abs(np.array(Hh[0]) - href) / href))
+        print(f"CASE c1-grid-lbfgs {k} iterations: rel omega {ew:.2e}, rel J history {eh:.2e}", flush=True)
+        assert it[0] == k and len(Hh[0]) == len(href) == k + 1
+        assert eh < 1e-9
+        assert ew < 1e-9
+
+
+def test_largest_grid_50_steps_against_oracle():
+    """The largest grid (1024^2, nu = 1e-4, dt = 5e-4) over 50 steps: the field after 50 steps
+    (1e-11) and the cost (1e-11) and gradient (1e-9) of a 3-time window at stride 16 against the
+    oracle's, stored at every 4th grid point in each direction by
+    tests/golden/make_oracle_fixtures.py; the gradient recomputes segments of 10 steps."""
+    from paper_2602_14016_amd import Observations, Solver
+    print("CASE grid-1024-50", flush=True)
+    N, H = 1024, 50
+    ref = _golden("grid1024_50_steps.npz")
+    ev = int(ref["sample_every"])
+    w0 = O.init_field(N, [3], kind=0, k0=N / 25.0, target=0.5)[0]
+    s = Solver(N, 1, nu=1e-4, dt=5e-4)
+    wT = s.forward(dev(w0[None]), H)["omega_T"].cpu().numpy()[0]
+    ef = rel(wT[::ev, ::ev], ref["omega_T"])
+    osteps = [int(x) for x in ref["obs_steps"]]
+    J, g = s.adjoint_gradient(dev(w0[None]), H, Observations(16, osteps, dev(ref["obs"][None])), ckpt_every=10)
+    ej = abs(float(J.cpu()[0]) - float(ref["J"])) / float(ref["J"])
+    eg = rel(g.cpu().numpy()[0][::ev, ::ev], ref["grad"])
+    print(f"CASE grid-1024-50 rel field {ef:.2e} cost {ej:.2e} gradient {eg:.2e}", flush=True)
+    assert ef < 1e-11
+    assert ej <= 1e-11
+    assert eg < 1e-9
 
 
 def test_largest_grid_gradient_parity():

@@ -53,6 +53,12 @@ def test_autograd_function_matches_adjoint_and_fd(lam):
     assert np.allclose(J.detach().cpu().numpy(), Jd.cpu().numpy(), rtol=0, atol=0)
     for b, wgt in enumerate([0.7, -1.3]):
         assert rel(g_auto[b], wgt * gd[b]) < 1e-14
+    # the backward against the oracle's gradient of the same cost (Eq. (12) in its discrete form)
+    w0np = w0.detach().cpu().numpy()
+    for b, wgt in enumerate([0.7, -1.3]):
+        J_ref, g_ref = O.adjoint_gradient(w0np[b], ph, steps, Obs(4, osteps, mo[b]), sobolev=lam)
+        assert abs(float(J.detach().cpu()[b]) - J_ref) <= 1e-11 * J_ref
+        assert rel(g_auto[b], wgt * g_ref) < 1e-9, (b, rel(g_auto[b], wgt * g_ref))
     # central finite differences on 5 directions (the GPU forward), eps = 1e-6
     for seed in range(1000, 1005):
         d = dev(synth.normal_field((2, N, N), seed))

@@ -3,10 +3,12 @@
 The backend stands for GpuBackend: footprint() sizes a group, run() "solves"
 it (sleeps, then returns identifiable host results, a NaN observation making
 that member's line search fail as the device solve would), release() frees
-it.  The tests check admission by bytes, slot recycling, batching of
-same-shape requests, rejection of oversize requests, a poisoned request
-failing alone, an exception failing only its group, cancellation of a
-queued request and arrival-order admission on a Poisson trace.
+it.  The tests check admission by bytes, slot recycling, batching of requests
+of one grid and physics whatever their horizons and strides, rejection of
+oversize requests, a poisoned request failing alone, an exception failing
+only its group, cancellation of a queued request and arrival-order admission
+on a Poisson trace.  Requests that must not batch differ in iteration count,
+which is part of the batch key.
 """
 
 import threading
@@ -30,10 +32,10 @@ class SleepBackend:
         self.calls = []          # (slot, [rids]) in start order
         self.released = []
 
-    def footprint(self, req, B):
-        return self.bytes_per_member * B * (req.N // 8)
+    def footprint(self, group, ckpt_every=None):
+        return self.bytes_per_member * len(group) * (group[0].N // 8)
 
-    def run(self, slot, group):
+    def run(self, slot, group, ckpt_every=None):
         with self.lock:
             self.active += 1
             self.max_active = max(self.max_active, self.active)
@@ -58,18 +60,19 @@ class SleepBackend:
         self.released.append([r.rid for r in group])
 
 
-def req(rid, arrival=0.0, N=8, n_steps=10, poisoned=False):
-    vals = torch.zeros((1, 2, 2, 2), dtype=torch.float64)
+def req(rid, arrival=0.0, N=8, n_steps=10, poisoned=False, iters=10, stride=4):
+    M = N // stride
+    vals = torch.zeros((1, 2, M, M), dtype=torch.float64)
     if poisoned:
         vals[0, 0, 0, 0] = float("nan")
-    return Request(rid=rid, N=N, flow="decaying", n_steps=n_steps, stride=4, obs_steps=[0], obs_values=vals,
-                   kernel=KernelSpec(0, 0.0), arrival=arrival)
+    return Request(rid=rid, N=N, flow="decaying", n_steps=n_steps, stride=stride, obs_steps=[0], obs_values=vals,
+                   kernel=KernelSpec(0, 0.0), iters=iters, arrival=arrival)
 
 
 def test_admission_respects_the_byte_budget_and_recycles_slots():
     be = SleepBackend(bytes_per_member=100, solve_s=0.05)
-    # distinct horizons: no batching; the budget holds two requests at once although four slots exist
-    reqs = [req(i, n_steps=10 + i) for i in range(6)]
+    # distinct iteration counts: no batching; the budget holds two requests at once although four slots exist
+    reqs = [req(i, iters=10 + i) for i in range(6)]
     res = Server(250, slots=4, backend=be).run_trace(reqs)
     assert all(res[r.rid].status == "ok" for r in reqs)
     assert be.max_active == 2
@@ -77,14 +80,14 @@ def test_admission_respects_the_byte_budget_and_recycles_slots():
     assert sorted(sum((c for _, c in be.calls), [])) == list(range(6))
     assert len(be.released) == 6
     be1 = SleepBackend(solve_s=0.02)
-    res1 = Server(10 ** 9, slots=2, backend=be1).run_trace([req(i, n_steps=10 + i) for i in range(5)])
+    res1 = Server(10 ** 9, slots=2, backend=be1).run_trace([req(i, iters=10 + i) for i in range(5)])
     assert all(r.status == "ok" for r in res1.values())
     assert {s for s, _ in be1.calls} == {0, 1} and be1.max_active <= 2
 
 
 def test_same_shape_requests_run_as_one_batch_up_to_max_batch():
     be = SleepBackend(solve_s=0.05)
-    reqs = [req(i) for i in range(3)]            # one shape
+    reqs = [req(i) for i in range(3)]            # one batch key
     res = Server(10 ** 9, slots=1, max_batch=2, backend=be).run_trace(reqs)
     assert [len(c) for _, c in be.calls] == [2, 1]
     assert [res[i].batch for i in range(3)] == [2, 2, 1]
@@ -92,9 +95,21 @@ def test_same_shape_requests_run_as_one_batch_up_to_max_batch():
         assert torch.all(res[i].omega0 == float(i))     # each member gets its own result
 
 
+def test_requests_of_one_grid_batch_across_horizons_and_strides():
+    """One grid and physics is one batch, whatever the horizons, strides and kernels; another grid
+    or flow is another."""
+    be = SleepBackend(solve_s=0.05)
+    reqs = [req(0, n_steps=200), req(1, n_steps=1500, stride=2), req(2, N=16, n_steps=300), req(3, n_steps=40)]
+    reqs[3].kernel = KernelSpec(2, 0.5)
+    res = Server(10 ** 9, slots=1, max_batch=8, backend=be).run_trace(reqs)
+    assert [c for _, c in be.calls] == [[0, 1, 3], [2]]
+    assert [res[i].batch for i in range(4)] == [3, 3, 1, 3]
+    assert all(res[i].status == "ok" for i in range(4))
+
+
 def test_oversize_request_is_rejected_alone():
     be = SleepBackend(bytes_per_member=100)
-    reqs = [req(0), req(1, N=800), req(2, n_steps=11)]   # request 1 needs 100 * 100 bytes
+    reqs = [req(0), req(1, N=800), req(2, iters=11)]   # request 1 needs 100 * 100 bytes
     res = Server(1000, slots=2, backend=be).run_trace(reqs)
     assert res[1].status.startswith("rejected")
     assert res[0].status == "ok" and res[2].status == "ok"
@@ -111,7 +126,7 @@ def test_poisoned_request_fails_alone_inside_a_batch():
 
 def test_backend_exception_fails_only_its_group():
     be = SleepBackend(fail_rids={1})
-    reqs = [req(0), req(1, n_steps=11), req(2, n_steps=12)]
+    reqs = [req(0), req(1, iters=11), req(2, iters=12)]
     res = Server(10 ** 9, slots=2, backend=be).run_trace(reqs)
     assert res[1].status.startswith("error")
     assert res[0].status == "ok" and res[2].status == "ok"
@@ -121,7 +136,7 @@ def test_backend_exception_fails_only_its_group():
 def test_cancel_a_queued_request():
     be = SleepBackend(solve_s=0.4)
     srv = Server(10 ** 9, slots=1, backend=be)
-    reqs = [req(0), req(1, n_steps=11), req(2, n_steps=12)]
+    reqs = [req(0), req(1, iters=11), req(2, iters=12)]
     out = {}
     th = threading.Thread(target=lambda: out.update(srv.run_trace(reqs)))
     th.start()
@@ -140,7 +155,7 @@ def test_poisson_trace_is_admitted_in_arrival_order():
     arrivals = poisson_arrivals(12, rate=200.0, seed=3)
     assert np.all(np.diff(arrivals) > 0)
     be = SleepBackend(solve_s=0.01)
-    reqs = [req(i, arrival=float(a), n_steps=10 + i) for i, a in enumerate(arrivals)]
+    reqs = [req(i, arrival=float(a), iters=10 + i) for i, a in enumerate(arrivals)]
     res = Server(10 ** 9, slots=1, backend=be).run_trace(list(reversed(reqs)))
     assert [c[0] for _, c in be.calls] == list(range(12))
     assert all(res[i].admitted >= reqs[i].arrival - 1e-3 for i in range(12))
@@ -157,7 +172,7 @@ class CancellableSleepBackend(SleepBackend):
         self.stop = set()
         self.running = set()
 
-    def run(self, slot, group):
+    def run(self, slot, group, ckpt_every=None):
         with self.lock:
             self.running |= {r.rid for r in group}
         try:
@@ -206,19 +221,20 @@ def test_cancel_a_running_request_stops_it_alone():
 class IntervalBackend(SleepBackend):
     """Footprint grows with the checkpoint interval, as the segment store does."""
 
-    def footprint(self, req, B):
-        return B * (1000 + 10 * req.ckpt_every)
+    def footprint(self, group, ckpt_every=None):
+        K = group[0].ckpt_every if ckpt_every is None else ckpt_every
+        return len(group) * (1000 + 10 * K)
 
-    def run(self, slot, group):
+    def run(self, slot, group, ckpt_every=None):
         with self.lock:
-            self.intervals = getattr(self, "intervals", []) + [(group[0].rid, group[0].ckpt_every)]
-        return super().run(slot, group)
+            self.intervals = getattr(self, "intervals", []) + [(group[0].rid, ckpt_every)]
+        return super().run(slot, group, ckpt_every)
 
 
 def test_admitted_groups_get_the_largest_interval_that_fits():
     be = IntervalBackend(solve_s=0.01)
     # budget 40000 over 2 slots: share 20000 -> 1000 + 10 K <= 20000 -> K = 1900 for one member
-    reqs = [req(0, n_steps=5000), req(1, n_steps=300), req(2, n_steps=40)]
+    reqs = [req(0, n_steps=5000), req(1, n_steps=300, iters=11), req(2, n_steps=40, iters=12)]
     for r in reqs:
         r.ckpt_every = 50
     res = Server(40000, slots=2, backend=be).run_trace(reqs)
