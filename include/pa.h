@@ -182,6 +182,31 @@ pa_status pa_adjoint_gradient(pa_ctx* ctx, const double* omega0, int32_t n_steps
                               const pa_obs* obs, double* J_out, double* grad_out,
                               int32_t ckpt_every, void* workspace, size_t workspace_bytes);
 
+/* Scratch that pa_adjoint_gradient_noalloc uses in place of a workspace:
+ * 128 MiB of device memory per device the library runs on, reserved when the
+ * library's code is loaded there and held until the process ends. */
+#define PA_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * gradient of pa_adjoint_gradient, bit for bit, with its workspace carved
+ * from a library-owned device array of PA_NOALLOC_SCRATCH_BYTES instead of a
+ * caller's buffer.  The caller passes inputs and outputs only (omega0, obs,
+ * J_out, grad_out as in pa_adjoint_gradient).  No device memory is allocated
+ * or freed, nor host memory on success (launch timing by pa_profile_start
+ * creates its events).  The internal checkpoints keep one state per segment
+ * boundary: PA_EINVAL if a snapshot budget (pa_set_checkpoint_slots) would
+ * make a binomial schedule, and PA_EINVAL, with the size needed, when
+ * pa_workspace_bytes(ctx, n_steps, ckpt_every, obs->n_times, 0) exceeds
+ * PA_NOALLOC_SCRATCH_BYTES (lower ckpt_every or use pa_adjoint_gradient).
+ * Every call on one device shares that device's array and leaves its
+ * contents behind; calls that overlap in time on one device (other streams,
+ * other threads, other contexts) race on it and must be serialised by the
+ * caller.  Contexts on different devices use different copies. */
+pa_status pa_adjoint_gradient_noalloc(pa_ctx* ctx, const double* omega0, int32_t n_steps,
+                                      const pa_obs* obs, double* J_out, double* grad_out,
+                                      int32_t ckpt_every);
+
 /* Same gradient from the checkpoints a previous pa_forward wrote (same
  * n_steps, ckpt_every, obs steps; ckpt 16-byte aligned).  scale: device [B]
  * or NULL; the gradient of member b is multiplied by scale[b] (the autograd

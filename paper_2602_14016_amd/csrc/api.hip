@@ -12,6 +12,7 @@
 #include <cstring>
 #include <initializer_list>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1135,6 +1136,39 @@ void host_twiddles(int N, std::vector<cd>& tw) {
 
 }  // namespace
 
+// ------------------------------------------------ allocation-free calls --
+// Scratch of pa_adjoint_gradient_noalloc: a file-scope device array, one copy
+// on every device the library runs on, held until the process ends.  In host
+// code `scratch` is only a stand-in for the symbol, not a device address: the
+// address of each device's copy is looked up once, with that device current,
+// when the first context is created on it (bind_scratch), and only that
+// address is ever handed to kernels.
+static __device__ __align__(256) unsigned char scratch[PA_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int SCRATCH_DEVICES = 256;
+std::once_flag g_scratch_once[SCRATCH_DEVICES];
+void* g_scratch_ptr[SCRATCH_DEVICES];
+hipError_t g_scratch_err[SCRATCH_DEVICES];
+
+// Device address of the current device `dev`'s copy of scratch (once per device).
+void bind_scratch(int dev) {
+    if (dev < 0 || dev >= SCRATCH_DEVICES) return;
+    std::call_once(g_scratch_once[dev], [dev] {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            p = nullptr;
+        }
+        g_scratch_err[dev] = e;
+        g_scratch_ptr[dev] = p;
+    });
+}
+
+}  // namespace
+
 // ================================================================= ABI ==
 
 extern "C" {
@@ -1160,6 +1194,7 @@ pa_status pa_create(const pa_physics* phys, int32_t N, int32_t B, void* hip_stre
 
     int dev = 0;
     PA_HIP(hipGetDevice(&dev));
+    bind_scratch(dev);   // the allocation-free calls' scratch on this device
     // owned until it is handed out: every early return (or a failed host
     // allocation below) frees it and whatever device tables it already holds
     std::unique_ptr<pa_ctx, pa_status (*)(pa_ctx*)> owner(new pa_ctx(), pa_destroy);
@@ -1498,6 +1533,43 @@ pa_status pa_adjoint_gradient(pa_ctx* c, const double* omega0, int32_t n_steps, 
         else PA_HIP(launch_fill(J_out, 0.0, c->d.B, c->stream));
     }
     return backward_sweep(c, w, w.ckpt, n_steps, K, &op, 0, -1, -1, nullptr, grad_out, Shells(), true, plan);
+} PA_CATCH_HOST
+
+// pa_adjoint_gradient with the workspace carved from this device's scratch.
+// Allocates nothing: no device memory, and on its success path no host memory
+// (the observation plan is a binary search over the caller's steps).
+pa_status pa_adjoint_gradient_noalloc(pa_ctx* c, const double* omega0, int32_t n_steps, const pa_obs* obs,
+                                      double* J_out, double* grad_out, int32_t ckpt_every) try {
+    g_err.clear();
+    if (!c || !omega0 || !grad_out) return fail(PA_EINVAL, "NULL argument");
+    if (n_steps < 0 || ckpt_every < 1) return fail(PA_EINVAL, "bad sizes");
+    const int K = seg_len(n_steps, ckpt_every);
+    if (plan_mode(c, n_segments(n_steps, K)))
+        return fail(PA_EINVAL, "pa_adjoint_gradient_noalloc keeps one state per segment boundary: "
+                               "set the snapshot budget to 0");
+    PA_TRY(require_device(c->stream, {{omega0, "omega0"}, {J_out, "J_out"}, {grad_out, "grad_out"},
+                           {obs ? obs->values : nullptr, "obs values"}}));
+    ObsPlan op;
+    PA_TRY(make_obs_plan(c, obs, n_steps, true, &op));
+    const size_t need = carve(c, n_steps, ckpt_every, op.max_times, 0, nullptr).total;
+    if (need > PA_NOALLOC_SCRATCH_BYTES)
+        return fail(PA_EINVAL, "this gradient needs " + std::to_string(need) +
+                                   " bytes of scratch, more than the PA_NOALLOC_SCRATCH_BYTES the library holds "
+                                   "per device: lower ckpt_every, or call pa_adjoint_gradient with a workspace");
+    void* ws = (c->device >= 0 && c->device < SCRATCH_DEVICES) ? g_scratch_ptr[c->device] : nullptr;
+    if (!ws)
+        return fail(PA_EDEVICE, std::string("no scratch address on this device: ") +
+                                    ((c->device >= 0 && c->device < SCRATCH_DEVICES)
+                                         ? hipGetErrorString(g_scratch_err[c->device])
+                                         : "device index out of range"));
+    WS w;
+    PA_TRY(check_ws(c, ws, PA_NOALLOC_SCRATCH_BYTES, n_steps, ckpt_every, op.max_times, 0, &w, true));
+    PA_TRY(forward_sweep(c, w, omega0, n_steps, op, nullptr, w.ckpt, K, true, nullptr));
+    if (J_out) {
+        if (op.n > 0) PA_HIP(launch_copy(J_out, w.J, c->d.B, c->stream));
+        else PA_HIP(launch_fill(J_out, 0.0, c->d.B, c->stream));
+    }
+    return backward_sweep(c, w, w.ckpt, n_steps, K, &op, 0, -1, -1, nullptr, grad_out, Shells(), true, nullptr);
 } PA_CATCH_HOST
 
 pa_status pa_ensemble_acc_bytes(const pa_ctx* c, int32_t n_steps, int32_t n_shells, size_t* lambda_bytes,

@@ -63,6 +63,8 @@ EXPORTS = {
                              c_int32, c_void_p, c_void_p, c_size_t]),
     "pa_adjoint_gradient": (c_int32, [c_void_p, c_void_p, c_int32, POINTER(Obs), c_void_p, c_void_p,
                                       c_int32, c_void_p, c_size_t]),
+    "pa_adjoint_gradient_noalloc": (c_int32, [c_void_p, c_void_p, c_int32, POINTER(Obs), c_void_p, c_void_p,
+                                              c_int32]),
     "pa_adjoint_from_checkpoints": (c_int32, [c_void_p, c_void_p, c_int32, POINTER(Obs), c_void_p,
                                               c_void_p, c_int32, c_void_p, c_size_t]),
     "pa_precondition": (c_int32, [c_void_p, POINTER(Kernel), c_double, c_void_p, c_void_p, c_void_p,

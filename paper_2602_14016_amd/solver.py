@@ -322,6 +322,22 @@ class Solver:
         del keep
         return J, g
 
+    def adjoint_gradient_noalloc(self, omega0, n_steps, obs: Observations, ckpt_every=50, J=None, grad=None):
+        """adjoint_gradient without a workspace (pa_adjoint_gradient_noalloc): the library's own
+        per-device scratch holds it, so nothing is allocated when J and grad are given.  Calls
+        that overlap on one device race on that scratch."""
+        _need(omega0, (self.B, self.N, self.N), "omega0")
+        J = torch.empty(self.B, dtype=torch.float64, device=self.device) if J is None else J
+        g = self.empty() if grad is None else grad
+        _need(J, (self.B,), "J")
+        _need(g, (self.B, self.N, self.N), "grad")
+        self._sync_stream()
+        o_c, keep = self._obs(obs, need_values=True)
+        nv.check(self.lib.pa_adjoint_gradient_noalloc(self.ctx, _ptr(omega0), int(n_steps), byref(o_c), _ptr(J),
+                                                      _ptr(g), int(ckpt_every)))
+        del keep
+        return J, g
+
     def adjoint_from_checkpoints(self, ckpt, n_steps, obs: Observations, ckpt_every, scale=None):
         _need_bytes(ckpt, self.checkpoint_bytes(n_steps, ckpt_every), "ckpt")
         if scale is not None:
