@@ -552,11 +552,10 @@ Dims slice_dims(const pa_ctx* c, int lo, int hi) {
 }
 
 // Observation of range r at its slot (velocity probes and cost partials) from the
-// stage-a fields (U, V first) of the state at that step.
+// stage-a fields (the packed pairs (u, w_x), (v, w_y)) of the state at that step.
 pa_status observe_range(pa_ctx* c, WS& w, const ObsRange& r, int slot, cd* const fields[4], double* obs_out) {
     RowArgs ra{};
-    ra.yin[0] = fields[0] + (size_t)r.b0 * per_y(c);
-    ra.yin[1] = fields[1] + (size_t)r.b0 * per_y(c);
+    for (int i = 0; i < 4; ++i) ra.yin[i] = fields[i] + (size_t)r.b0 * per_y(c);
     ra.tw = c->tw;
     ra.obs = row_obs_args(&r, slot, obs_out, w.jpart + r.jrow0);
     PA_HIP(launch_row_obs(slice_dims(c, r.b0, r.b0 + r.nb), ra, c->stream));
@@ -578,8 +577,7 @@ pa_status source_rows(pa_ctx* c, const ObsRange& r, int slot, int lo, int hi, cd
                       cd* const out[2]) {
     const size_t off = (size_t)lo * per_y(c);
     RowArgs rs{};
-    rs.yin[0] = fields[0] + off;
-    rs.yin[1] = fields[1] + off;
+    for (int i = 0; i < 4; ++i) rs.yin[i] = fields[i] + off;
     rs.yout[0] = out[0] + off;
     rs.yout[1] = out[1] + off;
     rs.tw = c->tw;
@@ -640,10 +638,10 @@ ColArgs col_base(const pa_ctx* c) {
 
 void set_stage_fields(ColArgs& a, cd* const f[4]) {
     a.nout = 4;
-    a.fields[0] = F_U;
-    a.fields[1] = F_V;
-    a.fields[2] = F_WX;
-    a.fields[3] = F_WY;
+    a.fields[0] = F_UP;
+    a.fields[1] = F_UQ;
+    a.fields[2] = F_VP;
+    a.fields[3] = F_VQ;
     for (int i = 0; i < 4; ++i) a.yout[i] = f[i];
 }
 
@@ -827,8 +825,9 @@ pa_status adj_stage(pa_ctx* c, WS& w, cd* const fields[4], int mode, const ObsPl
         a.nout = 1;
     } else {
         a.nout = 2;
+        a.fields[0] = F_LP;
         a.yout[1] = w.YL[1];
-        a.fields[1] = F_WY;
+        a.fields[1] = F_LQ;
     }
     const int cmode = (mode == COL_ADJ_N && a.nin > 2) ? COL_ADJ_NSRC : mode;
     PA_HIP(timed(c, PROF_COL_ADJ, [&] { return launch_col(dn, cmode, a, c->stream); }));
@@ -902,8 +901,9 @@ pa_status terminal(pa_ctx* c, WS& w, const ObsPlan* op, int step, cd* const fiel
         a.nout = 1;
     } else {
         a.nout = 2;
+        a.fields[0] = F_LP;
         a.yout[1] = w.YL[1] + offY;
-        a.fields[1] = F_WY;
+        a.fields[1] = F_LQ;
     }
     PA_HIP(launch_col(ds, COL_ADJ_SRC, a, c->stream));
     return PA_OK;
@@ -945,10 +945,10 @@ pa_status backward_sweep(pa_ctx* c, WS& w, const cd* ckpt, int n_steps, int K, c
         ColArgs a = col_base(c);
         a.state_in = ckpt_slot(c, ck, 0) + (size_t)lo * per_c(c);
         a.nout = 4;
-        a.fields[0] = F_U;
-        a.fields[1] = F_V;
-        a.fields[2] = F_WX;
-        a.fields[3] = F_WY;
+        a.fields[0] = F_UP;
+        a.fields[1] = F_UQ;
+        a.fields[2] = F_VP;
+        a.fields[3] = F_VQ;
         for (int i = 0; i < 4; ++i) a.yout[i] = f0[i] + offY;
         PA_HIP(launch_col(slice_dims(c, lo, B), COL_FROM_STATE, a, c->stream));
         return terminal(c, w, op, 0, f0, impulse, ix, iy, true, scale, lo, B);

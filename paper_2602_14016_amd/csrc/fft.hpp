@@ -409,4 +409,115 @@ __device__ __forceinline__ void fft(cd* v, int t, cd* lds, const TwReg<N, V>& tr
     }
 }
 
+// ---- 256 points on one wavefront with cross-lane digit exchanges (gfx950) ----
+// A row of 256 points is held by the 64 lanes of one wavefront, four values per
+// lane: element t + 64 m in register m of lane t (the layout of plan (256, 2)).
+// Writing an index in base 4 as i = i0 + 4 i1 + 16 i2 + 64 i3, lane t holds the
+// digits (i0, i1, i2) and register m the digit i3.  The transform runs four
+// radix-4 decimation-in-frequency stages; each needs the digit it transforms in
+// the register, so between stages the register digit trades places with one
+// lane digit:
+//   * i2 (lane bits 5:4) through the gfx950 lane-swap instructions, which run
+//     on the vector ALU and need no LDS: v_permlane32_swap trades lane bit 5
+//     with register bit 1, v_permlane16_swap lane bit 4 with register bit 0;
+//   * i1 and then i0 through LDS, in layouts where the 16 lanes of any aligned
+//     group write and read 16 distinct 16-byte slots (a XOR of the slot's low
+//     bits with the register index), so no access waits on a bank;
+// and the last exchange also places the output in natural order (element k in
+// register k / 64 of lane k mod 64).  Input and output therefore share the
+// layout of the Stockham plan, and chain with the pointwise products in the
+// same way, with one LDS exchange fewer per transform.
+// Twiddles (DIF): after the stage on digit i3 the output of digit k0 is
+// multiplied by w256^(k0 n1) (n1 = i0 + 4 i1 + 16 i2), after the stage on i2
+// by w64^(k1 n2) (n2 = i0 + 4 i1), after the stage on i1 by w16^(k2 i0).
+struct Tw256 {
+    cd w[9];
+};
+
+// The thread's nine factors from the natural table tw[m] = exp(-2 pi i m / 256).
+__device__ __forceinline__ void load_tw256(Tw256& tr, int t, const cd* __restrict__ tw) {
+    const int n2 = t & 15, i0 = t & 3;
+#pragma unroll
+    for (int k = 1; k < 4; ++k) {
+        tr.w[k - 1] = tw[(k * t) & 255];
+        tr.w[2 + k] = tw[(4 * k * n2) & 255];
+        tr.w[5 + k] = tw[(16 * k * i0) & 255];
+    }
+}
+
+// Lanes 32-63 of a trade places with lanes 0-31 of b (one v_permlane32_swap per dword).
+__device__ __forceinline__ void lane_swap32(double& a, double& b) {
+    const unsigned long long ua = __builtin_bit_cast(unsigned long long, a);
+    const unsigned long long ub = __builtin_bit_cast(unsigned long long, b);
+    const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)ua, (unsigned)ub, false, false);
+    const auto hi = __builtin_amdgcn_permlane32_swap((unsigned)(ua >> 32), (unsigned)(ub >> 32), false, false);
+    a = __builtin_bit_cast(double, ((unsigned long long)hi[0] << 32) | (unsigned long long)lo[0]);
+    b = __builtin_bit_cast(double, ((unsigned long long)hi[1] << 32) | (unsigned long long)lo[1]);
+}
+// The odd 16-lane rows of a trade places with the even rows of b (v_permlane16_swap).
+__device__ __forceinline__ void lane_swap16(double& a, double& b) {
+    const unsigned long long ua = __builtin_bit_cast(unsigned long long, a);
+    const unsigned long long ub = __builtin_bit_cast(unsigned long long, b);
+    const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)ua, (unsigned)ub, false, false);
+    const auto hi = __builtin_amdgcn_permlane16_swap((unsigned)(ua >> 32), (unsigned)(ub >> 32), false, false);
+    a = __builtin_bit_cast(double, ((unsigned long long)hi[0] << 32) | (unsigned long long)lo[0]);
+    b = __builtin_bit_cast(double, ((unsigned long long)hi[1] << 32) | (unsigned long long)lo[1]);
+}
+
+template <bool INV>
+__device__ __forceinline__ cd tw_apply(cd a, cd w) { return INV ? cmulc(a, w) : cmul(a, w); }
+
+// The transform of the wavefront's row (v: the lane's 4 values; lds: the
+// wavefront's 256-entry exchange area).  Every lane of the wavefront must be
+// active.  Forward: exp(-2 pi i jk / 256); INV: exp(+2 pi i jk / 256).
+template <bool INV>
+__device__ __forceinline__ void fft256_wave(cd* v, int t, cd* lds, const Tw256& tr) {
+    // stage on i3 (in the register)
+    dft4<INV>(v[0], v[1], v[2], v[3]);
+    v[1] = tw_apply<INV>(v[1], tr.w[0]);
+    v[2] = tw_apply<INV>(v[2], tr.w[1]);
+    v[3] = tw_apply<INV>(v[3], tr.w[2]);
+    // register digit k0 <-> lane digit i2 (bits 5:4): (reg, lane) = (i2, n2 + 16 k0)
+    lane_swap32(v[0].x, v[2].x);
+    lane_swap32(v[0].y, v[2].y);
+    lane_swap32(v[1].x, v[3].x);
+    lane_swap32(v[1].y, v[3].y);
+    lane_swap16(v[0].x, v[1].x);
+    lane_swap16(v[0].y, v[1].y);
+    lane_swap16(v[2].x, v[3].x);
+    lane_swap16(v[2].y, v[3].y);
+    // stage on i2
+    dft4<INV>(v[0], v[1], v[2], v[3]);
+    v[1] = tw_apply<INV>(v[1], tr.w[3]);
+    v[2] = tw_apply<INV>(v[2], tr.w[4]);
+    v[3] = tw_apply<INV>(v[3], tr.w[5]);
+    // (reg, lane) = (k1, i0 + 4 i1 + 16 k0) -> (i1, i0 + 4 k1 + 16 k0); slot 64 reg + (lane ^ 4 reg)
+    {
+        const int i1 = (t >> 2) & 3, keep = t & 0x33;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) lds[64 * i1 + ((keep | (r << 2)) ^ (i1 << 2))] = v[r];
+        wave_lds_sync();
+#pragma unroll
+        for (int m = 0; m < 4; ++m) v[m] = lds[64 * m + (t ^ (m << 2))];
+        wave_lds_sync();
+    }
+    // stage on i1
+    dft4<INV>(v[0], v[1], v[2], v[3]);
+    v[1] = tw_apply<INV>(v[1], tr.w[6]);
+    v[2] = tw_apply<INV>(v[2], tr.w[7]);
+    v[3] = tw_apply<INV>(v[3], tr.w[8]);
+    // (reg, lane) = (k2, i0 + 4 k1 + 16 k0) -> (i0, k0 + 4 k1 + 16 k2); slot 64 reg + (lane ^ reg)
+    {
+        const int i0 = t & 3, kk = (t >> 4) | (t & 12);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) lds[64 * i0 + ((kk | (r << 4)) ^ i0)] = v[r];
+        wave_lds_sync();
+#pragma unroll
+        for (int m = 0; m < 4; ++m) v[m] = lds[64 * m + (t ^ m)];
+        wave_lds_sync();
+    }
+    // stage on i0: register m now holds X[t + 64 m]
+    dft4<INV>(v[0], v[1], v[2], v[3]);
+}
+
 }  // namespace pa

@@ -77,7 +77,8 @@ hipError_t launch_row_nl(const Dims& d, const RowArgs& a, hipStream_t s) {
     PA_DISPATCH_N(row_nl(d, a, s));
 }
 hipError_t launch_row_obs(const Dims& d, const RowArgs& a, hipStream_t s) {
-    if (!a.yin[0] || !a.yin[1] || !a.tw || a.obs.slot < 0 || !obs_ok(a.obs)) return hipErrorInvalidValue;
+    if (!a.yin[0] || !a.yin[1] || !a.yin[2] || !a.yin[3] || !a.tw || a.obs.slot < 0 || !obs_ok(a.obs))
+        return hipErrorInvalidValue;
     PA_DISPATCH_N(row_obs(d, a, s));
 }
 hipError_t launch_row_adj(const Dims& d, const RowArgs& a, hipStream_t s) {
@@ -87,7 +88,8 @@ hipError_t launch_row_adj(const Dims& d, const RowArgs& a, hipStream_t s) {
     PA_DISPATCH_N(row_adj(d, a, s));
 }
 hipError_t launch_row_src(const Dims& d, const RowArgs& a, int impulse, hipStream_t s) {
-    if (!a.yout[0] || !a.yout[1] || !a.tw || (!impulse && (!a.yin[0] || !a.yin[1] || !obs_ok(a.obs))))
+    if (!a.yout[0] || !a.yout[1] || !a.tw ||
+        (!impulse && (!a.yin[0] || !a.yin[1] || !a.yin[2] || !a.yin[3] || !obs_ok(a.obs))))
         return hipErrorInvalidValue;
     PA_DISPATCH_N(row_src(d, a, impulse, s));
 }

@@ -11,6 +11,12 @@
 //                    real transform, kx = 0..Kc kept: the hand-off between the
 //                    row pass (physical space, x contiguous) and the column
 //                    pass (spectral space, transform along y).
+//   packed y-fields  the fields that row passes read in pairs (A, B) -- the
+//                    RK stage fields (u, w_x), (v, w_y) and the adjoint's
+//                    (Lam_x, Lam_y) -- are stored as P = A + i B and
+//                    Q = A - i B (each [B][N][KXP]): entry e of the row's full
+//                    complex signal A + i B is P[e] for e <= Kc and conj(Q[N-e])
+//                    for e >= N - Kc, one 16-byte load either way.
 // Every 2D transform is a row pass + a column pass over Y; pointwise spectral
 // work (projection, Poisson inversion, velocity, derivatives, Lawson RK4
 // combine, adjoint transposes) is fused into the column pass, products of
@@ -30,7 +36,9 @@ struct Dims {
     int cus;         // compute units of the device (persistent grids)
 };
 
-enum FieldKind : int { F_OMEGA = 0, F_U = 1, F_V = 2, F_WX = 3, F_WY = 4 };
+// Column-pass outputs: the field itself, or one half of a packed pair
+// (P = A + i B, Q = A - i B) with (A, B) = (u, w_x), (v, w_y) or (Lam_x, Lam_y).
+enum FieldKind : int { F_OMEGA = 0, F_UP = 1, F_UQ = 2, F_VP = 3, F_VQ = 4, F_LP = 5, F_LQ = 6 };
 
 // Multiplier applied to an adjoint column input after its y-transform.
 enum InMul : int { IN_INVK2 = 0, IN_ONE = 1, IN_IKY_INVK2 = 2, IN_MIKX_INVK2 = 3 };

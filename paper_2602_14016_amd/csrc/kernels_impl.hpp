@@ -54,6 +54,36 @@ __device__ __forceinline__ const cd* stage_twiddles(cd* lds_tw, const cd* __rest
     return lds_tw;
 }
 
+// Row transforms of a kernel whose rows run several transforms with one set of
+// twiddle factors per thread.  Plan (256, 2) (one row per wavefront, four
+// values per lane) uses the wavefront-resident transform with lane swaps
+// (fft256_wave), whose nine factors per thread come straight from the natural
+// table; every other plan runs its Stockham stages with the factors of the
+// stage-ordered table (staged in LDS by the workgroup) held in registers.
+template <int N, int V>
+__host__ __device__ constexpr bool wave256() { return N == 256 && V == 2; }
+
+template <int N, int V>
+struct RowTw {
+    TwReg<N, V> r;
+};
+template <>
+struct RowTw<256, 2> {
+    Tw256 r;
+};
+
+template <int N, int V>
+__device__ __forceinline__ void row_twiddles(RowTw<N, V>& tr, int t, const cd* __restrict__ tw_g, cd* tw_lds) {
+    if constexpr (wave256<N, V>()) load_tw256(tr.r, t, tw_g);
+    else load_twiddles<N, V>(tr.r, t, stage_twiddles<N, V>(tw_lds, tw_g));
+}
+
+template <int N, int V, bool INV, bool WL>
+__device__ __forceinline__ void row_fft(cd* v, int t, cd* lds, const RowTw<N, V>& tr) {
+    if constexpr (wave256<N, V>()) fft256_wave<INV>(v, t, lds, tr.r);
+    else fft<N, V, INV, WL>(v, t, lds, tr.r);
+}
+
 // Retained band of a grid of size N: the 2/3 rule keeps |kx|, |ky| <= (N-1)/3.
 template <int N>
 __host__ __device__ constexpr int band() { return (N - 1) / 3; }
@@ -73,18 +103,18 @@ template <int N, int V>
 __device__ constexpr bool slot_low(int m) { return Plan<N, V>::T * m <= band<N>(); }
 
 // z = A_full[e] + i B_full[e] for the Hermitian extensions of half-spectrum
-// rows A, B (only kx = 0..K stored, zero beyond).  The kx = 0 entry of a real
-// field's half spectrum is real; its imaginary round-off is discarded.  With
-// DX, A is replaced by its x-derivative i kx A.  Branch-free: the load index
-// is clamped to 0 off the band and the result selected, so the loads of all
-// slots issue back to back instead of each waiting inside a divergent branch.
-template <int N, bool DX = false>
+// rows A, B (only kx = 0..K stored, zero beyond): two rows of one field packed
+// into one transform (the row pass from a single field to physical space).
+// The kx = 0 entry of a real field's half spectrum is real; its imaginary
+// round-off is discarded.  Branch-free: the load index is clamped to 0 off the
+// band and the result selected, so the loads of all slots issue back to back
+// instead of each waiting inside a divergent branch.
+template <int N>
 __device__ __forceinline__ cd herm_pair(const cd* __restrict__ A, const cd* __restrict__ B, int e) {
     constexpr int K = band<N>();
     const bool lo = e <= K, hi = e >= N - K;
     const unsigned k = lo ? (unsigned)e : (hi ? (unsigned)(N - e) : 0u);
     cd a = ldc(A, k), bb = ldc(B, k);
-    if (DX) a = mul_i(cscale(a, (double)k));
     if (e == 0) { a.y = 0.0; bb.y = 0.0; }
     if (hi) { a.y = -a.y; bb.y = -bb.y; }
     const cd z = mk(a.x - bb.y, a.y + bb.x);
@@ -92,11 +122,47 @@ __device__ __forceinline__ cd herm_pair(const cd* __restrict__ A, const cd* __re
 }
 
 // Fills the E register slots of a team with the extension of (A, B).
-template <int N, int V, bool DX = false>
+template <int N, int V>
 __device__ __forceinline__ void herm_load(cd* z, const cd* __restrict__ A, const cd* __restrict__ B, int t) {
     constexpr int T = Plan<N, V>::T, E = Plan<N, V>::E;
 #pragma unroll
-    for (int m = 0; m < E; ++m) z[m] = slot_in_band<N, V>(m) ? herm_pair<N, DX>(A, B, t + T * m) : czero();
+    for (int m = 0; m < E; ++m) z[m] = slot_in_band<N, V>(m) ? herm_pair<N>(A, B, t + T * m) : czero();
+}
+
+// z = A_full[e] + i B_full[e] from the packed half spectra P = A + i B and
+// Q = A - i B of one row: P[e] on the low band, conj(Q[N - e]) on the high
+// band (the Hermitian extension of A and B), zero in the de-aliased gap.  Each
+// register slot issues one load; which band its lanes can meet is known at
+// compile time from the plan, so all-low and all-high slots carry no select.
+template <int N, int V>
+__device__ __forceinline__ void packed_load(cd* z, const cd* __restrict__ P, const cd* __restrict__ Q, int t) {
+    constexpr int T = Plan<N, V>::T, E = Plan<N, V>::E, K = band<N>();
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+        const int e = t + T * m;
+        const bool all_lo = T * m + T - 1 <= K, all_hi = T * m >= N - K;
+        const bool may_lo = T * m <= K, may_hi = T * m + T - 1 >= N - K;
+        if (all_lo) {
+            z[m] = ldc(P, (unsigned)e);
+        } else if (all_hi) {
+            const cd q = ldc(Q, (unsigned)(N - e));
+            z[m] = mk(q.x, -q.y);
+        } else if (may_lo && may_hi) {
+            const bool lo = e <= K, hi = e >= N - K;
+            const cd p = ldc(P, lo ? (unsigned)e : 0u), q = ldc(Q, hi ? (unsigned)(N - e) : 0u);
+            z[m] = lo ? p : (hi ? mk(q.x, -q.y) : czero());
+        } else if (may_lo) {
+            const bool lo = e <= K;
+            const cd p = ldc(P, lo ? (unsigned)e : 0u);
+            z[m] = lo ? p : czero();
+        } else if (may_hi) {
+            const bool hi = e >= N - K;
+            const cd q = ldc(Q, hi ? (unsigned)(N - e) : 0u);
+            z[m] = hi ? mk(q.x, -q.y) : czero();
+        } else {
+            z[m] = czero();
+        }
+    }
 }
 
 // Forward transform z of a + i b (a, b real) is split into the half spectra
@@ -213,7 +279,8 @@ __global__ void __launch_bounds__(256) row_c2r_kernel(Dims d, const cd* __restri
 }
 
 // Right-hand side products of one row:  q = u w_x + v w_y.  Inputs
-// yin[0..3] = U, V, Wx, Wy (Y layout), output yout[0] = row transform of q.
+// yin[0..3] = the packed pairs (u, w_x) P, Q and (v, w_y) P, Q of the stage,
+// output yout[0] = row transform of q.
 // Every input load is issued before the first transform, so the memory
 // latency is paid once per kernel rather than once per transform.
 // Observations are formed by row_obs_kernel from the same fields.
@@ -224,17 +291,16 @@ __device__ __forceinline__ void row_nl_body(const Dims& d, const RowArgs& a) {
     const int y = wi;
     const size_t roff = ((size_t)b * N + y) * kx_pad<N>();
     cd z1[E], z2[E];
-    herm_load<N, V>(z1, a.yin[0] + roff, a.yin[2] + roff, t);   // u + i w_x
-    herm_load<N, V>(z2, a.yin[1] + roff, a.yin[3] + roff, t);   // v + i w_y
-    const cd* twl = stage_twiddles<N, V>(tw_lds, tw_g);
-    TwReg<N, V> tr;   // the three transforms of the row share the thread's twiddles
-    load_twiddles<N, V>(tr, t, twl);
-    fft<N, V, true, WL>(z1, t, lds, tr);
-    fft<N, V, true, WL>(z2, t, lds, tr);
+    packed_load<N, V>(z1, a.yin[0] + roff, a.yin[1] + roff, t);   // u + i w_x
+    packed_load<N, V>(z2, a.yin[2] + roff, a.yin[3] + roff, t);   // v + i w_y
+    RowTw<N, V> tr;   // the three transforms of the row share the thread's twiddles
+    row_twiddles<N, V>(tr, t, tw_g, tw_lds);
+    row_fft<N, V, true, WL>(z1, t, lds, tr);
+    row_fft<N, V, true, WL>(z2, t, lds, tr);
     cd z[E];
 #pragma unroll
     for (int m = 0; m < E; ++m) z[m] = mk(z1[m].x * z1[m].y + z2[m].x * z2[m].y, 0.0);
-    fft<N, V, false, WL>(z, t, lds, tr);
+    row_fft<N, V, false, WL>(z, t, lds, tr);
     cd* o = a.yout[0] + roff;
 #pragma unroll
     for (int m = 0; m < E; ++m) {
@@ -262,20 +328,33 @@ __device__ __forceinline__ void row_nl_pair_body(const Dims& d, const RowArgs& a
     constexpr int KXP = kx_pad<N>();
     const size_t ra = ((size_t)b * N + 2 * wi) * KXP, rb = ra + KXP;
     cd z1[E], z2[E], y1[E], y2[E];
-    herm_load<N, V>(z1, a.yin[0] + ra, a.yin[2] + ra, t);   // row a: u + i w_x
-    herm_load<N, V>(z2, a.yin[1] + ra, a.yin[3] + ra, t);   //        v + i w_y
-    herm_load<N, V>(y1, a.yin[0] + rb, a.yin[2] + rb, t);   // row b
-    herm_load<N, V>(y2, a.yin[1] + rb, a.yin[3] + rb, t);
-    const cd* twl = stage_twiddles<N, V>(tw_lds, tw_g);
-    fft<N, V, true, WL>(z1, t, lds, twl);
-    fft<N, V, true, WL>(z2, t, lds, twl);
-    fft<N, V, true, WL>(y1, t, lds, twl);
-    fft<N, V, true, WL>(y2, t, lds, twl);
+    packed_load<N, V>(z1, a.yin[0] + ra, a.yin[1] + ra, t);   // row a: u + i w_x
+    packed_load<N, V>(z2, a.yin[2] + ra, a.yin[3] + ra, t);   //        v + i w_y
+    packed_load<N, V>(y1, a.yin[0] + rb, a.yin[1] + rb, t);   // row b
+    packed_load<N, V>(y2, a.yin[2] + rb, a.yin[3] + rb, t);
     cd z[E];
+    if constexpr (wave256<N, V>()) {
+        RowTw<N, V> tr;
+        row_twiddles<N, V>(tr, t, tw_g, tw_lds);
+        row_fft<N, V, true, WL>(z1, t, lds, tr);
+        row_fft<N, V, true, WL>(z2, t, lds, tr);
+        row_fft<N, V, true, WL>(y1, t, lds, tr);
+        row_fft<N, V, true, WL>(y2, t, lds, tr);
 #pragma unroll
-    for (int m = 0; m < E; ++m)
-        z[m] = mk(z1[m].x * z1[m].y + z2[m].x * z2[m].y, y1[m].x * y1[m].y + y2[m].x * y2[m].y);
-    fft<N, V, false, WL>(z, t, lds, twl);
+        for (int m = 0; m < E; ++m)
+            z[m] = mk(z1[m].x * z1[m].y + z2[m].x * z2[m].y, y1[m].x * y1[m].y + y2[m].x * y2[m].y);
+        row_fft<N, V, false, WL>(z, t, lds, tr);
+    } else {
+        const cd* twl = stage_twiddles<N, V>(tw_lds, tw_g);
+        fft<N, V, true, WL>(z1, t, lds, twl);
+        fft<N, V, true, WL>(z2, t, lds, twl);
+        fft<N, V, true, WL>(y1, t, lds, twl);
+        fft<N, V, true, WL>(y2, t, lds, twl);
+#pragma unroll
+        for (int m = 0; m < E; ++m)
+            z[m] = mk(z1[m].x * z1[m].y + z2[m].x * z2[m].y, y1[m].x * y1[m].y + y2[m].x * y2[m].y);
+        fft<N, V, false, WL>(z, t, lds, twl);
+    }
     split_store<N, V, WL>(z, t, lds, a.yout[0] + ra, a.yout[0] + rb);
 }
 
@@ -291,22 +370,26 @@ row_nl_kernel(Dims d, RowArgs a) {
     else row_nl_body<N, V>(d, a);
 }
 
-// Observation only (final time): team per observed row; yin[0..1] = U, V.
+// Observation of one step: team per observed row; yin[0..3] = the stage's
+// packed pairs (u, w_x) and (v, w_y); u and v are the real parts of their row
+// transforms.
 template <int N, int V>
 __global__ void __launch_bounds__(256) row_obs_kernel(Dims d, RowArgs a) {
     const cd* __restrict__ tw_g = a.tw;
     PA_TEAM_SETUP(N, V, a.obs.M)
     const int y = wi * a.obs.stride;
     const size_t roff = ((size_t)b * N + y) * kx_pad<N>();
-    cd z[E];
-    herm_load<N, V>(z, a.yin[0] + roff, a.yin[1] + roff, t);
+    cd z1[E], z2[E];
+    packed_load<N, V>(z1, a.yin[0] + roff, a.yin[1] + roff, t);
+    packed_load<N, V>(z2, a.yin[2] + roff, a.yin[3] + roff, t);
     const cd* twl = stage_twiddles<N, V>(tw_lds, tw_g);
-    fft<N, V, true, WL>(z, t, lds, twl);
+    fft<N, V, true, WL>(z1, t, lds, twl);
+    fft<N, V, true, WL>(z2, t, lds, twl);
     double part = 0.0;
 #pragma unroll
     for (int m = 0; m < E; ++m) {
-        part += observe_comp(a.obs, b, y, t + T * m, 0, z[m].x);
-        part += observe_comp(a.obs, b, y, t + T * m, 1, z[m].y);
+        part += observe_comp(a.obs, b, y, t + T * m, 0, z1[m].x);
+        part += observe_comp(a.obs, b, y, t + T * m, 1, z2[m].x);
     }
     const double s = team_sum<N, V, WL>(part, t, lds);
     if (t == 0) store_jpart(a.obs, b, y, s);
@@ -322,9 +405,10 @@ constexpr int adj_waves() { return Plan<N, V>::E <= 8 ? 3 : 1; }
 // applied to lambda, with Lam = P lambda, is on the de-aliased band
 //   (1/|k|^2) F[w_x Lam_y - w_y Lam_x] + F[u Lam_x + v Lam_y]
 // (the product rule holds on the band because the 2/3 rule keeps every alias
-// outside it, and u_x + v_y = 0).  Inputs yin[0..3] = U, V, Wx, Wy of the stage
-// state, yin[4] = Lam, yin[5] = Lam_y (Y layout).  Outputs: yout[0] = row
-// transform of G1 = w_x Lam_y - w_y Lam_x, yout[1] = of G2 = u Lam_x + v Lam_y.
+// outside it, and u_x + v_y = 0).  Inputs yin[0..3] = the packed pairs (u, w_x)
+// and (v, w_y) of the stage state, yin[4..5] = the packed pair (Lam_x, Lam_y).
+// Outputs: yout[0] = row transform of G1 = w_x Lam_y - w_y Lam_x, yout[1] = of
+// G2 = u Lam_x + v Lam_y.
 template <int N, int V>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(adj_waves<N, V>())))
 row_adj_kernel(Dims d, RowArgs a) {
@@ -333,25 +417,25 @@ row_adj_kernel(Dims d, RowArgs a) {
     const int y = wi;
     const size_t roff = ((size_t)b * N + y) * kx_pad<N>();
     cd L[E], z1[E], z2[E];   // (Lam_x, Lam_y), (u, w_x), (v, w_y)
-    herm_load<N, V, true>(L, a.yin[4] + roff, a.yin[5] + roff, t);
-    herm_load<N, V>(z1, a.yin[0] + roff, a.yin[2] + roff, t);
-    herm_load<N, V>(z2, a.yin[1] + roff, a.yin[3] + roff, t);
-    const cd* twl = stage_twiddles<N, V>(tw_lds, tw_g);
-    TwReg<N, V> tr;   // the four transforms of the row share the thread's twiddles
-    load_twiddles<N, V>(tr, t, twl);
-    fft<N, V, true, WL>(L, t, lds, tr);
-    fft<N, V, true, WL>(z1, t, lds, tr);
-    fft<N, V, true, WL>(z2, t, lds, tr);
+    packed_load<N, V>(L, a.yin[4] + roff, a.yin[5] + roff, t);
+    packed_load<N, V>(z1, a.yin[0] + roff, a.yin[1] + roff, t);
+    packed_load<N, V>(z2, a.yin[2] + roff, a.yin[3] + roff, t);
+    RowTw<N, V> tr;   // the four transforms of the row share the thread's twiddles
+    row_twiddles<N, V>(tr, t, tw_g, tw_lds);
+    row_fft<N, V, true, WL>(L, t, lds, tr);
+    row_fft<N, V, true, WL>(z1, t, lds, tr);
+    row_fft<N, V, true, WL>(z2, t, lds, tr);
     cd G[E];   // (G1, G2)
 #pragma unroll
     for (int m = 0; m < E; ++m)
         G[m] = mk(z1[m].y * L[m].y - z2[m].y * L[m].x, z1[m].x * L[m].x + z2[m].x * L[m].y);
-    fft<N, V, false, WL>(G, t, lds, tr);
+    row_fft<N, V, false, WL>(G, t, lds, tr);
     split_store<N, V, WL>(G, t, lds, a.yout[0] + roff, a.yout[1] + roff);
 }
 
 // Adjoint source rows.  mode 0: observation residual at one observed step
-// (yin[0..1] = U, V of that state); mode 1: unit u-impulse at (imp_x, imp_y).
+// (yin[0..3] = the packed pairs (u, w_x), (v, w_y) of that state); mode 1:
+// unit u-impulse at (imp_x, imp_y).
 // Outputs yout[0] = row transform of -S^T r_u, yout[1] = of -S^T r_v.
 template <int N, int V>
 __global__ void __launch_bounds__(256) row_src_kernel(Dims d, RowArgs a, int impulse) {
@@ -360,12 +444,16 @@ __global__ void __launch_bounds__(256) row_src_kernel(Dims d, RowArgs a, int imp
     const int y = wi;
     const size_t roff = ((size_t)b * N + y) * kx_pad<N>();
     const RowObs& o = a.obs;
-    cd z[E];
+    cd z[E], z2[E];
     if (!impulse) {
-        herm_load<N, V>(z, a.yin[0] + roff, a.yin[1] + roff, t);
+        packed_load<N, V>(z, a.yin[0] + roff, a.yin[1] + roff, t);
+        packed_load<N, V>(z2, a.yin[2] + roff, a.yin[3] + roff, t);
     }
     const cd* twl = stage_twiddles<N, V>(tw_lds, tw_g);
-    if (!impulse) fft<N, V, true, WL>(z, t, lds, twl);
+    if (!impulse) {
+        fft<N, V, true, WL>(z, t, lds, twl);
+        fft<N, V, true, WL>(z2, t, lds, twl);
+    }
 #pragma unroll
     for (int m = 0; m < E; ++m) {
         const int x = t + T * m;
@@ -376,7 +464,7 @@ __global__ void __launch_bounds__(256) row_src_kernel(Dims d, RowArgs a, int imp
             const int i = x / o.stride, j = y / o.stride, M = o.M;
             const size_t base = (((size_t)b * o.n_times + o.slot) * 2) * M * M + (size_t)j * M + i;
             A = -(z[m].x - o.values[base]);
-            Bv = -(z[m].y - o.values[base + (size_t)M * M]);
+            Bv = -(z2[m].x - o.values[base + (size_t)M * M]);
         }
         z[m] = mk(A, Bv);
     }
@@ -619,7 +707,9 @@ __global__ void __launch_bounds__(512) col_kernel(Dims d, ColArgs a) {
         }
     }
 
-    // derived fields: 1_S * multiplier * w / N^2, inverse transform along y
+    // derived fields: 1_S * multiplier * w / N^2, inverse transform along y; a
+    // packed pair half A +- i B is formed from the two multipliers before the
+    // transform (the transform is linear)
     const double inv_n2 = 1.0 / ((double)N * (double)N);
     for (int o = 0; o < a.nout; ++o) {
         const int f = a.fields[o];
@@ -630,11 +720,24 @@ __global__ void __launch_bounds__(512) col_kernel(Dims d, ColArgs a) {
             if (!inS(r)) { v[m] = czero(); continue; }
             const double ky = (double)((r <= K) ? r : r - KY);
             const cd s = cscale(w[m], inv_n2);
-            if (f == F_OMEGA) v[m] = s;
-            else if (f == F_U) v[m] = cscale(mul_i(s), ky * ik2t[(unsigned)c + (unsigned)r * (unsigned)KXP]);
-            else if (f == F_V) v[m] = cscale(mul_i(s), -dkx * ik2t[(unsigned)c + (unsigned)r * (unsigned)KXP]);
-            else if (f == F_WX) v[m] = cscale(mul_i(s), dkx);
-            else v[m] = cscale(mul_i(s), ky);
+            const double ik2 = ik2t[(unsigned)c + (unsigned)r * (unsigned)KXP];
+            if (f == F_OMEGA) {
+                v[m] = s;
+            } else {
+                cd A, Bf;
+                if (f == F_UP || f == F_UQ) {          // (u, w_x) = (i ky / k^2, i kx) s
+                    A = cscale(mul_i(s), ky * ik2);
+                    Bf = cscale(mul_i(s), dkx);
+                } else if (f == F_VP || f == F_VQ) {   // (v, w_y) = (-i kx / k^2, i ky) s
+                    A = cscale(mul_i(s), -dkx * ik2);
+                    Bf = cscale(mul_i(s), ky);
+                } else {                               // (Lam_x, Lam_y) = (i kx, i ky) s
+                    A = cscale(mul_i(s), dkx);
+                    Bf = cscale(mul_i(s), ky);
+                }
+                const bool plus = f == F_UP || f == F_VP || f == F_LP;
+                v[m] = plus ? mk(A.x - Bf.y, A.y + Bf.x) : mk(A.x + Bf.y, A.y - Bf.x);
+            }
         }
         fft<N, V, true>(v, t, lds, twl);
         if (colok) {
@@ -722,35 +825,36 @@ __global__ void __launch_bounds__(256) row_nl_pipe_kernel(Dims d, RowArgs a, int
     const int wpg = blockDim.x >> 6;
     cd* const stage = smem + wave * P::template wave_lds<NF>();
     cd* const lds = stage + NF * P::SPAN + team * lds_team<N>();
-    const cd* twl = stage_twiddles<N, V>(smem + wpg * P::template wave_lds<NF>(), a.tw);
+    RowTw<N, V> tr;
+    row_twiddles<N, V>(tr, t0, a.tw, smem + wpg * P::template wave_lds<NF>());
     const int nw = gridDim.x * wpg;
     int g = blockIdx.x * wpg + wave;
-    const cd* const src[NF] = {a.yin[0], a.yin[2], a.yin[1], a.yin[3]};   // (U, Wx), (V, Wy)
+    const cd* const src[NF] = {a.yin[0], a.yin[1], a.yin[2], a.yin[3]};   // packed (u, w_x), (v, w_y)
     const cd* const row = stage + team * KXP;
     cd z1[E], z2[E];
     if (g < n_groups) {
         pipe_fetch<N, NF>(stage, src, P::offset(g), lane);
         vm_wait();
-        herm_load<N, V>(z1, row, row + P::SPAN, t0);
+        packed_load<N, V>(z1, row, row + P::SPAN, t0);
         wave_lds_sync();
-        herm_load<N, V>(z2, row + 2 * P::SPAN, row + 3 * P::SPAN, t0);
+        packed_load<N, V>(z2, row + 2 * P::SPAN, row + 3 * P::SPAN, t0);
         wave_lds_sync();
         if (g + nw < n_groups) pipe_fetch<N, NF>(stage, src, P::offset(g + nw), lane);
     }
     for (; g < n_groups; g += nw) {
         const int t = opaque(t0);
-        fft<N, V, true, WL_>(z1, t, lds, twl);
-        fft<N, V, true, WL_>(z2, t, lds, twl);
+        row_fft<N, V, true, WL_>(z1, t, lds, tr);
+        row_fft<N, V, true, WL_>(z2, t, lds, tr);
         cd z[E];
 #pragma unroll
         for (int m = 0; m < E; ++m) z[m] = mk(z1[m].x * z1[m].y + z2[m].x * z2[m].y, 0.0);
-        fft<N, V, false, WL_>(z, t, lds, twl);
+        row_fft<N, V, false, WL_>(z, t, lds, tr);
         const int gn = g + nw;
         if (gn < n_groups) {
             vm_wait();
-            herm_load<N, V>(z1, row, row + P::SPAN, t);
+            packed_load<N, V>(z1, row, row + P::SPAN, t);
             wave_lds_sync();
-            herm_load<N, V>(z2, row + 2 * P::SPAN, row + 3 * P::SPAN, t);
+            packed_load<N, V>(z2, row + 2 * P::SPAN, row + 3 * P::SPAN, t);
             wave_lds_sync();
             if (gn + nw < n_groups) pipe_fetch<N, NF>(stage, src, P::offset(gn + nw), lane);
         }
@@ -772,21 +876,22 @@ __global__ void __launch_bounds__(256) row_adj_pipe_kernel(Dims d, RowArgs a, in
     const int wpg = blockDim.x >> 6;
     cd* const stage = smem + wave * P::template wave_lds<NF>();
     cd* const lds = stage + NF * P::SPAN + team * lds_team<N>();
-    const cd* twl = stage_twiddles<N, V>(smem + wpg * P::template wave_lds<NF>(), a.tw);
+    RowTw<N, V> tr;
+    row_twiddles<N, V>(tr, t0, a.tw, smem + wpg * P::template wave_lds<NF>());
     const int nw = gridDim.x * wpg;
     int g = blockIdx.x * wpg + wave;
-    // (Lam, Lam_y), (U, Wx), (V, Wy)
-    const cd* const src[NF] = {a.yin[4], a.yin[5], a.yin[0], a.yin[2], a.yin[1], a.yin[3]};
+    // packed (Lam_x, Lam_y), (u, w_x), (v, w_y)
+    const cd* const src[NF] = {a.yin[4], a.yin[5], a.yin[0], a.yin[1], a.yin[2], a.yin[3]};
     const cd* const row = stage + team * KXP;
     cd L[E], z1[E], z2[E];
     // one signal pair at a time: LDS latency is short, and the raw values of
     // all three pairs in flight at once would double the registers held
     auto read_inputs = [&](int t) {
-        herm_load<N, V, true>(L, row, row + P::SPAN, t);
+        packed_load<N, V>(L, row, row + P::SPAN, t);
         wave_lds_sync();
-        herm_load<N, V>(z1, row + 2 * P::SPAN, row + 3 * P::SPAN, t);
+        packed_load<N, V>(z1, row + 2 * P::SPAN, row + 3 * P::SPAN, t);
         wave_lds_sync();
-        herm_load<N, V>(z2, row + 4 * P::SPAN, row + 5 * P::SPAN, t);
+        packed_load<N, V>(z2, row + 4 * P::SPAN, row + 5 * P::SPAN, t);
         wave_lds_sync();
     };
     if (g < n_groups) {
@@ -797,14 +902,14 @@ __global__ void __launch_bounds__(256) row_adj_pipe_kernel(Dims d, RowArgs a, in
     }
     for (; g < n_groups; g += nw) {
         const int t = opaque(t0);
-        fft<N, V, true, WL_>(L, t, lds, twl);
-        fft<N, V, true, WL_>(z1, t, lds, twl);
-        fft<N, V, true, WL_>(z2, t, lds, twl);
+        row_fft<N, V, true, WL_>(L, t, lds, tr);
+        row_fft<N, V, true, WL_>(z1, t, lds, tr);
+        row_fft<N, V, true, WL_>(z2, t, lds, tr);
         cd G[E];
 #pragma unroll
         for (int m = 0; m < E; ++m)
             G[m] = mk(z1[m].y * L[m].y - z2[m].y * L[m].x, z1[m].x * L[m].x + z2[m].x * L[m].y);
-        fft<N, V, false, WL_>(G, t, lds, twl);
+        row_fft<N, V, false, WL_>(G, t, lds, tr);
         const int gn = g + nw;
         if (gn < n_groups) {
             vm_wait();
