@@ -801,8 +801,8 @@ pa_status adj_stage(pa_ctx* c, WS& w, cd* const fields[4], int mode, const ObsPl
     a.yin[0] = w.Yp[0];
     a.yin[1] = w.Yp[1];
     a.nin = 2;
-    a.inmul[0] = IN_INVK2;
-    a.inmul[1] = IN_ONE;
+    a.inmul[0] = IN_PAIRP;
+    a.inmul[1] = IN_PAIRQ;
     if (mode == COL_ADJ_N && op && op->values) {
         bool any = false;
         cd* const out[2] = {w.Yp[2], w.Yp[3]};

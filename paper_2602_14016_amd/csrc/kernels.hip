@@ -31,7 +31,7 @@ static bool col_ptrs_ok(int mode, const ColArgs& a) {
             if (a.nin < 2 || a.nin > (mode == COL_ADJ_NSRC ? 4 : 2) || !a.lam) return false;
             if (mode != COL_ADJ_SRC && !a.omb) return false;
             for (int p = 0; p < a.nin; ++p)
-                if (!a.yin[p] || a.inmul[p] < IN_INVK2 || a.inmul[p] > IN_MIKX_INVK2) return false;
+                if (!a.yin[p] || a.inmul[p] < IN_PAIRP || a.inmul[p] > IN_MIKX_INVK2) return false;
             return true;
         default: return false;
     }

@@ -40,8 +40,11 @@ struct Dims {
 // (P = A + i B, Q = A - i B) with (A, B) = (u, w_x), (v, w_y) or (Lam_x, Lam_y).
 enum FieldKind : int { F_OMEGA = 0, F_UP = 1, F_UQ = 2, F_VP = 3, F_VQ = 4, F_LP = 5, F_LQ = 6 };
 
-// Multiplier applied to an adjoint column input after its y-transform.
-enum InMul : int { IN_INVK2 = 0, IN_ONE = 1, IN_IKY_INVK2 = 2, IN_MIKX_INVK2 = 3 };
+// Multiplier applied to an adjoint column input after its y-transform.  The
+// adjoint row pass stores its two products (G1, G2) unsplit, as P = Z and
+// Q = conj Z(-k) of Z = F_x(G1 + i G2), so G1 = (P + Q)/2 and G2 = (P - Q)/(2i),
+// and the column pass's 1/|k|^2 G1 + G2 becomes P (1/|k|^2 - i)/2 + Q (1/|k|^2 + i)/2.
+enum InMul : int { IN_PAIRP = 0, IN_PAIRQ = 1, IN_IKY_INVK2 = 2, IN_MIKX_INVK2 = 3 };
 
 enum ColMode : int {
     COL_INIT = 0,     // Y -> P omega0 -> state (+checkpoint) -> derived fields

@@ -188,6 +188,23 @@ __device__ __forceinline__ void split_store(const cd* z, int t, cd* lds, cd* __r
     team_sync<WL>();
 }
 
+// Forward transform z of a + i b (a, b real) stored unsplit for k = 0..K:
+// P[k] = Z[k] and Q[k] = conj(Z[N - k]), so that a_hat = (P + Q) / 2 and
+// b_hat = (P - Q) / (2i) (the column pass forms them).  Each lane stores the
+// values it holds: no exchange.
+template <int N, int V>
+__device__ __forceinline__ void pair_store(const cd* z, int t, cd* __restrict__ outP, cd* __restrict__ outQ) {
+    constexpr int T = Plan<N, V>::T, E = Plan<N, V>::E, K = band<N>();
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+        const int k = t + T * m;
+        if (slot_low<N, V>(m) && k <= K) stc(outP, (unsigned)k, z[m]);
+        const bool q_slot = m == 0 || T * m + T - 1 >= N - K;   // holds k = 0 or some k >= N - K
+        const int kn = (N - k) & (N - 1);
+        if (q_slot && kn <= K) stc(outQ, (unsigned)kn, mk(z[m].x, -z[m].y));
+    }
+}
+
 // Team sum (fixed order) of one double per thread; result valid in thread t == 0.
 template <int N, int V, bool WL>
 __device__ __forceinline__ double team_sum(double v, int t, cd* lds) {
@@ -407,8 +424,8 @@ constexpr int adj_waves() { return Plan<N, V>::E <= 8 ? 3 : 1; }
 // (the product rule holds on the band because the 2/3 rule keeps every alias
 // outside it, and u_x + v_y = 0).  Inputs yin[0..3] = the packed pairs (u, w_x)
 // and (v, w_y) of the stage state, yin[4..5] = the packed pair (Lam_x, Lam_y).
-// Outputs: yout[0] = row transform of G1 = w_x Lam_y - w_y Lam_x, yout[1] = of
-// G2 = u Lam_x + v Lam_y.
+// Outputs: the row transform Z of G1 + i G2, G1 = w_x Lam_y - w_y Lam_x and
+// G2 = u Lam_x + v Lam_y, unsplit (pair_store): yout[0] = Z, yout[1] = conj Z(-k).
 template <int N, int V>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(adj_waves<N, V>())))
 row_adj_kernel(Dims d, RowArgs a) {
@@ -430,7 +447,7 @@ row_adj_kernel(Dims d, RowArgs a) {
     for (int m = 0; m < E; ++m)
         G[m] = mk(z1[m].y * L[m].y - z2[m].y * L[m].x, z1[m].x * L[m].x + z2[m].x * L[m].y);
     row_fft<N, V, false, WL>(G, t, lds, tr);
-    split_store<N, V, WL>(G, t, lds, a.yout[0] + roff, a.yout[1] + roff);
+    pair_store<N, V>(G, t, a.yout[0] + roff, a.yout[1] + roff);
 }
 
 // Adjoint source rows.  mode 0: observation residual at one observed step
@@ -640,12 +657,12 @@ __global__ void __launch_bounds__(512) col_kernel(Dims d, ColArgs a) {
                 if (!inS(r)) continue;
                 const double ky = (double)((r <= K) ? r : r - KY);
                 const double ik2 = ik2t[cidx(r)];
-                if (mk_ == IN_INVK2) {
-                    w[m].x += ik2 * v[m].x;
-                    w[m].y += ik2 * v[m].y;
-                } else if (mk_ == IN_ONE) {
-                    w[m].x += v[m].x;
-                    w[m].y += v[m].y;
+                if (mk_ == IN_PAIRP) {          // v (1/|k|^2 - i) / 2
+                    w[m].x += 0.5 * (ik2 * v[m].x + v[m].y);
+                    w[m].y += 0.5 * (ik2 * v[m].y - v[m].x);
+                } else if (mk_ == IN_PAIRQ) {   // v (1/|k|^2 + i) / 2
+                    w[m].x += 0.5 * (ik2 * v[m].x - v[m].y);
+                    w[m].y += 0.5 * (ik2 * v[m].y + v[m].x);
                 } else {
                     const double f = (mk_ == IN_IKY_INVK2) ? ky * ik2 : -dkx * ik2;   // i f v
                     w[m].x -= f * v[m].y;
@@ -917,7 +934,7 @@ __global__ void __launch_bounds__(256) row_adj_pipe_kernel(Dims d, RowArgs a, in
             if (gn + nw < n_groups) pipe_fetch<N, NF>(stage, src, P::offset(gn + nw), lane);
         }
         const size_t ro = P::offset(g) + team * KXP;
-        split_store<N, V, WL_>(G, t, lds, a.yout[0] + ro, a.yout[1] + ro);
+        pair_store<N, V>(G, t, a.yout[0] + ro, a.yout[1] + ro);
     }
 }
 
