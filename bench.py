@@ -13,8 +13,11 @@ the checkpointed form).  Inputs are resident in HBM before the timed region.  va
 (grid-point-steps/s, each unit one point advanced one forward and one adjoint
 step).  Beside it: the plain path (one member per solve, same kernels, the
 batch's members solved one after another: equal work), p50/p99 solve latency, the roofline of the dominant kernel measured with HIP
-events on its stream, the solve replayed from a captured HIP graph, and the
-CPU oracle timed on a bounded sample.
+events on its stream, the solve replayed from a captured HIP graph, the same
+solve with checkpoints every 50 steps (forward, segment recomputation and
+adjoint), a short serving trace of the mixed request workload (p50/p99
+latency and throughput, offered at 20 requests/s and then at 0.8 of the
+capacity that trace measured), and the CPU oracle timed on a bounded sample.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -62,6 +65,43 @@ def cpu_baseline(N, nu, dt, steps_sample, k0):
                       f"impulse-response solve (NumPy oracle with exact-twiddle DFT matrices), {t:.1f} s"}
 
 
+def serving_leg(n_requests, load, device):
+    """The mixed request workload (grids 128..1024, decaying and Kolmogorov flow, horizons
+    200..2000, strides 4..16, three kernels, 10 L-BFGS iterations each): a trace of n_requests
+    Poisson arrivals at 20/s (the offered rate; the queue grows), then the same requests at
+    `load` times the capacity it measured.  Tiles are autotuned per grid before the traces."""
+    import dataclasses
+    import numpy as np
+    import torch
+    from paper_2602_14016_amd import serving as sv
+    tiles = sv.tile_table(device=device)
+    reqs = sv.make_trace(n_requests, 20.0, seed=0, device=device)
+    out = {"requests": n_requests, "workload": "mixed requests: grids 128..1024, decaying and Kolmogorov flow, "
+           "horizons 200..2000, strides 4..16, kernels identity / exp(-0.05|k|) / |k|^-1, 10 L-BFGS iterations "
+           "each, 4 slots, 200 GB budget", "traces": []}
+    rate = 20.0
+    for label in ("offered", "at_load"):
+        srv = sv.Server(int(200 * (1 << 30)), slots=4, max_batch=8, tiles=tiles)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = srv.run_trace(reqs)
+        wall = time.perf_counter() - t0
+        rep = sv.trace_report(res, reqs, wall)
+        out["traces"].append({"trace": label, "rate_per_s": rate, "p50_s": rep.get("p50_s"), "p99_s": rep.get("p99_s"),
+                              "throughput_req_per_s": rep["throughput_req_per_s"], "completed": rep["completed"],
+                              "batched_requests": rep["batched_solves"], "wall_s": wall})
+        print("serving", json.dumps(out["traces"][-1]), file=sys.stderr, flush=True)
+        if label == "offered":
+            busy = max(r.finished for r in res.values()) - min(r.admitted for r in res.values())
+            capacity = rep["completed"] / busy if busy > 0 else rate
+            out["capacity_req_per_s"] = capacity
+            rate = load * capacity
+            arrivals = sv.poisson_arrivals(n_requests, rate, seed=1)
+            reqs = [dataclasses.replace(r, arrival=float(a), ckpt_every=50) for r, a in zip(reqs, arrivals)]
+    out["load"] = load
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -83,6 +123,12 @@ def main():
     for knob in ("row-variant", "row-teams", "adj-variant", "adj-teams", "col-variant", "col-block"):
         ap.add_argument("--" + knob, type=int, default=-1, help="FFT tile knob (pa_set_tiles); -1: autotuned")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--ckpt-leg", type=int, default=50,
+                    help="also time the solve with checkpoints every this many steps (0: skip)")
+    ap.add_argument("--serving-requests", type=int, default=20,
+                    help="requests of the short serving trace (0: skip)")
+    ap.add_argument("--serving-load", type=float, default=0.8,
+                    help="second serving trace at this fraction of the capacity the first one measured")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one torch copy of this many MiB first (HBM counter calibration)")
     args = ap.parse_args()
@@ -184,14 +230,30 @@ def main():
                  "grid_point_steps_per_s": B * N * N * H / (gms * 1e-3)}
         del cap
 
+    # the same solve with checkpoints every ckpt_leg steps: forward sweep, segment recomputation, adjoint
+    ckpt_leg = None
+    if args.ckpt_leg and args.ckpt_leg < H:
+        Kc = args.ckpt_leg
+        s.adjoint_impulse(w0, H, ix, iy, nshell, ckpt_every=Kc)
+        torch.cuda.synchronize()
+        reps = max(1, min(args.steps, 5))
+        c0 = time.perf_counter()
+        for _ in range(reps):
+            s.adjoint_impulse(w0, H, ix, iy, nshell, ckpt_every=Kc)
+        torch.cuda.synchronize()
+        cms = 1e3 * (time.perf_counter() - c0) / reps
+        ckpt_leg = {"ckpt_every": Kc, "value": B * N * N * H / (cms * 1e-3), "unit": "grid-point-steps/s",
+                    "ms_per_step": cms, "steps": reps}
+
     # plain path: one member per solve, same kernels, solved one after another
+    s.close()
+    del s
+    torch.cuda.empty_cache()
     p = Solver(N, 1, nu=nu, dt=dt, device=dev)
     plain_tiles = None
     if args.plain_solves:
         plain_tiles = tune(p, w0[:1].contiguous())
         plain_tiles.pop("trials", None)
-        s.close()
-        del s
         Kp = ckpt_interval(p)
         plain_tiles["ckpt_every"] = Kp
         p.adjoint_impulse(w0[:1].contiguous(), H, ix, iy, nshell, ckpt_every=Kp)
@@ -228,6 +290,14 @@ def main():
                 "algorithmic_bytes_per_launch": int(bytes_launch),
                 "timed_launches": prof["timed_launches"], "launches": prof["launches"]}
 
+    p.close()
+    del p
+    torch.cuda.empty_cache()
+    serving = None
+    if args.serving_requests:
+        serving = serving_leg(args.serving_requests, args.serving_load, dev)
+        torch.cuda.empty_cache()
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(N, nu, dt, args.cpu_steps, k0)
@@ -250,6 +320,8 @@ def main():
                   "speedup_batched_over_plain": value / plain_value if plain_value else None},
         "roofline": roofline,
         "graph": graph,
+        "checkpointed": ckpt_leg,
+        "serving": serving,
         "tiles": tiles,
         "cpu_baseline": cpu,
     }

@@ -30,7 +30,8 @@ def test_result_line_has_the_contract_keys():
     src = open(BENCH).read()
     line = src[src.index("line = {"):src.index("print(json.dumps(line)")]
     for key in ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step", "higher_is_better",
-                "scaling", "vs_baseline", "dtype", "data", "config", "roofline", "cpu_baseline"):
+                "scaling", "vs_baseline", "dtype", "data", "config", "roofline", "cpu_baseline", "checkpointed",
+                "serving"):
         assert re.search(r'"%s"\s*:' % key, line), key
     roof = src[src.index("roofline = {"):src.index("cpu = None")]
     for key in ("bound", "achieved", "peak", "unit", "frac", "traffic"):
