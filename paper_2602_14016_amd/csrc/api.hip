@@ -129,6 +129,9 @@ struct pa_ctx {
     std::vector<hipEvent_t> prof_ev;   // pairs (start, stop)
     // (kind, metric, param, power) of multiplier tables already found finite on this grid
     std::vector<std::array<double, 4>> mult_checked;
+    // pinned host staging of the optimiser's status reads and mask writes
+    void* pin = nullptr;
+    size_t pin_bytes = 0;
 };
 
 namespace {
@@ -162,8 +165,27 @@ struct WS {
     double *x, *g, *dv, *xt, *gt, *w, *gw;
     double* S;          // [m][B][N*N]
     double* Yv;         // [m][B][N*N]
+    // optimiser scalars per member (ring slot p of member b at [p * B + b])
+    double *oJ, *oalpha, *ogd, *ogg;   // [B] cost at the iterate, trial step, g.d, g.g
+    double *orho, *ogam, *oal;         // [m][B]
+    int *ook, *orun, *opend, *oreset;  // [m][B] stored-pair flags; [B] running, pending, reset
+    // line-search status, copied to the host after each trial: counts[4] (pending,
+    // accepted), acc[B] (accepted this iteration), Jt[B] (accepted trial cost)
+    char* ostat;
     size_t total;
 };
+
+// Layout of the line-search status block of B members.
+struct StatLayout {
+    size_t acc, Jt, bytes;
+};
+StatLayout stat_layout(int B) {
+    StatLayout l;
+    l.acc = 16;
+    l.Jt = (16 + sizeof(int) * (size_t)B + 15) & ~size_t(15);
+    l.bytes = l.Jt + sizeof(double) * (size_t)B;
+    return l;
+}
 
 struct Carver {
     char* base;
@@ -227,6 +249,18 @@ WS carve(const pa_ctx* c, int n_steps, int ckpt_every, int n_obs, int m, void* b
         w.gw = cv.take<double>(SP);
         w.S = cv.take<double>((size_t)m * SP);
         w.Yv = cv.take<double>((size_t)m * SP);
+        w.oJ = cv.take<double>(d.B);
+        w.oalpha = cv.take<double>(d.B);
+        w.ogd = cv.take<double>(d.B);
+        w.ogg = cv.take<double>(d.B);
+        w.orho = cv.take<double>((size_t)m * d.B);
+        w.ogam = cv.take<double>((size_t)m * d.B);
+        w.oal = cv.take<double>((size_t)m * d.B);
+        w.ook = cv.take<int>((size_t)m * d.B);
+        w.orun = cv.take<int>(d.B);
+        w.opend = cv.take<int>(d.B);
+        w.oreset = cv.take<int>(d.B);
+        w.ostat = cv.take<char>(stat_layout(d.B).bytes);
     }
     w.total = cv.off + 256;
     return w;
@@ -1280,6 +1314,7 @@ pa_status pa_destroy(pa_ctx* c) try {
     if (!c) return PA_OK;
     (void)hipStreamSynchronize(c->stream);
     for (hipEvent_t e : c->prof_ev) (void)hipEventDestroy(e);
+    if (c->pin) (void)hipHostFree(c->pin);
     (void)hipFree(c->tw);
     (void)hipFree(c->invk2);
     (void)hipFree(c->ex2);
@@ -1692,38 +1727,45 @@ pa_status pa_precondition(pa_ctx* c, const pa_kernel* k, double power, const dou
 
 namespace {
 
-// Host-side driver state for the batched optimiser.  All O(N^2) work (maps,
-// solves, dot products, axpys) runs on the device; only O(B m) scalars and
-// the accept/reject decisions of the line searches live on the host.
+// Host side of the batched optimiser.  Every O(N^2) operation and every
+// per-member scalar decision of the recursion runs on the device (misc.hip:
+// lbfgs_*); the host keeps only the loop control (which members still run,
+// how many iterations each has completed) and reads one status block per
+// line-search trial.  Transfers go through the context's pinned buffer.
 struct Opt {
     pa_ctx* c;
     WS& w;
     size_t n;        // N*N
     int B;
-    std::vector<double> hbuf;
 
-    pa_status sync() {
+    pa_status pinned(size_t bytes) {
+        if (c->pin_bytes >= bytes) return PA_OK;
+        if (c->pin) (void)hipHostFree(c->pin);
+        c->pin = nullptr;
+        c->pin_bytes = 0;
+        PA_HIP(hipHostMalloc(&c->pin, bytes, hipHostMallocDefault));
+        c->pin_bytes = bytes;
+        return PA_OK;
+    }
+    // device -> host (through the pinned buffer), then wait for it
+    pa_status read(const void* dev, size_t bytes, void* host) {
+        PA_TRY(pinned(bytes));
+        PA_HIP(hipMemcpyAsync(c->pin, dev, bytes, hipMemcpyDeviceToHost, c->stream));
+        PA_HIP(hipStreamSynchronize(c->stream));
+        std::memcpy(host, c->pin, bytes);
+        return PA_OK;
+    }
+    // host -> device (through the pinned buffer, which is free again on return)
+    pa_status write(void* dev, const void* host, size_t bytes) {
+        PA_TRY(pinned(bytes));
+        std::memcpy(c->pin, host, bytes);
+        PA_HIP(hipMemcpyAsync(dev, c->pin, bytes, hipMemcpyHostToDevice, c->stream));
         PA_HIP(hipStreamSynchronize(c->stream));
         return PA_OK;
     }
-    pa_status dot(const double* x, const double* y, std::vector<double>& out) {
-        PA_HIP(launch_dot(B, n, x, y, w.dots, w.partial, c->stream));
-        out.resize(B);
-        PA_HIP(hipMemcpyAsync(out.data(), w.dots, sizeof(double) * B, hipMemcpyDeviceToHost, c->stream));
-        return sync();
-    }
-    pa_status upload(const std::vector<double>& v, double* dst) {
-        PA_HIP(hipMemcpyAsync(dst, v.data(), sizeof(double) * B, hipMemcpyHostToDevice, c->stream));
-        return sync();
-    }
-    pa_status upload_mask(const std::vector<int>& v) {
-        PA_HIP(hipMemcpyAsync(w.active, v.data(), sizeof(int) * B, hipMemcpyHostToDevice, c->stream));
-        return sync();
-    }
-    pa_status read_J(std::vector<double>& out) {
-        out.resize(B);
-        PA_HIP(hipMemcpyAsync(out.data(), w.J, sizeof(double) * B, hipMemcpyDeviceToHost, c->stream));
-        return sync();
+    pa_status sync() {
+        PA_HIP(hipStreamSynchronize(c->stream));
+        return PA_OK;
     }
 };
 
@@ -1845,7 +1887,11 @@ static pa_status assimilate_impl(pa_ctx* c, double* omega_inout, int32_t n_steps
         PA_HIP(launch_make_mult(c->d, k->kind, k->metric, k->param, 0.5, mult_p + b * MT, c->stream));
         PA_HIP(launch_make_mult(c->d, k->kind, k->metric, k->param, -0.5, mult_m + b * MT, c->stream));
     }
-    Opt o{c, w, n, B, {}};
+    Opt o{c, w, n, B};
+    const StatLayout stl = stat_layout(B);
+    int* counts = reinterpret_cast<int*>(w.ostat);
+    int* acc_d = reinterpret_cast<int*>(w.ostat + stl.acc);
+    double* Jt_d = reinterpret_cast<double*>(w.ostat + stl.Jt);
     const std::vector<PlanAct>* plan = plan_for(c, n_segments(n_steps, K));
 
     auto eval_J = [&](const double* x) -> pa_status {
@@ -1857,16 +1903,17 @@ static pa_status assimilate_impl(pa_ctx* c, double* omega_inout, int32_t n_steps
         PA_TRY(backward_sweep(c, w, w.ckpt, n_steps, K, &op, 0, -1, -1, nullptr, w.gw, Shells(), true, plan));
         return apply_filter(c, w, mult_p, w.gw, gout, per_member);
     };
+    auto dev_copy = [&](void* dst, const void* src, size_t bytes) -> pa_status {
+        PA_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, c->stream));
+        return PA_OK;
+    };
 
     for (int i = 0; i < B * (max_iter + 1); ++i) J_hist[i] = NAN;
-    std::vector<double> J(B), Jt(B), gg, gd, alpha(B), coef(B), tmp;
-    std::vector<int> running(B, 1), done(B, 0), pend(B, 0), acc(B, 0), paused(B, 0);
-    // pair ring: push p lives in slot p % m; ok[slot][b] marks a stored pair of member b
-    std::vector<std::vector<int>> ok(m, std::vector<int>(B, 0));
-    std::vector<std::vector<double>> rho(m, std::vector<double>(B, 0.0)), gam(m, std::vector<double>(B, 1.0));
-    std::vector<std::vector<double>> al(m, std::vector<double>(B, 0.0));
-    int head = 0;
-    int it0 = 0;   // iterations completed before this call (the most any member has done)
+    // host loop control: members still iterating, iterations completed, members paused by a cancel flag
+    std::vector<int> running(B, 1), done(B, 0), paused(B, 0);
+    std::vector<double> Jh(B);
+    int head = 0;   // pushes into the pair ring so far: push p lives in slot p % m
+    int it0 = 0;    // iterations completed before this call (the most any member has done)
 
     if (state_in) {
         const unsigned char* h = hs.data();
@@ -1875,21 +1922,19 @@ static pa_status assimilate_impl(pa_ctx* c, double* omega_inout, int32_t n_steps
         it0 = got.iters;
         for (int b = 0; b < B; ++b) {
             int32_t r, d;
-            rd(sl_.J, b, &J[b]);
+            rd(sl_.J, b, &Jh[b]);
             rd(sl_.running, b, &r);
             rd(sl_.done, b, &d);
             running[b] = r;
             done[b] = d;
             if (!running[b]) iters_done[b] = -(done[b] + 1);
-            for (int q = 0; q < m; ++q) {
-                int32_t k;
-                rd(sl_.ok, (size_t)q * B + b, &k);
-                ok[q][b] = k;
-                rd(sl_.rho, (size_t)q * B + b, &rho[q][b]);
-                rd(sl_.gam, (size_t)q * B + b, &gam[q][b]);
-            }
         }
         const unsigned char* d = static_cast<const unsigned char*>(state_in);
+        PA_TRY(dev_copy(w.oJ, d + sl_.J, sizeof(double) * B));
+        PA_TRY(dev_copy(w.orun, d + sl_.running, sizeof(int32_t) * B));
+        PA_TRY(dev_copy(w.ook, d + sl_.ok, sizeof(int32_t) * (size_t)m * B));
+        PA_TRY(dev_copy(w.orho, d + sl_.rho, sizeof(double) * (size_t)m * B));
+        PA_TRY(dev_copy(w.ogam, d + sl_.gam, sizeof(double) * (size_t)m * B));
         PA_HIP(launch_copy(w.x, reinterpret_cast<const double*>(d + sl_.x), SP, c->stream));
         PA_HIP(launch_copy(w.g, reinterpret_cast<const double*>(d + sl_.g), SP, c->stream));
         for (int q = 0; q < m; ++q) {
@@ -1897,124 +1942,90 @@ static pa_status assimilate_impl(pa_ctx* c, double* omega_inout, int32_t n_steps
             PA_HIP(launch_copy(w.Yv + q * SP, reinterpret_cast<const double*>(d + sl_.Y) + q * SP, SP, c->stream));
         }
     } else {
+        PA_HIP(launch_fill_int(w.ook, 0, (size_t)m * B, c->stream));
+        PA_HIP(launch_fill(w.orho, 0.0, (size_t)m * B, c->stream));
+        PA_HIP(launch_fill(w.ogam, 1.0, (size_t)m * B, c->stream));
+        PA_HIP(launch_fill_int(w.orun, 1, B, c->stream));
         PA_TRY(apply_filter(c, w, mult_m, omega_inout, w.x, per_member));
         PA_TRY(eval_J(w.x));
         PA_TRY(eval_grad(w.g));
-        PA_TRY(o.read_J(J));
+        PA_HIP(launch_copy(w.oJ, w.J, B, c->stream));
+        PA_TRY(o.read(w.J, sizeof(double) * B, Jh.data()));
     }
-    for (int b = 0; b < B; ++b) J_hist[(size_t)b * (max_iter + 1)] = J[b];
+    for (int b = 0; b < B; ++b) J_hist[(size_t)b * (max_iter + 1)] = Jh[b];
 
+    std::vector<unsigned char> st(stl.bytes);   // the last trial's status block
     for (int it = 0; it < max_iter; ++it) {
         // members cancelled by the caller (another thread may set their flags at any time) stop here,
         // after their last completed iteration
-        if (c->cancel)
+        if (c->cancel) {
+            bool changed = false;
             for (int b = 0; b < B; ++b)
                 if (running[b] && __atomic_load_n(c->cancel + b, __ATOMIC_ACQUIRE)) {
                     running[b] = 0;
                     paused[b] = 1;
                     iters_done[b] = done[b];
+                    changed = true;
                 }
+            if (changed) PA_TRY(o.write(w.orun, running.data(), sizeof(int) * B));
+        }
         bool any = false;
         for (int b = 0; b < B; ++b) any = any || running[b];
         if (!any) break;
-        // ---- search direction
-        std::vector<int> mem(B, 0);
+        // ---- search direction d = -H g (two-loop recursion over the ring window [lo, hi)); members
+        // without pairs in it get zero coefficients and gamma = 1, i.e. d = -g
+        const int lo = std::max(0, head - m), hi = head;
         if (method == 0) {
-            for (int p = std::max(0, head - m); p < head; ++p)
-                for (int b = 0; b < B; ++b) mem[b] |= ok[p % m][b];
-        }
-        bool any_mem = false;
-        for (int b = 0; b < B; ++b) any_mem = any_mem || (mem[b] && running[b]);
-        if (any_mem) {
-            // two-loop recursion with per-member coefficients (0 for pairs a member does not hold)
             PA_HIP(launch_copy(w.dv, w.g, SP, c->stream));
-            for (int p = head - 1; p >= std::max(0, head - m); --p) {
+            for (int p = hi - 1; p >= lo; --p) {
                 const int sl = p % m;
-                PA_TRY(o.dot(w.S + sl * SP, w.dv, tmp));
-                for (int b = 0; b < B; ++b) {
-                    al[sl][b] = ok[sl][b] ? rho[sl][b] * tmp[b] : 0.0;
-                    coef[b] = -al[sl][b];
-                }
-                PA_TRY(o.upload(coef, w.coef));
+                PA_HIP(launch_dot(B, n, w.S + sl * SP, w.dv, w.dots, w.partial, c->stream));
+                PA_HIP(launch_lbfgs_first(B, sl, w.dots, w.ook, w.orho, w.oal, w.coef, c->stream));
                 PA_HIP(launch_axpy(B, n, w.coef, 1.0, w.Yv + sl * SP, w.dv, nullptr, c->stream));
             }
-            // H0 = gamma I from each member's newest stored pair
-            for (int b = 0; b < B; ++b) {
-                coef[b] = 1.0;
-                for (int p = head - 1; p >= std::max(0, head - m); --p)
-                    if (ok[p % m][b]) { coef[b] = gam[p % m][b]; break; }
-            }
-            PA_TRY(o.upload(coef, w.coef));
+            PA_HIP(launch_lbfgs_gamma(B, m, lo, hi, w.ook, w.ogam, w.coef, c->stream));
             PA_HIP(launch_scal_copy(B, n, w.coef, w.dv, w.dv, c->stream));
-            for (int p = std::max(0, head - m); p < head; ++p) {
+            for (int p = lo; p < hi; ++p) {
                 const int sl = p % m;
-                PA_TRY(o.dot(w.Yv + sl * SP, w.dv, tmp));
-                for (int b = 0; b < B; ++b) coef[b] = ok[sl][b] ? al[sl][b] - rho[sl][b] * tmp[b] : 0.0;
-                PA_TRY(o.upload(coef, w.coef));
+                PA_HIP(launch_dot(B, n, w.Yv + sl * SP, w.dv, w.dots, w.partial, c->stream));
+                PA_HIP(launch_lbfgs_second(B, sl, w.dots, w.ook, w.orho, w.oal, w.coef, c->stream));
                 PA_HIP(launch_axpy(B, n, w.coef, 1.0, w.S + sl * SP, w.dv, nullptr, c->stream));
             }
-            // d = -H g (members without pairs had zero coefficients and gamma = 1: H g = g)
-            for (int b = 0; b < B; ++b) coef[b] = -1.0;
-            PA_TRY(o.upload(coef, w.coef));
+            PA_HIP(launch_fill(w.coef, -1.0, B, c->stream));
             PA_HIP(launch_scal_copy(B, n, w.coef, w.dv, w.dv, c->stream));
         } else {
-            for (int b = 0; b < B; ++b) coef[b] = -1.0;
-            PA_TRY(o.upload(coef, w.coef));
+            PA_HIP(launch_fill(w.coef, -1.0, B, c->stream));
             PA_HIP(launch_scal_copy(B, n, w.coef, w.g, w.dv, c->stream));
         }
-        PA_TRY(o.dot(w.g, w.dv, gd));
-        PA_TRY(o.dot(w.g, w.g, gg));
-        std::vector<int> reset(B, 0);
-        bool any_reset = false;
-        for (int b = 0; b < B; ++b) {
-            if (mem[b] && gd[b] >= 0.0) {
-                reset[b] = 1;
-                any_reset = true;
-                for (int s2 = 0; s2 < m; ++s2) ok[s2][b] = 0;
-                mem[b] = 0;
-                gd[b] = -gg[b];
-            }
-        }
-        if (any_reset) {
-            for (int b = 0; b < B; ++b) coef[b] = -1.0;
-            PA_TRY(o.upload(coef, w.coef));
-            PA_TRY(o.upload_mask(reset));
-            PA_HIP(launch_axpby(B, n, w.coef, 1.0, w.g, nullptr, 0.0, w.g, w.dv, w.active, c->stream));
-        }
-        for (int b = 0; b < B; ++b) alpha[b] = mem[b] ? 1.0 : J[b] / gg[b];
-        // ---- backtracking Armijo line search, per member
+        PA_HIP(launch_dot(B, n, w.g, w.dv, w.ogd, w.partial, c->stream));
+        PA_HIP(launch_dot(B, n, w.g, w.g, w.ogg, w.partial, c->stream));
+        // a member whose d is not a descent direction drops its pairs and takes d = -g
+        PA_HIP(launch_lbfgs_direction(B, m, lo, hi, method == 0, w.ogd, w.ogg, w.oJ, w.ook, w.oreset, w.oalpha,
+                                      w.orun, w.opend, acc_d, c->stream));
+        PA_HIP(launch_fill(w.coef, -1.0, B, c->stream));
+        PA_HIP(launch_axpby(B, n, w.coef, 1.0, w.g, nullptr, 0.0, w.g, w.dv, w.oreset, c->stream));
+        // ---- backtracking Armijo line search, per member; one status read per trial
         PA_HIP(launch_copy(w.xt, w.x, SP, c->stream));
-        for (int b = 0; b < B; ++b) {
-            pend[b] = running[b];
-            acc[b] = 0;
-        }
         for (int trial = 0; trial < 30; ++trial) {
-            bool anyp = false;
-            for (int b = 0; b < B; ++b) anyp = anyp || pend[b];
-            if (!anyp) break;
-            PA_TRY(o.upload(alpha, w.coef));
-            PA_TRY(o.upload_mask(pend));
-            PA_HIP(launch_axpby(B, n, nullptr, 1.0, w.x, w.coef, 1.0, w.dv, w.xt, w.active, c->stream));
+            PA_HIP(launch_axpby(B, n, nullptr, 1.0, w.x, w.oalpha, 1.0, w.dv, w.xt, w.opend, c->stream));
             PA_TRY(eval_J(w.xt));
-            PA_TRY(o.read_J(tmp));
-            for (int b = 0; b < B; ++b) {
-                if (!pend[b]) continue;
-                if (tmp[b] <= J[b] + 1e-4 * alpha[b] * gd[b]) {
-                    pend[b] = 0;
-                    acc[b] = 1;
-                    Jt[b] = tmp[b];
-                } else {
-                    alpha[b] *= 0.5;
-                }
-            }
+            PA_HIP(launch_lbfgs_armijo(B, w.J, w.oJ, w.oalpha, w.ogd, w.opend, acc_d, Jt_d, counts, c->stream));
+            PA_TRY(o.read(w.ostat, stl.bytes, st.data()));
+            int pending;
+            std::memcpy(&pending, st.data(), sizeof(int));
+            if (pending == 0) break;
         }
+        // members still pending failed (step size collapsed); the accepted ones take their trial cost
+        PA_HIP(launch_lbfgs_close(B, w.opend, acc_d, Jt_d, w.orun, w.oJ, c->stream));
+        const int* acc_h = reinterpret_cast<const int*>(st.data() + stl.acc);
+        const double* Jt_h = reinterpret_cast<const double*>(st.data() + stl.Jt);
         bool any_acc = false;
         for (int b = 0; b < B; ++b) {
-            if (pend[b]) {   // step size collapsed
+            if (running[b] && !acc_h[b]) {
                 running[b] = 0;
                 iters_done[b] = -(done[b] + 1);
             }
-            any_acc = any_acc || acc[b];
+            any_acc = any_acc || acc_h[b];
         }
         if (!any_acc) break;
         // the last iteration skips the gradient at the new point, unless a state is kept for a resume
@@ -2026,56 +2037,51 @@ static pa_status assimilate_impl(pa_ctx* c, double* omega_inout, int32_t n_steps
                 const int sl = head % m;
                 PA_HIP(launch_axpby(B, n, nullptr, 1.0, w.xt, nullptr, -1.0, w.x, w.S + sl * SP, nullptr, c->stream));
                 PA_HIP(launch_axpby(B, n, nullptr, 1.0, w.gt, nullptr, -1.0, w.g, w.Yv + sl * SP, nullptr, c->stream));
-                std::vector<double> sy, ss, yy;
-                PA_TRY(o.dot(w.S + sl * SP, w.Yv + sl * SP, sy));
-                PA_TRY(o.dot(w.S + sl * SP, w.S + sl * SP, ss));
-                PA_TRY(o.dot(w.Yv + sl * SP, w.Yv + sl * SP, yy));
-                for (int b = 0; b < B; ++b) {
-                    ok[sl][b] = acc[b] && sy[b] > 1e-10 * std::sqrt(ss[b]) * std::sqrt(yy[b]);
-                    rho[sl][b] = ok[sl][b] ? 1.0 / sy[b] : 0.0;
-                    gam[sl][b] = ok[sl][b] ? sy[b] / yy[b] : 1.0;
-                }
+                double* sy = w.dots;
+                double* ss = w.dots + B;
+                double* yy = w.dots + 2 * B;
+                PA_HIP(launch_dot(B, n, w.S + sl * SP, w.Yv + sl * SP, sy, w.partial, c->stream));
+                PA_HIP(launch_dot(B, n, w.S + sl * SP, w.S + sl * SP, ss, w.partial, c->stream));
+                PA_HIP(launch_dot(B, n, w.Yv + sl * SP, w.Yv + sl * SP, yy, w.partial, c->stream));
+                PA_HIP(launch_lbfgs_pair(B, sl, sy, ss, yy, acc_d, w.ook, w.orho, w.ogam, c->stream));
                 ++head;
             }
-            PA_TRY(o.upload_mask(acc));
-            PA_HIP(launch_axpby(B, n, nullptr, 1.0, w.gt, nullptr, 0.0, w.gt, w.g, w.active, c->stream));
+            PA_HIP(launch_axpby(B, n, nullptr, 1.0, w.gt, nullptr, 0.0, w.gt, w.g, acc_d, c->stream));
         }
-        PA_TRY(o.upload_mask(acc));
-        PA_HIP(launch_axpby(B, n, nullptr, 1.0, w.xt, nullptr, 0.0, w.xt, w.x, w.active, c->stream));
+        PA_HIP(launch_axpby(B, n, nullptr, 1.0, w.xt, nullptr, 0.0, w.xt, w.x, acc_d, c->stream));
         for (int b = 0; b < B; ++b) {
-            if (!acc[b]) continue;
-            J[b] = Jt[b];
+            if (!acc_h[b]) continue;
+            Jh[b] = Jt_h[b];
             ++done[b];
-            J_hist[(size_t)b * (max_iter + 1) + it + 1] = J[b];
+            J_hist[(size_t)b * (max_iter + 1) + it + 1] = Jh[b];
         }
         if (last) break;
     }
     for (int b = 0; b < B; ++b)
         if (running[b]) iters_done[b] = done[b];
     PA_TRY(apply_filter(c, w, mult_p, w.x, omega_inout, per_member));
-    std::vector<unsigned char> out;   // staged header; lives until the stream is synchronised below
     if (state_out) {
         int iters = it0;
         for (int b = 0; b < B; ++b) iters = std::max(iters, done[b]);
         OptHeader hd = want;
         hd.head = head;
         hd.iters = iters;
-        out.assign(sl_.x, 0);
+        // header, running and done flags and kernels from the host; the scalars of the
+        // recursion, the iterate, its gradient and the pairs from the device
+        std::vector<unsigned char> out(sl_.x, 0);
         std::memcpy(out.data(), &hd, sizeof(hd));
         auto wr = [&](size_t off, size_t i, auto v) { std::memcpy(out.data() + off + i * sizeof(v), &v, sizeof(v)); };
         for (int b = 0; b < B; ++b) {
-            wr(sl_.J, b, J[b]);
             wr(sl_.running, b, (int32_t)(running[b] || paused[b]));   // a cancelled member resumes
             wr(sl_.done, b, (int32_t)done[b]);
-            for (int q = 0; q < m; ++q) {
-                wr(sl_.ok, (size_t)q * B + b, (int32_t)ok[q][b]);
-                wr(sl_.rho, (size_t)q * B + b, rho[q][b]);
-                wr(sl_.gam, (size_t)q * B + b, gam[q][b]);
-            }
         }
         std::memcpy(out.data() + sl_.kern, kernels, sizeof(pa_kernel) * nk);
         unsigned char* d = static_cast<unsigned char*>(state_out);
-        PA_HIP(hipMemcpyAsync(d, out.data(), out.size(), hipMemcpyHostToDevice, c->stream));
+        PA_TRY(o.write(d, out.data(), out.size()));
+        PA_TRY(dev_copy(d + sl_.J, w.oJ, sizeof(double) * B));
+        PA_TRY(dev_copy(d + sl_.ok, w.ook, sizeof(int32_t) * (size_t)m * B));
+        PA_TRY(dev_copy(d + sl_.rho, w.orho, sizeof(double) * (size_t)m * B));
+        PA_TRY(dev_copy(d + sl_.gam, w.ogam, sizeof(double) * (size_t)m * B));
         PA_HIP(launch_copy(reinterpret_cast<double*>(d + sl_.x), w.x, SP, c->stream));
         PA_HIP(launch_copy(reinterpret_cast<double*>(d + sl_.g), w.g, SP, c->stream));
         for (int q = 0; q < m; ++q) {
@@ -2086,6 +2092,7 @@ static pa_status assimilate_impl(pa_ctx* c, double* omega_inout, int32_t n_steps
     PA_TRY(o.sync());
     return PA_OK;
 }
+
 
 extern "C" pa_status pa_assimilate(pa_ctx* c, double* omega_inout, int32_t n_steps, const pa_obs* obs,
                                    const pa_kernel* kernel, int32_t method, int32_t max_iter, int32_t lbfgs_m,

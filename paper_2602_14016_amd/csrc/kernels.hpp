@@ -167,6 +167,24 @@ hipError_t launch_ens_stats(const Dims& d, int rows, int n_shells, double inv_co
 hipError_t launch_shell_growth(int B, int rows, int n_shells, const double* shells, double dt, double tau_min,
                                double tau_max, double* mean_out, double* rate_out, hipStream_t s);
 
+// batched L-BFGS scalars on the device (misc.hip): ring slot p of member b at [p * B + b]
+hipError_t launch_fill_int(int* p, int v, size_t n, hipStream_t s);
+hipError_t launch_lbfgs_first(int B, int sl, const double* dots, const int* ok, const double* rho, double* al,
+                              double* coef, hipStream_t s);
+hipError_t launch_lbfgs_gamma(int B, int m, int lo, int hi, const int* ok, const double* gam, double* coef,
+                              hipStream_t s);
+hipError_t launch_lbfgs_second(int B, int sl, const double* dots, const int* ok, const double* rho, const double* al,
+                               double* coef, hipStream_t s);
+hipError_t launch_lbfgs_direction(int B, int m, int lo, int hi, int use_pairs, double* gd, const double* gg,
+                                  const double* J, int* ok, int* reset, double* alpha, const int* running, int* pend,
+                                  int* acc, hipStream_t s);
+hipError_t launch_lbfgs_armijo(int B, const double* Jtrial, const double* J0, double* alpha, const double* gd,
+                               int* pend, int* acc, double* Jt, int* counts, hipStream_t s);
+hipError_t launch_lbfgs_close(int B, const int* pend, const int* acc, const double* Jt, int* running, double* J,
+                              hipStream_t s);
+hipError_t launch_lbfgs_pair(int B, int sl, const double* sy, const double* ss, const double* yy, const int* acc,
+                             int* ok, double* rho, double* gam, hipStream_t s);
+
 constexpr int DOT_BLOCKS = 64;   // partial sums per member in launch_dot
 
 // Events that the next row, column or pipelined-row kernel launched on this

@@ -545,4 +545,195 @@ hipError_t launch_shell_growth(int B, int rows, int n_shells, const double* shel
     return hipGetLastError();
 }
 
+// ------------------------------------------------- L-BFGS on the device --
+// The per-member scalars of the batched L-BFGS / steepest-descent loop live
+// in device arrays; these kernels take the decisions the recursion needs
+// (two-loop coefficients, memory reset, trial step, Armijo test, curvature
+// test) elementwise over the members, in the same operations and order as a
+// host loop would (no contraction into fused multiply-adds), so the iterates
+// do not depend on where the scalars live.  Ring slot p of member b is
+// [p * B + b]; pairs p in [lo, hi) of the ring are the stored window.
+
+namespace {
+__device__ __forceinline__ bool window_has_pair(const int* ok, int B, int b, int m, int lo, int hi) {
+    for (int p = lo; p < hi; ++p)
+        if (ok[(size_t)(p % m) * B + b]) return true;
+    return false;
+}
+}  // namespace
+
+__global__ void fill_int_kernel(int* __restrict__ p, int v, size_t n) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+hipError_t launch_fill_int(int* p, int v, size_t n, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    size_t blocks = (n + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(fill_int_kernel, dim3((unsigned)blocks), dim3(256), 0, s, p, v, n);
+    return hipGetLastError();
+}
+
+// first loop, pair slot sl: al = rho (s . q) where the member holds the pair, else 0; coef = -al
+__global__ void lbfgs_first_kernel(int B, int sl, const double* __restrict__ dots, const int* __restrict__ ok,
+                                   const double* __restrict__ rho, double* __restrict__ al, double* __restrict__ coef) {
+#pragma clang fp contract(off)
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    const size_t i = (size_t)sl * B + b;
+    const double a = ok[i] ? rho[i] * dots[b] : 0.0;
+    al[i] = a;
+    coef[b] = -a;
+}
+// H0 = gamma I from each member's newest stored pair of the window, else 1
+__global__ void lbfgs_gamma_kernel(int B, int m, int lo, int hi, const int* __restrict__ ok,
+                                   const double* __restrict__ gam, double* __restrict__ coef) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    double g = 1.0;
+    for (int p = hi - 1; p >= lo; --p) {
+        const size_t i = (size_t)(p % m) * B + b;
+        if (ok[i]) {
+            g = gam[i];
+            break;
+        }
+    }
+    coef[b] = g;
+}
+// second loop, pair slot sl: coef = al - rho (y . r) where the member holds the pair, else 0
+__global__ void lbfgs_second_kernel(int B, int sl, const double* __restrict__ dots, const int* __restrict__ ok,
+                                    const double* __restrict__ rho, const double* __restrict__ al,
+                                    double* __restrict__ coef) {
+#pragma clang fp contract(off)
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    const size_t i = (size_t)sl * B + b;
+    coef[b] = ok[i] ? al[i] - rho[i] * dots[b] : 0.0;
+}
+// Search-direction checks from gd = g . d and gg = g . g: a member with stored
+// pairs whose d is not a descent direction drops its pairs (reset = 1, d is
+// then set to -g) and takes gd = -gg; the trial step is 1 with pairs, else
+// J / gg.  Opens the line search: pending = running, accepted = 0.
+__global__ void lbfgs_direction_kernel(int B, int m, int lo, int hi, int use_pairs, double* __restrict__ gd,
+                                       const double* __restrict__ gg, const double* __restrict__ J,
+                                       int* __restrict__ ok, int* __restrict__ reset, double* __restrict__ alpha,
+                                       const int* __restrict__ running, int* __restrict__ pend,
+                                       int* __restrict__ acc) {
+#pragma clang fp contract(off)
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    bool mem = use_pairs && window_has_pair(ok, B, b, m, lo, hi);
+    int r = 0;
+    if (mem && gd[b] >= 0.0) {
+        r = 1;
+        for (int s = 0; s < m; ++s) ok[(size_t)s * B + b] = 0;
+        mem = false;
+        gd[b] = -gg[b];
+    }
+    reset[b] = r;
+    alpha[b] = mem ? 1.0 : J[b] / gg[b];
+    pend[b] = running[b];
+    acc[b] = 0;
+}
+// Armijo test of one trial for the pending members: accept (cost kept in Jt)
+// if J <= J0 + c1 alpha gd, else halve alpha.  One block counts the members
+// still pending and those accepted into counts[0..1].
+__global__ void lbfgs_armijo_kernel(int B, const double* __restrict__ Jtrial, const double* __restrict__ J0,
+                                    double* __restrict__ alpha, const double* __restrict__ gd, int* __restrict__ pend,
+                                    int* __restrict__ acc, double* __restrict__ Jt, int* __restrict__ counts) {
+#pragma clang fp contract(off)
+    __shared__ int np[256], na[256];
+    int cp = 0, ca = 0;
+    for (int b = threadIdx.x; b < B; b += blockDim.x) {
+        if (pend[b]) {
+            if (Jtrial[b] <= J0[b] + 1e-4 * alpha[b] * gd[b]) {
+                pend[b] = 0;
+                acc[b] = 1;
+                Jt[b] = Jtrial[b];
+            } else {
+                alpha[b] *= 0.5;
+            }
+        }
+        cp += pend[b];
+        ca += acc[b];
+    }
+    np[threadIdx.x] = cp;
+    na[threadIdx.x] = ca;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            np[threadIdx.x] += np[threadIdx.x + w];
+            na[threadIdx.x] += na[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        counts[0] = np[0];
+        counts[1] = na[0];
+    }
+}
+// After the line search: members still pending failed (running = 0); the
+// accepted ones take their trial cost.
+__global__ void lbfgs_close_kernel(int B, const int* __restrict__ pend, const int* __restrict__ acc,
+                                   const double* __restrict__ Jt, int* __restrict__ running, double* __restrict__ J) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    if (pend[b]) running[b] = 0;
+    if (acc[b]) J[b] = Jt[b];
+}
+// Curvature test of the new pair in slot sl (sy, ss, yy = s.y, s.s, y.y): kept
+// if the member accepted its step and sy > 1e-10 |s| |y|.
+__global__ void lbfgs_pair_kernel(int B, int sl, const double* __restrict__ sy, const double* __restrict__ ss,
+                                  const double* __restrict__ yy, const int* __restrict__ acc, int* __restrict__ ok,
+                                  double* __restrict__ rho, double* __restrict__ gam) {
+#pragma clang fp contract(off)
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    const size_t i = (size_t)sl * B + b;
+    const int k = acc[b] && sy[b] > 1e-10 * sqrt(ss[b]) * sqrt(yy[b]);
+    ok[i] = k;
+    rho[i] = k ? 1.0 / sy[b] : 0.0;
+    gam[i] = k ? sy[b] / yy[b] : 1.0;
+}
+
+static dim3 member_grid(int B) { return dim3((unsigned)((B + 255) / 256)); }
+
+hipError_t launch_lbfgs_first(int B, int sl, const double* dots, const int* ok, const double* rho, double* al,
+                              double* coef, hipStream_t s) {
+    hipLaunchKernelGGL(lbfgs_first_kernel, member_grid(B), dim3(256), 0, s, B, sl, dots, ok, rho, al, coef);
+    return hipGetLastError();
+}
+hipError_t launch_lbfgs_gamma(int B, int m, int lo, int hi, const int* ok, const double* gam, double* coef,
+                              hipStream_t s) {
+    hipLaunchKernelGGL(lbfgs_gamma_kernel, member_grid(B), dim3(256), 0, s, B, m, lo, hi, ok, gam, coef);
+    return hipGetLastError();
+}
+hipError_t launch_lbfgs_second(int B, int sl, const double* dots, const int* ok, const double* rho, const double* al,
+                               double* coef, hipStream_t s) {
+    hipLaunchKernelGGL(lbfgs_second_kernel, member_grid(B), dim3(256), 0, s, B, sl, dots, ok, rho, al, coef);
+    return hipGetLastError();
+}
+hipError_t launch_lbfgs_direction(int B, int m, int lo, int hi, int use_pairs, double* gd, const double* gg,
+                                  const double* J, int* ok, int* reset, double* alpha, const int* running, int* pend,
+                                  int* acc, hipStream_t s) {
+    hipLaunchKernelGGL(lbfgs_direction_kernel, member_grid(B), dim3(256), 0, s, B, m, lo, hi, use_pairs, gd, gg, J, ok,
+                       reset, alpha, running, pend, acc);
+    return hipGetLastError();
+}
+hipError_t launch_lbfgs_armijo(int B, const double* Jtrial, const double* J0, double* alpha, const double* gd,
+                               int* pend, int* acc, double* Jt, int* counts, hipStream_t s) {
+    hipLaunchKernelGGL(lbfgs_armijo_kernel, dim3(1), dim3(256), 0, s, B, Jtrial, J0, alpha, gd, pend, acc, Jt, counts);
+    return hipGetLastError();
+}
+hipError_t launch_lbfgs_close(int B, const int* pend, const int* acc, const double* Jt, int* running, double* J,
+                              hipStream_t s) {
+    hipLaunchKernelGGL(lbfgs_close_kernel, member_grid(B), dim3(256), 0, s, B, pend, acc, Jt, running, J);
+    return hipGetLastError();
+}
+hipError_t launch_lbfgs_pair(int B, int sl, const double* sy, const double* ss, const double* yy, const int* acc,
+                             int* ok, double* rho, double* gam, hipStream_t s) {
+    hipLaunchKernelGGL(lbfgs_pair_kernel, member_grid(B), dim3(256), 0, s, B, sl, sy, ss, yy, acc, ok, rho, gam);
+    return hipGetLastError();
+}
+
 }  // namespace pa
