@@ -205,13 +205,18 @@ class GpuBackend:
 
 class Server:
     def __init__(self, hbm_budget_bytes, slots=4, max_batch=8, device="cuda:0", tiles=None, verbose=False,
-                 backend=None, adaptive_ckpt=True):
+                 backend=None, adaptive_ckpt=True, min_interval_frac=0.5):
         """tiles: optional {N: pa_tiles dict} applied to every solver of grid size N;
         verbose: print one line per finished group; backend: the device work
         (GpuBackend by default; anything with footprint/run/release);
         adaptive_ckpt: give each admitted group the largest checkpoint interval
         that fits its share of the budget (fewer recomputed segments, the same
-        result bit for bit) instead of the requests' own."""
+        result bit for bit) instead of the requests' own; min_interval_frac: a group is
+        trimmed (latest arrivals first) until its checkpoint interval covers at least this
+        fraction of its horizon, so that batching never buys its per-member efficiency with
+        a recomputation sweep over most of the horizon (at 1024^2 a member's whole
+        trajectory is tens of GB, and eight of them would leave segments of a few dozen
+        steps)."""
         self.backend = backend if backend is not None else GpuBackend(slots, device, tiles)
         self.verbose = verbose
         self.budget = int(hbm_budget_bytes)
@@ -223,6 +228,7 @@ class Server:
         self.results = {}
         self.cancelled = set()   # running requests asked to stop
         self.adaptive_ckpt = adaptive_ckpt
+        self.min_interval_frac = float(min_interval_frac)
         self.free_slots = list(range(slots))
         self.t0 = None
 
@@ -273,6 +279,10 @@ class Server:
             if need > self.budget - self.in_use:
                 break   # wait for memory to free up
             K = self._interval(group)
+            while (self.adaptive_ckpt and len(group) > 1
+                   and K < self.min_interval_frac * max(r.n_steps for r in group)):
+                group = group[:-1]
+                K = self._interval(group)
             need = self.backend.footprint(group, K)
             for r in group:
                 self.queue.remove(r)

@@ -248,3 +248,20 @@ def test_admitted_groups_get_the_largest_interval_that_fits():
     r.ckpt_every = 50
     Server(40000, slots=2, backend=be2, adaptive_ckpt=False).run_trace([r])
     assert dict(be2.intervals)[3] == 50
+
+
+def test_groups_are_trimmed_until_their_interval_covers_half_the_horizon():
+    """A group whose checkpoint interval would fall below half its horizon (a recomputation sweep
+    over most of it) loses its latest arrivals until the interval fits or one member is left."""
+    be = IntervalBackend(solve_s=0.01)
+    # share 20000 per slot: B members fit an interval K <= 20000 / B / 10 - 100
+    long = [req(i, n_steps=2000) for i in range(4)]        # B = 4 gives K = 400 < 1000: run one by one
+    short = [req(10 + i, n_steps=800, iters=11) for i in range(4)]   # B = 4 gives K = 400 = 800 / 2: one batch
+    for r in long + short:
+        r.ckpt_every = 50
+    res = Server(40000, slots=2, max_batch=8, backend=be).run_trace(long + short)
+    assert all(r.status == "ok" for r in res.values())
+    assert [res[i].batch for i in range(4)] == [1, 1, 1, 1]
+    assert [res[10 + i].batch for i in range(4)] == [4, 4, 4, 4]
+    got = dict(be.intervals)
+    assert got[0] == 1900 and got[10] == 400
