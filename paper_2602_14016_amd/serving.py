@@ -205,7 +205,7 @@ class GpuBackend:
 
 class Server:
     def __init__(self, hbm_budget_bytes, slots=4, max_batch=8, device="cuda:0", tiles=None, verbose=False,
-                 backend=None, adaptive_ckpt=True, min_interval_frac=0.5):
+                 backend=None, adaptive_ckpt=True, min_interval_frac=0.0):
         """tiles: optional {N: pa_tiles dict} applied to every solver of grid size N;
         verbose: print one line per finished group; backend: the device work
         (GpuBackend by default; anything with footprint/run/release);

@@ -259,7 +259,7 @@ def test_groups_are_trimmed_until_their_interval_covers_half_the_horizon():
     short = [req(10 + i, n_steps=800, iters=11) for i in range(4)]   # B = 4 gives K = 400 = 800 / 2: one batch
     for r in long + short:
         r.ckpt_every = 50
-    res = Server(40000, slots=2, max_batch=8, backend=be).run_trace(long + short)
+    res = Server(40000, slots=2, max_batch=8, backend=be, min_interval_frac=0.5).run_trace(long + short)
     assert all(r.status == "ok" for r in res.values())
     assert [res[i].batch for i in range(4)] == [1, 1, 1, 1]
     assert [res[10 + i].batch for i in range(4)] == [4, 4, 4, 4]
