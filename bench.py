@@ -120,7 +120,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--graph-replays", type=int, default=3,
                     help="also capture the batched solve in a HIP graph and time this many replays (0: skip)")
-    for knob in ("row-variant", "row-teams", "adj-variant", "adj-teams", "col-variant", "col-block"):
+    for knob in ("row-variant", "row-teams", "adj-variant", "adj-teams", "col-variant", "col-block", "col-split"):
         ap.add_argument("--" + knob, type=int, default=-1, help="FFT tile knob (pa_set_tiles); -1: autotuned")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--ckpt-leg", type=int, default=50,
@@ -164,7 +164,7 @@ def main():
     s = Solver(N, B, nu=nu, dt=dt, device=dev)
     w0 = s.init_field(list(range(B)), kind=0, k0=k0, target=0.5)
     torch.cuda.synchronize()
-    knobs = ("row_variant", "row_teams", "adj_variant", "adj_teams", "col_variant", "col_block")
+    knobs = ("row_variant", "row_teams", "adj_variant", "adj_teams", "col_variant", "col_block", "col_split")
     manual = any(getattr(args, k) >= 0 for k in knobs)
 
     def tune(solver, omega0):

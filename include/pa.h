@@ -393,12 +393,17 @@ pa_status pa_shell_growth(pa_ctx* ctx, const double* shells, int32_t rows, int32
  * 2, 4 or 8, capped at 256 threads and 64 KiB of LDS per workgroup; with
  * variant 3, wavefronts per workgroup, capped at 4); col_block =
  * kx columns per column-pass workgroup (1, 2, 4 or 8, with col_block times
- * threads per transform <= 512 and LDS <= 64 KiB).  Results do not depend on
- * the choice beyond rounding of the transforms. */
+ * threads per transform <= 512 and LDS <= 64 KiB); col_split = workgroups
+ * per column that share out the column's output transforms, each recomputing
+ * the input transform (0: chosen per launch, 2 or 4 shares where the launch
+ * has fewer than two wavefronts per SIMD without them; 1, 2 or 4: fixed,
+ * capped at the launch's output count).  Results do not depend on the choice
+ * beyond rounding of the transforms, and not at all on col_split. */
 typedef struct pa_tiles {
     int32_t row_variant, row_teams;
     int32_t adj_variant, adj_teams;
     int32_t col_variant, col_block;
+    int32_t col_split;
 } pa_tiles;
 
 /* Sets the tiles; a negative field keeps its current value (a kept col_block

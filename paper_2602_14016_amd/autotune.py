@@ -5,15 +5,18 @@ transforms (variant 0: more elements per thread; 1: more threads per
 transform; 2: four elements per thread where the length allows; 3, row
 passes only: variant 2's plan in persistent wavefronts that prefetch their
 next rows into LDS) and the workgroup shape (rows per workgroup for the forward and the adjoint row
-passes, kx columns per workgroup for the column pass).  The three passes are
+passes, kx columns per workgroup for the column pass), and for the column
+pass the number of workgroups that share out each column's output transforms
+(0: chosen per launch from the wavefronts it has; 1, 2 or 4 fixed).  The three passes are
 separate kernels reading and writing fixed layouts, so each is tuned on its
 own: every candidate runs a short batched forward + adjoint solve of the
 solver's own shape while the library times that pass's launches with HIP
 events on the solver's stream (pa_profile_start).  Forward rows are scored by
 the right-hand-side row kernel, adjoint rows by the adjoint-product row
-kernel, and the column pass by its forward plus adjoint stage launches.  The
-best of each is applied and returned.  Results depend on the choice only
-through the rounding of the transforms.
+kernel, and the column pass by its forward plus adjoint stage launches; the
+column shares are tried last, on the chosen column tiles.  The best of each
+is applied and returned.  Results depend on the choice only through the
+rounding of the transforms (not at all on the column shares).
 """
 
 import time
@@ -23,6 +26,7 @@ import torch
 ROW_VARIANTS = (0, 1, 2, 3)
 COL_VARIANTS = (0, 1, 2)
 BLOCKS = (1, 2, 4, 8)
+COL_SPLITS = (0, 1, 2, 4)
 ROW_NL, COL_FWD, ROW_ADJ, COL_ADJ = 0, 1, 2, 3
 
 
@@ -67,6 +71,7 @@ def autotune(solver, omega0=None, n_steps=8, reps=2, verbose=False):
         ("adj", ROW_VARIANTS, "adj_variant", "adj_teams", (ROW_ADJ,)),
         ("col", COL_VARIANTS, "col_variant", "col_block", (COL_FWD, COL_ADJ)),
     )
+    solver.set_tiles(col_split=0)
     for name, variants, vkey, bkey, classes in searches:
         best = None
         for v in variants:
@@ -81,6 +86,15 @@ def autotune(solver, omega0=None, n_steps=8, reps=2, verbose=False):
                     best = (ms, v, blk)
         chosen[vkey], chosen[bkey] = best[1], best[2]
         solver.set_tiles(**{vkey: best[1], bkey: best[2]})
+    best = None
+    for sp in COL_SPLITS:
+        solver.set_tiles(col_split=sp)
+        ms = _class_cost(solver, omega0, n_steps, (COL_FWD, COL_ADJ), reps)
+        trials.append({"pass": "split", "variant": sp, "block": chosen["col_block"], "ms": ms})
+        if best is None or ms < best[0]:
+            best = (ms, sp)
+    chosen["col_split"] = best[1]
+    solver.set_tiles(col_split=best[1])
     out = dict(solver.get_tiles())
     out["ms"] = _time_solve(solver, omega0, n_steps, reps)
     out["trials"] = trials

@@ -146,6 +146,7 @@ struct WS {
     double* P0;         // physical scratch [B][N][N]
     double* P1;         // physical scratch [B][N][N]
     cd* omega;
+    cd* omega2;         // the other state buffer: stage D writes the new state there (then swapped)
     cd* acc;
     cd* lam;
     cd* omb;
@@ -224,6 +225,7 @@ WS carve(const pa_ctx* c, int n_steps, int ckpt_every, int n_obs, int m, void* b
     w.P0 = cv.take<double>(SP);
     w.P1 = cv.take<double>(SP);
     w.omega = cv.take<cd>(SC);
+    w.omega2 = cv.take<cd>(SC);
     w.acc = cv.take<cd>(SC);
     w.lam = cv.take<cd>(SC);
     w.omb = cv.take<cd>(SC);
@@ -745,8 +747,12 @@ pa_status run_steps(pa_ctx* c, WS& w, int n0, int n1, int n_total, int K, bool s
                     if (slot >= 0) a.ckpt = ckpt_slot(c, ckpt.base, slot);
                 }
                 if (nn == n1 && !final_fields) a.nout = 0;
+                // the new state goes to the other buffer, so that no workgroup of the launch
+                // overwrites a state another one still reads
+                a.omega_out = w.omega2;
             }
             PA_HIP(timed(c, PROF_COL_FWD, [&] { return launch_col(dn, COL_A + s, a, c->stream); }));
+            if (s == 3) std::swap(w.omega, w.omega2);
         }
     }
     return PA_OK;
@@ -1252,6 +1258,7 @@ pa_status pa_create(const pa_physics* phys, int32_t N, int32_t B, void* hip_stre
     d.atpb = 4;
     d.cvar = 0;
     d.cb = 8;
+    d.csplit = 0;
     while (d.cb > 1 && (d.cb * fft_threads(N, d.cvar) > 512 ||
                         ((size_t)d.cb * (N + N / 16 + 1) + N) * sizeof(cd) > 65536)) d.cb >>= 1;
 
@@ -1348,12 +1355,15 @@ pa_status pa_set_tiles(pa_ctx* c, const pa_tiles* t) try {
         return fail(PA_EINVAL, "row FFT variants must be 0..3, column variants 0..2 (negative keeps)");
     if (!block_ok(t->row_teams) || !block_ok(t->adj_teams) || !block_ok(t->col_block))
         return fail(PA_EINVAL, "row teams and col_block must be 1, 2, 4 or 8 (negative keeps)");
+    if (!(t->col_split < 0 || t->col_split == 0 || t->col_split == 1 || t->col_split == 2 || t->col_split == 4))
+        return fail(PA_EINVAL, "col_split must be 0 (automatic), 1, 2 or 4 (negative keeps)");
     Dims d = c->d;
     if (t->row_variant >= 0) d.var = t->row_variant;
     if (t->row_teams > 0) d.tpb = t->row_teams;
     if (t->adj_variant >= 0) d.avar = t->adj_variant;
     if (t->adj_teams > 0) d.atpb = t->adj_teams;
     if (t->col_variant >= 0) d.cvar = t->col_variant;
+    if (t->col_split >= 0) d.csplit = t->col_split;
     const int T = fft_threads(d.N, d.cvar);
     auto col_fits = [&](int cb) {
         return cb * T <= 512 && ((size_t)cb * (d.N + d.N / 16 + 1) + d.N) * sizeof(cd) <= 65536;
@@ -1440,6 +1450,7 @@ pa_status pa_get_tiles(const pa_ctx* c, pa_tiles* t) try {
     t->adj_teams = c->d.atpb;
     t->col_variant = c->d.cvar;
     t->col_block = c->d.cb;
+    t->col_split = c->d.csplit;
     return PA_OK;
 } PA_CATCH_HOST
 

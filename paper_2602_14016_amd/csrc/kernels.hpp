@@ -33,6 +33,7 @@ struct Dims {
     int var, tpb;    // forward row passes: FFT plan variant (0..3; 3 = pipelined), rows (waves) per workgroup
     int avar, atpb;  // adjoint row passes: FFT plan variant (0..3), rows (waves) per workgroup
     int cvar, cb;    // column pass: FFT plan variant, kx columns per workgroup
+    int csplit;      // column pass: workgroups per column sharing its outputs (0: chosen per launch)
     int cus;         // compute units of the device (persistent grids)
 };
 
@@ -82,6 +83,10 @@ struct ColArgs {
     int final_out;           // adjoint: emit the gradient field instead of Lambda
     int mult_per_member;     // COL_FILTER: multiplier table per member
     int lowpass;             // COL_FIRST_GUESS: keep |kx|, |ky| <= lowpass
+    cd* omega_out;           // COL_D: the new state, in a buffer other than omega (null: in place)
+    int split;               // set by the launcher: the derived fields of a column are shared out
+                             // over this many workgroups (blockIdx.z, round robin); the first also
+                             // writes the compact outputs
 };
 
 struct RowObs {

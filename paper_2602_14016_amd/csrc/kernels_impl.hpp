@@ -497,6 +497,17 @@ __device__ __forceinline__ int band_row(int q, int N, int K, int KY) {
     return -1;
 }
 
+// Position of workgroup `id` of a one-dimensional grid of `n` in an order in
+// which each XCD holds a contiguous run: workgroup id runs on XCD id % XCDS
+// (round-robin dispatch), and that XCD's k-th workgroup takes the k-th entry
+// of its run.  A bijection of 0..n-1 for any n, so only locality depends on it.
+constexpr unsigned XCDS = 8;
+__device__ __forceinline__ unsigned xcd_order(unsigned id, unsigned n) {
+    const unsigned x = id % XCDS, k = id / XCDS;
+    const unsigned q = n / XCDS, r = n % XCDS;   // XCDs below r hold q + 1 workgroups
+    return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + k;
+}
+
 // Up to 512 threads: CB columns of T threads each (CB * T <= 512).
 template <int N, int V, int MODE>
 __global__ void __launch_bounds__(512) col_kernel(Dims d, ColArgs a) {
@@ -508,8 +519,18 @@ __global__ void __launch_bounds__(512) col_kernel(Dims d, ColArgs a) {
     const int CB = d.cb;
     const int c = threadIdx.x % CB, t = threadIdx.x / CB;
     cd* lds = smem + c * lds_team<N>();
-    const int b = blockIdx.y;
-    const int kx0 = blockIdx.x * CB;           // uniform first column of the block
+    // One-dimensional grid of (member, column block, share) in that order,
+    // share fastest.  The hardware hands workgroups to the XCDs round robin by
+    // id; each XCD is given a contiguous run of that order instead, so that the
+    // column blocks of one 128-byte line and the shares of one column meet in
+    // one L2 rather than fetching and writing the line from several.
+    const unsigned wg = xcd_order(blockIdx.x, gridDim.x);
+    const int zs = (int)(wg % (unsigned)a.split);   // share of the derived fields
+    const unsigned cbk = wg / (unsigned)a.split;
+    const unsigned nblk = (unsigned)(d.KXP / CB);
+    const int b = (int)(cbk / nblk);
+    const bool writer = zs == 0;               // the share that writes the compact outputs
+    const int kx0 = (int)(cbk % nblk) * CB;    // uniform first column of the block
     const int kx = kx0 + c;
     constexpr int K = band<N>(), KXP = kx_pad<N>(), KY = 2 * K + 1;
     const bool colok = kx <= K;
@@ -582,9 +603,10 @@ __global__ void __launch_bounds__(512) col_kernel(Dims d, ColArgs a) {
 
     if constexpr (MODE <= COL_FILTER) {
         fft<N, V, false>(v0, t, lds, twl);
-        cd* __restrict__ om = a.omega ? a.omega + cmem : nullptr;
-        cd* __restrict__ ac = a.acc ? a.acc + cmem : nullptr;
-        cd* __restrict__ ck = a.ckpt ? a.ckpt + cmem : nullptr;
+        cd* __restrict__ om = (writer && a.omega) ? (MODE == COL_D && a.omega_out ? a.omega_out : a.omega) + cmem
+                                                  : nullptr;
+        cd* __restrict__ ac = (writer && a.acc) ? a.acc + cmem : nullptr;
+        cd* __restrict__ ck = (writer && a.ckpt) ? a.ckpt + cmem : nullptr;
 #pragma unroll
         for (int m = 0; m < E; ++m) {
             const int r = rowof(m);
@@ -593,7 +615,7 @@ __global__ void __launch_bounds__(512) col_kernel(Dims d, ColArgs a) {
             const bool ins = inS(r);
             if constexpr (MODE == COL_INIT) {
                 const cd s = ins ? v0[m] : czero();
-                stc(om, ci, s);
+                if (om) stc(om, ci, s);
                 if (ck) stc(ck, ci, s);
                 w[m] = s;
             } else if constexpr (MODE == COL_FILTER) {
@@ -607,21 +629,21 @@ __global__ void __launch_bounds__(512) col_kernel(Dims d, ColArgs a) {
                 const double e1 = e2 * e2;
                 const cd wn = s0[m];
                 if constexpr (MODE == COL_A) {
-                    stc(ac, ci, cscale(nl, e1));
+                    if (ac) stc(ac, ci, cscale(nl, e1));
                     w[m] = cscale(mk(wn.x + 0.5 * h * nl.x, wn.y + 0.5 * h * nl.y), e2);
                 } else if constexpr (MODE == COL_B) {
                     const cd q = s1[m];
-                    stc(ac, ci, mk(q.x + 2.0 * e2 * nl.x, q.y + 2.0 * e2 * nl.y));
+                    if (ac) stc(ac, ci, mk(q.x + 2.0 * e2 * nl.x, q.y + 2.0 * e2 * nl.y));
                     w[m] = mk(e2 * wn.x + 0.5 * h * nl.x, e2 * wn.y + 0.5 * h * nl.y);
                 } else if constexpr (MODE == COL_C) {
                     const cd q = s1[m];
-                    stc(ac, ci, mk(q.x + 2.0 * e2 * nl.x, q.y + 2.0 * e2 * nl.y));
+                    if (ac) stc(ac, ci, mk(q.x + 2.0 * e2 * nl.x, q.y + 2.0 * e2 * nl.y));
                     w[m] = mk(e1 * wn.x + h * e2 * nl.x, e1 * wn.y + h * e2 * nl.y);
                 } else {   // COL_D
                     const cd q = s1[m];
                     const double h6 = h / 6.0;
                     const cd s = mk(e1 * wn.x + h6 * (q.x + nl.x), e1 * wn.y + h6 * (q.y + nl.y));
-                    stc(om, ci, s);
+                    if (om) stc(om, ci, s);
                     if (ck) stc(ck, ci, s);
                     w[m] = s;
                 }
@@ -639,7 +661,7 @@ __global__ void __launch_bounds__(512) col_kernel(Dims d, ColArgs a) {
             w[m] = keep ? mk(-dkx * v1[m].y + (double)ky * v0[m].y, dkx * v1[m].x - (double)ky * v0[m].x) : czero();
         }
     } else if constexpr (MODE == COL_FROM_STATE) {
-        cd* __restrict__ om = a.omega ? a.omega + cmem : nullptr;
+        cd* __restrict__ om = (writer && a.omega) ? a.omega + cmem : nullptr;
 #pragma unroll
         for (int m = 0; m < E; ++m) {
             const int r = rowof(m);
@@ -690,8 +712,8 @@ __global__ void __launch_bounds__(512) col_kernel(Dims d, ColArgs a) {
             accumulate(v0, a.inmul[p]);
         }
         const double sc = a.scale ? a.scale[b] : 1.0;
-        cd* __restrict__ lm_p = a.lam + cmem;
-        cd* __restrict__ ob_p = a.omb ? a.omb + cmem : nullptr;
+        cd* __restrict__ lm_p = writer ? a.lam + cmem : nullptr;
+        cd* __restrict__ ob_p = (writer && a.omb) ? a.omb + cmem : nullptr;
 #pragma unroll
         for (int m = 0; m < E; ++m) {
             const int r = rowof(m);
@@ -702,15 +724,15 @@ __global__ void __launch_bounds__(512) col_kernel(Dims d, ColArgs a) {
             const double e1 = e2 * e2;
             if constexpr (MODE == COL_ADJ_C) {
                 const cd lm = s0[m];
-                stc(ob_p, ci, mk(e1 * (lm.x + wb.x), e1 * (lm.y + wb.y)));
+                if (ob_p) stc(ob_p, ci, mk(e1 * (lm.x + wb.x), e1 * (lm.y + wb.y)));
                 w[m] = mk((h / 3.0) * e2 * lm.x + h * e2 * wb.x, (h / 3.0) * e2 * lm.y + h * e2 * wb.y);
             } else if constexpr (MODE == COL_ADJ_B) {
                 const cd lm = s0[m], ob = s1[m];
-                stc(ob_p, ci, mk(ob.x + e2 * wb.x, ob.y + e2 * wb.y));
+                if (ob_p) stc(ob_p, ci, mk(ob.x + e2 * wb.x, ob.y + e2 * wb.y));
                 w[m] = mk((h / 3.0) * e2 * lm.x + 0.5 * h * wb.x, (h / 3.0) * e2 * lm.y + 0.5 * h * wb.y);
             } else if constexpr (MODE == COL_ADJ_A) {
                 const cd lm = s0[m], ob = s1[m];
-                stc(ob_p, ci, mk(ob.x + e2 * wb.x, ob.y + e2 * wb.y));
+                if (ob_p) stc(ob_p, ci, mk(ob.x + e2 * wb.x, ob.y + e2 * wb.y));
                 w[m] = mk((h / 6.0) * e1 * lm.x + 0.5 * h * e2 * wb.x, (h / 6.0) * e1 * lm.y + 0.5 * h * e2 * wb.y);
             } else {   // stage n (with or without sources), COL_ADJ_SRC
                 cd ln = wb;
@@ -718,7 +740,7 @@ __global__ void __launch_bounds__(512) col_kernel(Dims d, ColArgs a) {
                     const cd ob = s1[m];
                     ln = mk(ob.x + wb.x, ob.y + wb.y);
                 }
-                stc(lm_p, ci, ln);
+                if (lm_p) stc(lm_p, ci, ln);
                 w[m] = a.final_out ? cscale(ln, sc) : cscale(ln, h / 6.0);
             }
         }
@@ -728,7 +750,7 @@ __global__ void __launch_bounds__(512) col_kernel(Dims d, ColArgs a) {
     // packed pair half A +- i B is formed from the two multipliers before the
     // transform (the transform is linear)
     const double inv_n2 = 1.0 / ((double)N * (double)N);
-    for (int o = 0; o < a.nout; ++o) {
+    for (int o = zs; o < a.nout; o += a.split) {
         const int f = a.fields[o];
         cd v[E];
 #pragma unroll
@@ -1034,12 +1056,34 @@ hipError_t Launch<N>::row_src(const Dims& d, const RowArgs& a, int impulse, hipS
     PA_ROW_LAUNCH(d.avar, d.atpb, row_src_kernel, N, d, a, impulse);
 }
 
+// Workgroups that share out one column's derived fields.  A launch whose
+// columns cannot keep two wavefronts per SIMD busy (small batches of large
+// grids: 1024^2 has 344 columns) is latency-bound by each column's chain of
+// transforms; each share recomputes the input transform(s) and combine and
+// runs its part of the output transforms, so the chain is shorter and more
+// wavefronts are in flight.  The derived fields are the same whatever the
+// split (each share runs the same operations), so results do not depend on it.
+// d.csplit > 0 fixes the number of shares (capped at the output count);
+// 0 picks 1, 2 or 4 from the wavefronts the launch has without a split.
+template <int N, int V>
+int col_split(const Dims& d, int nout) {
+    if (nout <= 1) return 1;
+    if (d.csplit > 0) return std::min(d.csplit, nout);
+    const long waves = (long)(d.KXP / d.cb) * d.B * ((d.cb * Plan<N, V>::T + 63) / 64);
+    const long target = 8L * std::max(d.cus, 1);   // two wavefronts per SIMD
+    int split = 1;
+    while (split < nout && waves * split < target) split *= 2;
+    return std::min(split, nout);
+}
+
 template <int N, int V, int MODE>
 hipError_t col_mode(const Dims& d, const ColArgs& a, hipStream_t s) {
-    const dim3 grid((unsigned)(d.KXP / d.cb), (unsigned)d.B);
+    ColArgs ak = a;
+    ak.split = col_split<N, V>(d, a.nout);
+    const dim3 grid((unsigned)(d.KXP / d.cb) * (unsigned)d.B * (unsigned)ak.split);
     const dim3 block((unsigned)(d.cb * Plan<N, V>::T));
     const size_t lds = ((size_t)d.cb * lds_team<N>() + N) * sizeof(cd);
-    launch_kernel(col_kernel<N, V, MODE>, grid, block, lds, s, d, a);
+    launch_kernel(col_kernel<N, V, MODE>, grid, block, lds, s, d, ak);
     return hipGetLastError();
 }
 

@@ -42,7 +42,7 @@ class EnsembleAcc(Structure):
                 ("count", ctypes.c_int64)]
 
 
-TILE_FIELDS = ("row_variant", "row_teams", "adj_variant", "adj_teams", "col_variant", "col_block")
+TILE_FIELDS = ("row_variant", "row_teams", "adj_variant", "adj_teams", "col_variant", "col_block", "col_split")
 
 
 class Tiles(Structure):

@@ -188,6 +188,38 @@ def test_tile_variants_gradient_parity(N):
                     assert rel(gh[b], ref[b][1]) < GRAD_TOL, (tiles, b, rel(gh[b], ref[b][1]))
 
 
+@pytest.mark.parametrize("N,B", [(64, 3), (512, 1), (1024, 2)])
+def test_column_shares_bitwise(N, B):
+    """Column launches whose output transforms are shared out over 1, 2 or 4 workgroups per column
+    (each recomputing the input transform), or as many as each launch picks: the forward fields,
+    observations, cost and gradient are bitwise the same, through checkpoint recomputation (the
+    interval is shorter than the horizon) and a horizon whose last step derives no fields; at 64^2
+    they also match the oracle."""
+    from paper_2602_14016_amd import Observations
+    announce("column-shares", N, B)
+    ph = _hit(N, nu=1e-3, dt=2e-3)
+    steps, osteps = 5, [0, 2, 5]
+    w0 = np.stack([O.init_field(N, [60 + b], kind=0, k0=min(8.0, N / 8))[0] for b in range(B)])
+    s = solver(N, B, ph)
+    M = N // 8
+    mo = dev(np.random.default_rng(3).standard_normal((B, len(osteps), 2, M, M)) * 0.1)
+    obs = Observations(8, osteps, mo)
+    res = {}
+    for sp in (1, 2, 4, 0):
+        s.set_tiles(col_variant=1, col_block=2, col_split=sp)
+        f = s.forward(dev(w0), steps, Observations(8, osteps), want_obs=True)
+        J, g = s.adjoint_gradient(dev(w0), steps, obs, ckpt_every=2)
+        res[sp] = [host(f["omega_T"]), host(f["obs"]), host(J), host(g)]
+    for sp in (2, 4, 0):
+        for a, b in zip(res[1], res[sp]):
+            assert np.array_equal(a, b), sp
+    if N == 64:
+        for b in range(B):
+            Jref, gref = O.adjoint_gradient(w0[b], ph, steps, Obs(8, osteps, host(mo)[b]))
+            assert abs(float(res[0][2][b]) - Jref) <= FIELD_TOL * Jref
+            assert rel(res[0][3][b], gref) < GRAD_TOL
+
+
 @pytest.mark.parametrize("N,B", [(64, 64), (128, 48), (256, 24)])
 def test_pipelined_rows_against_plain_rows(N, B):
     """Variant 3 (persistent wavefronts, next row group prefetched into LDS).  Its adjoint rows run
@@ -240,12 +272,15 @@ def test_set_tiles_validation_and_readback():
     announce("tiles-api")
     from paper_2602_14016_amd.native import PaError
     s = solver(256, 1, _hit(256))
-    s.set_tiles(row_variant=2, row_teams=2, adj_variant=1, adj_teams=8, col_variant=1, col_block=4)
+    assert s.get_tiles()["col_split"] == 0            # chosen per launch by default
+    s.set_tiles(row_variant=2, row_teams=2, adj_variant=1, adj_teams=8, col_variant=1, col_block=4, col_split=2)
     assert s.get_tiles() == dict(row_variant=2, row_teams=2, adj_variant=1, adj_teams=8, col_variant=1,
-                                 col_block=4)
+                                 col_block=4, col_split=2)
     s.set_tiles(adj_teams=4)   # others kept
     assert s.get_tiles()["adj_teams"] == 4 and s.get_tiles()["row_variant"] == 2
-    for bad in (dict(row_variant=4), dict(col_variant=3), dict(col_block=3), dict(adj_teams=16)):
+    assert s.get_tiles()["col_split"] == 2
+    for bad in (dict(row_variant=4), dict(col_variant=3), dict(col_block=3), dict(adj_teams=16),
+                dict(col_split=3), dict(col_split=8)):
         with pytest.raises(PaError):
             s.set_tiles(**bad)
     assert s.get_tiles()["col_block"] == 4
@@ -268,8 +303,9 @@ def test_autotune_applies_valid_tiles():
     assert at["col_variant"] in (0, 1, 2)
     for k in ("row_teams", "adj_teams", "col_block"):
         assert at[k] in (1, 2, 4, 8)
+    assert at["col_split"] in (0, 1, 2, 4)
     assert s.get_tiles() == {k: at[k] for k in s.get_tiles()}
-    assert {r["pass"] for r in at["trials"]} == {"row", "adj", "col"}
+    assert {r["pass"] for r in at["trials"]} == {"row", "adj", "col", "split"}
     J, g = s.adjoint_gradient(dev(w0[None]), steps, Observations(4, osteps, dev(mo[None])), ckpt_every=3)
     assert rel(host(g)[0], gref) < GRAD_TOL
 
