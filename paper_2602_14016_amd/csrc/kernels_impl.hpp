@@ -418,6 +418,15 @@ __global__ void __launch_bounds__(256) row_obs_kernel(Dims d, RowArgs a) {
 template <int N, int V>
 constexpr int adj_waves() { return Plan<N, V>::E <= 8 ? 3 : 1; }
 
+// The 1024-point plans of eight values per thread (two wavefronts per row)
+// read their twiddles from the LDS table in the adjoint rows: their 19
+// register factors would spill 64 values per thread at three waves per SIMD,
+// and from LDS the kernel fits in 162 VGPRs.  Measured at 1024^2 with four
+// and eight members: 69.0 -> 55.0 and 131 -> 96 us per launch.  The forward
+// rows keep register twiddles (there LDS is 6-7 % slower).
+template <int N, int V>
+constexpr bool adj_tw_lds() { return (N == 1024 || N == 512) && Plan<N, V>::E == 8; }
+
 // Adjoint products of one row.  The transpose of the tangent right-hand side
 // applied to lambda, with Lam = P lambda, is on the de-aliased band
 //   (1/|k|^2) F[w_x Lam_y - w_y Lam_x] + F[u Lam_x + v Lam_y]
@@ -437,16 +446,28 @@ row_adj_kernel(Dims d, RowArgs a) {
     packed_load<N, V>(L, a.yin[4] + roff, a.yin[5] + roff, t);
     packed_load<N, V>(z1, a.yin[0] + roff, a.yin[1] + roff, t);
     packed_load<N, V>(z2, a.yin[2] + roff, a.yin[3] + roff, t);
-    RowTw<N, V> tr;   // the four transforms of the row share the thread's twiddles
-    row_twiddles<N, V>(tr, t, tw_g, tw_lds);
-    row_fft<N, V, true, WL>(L, t, lds, tr);
-    row_fft<N, V, true, WL>(z1, t, lds, tr);
-    row_fft<N, V, true, WL>(z2, t, lds, tr);
     cd G[E];   // (G1, G2)
+    auto products = [&]() {
 #pragma unroll
-    for (int m = 0; m < E; ++m)
-        G[m] = mk(z1[m].y * L[m].y - z2[m].y * L[m].x, z1[m].x * L[m].x + z2[m].x * L[m].y);
-    row_fft<N, V, false, WL>(G, t, lds, tr);
+        for (int m = 0; m < E; ++m)
+            G[m] = mk(z1[m].y * L[m].y - z2[m].y * L[m].x, z1[m].x * L[m].x + z2[m].x * L[m].y);
+    };
+    if constexpr (adj_tw_lds<N, V>()) {
+        const cd* twl = stage_twiddles<N, V>(tw_lds, tw_g);
+        fft<N, V, true, WL>(L, t, lds, twl);
+        fft<N, V, true, WL>(z1, t, lds, twl);
+        fft<N, V, true, WL>(z2, t, lds, twl);
+        products();
+        fft<N, V, false, WL>(G, t, lds, twl);
+    } else {
+        RowTw<N, V> tr;   // the four transforms of the row share the thread's twiddles
+        row_twiddles<N, V>(tr, t, tw_g, tw_lds);
+        row_fft<N, V, true, WL>(L, t, lds, tr);
+        row_fft<N, V, true, WL>(z1, t, lds, tr);
+        row_fft<N, V, true, WL>(z2, t, lds, tr);
+        products();
+        row_fft<N, V, false, WL>(G, t, lds, tr);
+    }
     pair_store<N, V>(G, t, a.yout[0] + roff, a.yout[1] + roff);
 }
 
