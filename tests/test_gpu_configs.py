@@ -202,7 +202,9 @@ def test_largest_grid_50_steps_against_oracle():
     """The largest grid (1024^2, nu = 1e-4, dt = 5e-4) over 50 steps: the field after 50 steps
     (1e-11) and the cost (1e-11) and gradient (1e-9) of a 3-time window at stride 16 against the
     oracle's, stored at every 4th grid point in each direction by
-    tests/golden/make_oracle_fixtures.py; the gradient recomputes segments of 10 steps."""
+    tests/golden/make_oracle_fixtures.py; the gradient recomputes segments of 10 steps.  Checked
+    with the default tiles and with the two-wavefront transform plans (variants 1 and 2, whose
+    adjoint rows read their twiddles from LDS) and shared column outputs."""
     from paper_2602_14016_amd import Observations, Solver
     print("CASE grid-1024-50", flush=True)
     N, H = 1024, 50
@@ -213,13 +215,18 @@ def test_largest_grid_50_steps_against_oracle():
     wT = s.forward(dev(w0[None]), H)["omega_T"].cpu().numpy()[0]
     ef = rel(wT[::ev, ::ev], ref["omega_T"])
     osteps = [int(x) for x in ref["obs_steps"]]
-    J, g = s.adjoint_gradient(dev(w0[None]), H, Observations(16, osteps, dev(ref["obs"][None])), ckpt_every=10)
-    ej = abs(float(J.cpu()[0]) - float(ref["J"])) / float(ref["J"])
-    eg = rel(g.cpu().numpy()[0][::ev, ::ev], ref["grad"])
-    print(f"CASE grid-1024-50 rel field {ef:.2e} cost {ej:.2e} gradient {eg:.2e}", flush=True)
     assert ef < 1e-11
-    assert ej <= 1e-11
-    assert eg < 1e-9
+    for tiles in ({}, dict(row_variant=1, row_teams=2, adj_variant=1, adj_teams=2, col_variant=1, col_block=2,
+                           col_split=4),
+                  dict(row_variant=2, row_teams=1, adj_variant=2, adj_teams=1, col_variant=2, col_block=1,
+                       col_split=2)):
+        s.set_tiles(**tiles)
+        J, g = s.adjoint_gradient(dev(w0[None]), H, Observations(16, osteps, dev(ref["obs"][None])), ckpt_every=10)
+        ej = abs(float(J.cpu()[0]) - float(ref["J"])) / float(ref["J"])
+        eg = rel(g.cpu().numpy()[0][::ev, ::ev], ref["grad"])
+        print(f"CASE grid-1024-50 {tiles} rel field {ef:.2e} cost {ej:.2e} gradient {eg:.2e}", flush=True)
+        assert ej <= 1e-11, tiles
+        assert eg < 1e-9, tiles
 
 
 def test_largest_grid_gradient_parity():
