@@ -595,29 +595,29 @@ __global__ void __launch_bounds__(512) col_kernel(Dims d, ColArgs a) {
     // compact operands; the adjoint modes issue them after their first input
     // transform, which keeps two input columns, the accumulator and these
     // operands from being live at once (the registers set the occupancy)
-    auto load_compact = [&]() {
+    const bool need1 = (FWD_STAGE && MODE != COL_A) || (ADJ && MODE != COL_ADJ_C && MODE != COL_ADJ_SRC);
+    const bool need0 = !(ADJ && (STAGE_N || MODE == COL_ADJ_SRC));
+    auto load_compact = [&](bool do0, bool do1) {
         const cd* __restrict__ p0 = FWD_STAGE ? a.omega + cmem : ADJ ? a.lam + cmem : a.state_in + cmem;
         const cd* __restrict__ p1 = FWD_STAGE ? a.acc + cmem : (ADJ && MODE != COL_ADJ_SRC) ? a.omb + cmem : nullptr;
-        const bool need1 = (FWD_STAGE && MODE != COL_A) || (ADJ && MODE != COL_ADJ_C && MODE != COL_ADJ_SRC);
-        const bool need0 = !(ADJ && (STAGE_N || MODE == COL_ADJ_SRC));
 #pragma unroll
         for (int m = 0; m < E; ++m) {
-            s0[m] = czero();
-            s1[m] = czero();
+            if (do0) s0[m] = czero();
+            if (do1) s1[m] = czero();
             if (!slot_in_band<N, V>(m)) continue;
             const int r = rowof(m);
             const unsigned ci = cidx(r >= 0 ? r : 0);
-            if (need0) {
+            if (do0 && need0) {
                 const cd x = ldc(p0, ci);
                 s0[m] = r >= 0 ? x : czero();
             }
-            if (need1) {
+            if (do1 && need1) {
                 const cd x = ldc(p1, ci);
                 s1[m] = r >= 0 ? x : czero();
             }
         }
     };
-    if constexpr (FWD_STAGE || MODE == COL_FROM_STATE) load_compact();
+    if constexpr (FWD_STAGE || MODE == COL_FROM_STATE) load_compact(true, true);
     const cd* twl = stage_twiddles<N, V>(smem + CB * lds_team<N>(), a.tw);
 
     cd w[E];   // spectral values handed to the output transforms
@@ -717,9 +717,14 @@ __global__ void __launch_bounds__(512) col_kernel(Dims d, ColArgs a) {
         for (int m = 0; m < E; ++m) w[m] = czero();
         fft<N, V, false>(v0, t, lds, twl);
         accumulate(v0, a.inmul[0]);
+        // a stage with one compact operand has it in flight during the second
+        // input transform; with two, they are issued after it (either one live
+        // through the transform would cost a wave per SIMD)
+        const bool both = need0 && need1;
+        if (!both) load_compact(true, true);
         fft<N, V, false>(v1, t, lds, twl);
         accumulate(v1, a.inmul[1]);
-        load_compact();
+        if (both) load_compact(true, true);
         // observation sources enter at stage n of an observed step only (two more inputs)
         if constexpr (MODE == COL_ADJ_NSRC)
         for (int p = 2; p < a.nin; ++p) {
