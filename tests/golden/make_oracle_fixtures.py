@@ -31,6 +31,16 @@ here from the oracle's seeded initial fields.  The GPU tests load the files
                         t = 0 probes, kernel exp(-0.05 |k|) in the velocity
                         metric, memory 10: the cost after each of 10
                         iterations and the estimates after 1, 5 and 10.
+  c2_grid_lbfgs.npz     L-BFGS at the Kolmogorov configuration's grid and
+                        physics (512^2, nu = 1/40, drag 0.1, f_x = sin 4y,
+                        dt = 1e-3) over a 40-step window: probes at stride 16
+                        at steps 0, 20, 40 from the random-phase field of
+                        seed 1 (k0 = 6, energy 0.5), the interpolated first
+                        guess from the t = 0 probes, kernel |k|^-1 in the
+                        velocity metric, memory 10: the cost after each of 5
+                        iterations and the estimates after 1, 3 and 5, kept at
+                        every 2nd grid point in each direction (the first
+                        guess in full).
   grid1024_50_steps.npz the largest grid (1024^2, nu = 1e-4, dt = 5e-4) over 50
                         steps from the random-phase field of seed 3 (k0 =
                         1024/25, energy 0.5): the field after 50 steps and the
@@ -109,6 +119,25 @@ def c1_grid_lbfgs():
     np.savez(os.path.join(HERE, "c1_grid_lbfgs.npz"), **out)
 
 
+def c2_grid_lbfgs():
+    from oracle.precond import Kernel
+    N, H, stride, every = 512, 40, 16, 2
+    ph = Physics(N=N, nu=1.0 / 40, dt=1e-3, mu=0.1, forcing_amp=1.0, forcing_k=4)
+    osteps = [0, 20, 40]
+    truth = O.init_field(N, [1], kind=0, k0=6.0, target=0.5)[0]
+    _, _, mo = O.forward(truth, ph, H, Obs(stride, osteps))
+    fg = O.first_guess(N, stride, mo[0])
+    kern = Kernel(2, 0.5, 0)
+    out = {"obs_steps": np.array(osteps), "obs": np.asarray(mo), "first_guess": fg, "sample_every": np.array(every)}
+    for k in (1, 3, 5):
+        w, hist, it, status = O.assimilate(fg, ph, H, Obs(stride, osteps, mo), kern, "lbfgs", k, 10)
+        assert status == 0 and it == k, (status, it)
+        out[f"omega_{k}"] = np.asarray(w)[::every, ::every].copy()
+        out[f"J_hist_{k}"] = np.array(hist)
+        print(f"c2 grid L-BFGS: {k} iterations, J {hist[0]:.6e} -> {hist[-1]:.6e}", flush=True)
+    np.savez(os.path.join(HERE, "c2_grid_lbfgs.npz"), **out)
+
+
 def grid1024_50_steps():
     N, H, stride, every = 1024, 50, 16, 4
     ph = Physics(N=N, nu=1e-4, dt=5e-4)
@@ -124,7 +153,7 @@ def grid1024_50_steps():
 
 
 if __name__ == "__main__":
-    which = sys.argv[1:] or ["c1", "ensemble", "c2", "lbfgs", "1024"]
+    which = sys.argv[1:] or ["c1", "ensemble", "c2", "lbfgs", "c2lbfgs", "1024"]
     if "c1" in which:
         c1_full_horizon()
     if "ensemble" in which:
@@ -133,5 +162,7 @@ if __name__ == "__main__":
         c2_100_steps()
     if "lbfgs" in which:
         c1_grid_lbfgs()
+    if "c2lbfgs" in which:
+        c2_grid_lbfgs()
     if "1024" in which:
         grid1024_50_steps()

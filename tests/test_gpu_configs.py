@@ -198,6 +198,36 @@ def test_c1_grid_lbfgs_iterates_against_oracle():
         assert ew < 1e-9
 
 
+def test_c2_grid_lbfgs_iterates_against_oracle():
+    """L-BFGS at the Kolmogorov configuration's grid and physics (512^2, nu = 1/40, drag 0.1,
+    f_x = sin 4y, dt = 1e-3) over a 40-step window (3 observation times, stride 16), kernel
+    |k|^-1, memory 10, from the oracle's interpolated first guess: the cost after each of 5
+    iterations and the estimates after 1, 3 and 5 (at every 2nd grid point) against the oracle's
+    (1e-9), stored by
+    tests/golden/make_oracle_fixtures.py; the gradients recompute segments of 20 steps."""
+    from paper_2602_14016_amd import KernelSpec, Observations, Solver
+    print("CASE c2-grid-lbfgs", flush=True)
+    N, H = 512, 40
+    ref = _golden("c2_grid_lbfgs.npz")
+    osteps = [int(x) for x in ref["obs_steps"]]
+    mo = dev(ref["obs"][None])
+    s = Solver(N, 1, nu=1.0 / 40, dt=1e-3, mu=0.1, forcing_amp=1.0, forcing_k=4)
+    fg = s.first_guess(16, mo[:, 0].contiguous())
+    assert rel(fg.cpu().numpy()[0], ref["first_guess"]) < 1e-13
+    obs = Observations(16, osteps, mo)
+    for k in (1, 3, 5):
+        w, Hh, it = s.assimilate(dev(ref["first_guess"][None]), H, obs, KernelSpec(2, 0.5), "lbfgs", max_iter=k,
+                                 lbfgs_m=10, ckpt_every=20)
+        href = ref[f"J_hist_{k}"]
+        ev = int(ref["sample_every"])
+        ew = rel(w.cpu().numpy()[0][::ev, ::ev], ref[f"omega_{k}"])
+        eh = float(np.max(np.abs(np.array(Hh[0]) - href) / href))
+        print(f"CASE c2-grid-lbfgs {k} iterations: rel omega {ew:.2e}, rel J history {eh:.2e}", flush=True)
+        assert it[0] == k and len(Hh[0]) == len(href) == k + 1
+        assert eh < 1e-9
+        assert ew < 1e-9
+
+
 def test_largest_grid_50_steps_against_oracle():
     """The largest grid (1024^2, nu = 1e-4, dt = 5e-4) over 50 steps: the field after 50 steps
     (1e-11) and the cost (1e-11) and gradient (1e-9) of a 3-time window at stride 16 against the

@@ -728,3 +728,27 @@ def test_stored_oracle_fixtures_are_intact():
     truth2 = O.init_field(512, [1], kind=0, k0=6.0, target=0.5)[0]
     obs20 = O.forward(truth2, ph2, 0, Obs(16, [0]))[2][0]
     assert np.allclose(c2["obs"][0], obs20, rtol=0, atol=1e-13 * np.abs(obs20).max())
+    # the L-BFGS fixtures: shapes, the step-0 probes and the interpolated first guess recomputed,
+    # cost histories finite, decreasing and sharing their prefixes (a longer run repeats a shorter one)
+    for name, N, stride, seed, k0, ph_f, iters in (
+            ("c1_grid_lbfgs.npz", 256, 8, 0, 10.0, ph, (1, 5, 10)),
+            ("c2_grid_lbfgs.npz", 512, 16, 1, 6.0, ph2, (1, 3, 5))):
+        lb = np.load(os.path.join(gold, name))
+        M = N // stride
+        assert lb["obs"].shape[1:] == (2, M, M) and lb["first_guess"].shape == (N, N)
+        tr = O.init_field(N, [seed], kind=0, k0=k0, target=0.5)[0]
+        o0 = O.forward(tr, ph_f, 0, Obs(stride, [0]))[2][0]
+        assert np.allclose(lb["obs"][0], o0, rtol=0, atol=1e-13 * np.abs(o0).max())
+        assert np.allclose(lb["first_guess"], O.first_guess(N, stride, lb["obs"][0]), rtol=0, atol=1e-13)
+        hists = [lb[f"J_hist_{k}"] for k in iters]
+        ev = int(lb["sample_every"]) if "sample_every" in lb else 1
+        for k, h in zip(iters, hists):
+            assert h.shape == (k + 1,) and np.all(np.isfinite(h)) and np.all(np.diff(h) < 0)
+            assert lb[f"omega_{k}"].shape == (N // ev, N // ev) and np.all(np.isfinite(lb[f"omega_{k}"]))
+        for a, b in zip(hists, hists[1:]):   # equal up to the BLAS's summation order
+            assert np.allclose(a, b[:len(a)], rtol=1e-12, atol=0)
+    g1k = np.load(os.path.join(gold, "grid1024_50_steps.npz"))
+    ev = int(g1k["sample_every"])
+    assert g1k["omega_T"].shape == (1024 // ev, 1024 // ev) and g1k["grad"].shape == (1024 // ev, 1024 // ev)
+    assert list(g1k["obs_steps"]) == [0, 25, 50] and g1k["obs"].shape == (3, 2, 64, 64)
+    assert np.all(np.isfinite(g1k["grad"])) and float(g1k["J"]) > 0
