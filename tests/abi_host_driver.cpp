@@ -105,7 +105,7 @@ int main() {
     EXPECT(pa_set_stream(nullptr, nullptr) == PA_EINVAL);
     size_t bytes = 0;
     EXPECT(pa_workspace_bytes(nullptr, 10, 5, 0, 0, &bytes) == PA_EINVAL);
-    pa_tiles t = {1, 2, 1, 2, 1, 2};
+    pa_tiles t = {1, 2, 1, 2, 1, 2, 0};
     EXPECT(pa_set_tiles(nullptr, &t) == PA_EINVAL);
     EXPECT(pa_set_checkpoint_slots(nullptr, 2) == PA_EINVAL);
     EXPECT(pa_set_sobolev(nullptr, 1.0) == PA_EINVAL);
