@@ -173,7 +173,8 @@ def main():
             return solver.get_tiles() | {"autotuned": False}
         at = autotune(solver, omega0, n_steps=8)
         out = {k: at[k] for k in knobs} | {"autotuned": True}
-        out["trials"] = [[r["pass"], r["variant"], r["block"], round(r["ms"], 3)] for r in at["trials"]]
+        out["trials"] = [[r["pass"], r["variant"], r["block"]] + ([r["split"]] if "split" in r else [])
+                         + [round(r["ms"], 3)] for r in at["trials"]]
         print("autotune", json.dumps(out), file=sys.stderr, flush=True)
         return out
 

@@ -393,7 +393,8 @@ pa_status pa_shell_growth(pa_ctx* ctx, const double* shells, int32_t rows, int32
  * 2, 4 or 8, capped at 256 threads and 64 KiB of LDS per workgroup; with
  * variant 3, wavefronts per workgroup, capped at 4); col_block =
  * kx columns per column-pass workgroup (1, 2, 4 or 8, with col_block times
- * threads per transform <= 512 and LDS <= 64 KiB); col_split = workgroups
+ * threads per transform <= 512 and LDS within the device's per-workgroup
+ * limit, 160 KiB on gfx950; the default stays within 64 KiB); col_split = workgroups
  * per column that share out the column's output transforms, each recomputing
  * the input transform (0: chosen per launch, 2 or 4 shares where the launch
  * has fewer than two wavefronts per SIMD without them; 1, 2 or 4: fixed,

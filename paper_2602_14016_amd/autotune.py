@@ -13,9 +13,10 @@ own: every candidate runs a short batched forward + adjoint solve of the
 solver's own shape while the library times that pass's launches with HIP
 events on the solver's stream (pa_profile_start).  Forward rows are scored by
 the right-hand-side row kernel, adjoint rows by the adjoint-product row
-kernel, and the column pass by its forward plus adjoint stage launches; the
-column shares are tried last, on the chosen column tiles.  The best of each
-is applied and returned.  Results depend on the choice only through the
+kernel, and the column pass by its forward plus adjoint stage launches; for
+the column pass every (variant, block) pair is tried with each share count,
+since the best count depends on the block (wide blocks fill a CU alone and
+want fewer shares).  The best of each is applied and returned.  Results depend on the choice only through the
 rounding of the transforms (not at all on the column shares).
 """
 
@@ -73,6 +74,7 @@ def autotune(solver, omega0=None, n_steps=8, reps=2, verbose=False):
     )
     solver.set_tiles(col_split=0)
     for name, variants, vkey, bkey, classes in searches:
+        splits = COL_SPLITS if name == "col" else (None,)
         best = None
         for v in variants:
             for blk in BLOCKS:
@@ -80,21 +82,19 @@ def autotune(solver, omega0=None, n_steps=8, reps=2, verbose=False):
                     solver.set_tiles(**{vkey: v, bkey: blk})
                 except Exception:
                     continue
-                ms = _class_cost(solver, omega0, n_steps, classes, reps)
-                trials.append({"pass": name, "variant": v, "block": blk, "ms": ms})
-                if best is None or ms < best[0]:
-                    best = (ms, v, blk)
+                for sp in splits:
+                    if sp is not None:
+                        solver.set_tiles(col_split=sp)
+                    ms = _class_cost(solver, omega0, n_steps, classes, reps)
+                    trials.append({"pass": name, "variant": v, "block": blk, "ms": ms}
+                                  | ({} if sp is None else {"split": sp}))
+                    if best is None or ms < best[0]:
+                        best = (ms, v, blk, sp)
         chosen[vkey], chosen[bkey] = best[1], best[2]
         solver.set_tiles(**{vkey: best[1], bkey: best[2]})
-    best = None
-    for sp in COL_SPLITS:
-        solver.set_tiles(col_split=sp)
-        ms = _class_cost(solver, omega0, n_steps, (COL_FWD, COL_ADJ), reps)
-        trials.append({"pass": "split", "variant": sp, "block": chosen["col_block"], "ms": ms})
-        if best is None or ms < best[0]:
-            best = (ms, sp)
-    chosen["col_split"] = best[1]
-    solver.set_tiles(col_split=best[1])
+        if best[3] is not None:
+            chosen["col_split"] = best[3]
+            solver.set_tiles(col_split=best[3])
     out = dict(solver.get_tiles())
     out["ms"] = _time_solve(solver, omega0, n_steps, reps)
     out["trials"] = trials

@@ -1252,6 +1252,10 @@ pa_status pa_create(const pa_physics* phys, int32_t N, int32_t B, void* hip_stre
     d.cus = 0;
     if (hipDeviceGetAttribute(&d.cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || d.cus < 1)
         d.cus = 1;
+    d.lds_max = 0;
+    if (hipDeviceGetAttribute(&d.lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess ||
+        d.lds_max < 65536)
+        d.lds_max = 65536;
     d.var = 0;
     d.tpb = 4;
     d.avar = 0;
@@ -1366,7 +1370,7 @@ pa_status pa_set_tiles(pa_ctx* c, const pa_tiles* t) try {
     if (t->col_split >= 0) d.csplit = t->col_split;
     const int T = fft_threads(d.N, d.cvar);
     auto col_fits = [&](int cb) {
-        return cb * T <= 512 && ((size_t)cb * (d.N + d.N / 16 + 1) + d.N) * sizeof(cd) <= 65536;
+        return cb * T <= 512 && ((size_t)cb * (d.N + d.N / 16 + 1) + d.N) * sizeof(cd) <= (size_t)d.lds_max;
     };
     if (t->col_block > 0) {
         if (!col_fits(t->col_block)) return fail(PA_EINVAL, "col_block too large for this N and column FFT variant");

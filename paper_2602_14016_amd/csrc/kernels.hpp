@@ -35,6 +35,7 @@ struct Dims {
     int cvar, cb;    // column pass: FFT plan variant, kx columns per workgroup
     int csplit;      // column pass: workgroups per column sharing its outputs (0: chosen per launch)
     int cus;         // compute units of the device (persistent grids)
+    int lds_max;     // bytes of LDS a workgroup may use on the device (column blocks beyond 64 KiB)
 };
 
 // Column-pass outputs: the field itself, or one half of a packed pair

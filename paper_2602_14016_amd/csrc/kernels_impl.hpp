@@ -1109,6 +1109,17 @@ hipError_t col_mode(const Dims& d, const ColArgs& a, hipStream_t s) {
     const dim3 grid((unsigned)(d.KXP / d.cb) * (unsigned)d.B * (unsigned)ak.split);
     const dim3 block((unsigned)(d.cb * Plan<N, V>::T));
     const size_t lds = ((size_t)d.cb * lds_team<N>() + N) * sizeof(cd);
+    // Column blocks wider than 64 KiB of LDS (1024-point columns, four or more
+    // per workgroup): the kernel's dynamic LDS limit is raised to the
+    // device's once per instantiation.  Such a block fills a CU alone, so it
+    // pays only where a launch has few columns (one 1024^2 member: 25.1
+    // against 26.8 us per forward stage); the autotuner decides.
+    if (lds > 65536) {
+        static const hipError_t raised = hipFuncSetAttribute(
+            reinterpret_cast<const void*>(&col_kernel<N, V, MODE>), hipFuncAttributeMaxDynamicSharedMemorySize,
+            d.lds_max);
+        if (raised != hipSuccess) return raised;
+    }
     launch_kernel(col_kernel<N, V, MODE>, grid, block, lds, s, d, ak);
     return hipGetLastError();
 }

@@ -233,8 +233,9 @@ def test_largest_grid_50_steps_against_oracle():
     (1e-11) and the cost (1e-11) and gradient (1e-9) of a 3-time window at stride 16 against the
     oracle's, stored at every 4th grid point in each direction by
     tests/golden/make_oracle_fixtures.py; the gradient recomputes segments of 10 steps.  Checked
-    with the default tiles and with the two-wavefront transform plans (variants 1 and 2, whose
-    adjoint rows read their twiddles from LDS) and shared column outputs."""
+    with the default tiles, with the two-wavefront transform plans (variants 1 and 2, whose
+    adjoint rows read their twiddles from LDS) and shared column outputs, and with column blocks
+    whose LDS exceeds 64 KiB."""
     from paper_2602_14016_amd import Observations, Solver
     print("CASE grid-1024-50", flush=True)
     N, H = 1024, 50
@@ -249,7 +250,9 @@ def test_largest_grid_50_steps_against_oracle():
     for tiles in ({}, dict(row_variant=1, row_teams=2, adj_variant=1, adj_teams=2, col_variant=1, col_block=2,
                            col_split=4),
                   dict(row_variant=2, row_teams=1, adj_variant=2, adj_teams=1, col_variant=2, col_block=1,
-                       col_split=2)):
+                       col_split=2),
+                  dict(col_variant=1, col_block=4, col_split=2),     # 84 KiB of LDS per workgroup
+                  dict(col_variant=0, col_block=8, col_split=4)):    # 152 KiB
         s.set_tiles(**tiles)
         J, g = s.adjoint_gradient(dev(w0[None]), H, Observations(16, osteps, dev(ref["obs"][None])), ckpt_every=10)
         ej = abs(float(J.cpu()[0]) - float(ref["J"])) / float(ref["J"])
