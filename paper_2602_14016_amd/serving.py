@@ -421,14 +421,19 @@ def make_trace(n, rate, seed=0, iters=10, grids=GRIDS, h_range=(200, 2000), stri
     return reqs
 
 
-def tile_table(grids=GRIDS, device="cuda:0"):
-    """One autotuned tile set per grid size (at B = 1), fixed for the whole trace."""
+def tile_table(grids=GRIDS, device="cuda:0", batch=4):
+    """One autotuned tile set per grid size, fixed for the whole trace so that a request's result
+    does not depend on its batch (the plan variants set the rounding).  It is tuned on a batch of
+    `batch` members, the size the groups of a loaded server run at (tuned on one member, the
+    1024^2 set took the one-wavefront adjoint-row plan and wide column blocks, 25-40 % slower per
+    launch at four to eight members); the column share count is left to each launch (0), which
+    gives one-member launches their shares."""
     from .autotune import autotune
     table = {}
     for N in grids:
-        sv = Solver(N, 1, device=device, **physics_for(DECAYING, N))
-        at = autotune(sv, n_steps=4)
-        table[N] = sv.get_tiles()
+        sv = Solver(N, batch, device=device, **physics_for(DECAYING, N))
+        autotune(sv, n_steps=4)
+        table[N] = sv.get_tiles() | {"col_split": 0}
         sv.close()
     return table
 
