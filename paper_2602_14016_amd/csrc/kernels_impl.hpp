@@ -529,9 +529,15 @@ __device__ __forceinline__ unsigned xcd_order(unsigned id, unsigned n) {
     return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + k;
 }
 
+// Occupancy hint for the column pass: three waves per SIMD (168 VGPRs) for the
+// plans of up to eight values per thread; sixteen values per thread are left
+// unconstrained (a cap there spills hundreds of bytes).
+template <int N, int V>
+constexpr int col_waves() { return Plan<N, V>::E <= 8 ? 3 : 1; }
+
 // Up to 512 threads: CB columns of T threads each (CB * T <= 512).
 template <int N, int V, int MODE>
-__global__ void __launch_bounds__(512) col_kernel(Dims d, ColArgs a) {
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(col_waves<N, V>()))) col_kernel(Dims d, ColArgs a) {
     constexpr int T = Plan<N, V>::T, E = Plan<N, V>::E;
     constexpr bool FWD_STAGE = MODE >= COL_A && MODE <= COL_D;
     constexpr bool ADJ = (MODE >= COL_ADJ_C && MODE <= COL_ADJ_SRC) || MODE == COL_ADJ_NSRC;
@@ -717,14 +723,15 @@ __global__ void __launch_bounds__(512) col_kernel(Dims d, ColArgs a) {
         for (int m = 0; m < E; ++m) w[m] = czero();
         fft<N, V, false>(v0, t, lds, twl);
         accumulate(v0, a.inmul[0]);
-        // a stage with one compact operand has it in flight during the second
-        // input transform; with two, they are issued after it (either one live
-        // through the transform would cost a wave per SIMD)
+        // compact operands in flight during the second input transform: a
+        // stage's only one, or of two (B and A) lambda, up to 256 points; from
+        // 512 points the pair is issued after it (lambda live through the
+        // transform spills there under the three-wave cap)
         const bool both = need0 && need1;
-        if (!both) load_compact(true, true);
+        if (!both || N <= 256) load_compact(true, !both);
         fft<N, V, false>(v1, t, lds, twl);
         accumulate(v1, a.inmul[1]);
-        if (both) load_compact(true, true);
+        if (both) load_compact(N > 256, true);
         // observation sources enter at stage n of an observed step only (two more inputs)
         if constexpr (MODE == COL_ADJ_NSRC)
         for (int p = 2; p < a.nin; ++p) {
