@@ -191,10 +191,11 @@ def test_tile_variants_gradient_parity(N):
 @pytest.mark.parametrize("N,B", [(64, 3), (512, 1), (1024, 2)])
 def test_column_shares_bitwise(N, B):
     """Column launches whose output transforms are shared out over 1, 2 or 4 workgroups per column
-    (each recomputing the input transform), or as many as each launch picks: the forward fields,
-    observations, cost and gradient are bitwise the same, through checkpoint recomputation (the
-    interval is shorter than the horizon) and a horizon whose last step derives no fields; at 64^2
-    they also match the oracle."""
+    (each recomputing the input transform), or as many as each launch picks, and from 512 points
+    column blocks whose LDS exceeds the default 64 KiB: the forward fields, observations,
+    cost and gradient are bitwise the same, through checkpoint recomputation (the interval is
+    shorter than the horizon) and a horizon whose last step derives no fields; at 64^2 they also
+    match the oracle."""
     from paper_2602_14016_amd import Observations
     announce("column-shares", N, B)
     ph = _hit(N, nu=1e-3, dt=2e-3)
@@ -210,7 +211,13 @@ def test_column_shares_bitwise(N, B):
         f = s.forward(dev(w0), steps, Observations(8, osteps), want_obs=True)
         J, g = s.adjoint_gradient(dev(w0), steps, obs, ckpt_every=2)
         res[sp] = [host(f["omega_T"]), host(f["obs"]), host(J), host(g)]
-    for sp in (2, 4, 0):
+    if N >= 512:
+        # 512 threads per workgroup: 70 KiB of LDS at 512 points (eight columns), 86 KiB at 1024 (four)
+        s.set_tiles(col_variant=1, col_block=8 if N == 512 else 4, col_split=0)
+        f = s.forward(dev(w0), steps, Observations(8, osteps), want_obs=True)
+        J, g = s.adjoint_gradient(dev(w0), steps, obs, ckpt_every=2)
+        res["wide"] = [host(f["omega_T"]), host(f["obs"]), host(J), host(g)]
+    for sp in [k for k in res if k != 1]:
         for a, b in zip(res[1], res[sp]):
             assert np.array_equal(a, b), sp
     if N == 64:
