@@ -2,9 +2,10 @@
 C ABI against the oracle: grid 8..64, 1..3 members, horizon 1..10 steps, any
 checkpoint interval (ragged last segments included) and snapshot budget
 (binomial schedule), any observation stride and set of observed steps, random
-viscosity, drag and forcing.  The cost of
-every member within 1e-11 and its gradient within 1e-9 (relative), as the
-fixed parity cases."""
+viscosity, drag and forcing; and problems up to 128^2 under randomly drawn tile
+settings (plans, workgroup shapes, column shares).  The cost of every member
+within 1e-11 and its gradient within 1e-9 (relative), as the fixed parity
+cases."""
 
 import numpy as np
 import pytest
@@ -144,3 +145,48 @@ def test_random_impulse_cases_against_oracle(p):
         rows = np.asarray(rows)
         assert np.linalg.norm(shh[b] - rows) <= 1e-9 * np.linalg.norm(rows), b
         assert np.linalg.norm(fh[b] - field) <= 1e-9 * np.linalg.norm(field), b
+
+
+@st.composite
+def tiled_problems(draw):
+    N = draw(st.sampled_from([16, 32, 64, 128]))
+    B = draw(st.integers(1, 4))
+    steps = draw(st.integers(1, 6))
+    K = draw(st.integers(1, 6))
+    osteps = sorted(draw(st.sets(st.integers(0, steps), min_size=1, max_size=3)))
+    ph = Physics(N=N, nu=draw(st.floats(1e-4, 1e-2)), dt=draw(st.floats(1e-3, 6e-3)))
+    tiles = dict(row_variant=draw(st.integers(0, 3)), row_teams=draw(st.sampled_from([1, 2, 4, 8])),
+                 adj_variant=draw(st.integers(0, 3)), adj_teams=draw(st.sampled_from([1, 2, 4, 8])),
+                 col_variant=draw(st.integers(0, 2)), col_block=draw(st.sampled_from([1, 2, 4, 8])),
+                 col_split=draw(st.sampled_from([0, 1, 2, 4])))
+    seed = draw(st.integers(0, 10 ** 6))
+    return N, B, steps, K, osteps, ph, tiles, seed
+
+
+@settings(max_examples=20, deadline=None, derandomize=True)
+@given(p=tiled_problems())
+def test_random_tiles_against_oracle(p):
+    """Randomly drawn problems under randomly drawn tiles: FFT plan per pass, teams per workgroup,
+    column block width and column shares (a setting the library refuses for the grid keeps the
+    previous one).  Cost within 1e-11 and gradient within 1e-9 of the oracle for every member."""
+    from paper_2602_14016_amd import Observations, Solver
+    from paper_2602_14016_amd.native import PaError
+    N, B, steps, K, osteps, ph, tiles, seed = p
+    w0 = O.init_field(N, [seed + b for b in range(B)], kind=0, k0=min(4.0, N / 4))
+    mo = np.stack([O.forward(O.init_field(N, [seed + 100 + b], kind=0, k0=min(4.0, N / 4))[0], ph, steps,
+                             Obs(4, osteps))[2] for b in range(B)])
+    s = Solver(N, B, nu=ph.nu, dt=ph.dt)
+    for k, v in tiles.items():   # in order: a block width is checked against its plan
+        try:
+            s.set_tiles(**{k: v})
+        except PaError:
+            pass
+    print("CASE random-tiles", N, B, steps, K, osteps, seed, s.get_tiles(), flush=True)
+    J, g = s.adjoint_gradient(torch.from_numpy(w0).cuda(), steps, Observations(4, osteps, torch.from_numpy(mo).cuda()),
+                              ckpt_every=K)
+    torch.cuda.synchronize()
+    Jh, gh = J.cpu().numpy(), g.cpu().numpy()
+    for b in range(B):
+        Jr, gr = O.adjoint_gradient(w0[b], ph, steps, Obs(4, osteps, mo[b]))
+        assert abs(float(Jh[b]) - Jr) <= 1e-11 * Jr, (b, float(Jh[b]), Jr)
+        assert np.linalg.norm(gh[b] - gr) <= 1e-9 * np.linalg.norm(gr), b
